@@ -1,0 +1,188 @@
+"""Pins of the oracle's full step against closed forms and exact identities.
+
+- Poiseuille channel (walls halfway outside the outermost nodes, Guo body
+  force): the steady BGK solution with simple bounce-back is the parabola
+  u(y) = g/(2 nu) [(H/2)^2 - y^2] + g/nu (16 L - 3)/24, L = (tau - 1/2)^2,
+  nu = (tau - 1/2)/3; at tau = 1/2 + sqrt(3)/4 the slip term vanishes.
+- Bounce-back on a resting body conserves fluid mass exactly, and the
+  fluid momentum changes by exactly (body force) - (momentum-exchange force)
+  per step (sec. 2.3.2, MEM paragraph).
+- A body moving with a uniform flow leaves the equilibrium f = feq(rho0, U)
+  unchanged through interpolated bounce-back, covering and refilling
+  (sec. 2.3.2, Eqs. eqneq1-neqd and the refilling equation), with zero force.
+- Drag on a simple-cubic array of spheres (Hasimoto 1959; Sangani & Acrivos
+  1982): K = F/(6 pi mu R U) = 1/(1 - 1.7601 c^(1/3) + c - 1.5593 c^2).
+- The refilled-node count equals the brute-force count of nodes that are
+  solid before and fluid after a step.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from test_oracle_geometry import brute_flags
+
+
+def poiseuille_profile(tau, H, g):
+    nu = (tau - 0.5) / 3
+    lam = (tau - 0.5) ** 2
+    eta = np.arange(H) - (H - 1) / 2
+    return g / (2 * nu) * ((H / 2) ** 2 - eta ** 2) + g / nu * (16 * lam - 3) / 24
+
+
+@pytest.mark.parametrize("tau", [0.8, 0.5 + np.sqrt(3) / 4, 1.2])
+def test_poiseuille_closed_form(tau):
+    H, g = 32, 1e-6
+    cfg = workloads.poiseuille(tau, H=H, g=g)
+    o = oracle.Oracle(cfg)
+    o.step(40000 if tau < 1 else 25000)
+    rho, u = o.macros()
+    ux = u[:, 0].reshape(cfg.nz, cfg.ny, cfg.nx)
+    ua = poiseuille_profile(tau, H, g)
+    assert np.abs(ux - ua[None, :, None]).max() / ua.max() < 1e-10
+    assert np.abs(u[:, 1:]).max() < 1e-9 * ua.max()
+    assert np.abs(rho - 1.0).max() < 1e-11
+
+
+def test_poiseuille_slip_term_vanishes_at_magic_tau():
+    tau = 0.5 + np.sqrt(3) / 4
+    prof = poiseuille_profile(tau, 16, 1e-6)
+    nu = (tau - 0.5) / 3
+    eta = np.arange(16) - 7.5
+    assert np.allclose(prof, 1e-6 / (2 * nu) * (64 - eta ** 2), rtol=1e-14)
+
+
+@pytest.mark.parametrize("bc", [workloads.BC_SBB, workloads.BC_IBB])
+def test_mass_and_momentum_identities_resting_body(bc):
+    cfg = workloads.config1(bc=bc, n=32)
+    cfg.particles[0].cp_k = np.array([36.0])
+    cfg.g_fluid = np.array([2e-5, -1e-5, 5e-6])
+    o = oracle.Oracle(cfg)
+    e, _, _ = oracle.lattice()
+    fl = o.owner() < 0
+    f = o.f()
+    M0 = f[:, fl].sum()
+    P0 = (e.T.astype(float) @ f[:, fl]).sum(1)
+    for _ in range(6):
+        o.step(1)
+        f = o.f()
+        M1 = f[:, fl].sum()
+        P1 = (e.T.astype(float) @ f[:, fl]).sum(1)
+        F = o.particle(0)["F"]
+        if bc == workloads.BC_SBB:
+            assert abs(M1 - M0) / M0 < 1e-13
+        expect = P0 + cfg.g_fluid * M0 - F
+        assert np.abs(P1 - expect).max() < 1e-13 * M0 * np.abs(cfg.g_fluid).max() * 1e3
+        M0, P0 = M1, P1
+
+
+@pytest.mark.parametrize("bc", [workloads.BC_SBB, workloads.BC_IBB])
+def test_comoving_body_keeps_equilibrium(bc):
+    U = np.array([0.02, 0.011, -0.007])
+    cfg = workloads.comoving(U=U, n=24, bc=bc)
+    o = oracle.Oracle(cfg)
+    feq = oracle.feq(1.0, U)
+    o.set_f(np.tile(feq[:, None], (1, o.N)))
+    refilled = 0
+    for _ in range(60):
+        o.step(1)
+        refilled += o.n_refilled
+        fl = o.owner() < 0
+        f = o.f()
+        assert np.abs(f[:, fl] - feq[:, None]).max() < 1e-14
+        assert np.abs(o.particle(0)["F"]).max() < 1e-13
+    assert refilled > 20  # the body moved across nodes, so refilling was exercised
+
+
+def sangani_acrivos_K(c):
+    chi = c ** (1.0 / 3.0)
+    return 1.0 / (1.0 - 1.7601 * chi + chi ** 3 - 1.5593 * chi ** 6)
+
+
+def test_drag_periodic_sphere_array():
+    """32^3 cell, R = 4 (c = 0.00818, K = 1.5304), tau = 0.8, interpolated
+    bounce-back.  The fluid starts at a uniform velocity near the steady
+    value so that only the fast spatial transients need to decay;
+    K is formed from the instantaneous force and mean (superficial) velocity."""
+    L, R, tau, g = 32, 4.0, 0.8, 1e-6
+    cfg = workloads.drag_array(L=L, R=R, tau=tau, g=g)
+    o = oracle.Oracle(cfg)
+    mu = (tau - 0.5) / 3
+    c = 4 / 3 * np.pi * R ** 3 / L ** 3
+    K = sangani_acrivos_K(c)
+    assert K == pytest.approx(1.5304, abs=1e-4)
+    fl = o.owner() < 0
+    U0 = g * fl.sum() / (6 * np.pi * mu * R * K) * L ** 3 / fl.sum()
+    o.set_f(np.tile(oracle.feq(1.0, [U0, 0, 0])[:, None], (1, o.N)))
+    Ks = []
+    for _ in range(3):
+        o.step(500)
+        rho, u = o.macros()
+        Ks.append(o.particle(0)["F"][0] / (6 * np.pi * mu * R * u[fl, 0].sum() / L ** 3))
+    assert abs(Ks[-1] - Ks[-2]) < 2e-3 * K  # settled
+    assert Ks[-1] == pytest.approx(K, rel=0.02)
+
+
+def test_refill_count_matches_brute_force():
+    cfg = workloads.small_settling(n=24, nz=40, R=4.0, g=2e-3)
+    o = oracle.Oracle(cfg)
+    total = 0
+    for _ in range(25):
+        lab0, k0 = o.cps(0)
+        own0, _ = brute_flags(cfg, [(lab0, k0)])
+        o.step(1)
+        lab1, k1 = o.cps(0)
+        own1, _ = brute_flags(cfg, [(lab1, k1)])
+        assert np.array_equal(o.owner(), own1)
+        expect = int(((own0 >= 0) & (own1 < 0)).sum())
+        assert o.n_refilled == expect
+        total += expect
+    assert total > 0
+
+
+@pytest.mark.parametrize("bc", [workloads.BC_SBB, workloads.BC_IBB])
+def test_bounce_back_in_rigid_motion_field(bc):
+    """Fluid at equilibrium with the rigid-body field u(x) = v + w x (x - X)
+    of a kinematic body (no body force).  Both of the paper's interpolants
+    are linear in position, so for this linear field u_d is exactly the
+    velocity at the departure point x_f + (1 - 2q) e_i, and after one step
+    every cut link carries
+        IBB: feq_ib(rho0, u(x_f + (1-2q) e_i)) + 6 w rho0 e_i . u(x_f - q e_i)
+        SBB (or x_f + e_i not fluid): feq_ib(rho0, u(x_f)) + 6 w rho0 e_i . u(x_f - e_i/2).
+    """
+    n = 24
+    off, k = workloads.random_body(np.random.Generator(np.random.PCG64(5)), 5, 4.0)
+    v = np.array([0.003, -0.002, 0.004])
+    w = np.array([0.0005, 0.0011, -0.0007])
+    p = workloads.Particle(cp_xyz=off, cp_k=k, x=np.array([12.2, 11.7, 12.4]), v=v, omega=w,
+                           density=1.0, mode=workloads.MODE_KINEMATIC)
+    cfg = workloads.Config(nx=n, ny=n, nz=n, periodic=7, tau=0.7, bc=bc, particles=[p])
+    o = oracle.Oracle(cfg)
+    X = o.particle(0)["x"]
+    e, wt, op = oracle.lattice()
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(float)
+
+    def field(P):
+        return v + np.cross(w, P - X)
+
+    U = field(pts)
+    f0 = np.stack([oracle.feq(1.0, uu) for uu in U], 1)
+    o.set_f(f0)
+    own = o.owner()
+    node, d, ow, q = o.links()
+    o.step(1)
+    f1 = o.f()
+    xf = pts[node]
+    ev = e[d].astype(float)
+    ff_node = ((node % n + e[d, 0]) % n) + n * (((node // n) % n + e[d, 1]) % n) \
+        + n * n * ((node // (n * n) + e[d, 2]) % n)
+    ibb = (bc == workloads.BC_IBB) & (own[ff_node] < 0)
+    qq = np.where(ibb, q, 0.5)
+    ud = np.where(ibb[:, None], field(xf + (1 - 2 * qq)[:, None] * ev), field(xf))
+    uw = field(xf - qq[:, None] * ev)
+    expect = np.array([oracle.feq(1.0, ud[j])[op[d[j]]] for j in range(len(d))]) \
+        + 6 * wt[d] * (ev * uw).sum(1)
+    got = f1[d, node]
+    assert ibb.sum() > 0 or bc == workloads.BC_SBB
+    assert np.abs(got - expect).max() < 1e-15

@@ -1,0 +1,254 @@
+"""Seeded synthetic inputs for the metaball-coupled lattice Boltzmann step.
+
+This module only draws numbers and lays them out; it holds none of the
+method's arithmetic (no lattice tables, no metaball evaluation, no body
+properties).  Both the CPU oracle and the HIP library read exactly what it
+returns, so the two sides start from identical inputs.
+
+A metaball body (paper section 2.1, Eq. metaballM) is a set of control points
+p_i with positive weights k_i; its surface is sum_i k_i/|x - p_i|^2 = 1.  The
+paper fits bodies to X-ray CT scans, which are not available, so bodies are
+drawn at random: offsets p_i ~ N(0, (0.4 R)^2) per axis and k_i = R^2 u_i /
+sum(u), u_i ~ U[20, 60], so that sum(k) = R^2 and the far field looks like a
+sphere of radius R.  Control points are given in a body frame whose origin is
+placed at ``x``; the library and the oracle each compute the true centroid
+themselves.
+
+RNG: numpy.random.Generator(PCG64(seed)); per body the draw order is n_cp,
+R (only where they are random), offsets, then u.
+"""
+from __future__ import annotations
+
+import copy
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+PERIODIC_X, PERIODIC_Y, PERIODIC_Z = 1, 2, 4
+BC_SBB, BC_IBB = 0, 1
+STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
+MODE_FREE, MODE_KINEMATIC = 0, 1
+
+
+@dataclasses.dataclass
+class Particle:
+    cp_xyz: np.ndarray            # (n_cp, 3) float64, body frame
+    cp_k: np.ndarray              # (n_cp,)  float64, > 0
+    x: np.ndarray                 # (3,) lab position of the body-frame origin
+    quat: np.ndarray = dataclasses.field(default_factory=lambda: np.array([1.0, 0, 0, 0]))
+    v: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))
+    omega: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))
+    density: float = 1.5          # absolute density (lattice units, rho0 = 1)
+    mode: int = MODE_FREE         # MODE_FREE: Newton-Euler; MODE_KINEMATIC: moves with v, omega
+
+    @property
+    def n_cp(self) -> int:
+        return int(self.cp_k.shape[0])
+
+    def bounding_radius(self) -> float:
+        """Radius about the body-frame origin that contains the body (C >= 1
+        needs some |x - p_i|^2 <= sum k)."""
+        return float(np.max(np.linalg.norm(self.cp_xyz, axis=1)) + math.sqrt(self.cp_k.sum()))
+
+
+@dataclasses.dataclass
+class Config:
+    nx: int
+    ny: int
+    nz: int
+    periodic: int = 0
+    tau: float = 0.8
+    rho0: float = 1.0
+    g_fluid: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))
+    g_particle: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(3))
+    bc: int = BC_IBB
+    n_sub: int = 1
+    counter_force: int = 0
+    quad_h: float = 0.125
+    storage: int = STORE_F32
+    particles: List[Particle] = dataclasses.field(default_factory=list)
+    name: str = ""
+    steps: int = 0
+
+    @property
+    def n_nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def copy(self) -> "Config":
+        return copy.deepcopy(self)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def random_body(rng: np.random.Generator, n_cp: int, R: float):
+    offsets = rng.normal(0.0, 0.4 * R, size=(n_cp, 3))
+    u = rng.uniform(20.0, 60.0, size=n_cp)
+    k = R * R * u / u.sum()
+    return offsets.astype(np.float64), k.astype(np.float64)
+
+
+# ---------------------------------------------------------------- configs
+def config1(center: str = "integer", bc: int = BC_SBB, n: int = 64) -> Config:
+    """64^3 periodic, tau 0.8, one fixed single-control-point body (k = 64,
+    sphere of radius 8) at the box centre, body force 1e-6 along +x, 200 steps."""
+    c = n / 2 if center == "integer" else n / 2 - 0.5
+    p = Particle(cp_xyz=np.zeros((1, 3)), cp_k=np.array([64.0 * (n / 64) ** 2]),
+                 x=np.array([c, c, c]), density=1.0, mode=MODE_KINEMATIC)
+    return Config(nx=n, ny=n, nz=n, periodic=7, tau=0.8, rho0=1.0,
+                  g_fluid=np.array([1e-6, 0.0, 0.0]), bc=bc, particles=[p],
+                  name=f"cfg1-{n}^3-{center}", steps=200)
+
+
+def config2(scale: float = 1.0, seed: int = 1, bc: int = BC_IBB) -> Config:
+    """128x128x384 walled box, tau 0.6, one free 8-control-point body (R = 10,
+    density ratio 1.5), gravity 2e-5 along -z, 2000 steps.  ``scale`` < 1
+    shrinks box and body together for oracle-sized runs."""
+    rng = _rng(seed)
+    R = 10.0 * scale
+    off, k = random_body(rng, 8, R)
+    nx, ny, nz = int(round(128 * scale)), int(round(128 * scale)), int(round(384 * scale))
+    p = Particle(cp_xyz=off, cp_k=k, x=np.array([nx / 2, ny / 2, 326.0 * scale]), density=1.5)
+    return Config(nx=nx, ny=ny, nz=nz, periodic=0, tau=0.6, rho0=1.0,
+                  g_particle=np.array([0.0, 0.0, -2e-5]), bc=bc, particles=[p],
+                  name=f"cfg2-{nx}x{ny}x{nz}", steps=2000)
+
+
+def config3(scale: float = 1.0, storage: int = STORE_F16, bc: int = BC_IBB) -> Config:
+    """160x160x640 walled box, tau 0.6, two bodies (6 control points seed 2
+    leading at z = 544, 12 control points seed 3 at z = 584) on the axis
+    x = y = 80, density ratio 1.2, gravity 2e-5, 5000 steps."""
+    R = 10.0 * scale
+    bodies = []
+    for seed, n_cp, z in ((2, 6, 544.0), (3, 12, 584.0)):
+        off, k = random_body(_rng(seed), n_cp, R)
+        bodies.append(Particle(cp_xyz=off, cp_k=k,
+                               x=np.array([80.0 * scale, 80.0 * scale, z * scale]), density=1.2))
+    nx, ny, nz = int(round(160 * scale)), int(round(160 * scale)), int(round(640 * scale))
+    return Config(nx=nx, ny=ny, nz=nz, periodic=0, tau=0.6, rho0=1.0,
+                  g_particle=np.array([0.0, 0.0, -2e-5]), bc=bc, storage=storage,
+                  particles=bodies, name=f"cfg3-{nx}x{ny}x{nz}", steps=5000)
+
+
+def config4_case(b: int, ragged: bool = False) -> Config:
+    """One case of the 64-case settling ensemble (seed 4000 + b)."""
+    rng = _rng(4000 + b)
+    nx = int(rng.integers(8, 17)) * 8
+    ny = int(rng.integers(8, 17)) * 8
+    nz = int(rng.integers(8, 33)) * 8
+    if ragged:
+        nx, ny, nz = nx - 3, ny - 5, nz - 1
+    n_cp = int(rng.integers(4, 17))
+    tau = float(rng.uniform(0.55, 1.0))
+    ratio = float(rng.uniform(1.1, 2.5))
+    R = 10.0 * min(nx, ny) / 128.0
+    off, k = random_body(rng, n_cp, R)
+    p = Particle(cp_xyz=off, cp_k=k, x=np.zeros(3), density=ratio)
+    rb = p.bounding_radius()
+    p.x = np.array([nx / 2, ny / 2, max(nz - rb - 4.0, nz / 2)])
+    return Config(nx=nx, ny=ny, nz=nz, periodic=0, tau=tau, rho0=1.0,
+                  g_particle=np.array([0.0, 0.0, -2e-5]), bc=BC_IBB, particles=[p],
+                  name=f"cfg4-case{b}", steps=1000)
+
+
+def config4(n_cases: int = 64) -> List[Config]:
+    return [config4_case(b) for b in range(n_cases)]
+
+
+def config5(n_bodies: int = 200, box: int = 256, seed: int = 5,
+            max_tries: int = 200000) -> Config:
+    """256^3 periodic suspension: bodies with 6..20 control points and
+    R ~ U[6, 12], placed by random sequential addition with bounding spheres
+    and a 1 lu gap, density ratio 1.5, gravity 2e-5, fluid counter-force."""
+    rng = _rng(seed)
+    bodies: List[Particle] = []
+    centers, radii = [], []
+    tries = 0
+    while len(bodies) < n_bodies:
+        n_cp = int(rng.integers(6, 21))
+        R = float(rng.uniform(6.0, 12.0))
+        off, k = random_body(rng, n_cp, R)
+        p = Particle(cp_xyz=off, cp_k=k, x=np.zeros(3), density=1.5)
+        rb = p.bounding_radius()
+        while True:
+            tries += 1
+            if tries > max_tries:
+                raise RuntimeError("random sequential placement did not finish")
+            c = rng.uniform(0.0, box, size=3)
+            ok = True
+            for c2, r2 in zip(centers, radii):
+                d = c - c2
+                d -= box * np.floor(d / box + 0.5)
+                if np.linalg.norm(d) < rb + r2 + 1.0:
+                    ok = False
+                    break
+            if ok:
+                break
+        p.x = c
+        centers.append(c)
+        radii.append(rb)
+        bodies.append(p)
+    return Config(nx=box, ny=box, nz=box, periodic=7, tau=0.6, rho0=1.0,
+                  g_particle=np.array([0.0, 0.0, -2e-5]), bc=BC_IBB, counter_force=1,
+                  particles=bodies, name=f"cfg5-{box}^3-{n_bodies}", steps=200)
+
+
+# ------------------------------------------------------- validation cases
+def poiseuille(tau: float, H: int = 32, g: float = 1e-6, nx: int = 4, nz: int = 4) -> Config:
+    """Channel: walls normal to y (H fluid nodes), periodic in x and z,
+    uniform body force g along +x, no particles."""
+    return Config(nx=nx, ny=H, nz=nz, periodic=PERIODIC_X | PERIODIC_Z, tau=tau, rho0=1.0,
+                  g_fluid=np.array([g, 0.0, 0.0]), bc=BC_SBB, name=f"poiseuille-H{H}-tau{tau}")
+
+
+def drag_array(L: int = 32, R: float = 4.0, tau: float = 0.8, g: float = 1e-6,
+               bc: int = BC_IBB) -> Config:
+    """Simple-cubic array of fixed spheres: one sphere of radius R in a
+    periodic L^3 cell, fluid driven by a uniform body force along +x."""
+    p = Particle(cp_xyz=np.zeros((1, 3)), cp_k=np.array([R * R]),
+                 x=np.array([L / 2 - 0.5, L / 2 - 0.5, L / 2 - 0.5]), density=1.0,
+                 mode=MODE_KINEMATIC)
+    return Config(nx=L, ny=L, nz=L, periodic=7, tau=tau, rho0=1.0,
+                  g_fluid=np.array([g, 0.0, 0.0]), bc=bc, particles=[p], name=f"drag-L{L}-R{R}")
+
+
+def comoving(U=(0.01, 0.005, 0.0), n: int = 32, seed: int = 11, bc: int = BC_IBB) -> Config:
+    """Periodic box; one kinematic body moving with the uniform flow U."""
+    off, k = random_body(_rng(seed), 6, 5.0)
+    p = Particle(cp_xyz=off, cp_k=k, x=np.array([n / 2, n / 2, n / 2]), density=1.0,
+                 v=np.array(U, dtype=np.float64), mode=MODE_KINEMATIC)
+    return Config(nx=n, ny=n, nz=n, periodic=7, tau=0.7, rho0=1.0, bc=bc,
+                  particles=[p], name=f"comoving-{n}")
+
+
+def random_populations(seed: int, n_nodes: int, rho0: float = 1.0, amp: float = 1e-3):
+    """Deviations f_i - w_i rho0 drawn uniformly in [-amp, amp]; shape (19, N).
+    A post-collision state for one-step tests (positivity is not needed)."""
+    return _rng(seed).uniform(-amp, amp, size=(19, n_nodes))
+
+
+def small_settling(seed: int = 21, n: int = 40, nz: int = 64, n_cp: int = 6, R: float = 5.0,
+                   bc: int = BC_IBB, ratio: float = 1.5, g: float = 2e-4) -> Config:
+    """Oracle-sized settling case with a stronger gravity so that the body
+    crosses lattice nodes (covering and uncovering) within tens of steps."""
+    off, k = random_body(_rng(seed), n_cp, R)
+    p = Particle(cp_xyz=off, cp_k=k, x=np.array([n / 2 - 0.3, n / 2 + 0.2, nz * 0.6]),
+                 density=ratio, omega=np.array([0.0, 0.002, 0.001]))
+    return Config(nx=n, ny=n, nz=nz, periodic=0, tau=0.7, rho0=1.0,
+                  g_particle=np.array([0.0, 0.0, -g]), bc=bc, particles=[p],
+                  name=f"settle-{n}x{n}x{nz}")
+
+
+def two_body(seed: int = 31, n: int = 48, nz: int = 80, bc: int = BC_IBB) -> Config:
+    """Two bodies on the axis of a walled box (small drafting case)."""
+    bodies = []
+    for j, (s, n_cp, z) in enumerate(((seed, 6, nz * 0.45), (seed + 1, 9, nz * 0.75))):
+        off, k = random_body(_rng(s), n_cp, 5.0)
+        bodies.append(Particle(cp_xyz=off, cp_k=k, x=np.array([n / 2 + 0.4 * j, n / 2, z]),
+                               density=1.3))
+    return Config(nx=n, ny=n, nz=nz, periodic=0, tau=0.65, rho0=1.0,
+                  g_particle=np.array([0.0, 0.0, -1e-4]), bc=bc, particles=bodies,
+                  name=f"twobody-{n}x{n}x{nz}")
