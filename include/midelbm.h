@@ -1,0 +1,194 @@
+/*
+ * midelbm.h -- C ABI of the MI355X (gfx950) implementation of the per-step
+ * hot path of the Metaball-Imaging Discrete Element Lattice Boltzmann
+ * Method (MI-DELBM, arXiv 2209.10411).
+ *
+ * One call of lbm_step(..., LBM_STEP_COUPLED) advances the coupled system by
+ * one lattice time unit:
+ *   1. bounce-back on every link cut by a metaball surface (paper sec. 2.3.2,
+ *      Eqs. eqneq1, eqneq2, neqd) and the momentum exchange on those links
+ *      (sec. 2.3.2, MEM paragraph; Galilean-invariant per-link form);
+ *   2. the FP64 Newton-Euler update of every particle (sec. 2.3.1);
+ *   3. metaball flagging of the nodes near each particle (sec. 2.1,
+ *      Eq. metaballM; C(x) >= 1 is solid);
+ *   4. D3Q19 BGK stream-and-collide of every fluid node, with the local
+ *      refilling of uncovered nodes (sec. 2.3.2, refilling equation) between
+ *      streaming and collision;
+ *   5. the cut-link list and link fractions q of the new geometry
+ *      (sec. 2.3.2: q solves C(x_f - q e_i) = 1 along the link).
+ * The paper gives no lattice, collision operator or forcing; this library
+ * uses D3Q19 BGK with Guo forcing.
+ *
+ * Conventions
+ *   - Lattice units.  Node (x, y, z) sits at integer coordinates; its linear
+ *     index is x + nx*(y + ny*z).  Non-periodic faces are resting no-slip
+ *     walls halfway outside the outermost nodes.
+ *   - Populations are stored post-collision, as deviations f_i - w_i rho0,
+ *     structure-of-arrays [19][N] in FP32, FP16 (times fp16_scale) or BF16,
+ *     in two ping-pong buffers.  Velocity i = 0 is rest, 1..6 are +x,-x,+y,
+ *     -y,+z,-z, 7..18 the edges (+x+y,-x-y,+x-y,-x+y,+x+z,-x-z,+x-z,-x+z,
+ *     +y+z,-y-z,+y-z,-y+z); opposites are adjacent.
+ *   - Particles: FP64 state on the device.  cp_xyz are control points in a
+ *     body frame whose origin is placed at x with orientation quat
+ *     (w, x, y, z); the library computes volume, centroid and inertia by
+ *     midpoint quadrature with cell size quad_h and thereafter refers the
+ *     particle to its centroid.  A node covered by several bodies belongs to
+ *     the lowest-index one.
+ *
+ * Memory and ownership
+ *   - Device memory is one caller-owned arena (any device allocation, e.g. a
+ *     torch uint8 tensor) of at least lbm_arena_bytes() bytes, passed to
+ *     lbm_init; the library sub-allocates it and never allocates device
+ *     memory itself nor frees the arena.  Host input arrays are copied
+ *     during the call and not retained.  lbm_destroy frees host state only.
+ *   - All device work is enqueued on the caller's HIP stream given to
+ *     lbm_init.  Calls that return data to the host synchronise that stream.
+ *
+ * Errors
+ *   - Every call returns an lbm_status; lbm_last_error() gives a message for
+ *     the last failure on the calling thread.  Device-side conditions (link
+ *     list overflow, a particle moving more than one lattice unit per step,
+ *     a non-finite particle state) are recorded on the device and reported
+ *     as LBM_E_DIVERGED or LBM_E_NOMEM by the next synchronising call.
+ */
+#ifndef MIDELBM_H
+#define MIDELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_INVALID = -1,  /* argument out of range, NaN input, bad geometry        */
+    LBM_E_NOMEM = -2,    /* arena too small, or a device list ran out of capacity */
+    LBM_E_HIP = -3,      /* a HIP runtime call failed                             */
+    LBM_E_DIVERGED = -4, /* non-finite or too fast particle state                 */
+    LBM_E_STATE = -5     /* call not valid in the current state                   */
+} lbm_status;
+
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
+enum { LBM_BC_SBB = 0, LBM_BC_IBB = 1 };
+enum { LBM_STEP_FLUID_ONLY = 0, LBM_STEP_COUPLED = 1 };
+enum { LBM_MODE_FREE = 0, LBM_MODE_KINEMATIC = 1 };
+enum { LBM_PERIODIC_X = 1, LBM_PERIODIC_Y = 2, LBM_PERIODIC_Z = 4 };
+
+typedef struct {
+    int32_t nx, ny, nz;   /* lattice size, each >= 3                              */
+    uint32_t periodic;    /* LBM_PERIODIC_* bits; other faces are walls            */
+    double tau;           /* BGK relaxation time, > 0.5                            */
+    double rho0;          /* reference density, > 0                                */
+    double g_fluid[3];    /* body acceleration of the fluid (Guo forcing, F = rho g) */
+    double g_particle[3]; /* gravity on free particles, applied as (m - rho0 V) g  */
+    int32_t storage;      /* LBM_STORE_*                                           */
+    int32_t bc;           /* LBM_BC_SBB: halfway bounce-back; LBM_BC_IBB: paper's
+                             interpolated bounce-back (Eqs. eqneq1-neqd)           */
+    int32_t n_sub;        /* rigid-body sub-steps per lattice step, >= 1           */
+    int32_t counter_force;/* 1: add to g_fluid minus the net weight of the free
+                             particles spread over the fluid (periodic settling)   */
+    double quad_h;        /* cell size of the body-property quadrature, > 0       */
+    float fp16_scale;     /* FP16 storage multiplies deviations by this power of
+                             two (0 selects 1024); ignored for FP32 and BF16       */
+    int32_t reserved;
+} lbm_config;
+
+typedef struct {
+    int32_t n_cp;         /* 1..20 control points                                  */
+    int32_t mode;         /* LBM_MODE_FREE or LBM_MODE_KINEMATIC (moves with v, omega) */
+    const double *cp_xyz; /* [n_cp][3] body frame                                  */
+    const double *cp_k;   /* [n_cp] weights, > 0                                   */
+    double x[3];          /* lab position of the body-frame origin                 */
+    double quat[4];       /* body-to-lab rotation (w, x, y, z), normalised here    */
+    double v[3];          /* initial velocity (lab)                                */
+    double omega[3];      /* initial angular velocity (lab)                        */
+    double density;       /* particle density (lattice units)                      */
+} lbm_particle;
+
+typedef struct {
+    double x[3];          /* centroid (lab)                                        */
+    double quat[4];       /* body-to-lab rotation                                  */
+    double v[3], omega[3];/* velocity, angular velocity (lab)                      */
+    double F[3], T[3];    /* hydrodynamic force and torque of the last step       */
+    double mass, volume;
+    double inertia[9];    /* body frame, about the centroid                       */
+} lbm_particle_state;
+
+/* Bytes of device arena needed for this configuration. */
+lbm_status lbm_arena_bytes(const lbm_config *cfg, int32_t n_p, const lbm_particle *p, size_t *bytes);
+
+/* Validates the configuration (tau > 0.5, sizes >= 3, 1..20 control points
+ * with k > 0, finite inputs, particles clear of walls and of each other),
+ * computes body properties, uploads the state, flags the nodes, builds the
+ * cut links and sets every fluid node to the collided rest state
+ * f = feq(rho0, 0).  dev_arena must hold arena_bytes >= lbm_arena_bytes();
+ * hip_stream is a hipStream_t (NULL = default stream). */
+lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *p, void *dev_arena,
+                    size_t arena_bytes, void *hip_stream, lbm_ctx **out);
+
+/* Metaball flagging (sec. 2.1): re-derives flags and owners of every node from
+ * the current particle poses and rebuilds the cut-link list with its link
+ * fractions.  Nodes uncovered by the change are remembered for refill().
+ * n_solid and n_links are optional outputs (non-NULL makes the call sync). */
+lbm_status metaball_flag(lbm_ctx *ctx, int64_t *n_solid, int64_t *n_links);
+
+/* Advances n_steps steps.  LBM_STEP_COUPLED runs the full coupled step listed
+ * at the top of this header; LBM_STEP_FLUID_ONLY keeps particles, flags and
+ * links fixed (bounce-back and momentum exchange still use the particle
+ * velocities).  Asynchronous on the context's stream. */
+lbm_status lbm_step(lbm_ctx *ctx, int32_t n_steps, int32_t mode);
+
+/* Hydrodynamic force and torque (about the centroid) on each particle from the
+ * momentum exchange of the last step; F and T are [n_p][3] host arrays.
+ * Synchronises. */
+lbm_status particle_forces(lbm_ctx *ctx, double *F, double *T);
+
+/* Local refilling (sec. 2.3.2) of the nodes uncovered by the last
+ * metaball_flag() call: populations streaming in from fluid neighbours are
+ * kept, a missing f_i takes f_opp(i) + 6 w_i rho0 e_i.u_new when its opposite
+ * came from a fluid node and feq_i(rho0, u_new) otherwise, with u_new the
+ * covering body's rigid velocity at the node; the node is then collided.
+ * lbm_step in coupled mode does this internally every step.  n_refilled is
+ * optional (non-NULL makes the call sync). */
+lbm_status refill(lbm_ctx *ctx, int64_t *n_refilled);
+
+/* ---- state access for tests and I/O (host FP64 arrays; all synchronise) ---- */
+/* rho [N] and u [N][3] of the stored state (u excludes the half body force). */
+lbm_status lbm_get_macros(lbm_ctx *ctx, double *rho, double *u);
+/* Full post-collision populations f_i = w_i rho0 + deviation, [19][N]. */
+lbm_status lbm_get_populations(lbm_ctx *ctx, double *f);
+/* Sets the populations [19][N]; post_collision = 0 means f is a post-stream
+ * state and fluid nodes are collided before storing. */
+lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f, int32_t post_collision);
+/* owner [N]: -1 fluid, else the particle index. */
+lbm_status lbm_get_flags(lbm_ctx *ctx, int32_t *owner);
+/* Cut links of the current geometry in the library's order (particle-major):
+ * node index, direction, owner and q.  Pass NULL arrays to get the count. */
+lbm_status lbm_get_links(lbm_ctx *ctx, int64_t *n_links, uint32_t *node, int32_t *dir,
+                         int32_t *owner, double *q);
+lbm_status lbm_get_particles(lbm_ctx *ctx, lbm_particle_state *out /* [n_p] */);
+/* Overwrites pose and velocities (x = centroid); call metaball_flag after. */
+lbm_status lbm_set_particles(lbm_ctx *ctx, const lbm_particle_state *in /* [n_p] */);
+/* Effective fluid body acceleration (includes the counter-force). */
+lbm_status lbm_get_gfluid(lbm_ctx *ctx, double *g3);
+
+/* ---- measurement ---- */
+/* When enabled, the stream-collide kernel of every step is bracketed by HIP
+ * events on the context's stream; lbm_timing_read returns the summed elapsed
+ * milliseconds and launch count since the last reset (synchronises). */
+lbm_status lbm_timing_enable(lbm_ctx *ctx, int32_t on);
+lbm_status lbm_timing_read(lbm_ctx *ctx, double *ms, int64_t *launches, int64_t *nodes_per_launch);
+/* Waits for the context's stream and reports device-side errors. */
+lbm_status lbm_sync(lbm_ctx *ctx);
+
+void lbm_destroy(lbm_ctx *ctx);
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIDELBM_H */

@@ -1,0 +1,281 @@
+"""Python binding of libmidelbm.so, the MI355X (gfx950) HIP implementation of
+the per-step hot path of MI-DELBM (arXiv 2209.10411): metaball flagging,
+D3Q19 BGK stream-collide with (interpolated) bounce-back on metaball-cut
+links, momentum-exchange force and torque, FP64 rigid-body update and local
+refilling.
+
+This module only marshals arguments.  Every step of the path runs in the HIP
+kernels behind the C ABI declared in include/midelbm.h; PyTorch provides the
+device arena and the stream.  If the shared library is missing the import of
+``lib()`` raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmidelbm.so")
+
+LBM_STORE_F32, LBM_STORE_F16, LBM_STORE_BF16 = 0, 1, 2
+LBM_BC_SBB, LBM_BC_IBB = 0, 1
+LBM_STEP_FLUID_ONLY, LBM_STEP_COUPLED = 0, 1
+
+_STATUS = {0: "LBM_OK", -1: "LBM_E_INVALID", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP",
+           -4: "LBM_E_DIVERGED", -5: "LBM_E_STATE"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class lbm_config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("periodic", C.c_uint32),
+                ("tau", C.c_double), ("rho0", C.c_double), ("g_fluid", C.c_double * 3),
+                ("g_particle", C.c_double * 3), ("storage", C.c_int32), ("bc", C.c_int32),
+                ("n_sub", C.c_int32), ("counter_force", C.c_int32), ("quad_h", C.c_double),
+                ("fp16_scale", C.c_float), ("reserved", C.c_int32)]
+
+
+class lbm_particle(C.Structure):
+    _fields_ = [("n_cp", C.c_int32), ("mode", C.c_int32), ("cp_xyz", C.POINTER(C.c_double)),
+                ("cp_k", C.POINTER(C.c_double)), ("x", C.c_double * 3), ("quat", C.c_double * 4),
+                ("v", C.c_double * 3), ("omega", C.c_double * 3), ("density", C.c_double)]
+
+
+class lbm_particle_state(C.Structure):
+    _fields_ = [("x", C.c_double * 3), ("quat", C.c_double * 4), ("v", C.c_double * 3),
+                ("omega", C.c_double * 3), ("F", C.c_double * 3), ("T", C.c_double * 3),
+                ("mass", C.c_double), ("volume", C.c_double), ("inertia", C.c_double * 9)]
+
+
+EXPORTS = ["lbm_arena_bytes", "lbm_init", "metaball_flag", "lbm_step", "particle_forces", "refill",
+           "lbm_get_macros", "lbm_get_populations", "lbm_set_populations", "lbm_get_flags",
+           "lbm_get_links", "lbm_get_particles", "lbm_set_particles", "lbm_get_gfluid",
+           "lbm_timing_enable", "lbm_timing_read", "lbm_sync", "lbm_destroy", "lbm_last_error"]
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python paper_2209_10411_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.lbm_arena_bytes.argtypes = [C.POINTER(lbm_config), C.c_int32, C.POINTER(lbm_particle),
+                                      C.POINTER(C.c_size_t)]
+        L.lbm_init.argtypes = [C.POINTER(lbm_config), C.c_int32, C.POINTER(lbm_particle), vp,
+                               C.c_size_t, vp, C.POINTER(vp)]
+        L.metaball_flag.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.lbm_step.argtypes = [vp, C.c_int32, C.c_int32]
+        L.particle_forces.argtypes = [vp, dp, dp]
+        L.refill.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.lbm_get_macros.argtypes = [vp, dp, dp]
+        L.lbm_get_populations.argtypes = [vp, dp]
+        L.lbm_set_populations.argtypes = [vp, dp, C.c_int32]
+        L.lbm_get_flags.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.lbm_get_links.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
+        L.lbm_get_particles.argtypes = [vp, C.POINTER(lbm_particle_state)]
+        L.lbm_set_particles.argtypes = [vp, C.POINTER(lbm_particle_state)]
+        L.lbm_get_gfluid.argtypes = [vp, dp]
+        L.lbm_timing_enable.argtypes = [vp, C.c_int32]
+        L.lbm_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.lbm_sync.argtypes = [vp]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_destroy.restype = None
+        L.lbm_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("lbm_destroy", "lbm_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LbmError(rc, lib().lbm_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_config(cfg) -> lbm_config:
+    c = lbm_config()
+    c.nx, c.ny, c.nz, c.periodic = cfg.nx, cfg.ny, cfg.nz, cfg.periodic
+    c.tau, c.rho0 = cfg.tau, cfg.rho0
+    c.g_fluid[:] = [float(v) for v in cfg.g_fluid]
+    c.g_particle[:] = [float(v) for v in cfg.g_particle]
+    c.storage, c.bc, c.n_sub = int(cfg.storage), int(cfg.bc), int(cfg.n_sub)
+    c.counter_force = int(cfg.counter_force)
+    c.quad_h = float(cfg.quad_h)
+    c.fp16_scale = float(getattr(cfg, "fp16_scale", 0.0))
+    return c
+
+
+def make_particles(parts):
+    """ctypes array of lbm_particle plus the numpy buffers it points into."""
+    arr = (lbm_particle * max(len(parts), 1))()
+    keep = []
+    for j, p in enumerate(parts):
+        cp = np.ascontiguousarray(p.cp_xyz, dtype=np.float64).reshape(-1)
+        k = np.ascontiguousarray(p.cp_k, dtype=np.float64)
+        keep += [cp, k]
+        a = arr[j]
+        a.n_cp, a.mode = int(k.size), int(p.mode)
+        a.cp_xyz, a.cp_k = _dptr(cp), _dptr(k)
+        a.x[:] = [float(v) for v in p.x]
+        a.quat[:] = [float(v) for v in p.quat]
+        a.v[:] = [float(v) for v in p.v]
+        a.omega[:] = [float(v) for v in p.omega]
+        a.density = float(p.density)
+    return arr, keep
+
+
+def arena_bytes(cfg) -> int:
+    c = make_config(cfg)
+    parts, keep = make_particles(cfg.particles)
+    n = C.c_size_t(0)
+    _check(lib().lbm_arena_bytes(C.byref(c), len(cfg.particles), parts, C.byref(n)))
+    return int(n.value)
+
+
+class Simulation:
+    """A coupled metaball/LBM system on one GPU.  ``cfg`` is any object with
+    the fields of ``workloads.Config`` (sizes, tau, rho0, forces, storage,
+    boundary rule, particles)."""
+
+    def __init__(self, cfg, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.cfg = cfg
+        self.N = cfg.nx * cfg.ny * cfg.nz
+        self.np = len(cfg.particles)
+        self.device = torch.device(device)
+        L = lib()
+        c = make_config(cfg)
+        parts, keep = make_particles(cfg.particles)
+        n = C.c_size_t(0)
+        _check(L.lbm_arena_bytes(C.byref(c), self.np, parts, C.byref(n)))
+        self.arena = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = C.c_void_p()
+        _check(L.lbm_init(C.byref(c), self.np, parts, C.c_void_p(self.arena.data_ptr()),
+                          self.arena.numel(), C.c_void_p(self.stream.cuda_stream),
+                          C.byref(self._ctx)))
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib().lbm_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- the five calls of the hot path
+    def metaball_flag(self, counts: bool = True):
+        ns, nl = C.c_int64(0), C.c_int64(0)
+        if counts:
+            _check(lib().metaball_flag(self._ctx, C.byref(ns), C.byref(nl)))
+            return int(ns.value), int(nl.value)
+        _check(lib().metaball_flag(self._ctx, None, None))
+        return None
+
+    def step(self, n: int = 1, coupled: bool = True):
+        _check(lib().lbm_step(self._ctx, int(n), LBM_STEP_COUPLED if coupled else LBM_STEP_FLUID_ONLY))
+
+    def particle_forces(self):
+        F, T = np.zeros(3 * self.np), np.zeros(3 * self.np)
+        _check(lib().particle_forces(self._ctx, _dptr(F), _dptr(T)))
+        return F.reshape(-1, 3), T.reshape(-1, 3)
+
+    def refill(self) -> int:
+        n = C.c_int64(0)
+        _check(lib().refill(self._ctx, C.byref(n)))
+        return int(n.value)
+
+    # ---- state access
+    def sync(self):
+        _check(lib().lbm_sync(self._ctx))
+
+    def macros(self):
+        rho, u = np.zeros(self.N), np.zeros(3 * self.N)
+        _check(lib().lbm_get_macros(self._ctx, _dptr(rho), _dptr(u)))
+        return rho, u.reshape(self.N, 3)
+
+    def populations(self) -> np.ndarray:
+        f = np.zeros(19 * self.N)
+        _check(lib().lbm_get_populations(self._ctx, _dptr(f)))
+        return f.reshape(19, self.N)
+
+    def set_populations(self, f, post_collision: bool = False):
+        a = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        if a.size != 19 * self.N:
+            raise ValueError("populations must have 19*N values")
+        _check(lib().lbm_set_populations(self._ctx, _dptr(a), int(bool(post_collision))))
+
+    def owner(self) -> np.ndarray:
+        o = np.zeros(self.N, dtype=np.int32)
+        _check(lib().lbm_get_flags(self._ctx, o.ctypes.data_as(C.POINTER(C.c_int32))))
+        return o
+
+    def links(self):
+        n = C.c_int64(0)
+        _check(lib().lbm_get_links(self._ctx, C.byref(n), None, None, None, None))
+        nl = int(n.value)
+        node, d = np.zeros(nl, np.uint32), np.zeros(nl, np.int32)
+        o, q = np.zeros(nl, np.int32), np.zeros(nl)
+        if nl:
+            _check(lib().lbm_get_links(self._ctx, C.byref(n),
+                                       node.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                       d.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       o.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(q)))
+        return node.astype(np.int64), d, o, q
+
+    def particles(self):
+        arr = (lbm_particle_state * max(self.np, 1))()
+        _check(lib().lbm_get_particles(self._ctx, arr))
+        out = []
+        for j in range(self.np):
+            s = arr[j]
+            out.append({"x": np.array(s.x[:]), "quat": np.array(s.quat[:]), "v": np.array(s.v[:]),
+                        "omega": np.array(s.omega[:]), "F": np.array(s.F[:]), "T": np.array(s.T[:]),
+                        "m": s.mass, "V": s.volume, "I": np.array(s.inertia[:]).reshape(3, 3)})
+        return out
+
+    def set_particles(self, states):
+        arr = (lbm_particle_state * max(self.np, 1))()
+        for j, st in enumerate(states):
+            a = arr[j]
+            a.x[:] = [float(v) for v in st["x"]]
+            a.quat[:] = [float(v) for v in st["quat"]]
+            a.v[:] = [float(v) for v in st["v"]]
+            a.omega[:] = [float(v) for v in st["omega"]]
+        _check(lib().lbm_set_particles(self._ctx, arr))
+
+    def g_fluid(self) -> np.ndarray:
+        g = np.zeros(3)
+        _check(lib().lbm_get_gfluid(self._ctx, _dptr(g)))
+        return g
+
+    # ---- measurement
+    def timing(self, on: bool = True):
+        _check(lib().lbm_timing_enable(self._ctx, int(bool(on))))
+
+    def timing_read(self):
+        ms, n, nodes = C.c_double(0), C.c_int64(0), C.c_int64(0)
+        _check(lib().lbm_timing_read(self._ctx, C.byref(ms), C.byref(n), C.byref(nodes)))
+        return float(ms.value), int(n.value), int(nodes.value)

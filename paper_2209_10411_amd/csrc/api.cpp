@@ -1,0 +1,850 @@
+// Host side of the C ABI declared in include/midelbm.h: validation, body
+// properties, arena layout, and the order in which the kernels of one
+// coupled step are enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/midelbm.h"
+#include "device.h"
+#include "launch.h"
+
+using namespace mdl;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(LBM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Body properties by midpoint quadrature: cells of size h on a grid centred
+// on the box [min p - sqrt(sum k), max p + sqrt(sum k)] (C >= 1 needs some
+// |x - p_i|^2 <= sum k).  Volume, centroid (from exact integer index sums)
+// and inertia tensor per unit density about the centroid.
+struct BodyProps {
+    double V, c[3], I[9];
+};
+
+bool body_properties(int n_cp, const double *cp, const double *k, double h, BodyProps &out) {
+    double sk = 0;
+    for (int i = 0; i < n_cp; ++i) sk += k[i];
+    const double rs = std::sqrt(sk);
+    double lo[3];
+    int n[3];
+    for (int a = 0; a < 3; ++a) {
+        double mn = cp[a], mx = cp[a];
+        for (int i = 1; i < n_cp; ++i) {
+            mn = std::min(mn, cp[3 * i + a]);
+            mx = std::max(mx, cp[3 * i + a]);
+        }
+        mn -= rs; mx += rs;
+        n[a] = (int)std::ceil((mx - mn) / h);
+        lo[a] = 0.5 * (mn + mx) - 0.5 * n[a] * h;
+    }
+    auto inside = [&](double x, double y, double z) {
+        double C = 0;
+        for (int i = 0; i < n_cp; ++i) {
+            const double dx = x - cp[3 * i], dy = y - cp[3 * i + 1], dz = z - cp[3 * i + 2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0) return true;
+            C += k[i] / r2;
+        }
+        return C >= 1.0;
+    };
+    const int nth = 8;  // fixed chunking: results do not depend on the host
+    std::vector<long long> cnt(nth, 0), sx(nth, 0), sy(nth, 0), sz(nth, 0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t] {
+            for (int kz = t; kz < n[2]; kz += nth)
+                for (int ky = 0; ky < n[1]; ++ky)
+                    for (int kx = 0; kx < n[0]; ++kx)
+                        if (inside(lo[0] + (kx + 0.5) * h, lo[1] + (ky + 0.5) * h, lo[2] + (kz + 0.5) * h)) {
+                            ++cnt[t]; sx[t] += kx; sy[t] += ky; sz[t] += kz;
+                        }
+        });
+    for (auto &x : th) x.join();
+    th.clear();
+    long long C = 0, S[3] = {0, 0, 0};
+    for (int t = 0; t < nth; ++t) { C += cnt[t]; S[0] += sx[t]; S[1] += sy[t]; S[2] += sz[t]; }
+    if (C == 0) return false;
+    for (int a = 0; a < 3; ++a) out.c[a] = lo[a] + h * ((double)S[a] / (double)C + 0.5);
+    std::vector<double> J(6 * nth, 0.0);
+    for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t] {
+            double *j = &J[6 * t];
+            for (int kz = t; kz < n[2]; kz += nth)
+                for (int ky = 0; ky < n[1]; ++ky)
+                    for (int kx = 0; kx < n[0]; ++kx) {
+                        const double x = lo[0] + (kx + 0.5) * h, y = lo[1] + (ky + 0.5) * h,
+                                     z = lo[2] + (kz + 0.5) * h;
+                        if (!inside(x, y, z)) continue;
+                        const double r0 = x - out.c[0], r1 = y - out.c[1], r2 = z - out.c[2];
+                        j[0] += r0 * r0; j[1] += r1 * r1; j[2] += r2 * r2;
+                        j[3] += r0 * r1; j[4] += r0 * r2; j[5] += r1 * r2;
+                    }
+        });
+    for (auto &x : th) x.join();
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < nth; ++t)
+        for (int c = 0; c < 6; ++c) s[c] += J[6 * t + c];
+    const double h3 = h * h * h;
+    out.V = (double)C * h3;
+    out.I[0] = (s[1] + s[2]) * h3; out.I[4] = (s[0] + s[2]) * h3; out.I[8] = (s[0] + s[1]) * h3;
+    out.I[1] = out.I[3] = -s[3] * h3;
+    out.I[2] = out.I[6] = -s[4] * h3;
+    out.I[5] = out.I[7] = -s[5] * h3;
+    return true;
+}
+
+bool invert3(const double *A, double *B) {
+    const double d = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(std::fabs(d) > 0)) return false;
+    B[0] = (A[4] * A[8] - A[5] * A[7]) / d; B[1] = (A[2] * A[7] - A[1] * A[8]) / d;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) / d; B[3] = (A[5] * A[6] - A[3] * A[8]) / d;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) / d; B[5] = (A[2] * A[3] - A[0] * A[5]) / d;
+    B[6] = (A[3] * A[7] - A[4] * A[6]) / d; B[7] = (A[1] * A[6] - A[0] * A[7]) / d;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) / d;
+    return true;
+}
+
+void rot_of_quat(const double *q, double *R) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+bool finite_all(const double *v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// Everything the arena holds, in order.  Offsets are computed once from the
+// configuration; lbm_arena_bytes and lbm_init share this plan.
+struct Plan {
+    long long N;
+    int np;
+    int storage_bytes;
+    int region_blocks;
+    int link_cap, special_cap;
+    std::vector<int> dims;            // [np][3]
+    std::vector<int> part, first;     // [region_blocks]
+    std::vector<int> part_first_blk;  // [np]
+    std::vector<int> half;            // [np]
+    size_t off_A, off_B, off_own0, off_own1, off_cls, off_stamp, off_P, off_part, off_first, off_dims,
+        off_pfb, off_bcnt, off_boff, off_loff, off_lnode, off_ldo, off_lq, off_lft, off_special,
+        off_cnt, off_iters, total;
+};
+
+struct HostParticle {
+    DevParticle d;
+};
+
+lbm_status validate_config(const lbm_config *c) {
+    if (!c) return fail(LBM_E_INVALID, "config is NULL");
+    if (c->nx < 3 || c->ny < 3 || c->nz < 3) return fail(LBM_E_INVALID, "lattice sizes must be >= 3");
+    const long long N = (long long)c->nx * c->ny * c->nz;
+    if (N > 0x7fffffffll) return fail(LBM_E_INVALID, "lattice has more than 2^31-1 nodes");
+    if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_E_INVALID, "tau must be > 0.5");
+    if (!(c->rho0 > 0) || !std::isfinite(c->rho0)) return fail(LBM_E_INVALID, "rho0 must be > 0");
+    if (!finite_all(c->g_fluid, 3) || !finite_all(c->g_particle, 3))
+        return fail(LBM_E_INVALID, "non-finite gravity");
+    if (c->storage < 0 || c->storage > 2) return fail(LBM_E_INVALID, "unknown storage %d", c->storage);
+    if (c->bc < 0 || c->bc > 1) return fail(LBM_E_INVALID, "unknown boundary rule %d", c->bc);
+    if (c->n_sub < 1) return fail(LBM_E_INVALID, "n_sub must be >= 1");
+    if (!(c->quad_h > 0) || !std::isfinite(c->quad_h)) return fail(LBM_E_INVALID, "quad_h must be > 0");
+    if (c->storage == 1 && c->fp16_scale != 0.f) {
+        int e;
+        const float m = std::frexp(c->fp16_scale, &e);
+        if (!(c->fp16_scale > 0) || m != 0.5f) return fail(LBM_E_INVALID, "fp16_scale must be a power of two");
+    }
+    return LBM_OK;
+}
+
+lbm_status validate_particle(const lbm_config *c, const lbm_particle *p, int idx) {
+    if (p->n_cp < 1 || p->n_cp > MAXCP) return fail(LBM_E_INVALID, "particle %d: n_cp must be 1..%d", idx, MAXCP);
+    if (!p->cp_xyz || !p->cp_k) return fail(LBM_E_INVALID, "particle %d: NULL control points", idx);
+    if (!finite_all(p->cp_xyz, 3 * p->n_cp)) return fail(LBM_E_INVALID, "particle %d: non-finite control point", idx);
+    for (int i = 0; i < p->n_cp; ++i)
+        if (!(p->cp_k[i] > 0) || !std::isfinite(p->cp_k[i]))
+            return fail(LBM_E_INVALID, "particle %d: k must be > 0", idx);
+    if (!finite_all(p->x, 3) || !finite_all(p->quat, 4) || !finite_all(p->v, 3) || !finite_all(p->omega, 3))
+        return fail(LBM_E_INVALID, "particle %d: non-finite state", idx);
+    const double qn = p->quat[0] * p->quat[0] + p->quat[1] * p->quat[1] + p->quat[2] * p->quat[2] + p->quat[3] * p->quat[3];
+    if (!(qn > 0)) return fail(LBM_E_INVALID, "particle %d: zero quaternion", idx);
+    if (!(p->density > 0) || !std::isfinite(p->density)) return fail(LBM_E_INVALID, "particle %d: density must be > 0", idx);
+    if (p->mode != LBM_MODE_FREE && p->mode != LBM_MODE_KINEMATIC)
+        return fail(LBM_E_INVALID, "particle %d: unknown mode", idx);
+    (void)c;
+    return LBM_OK;
+}
+
+// Bounding radius of the body about its centroid.
+double bounding_radius(int n_cp, const double *cp, const double *k, const double *cen) {
+    double sk = 0, rm = 0;
+    for (int i = 0; i < n_cp; ++i) {
+        sk += k[i];
+        double r2 = 0;
+        for (int a = 0; a < 3; ++a) r2 += (cp[3 * i + a] - cen[a]) * (cp[3 * i + a] - cen[a]);
+        rm = std::max(rm, std::sqrt(r2));
+    }
+    return rm + std::sqrt(sk);
+}
+
+lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb, Plan &pl) {
+    pl.N = (long long)c->nx * c->ny * c->nz;
+    pl.np = np;
+    pl.storage_bytes = c->storage == 0 ? 4 : 2;
+    pl.dims.assign(3 * np, 0);
+    pl.half.assign(np, 0);
+    pl.part.clear();
+    pl.first.clear();
+    pl.part_first_blk.assign(np, 0);
+    const int L[3] = {c->nx, c->ny, c->nz};
+    long long lcap = 0, scap = 0;
+    for (int p = 0; p < np; ++p) {
+        const int half = (int)std::ceil(rb[p]) + PAD;
+        pl.half[p] = half;
+        long long vol = 1;
+        for (int a = 0; a < 3; ++a) {
+            int d = 2 * half + 1;
+            if (((c->periodic >> a) & 1u) && d >= L[a]) d = L[a];
+            if (!((c->periodic >> a) & 1u)) d = std::min(d, L[a] + 2 * half + 1);
+            pl.dims[3 * p + a] = d;
+            vol *= d;
+        }
+        if (vol > 0x7fffffffll) return fail(LBM_E_INVALID, "particle %d is too large", p);
+        pl.part_first_blk[p] = (int)pl.part.size();
+        for (long long f = 0; f < vol; f += BLK) {
+            pl.part.push_back(p);
+            pl.first.push_back((int)f);
+        }
+        const double area = 4.0 * M_PI * (rb[p] + 2.0) * (rb[p] + 2.0);
+        lcap += (long long)(12.0 * area) + 4096;
+        scap += (long long)(4.0 * area) + 4096;
+    }
+    if (lcap > 0x3fffffffll || scap > 0x3fffffffll) return fail(LBM_E_INVALID, "particles too large");
+    pl.region_blocks = (int)pl.part.size();
+    pl.link_cap = (int)lcap;
+    pl.special_cap = (int)scap;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    const size_t pop = (size_t)Q * pl.N * pl.storage_bytes;
+    pl.off_A = take(pop);
+    pl.off_B = take(pop);
+    pl.off_own0 = take(4 * pl.N);
+    pl.off_own1 = take(4 * pl.N);
+    pl.off_cls = take(pl.N);
+    pl.off_stamp = take(4 * pl.N);
+    pl.off_P = take(sizeof(DevParticle) * std::max(np, 1));
+    pl.off_part = take(4 * std::max(pl.region_blocks, 1));
+    pl.off_first = take(4 * std::max(pl.region_blocks, 1));
+    pl.off_dims = take(4 * 3 * std::max(np, 1));
+    pl.off_pfb = take(4 * std::max(np, 1));
+    pl.off_bcnt = take(4 * std::max(pl.region_blocks, 1));
+    pl.off_boff = take(4 * std::max(pl.region_blocks, 1));
+    pl.off_loff = take(4 * (np + 1));
+    pl.off_lnode = take(4 * (size_t)std::max(pl.link_cap, 1));
+    pl.off_ldo = take(4 * (size_t)std::max(pl.link_cap, 1));
+    pl.off_lq = take(8 * (size_t)std::max(pl.link_cap, 1));
+    pl.off_lft = take(48 * (size_t)std::max(pl.link_cap, 1));
+    pl.off_special = take(4 * (size_t)std::max(pl.special_cap, 1));
+    pl.off_cnt = take(sizeof(Counters));
+    pl.off_iters = take(64);
+    pl.total = o;
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_config cfg;
+    Plan pl;
+    Params p;
+    hipStream_t stream;
+    char *arena;
+    void *A, *B;
+    int32_t *own_cur, *own_nxt;
+    uint8_t *cls;
+    uint32_t *stamp;
+    DevParticle *P;
+    RegionMap rm;
+    int *part_first_blk, *blk_cnt, *blk_off, *l_off, *iters;
+    uint32_t *l_node, *l_do, *special;
+    double *l_q, *lft;
+    Counters *cnt;
+    uint32_t tag;
+    bool pending_refill;
+    bool timing;
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    size_t ev_used;
+    long long timed_launches;
+    double timed_ms;
+    long long steps;
+};
+
+namespace {
+
+StepArgs base_args(lbm_ctx *c) {
+    StepArgs a{};
+    a.p = c->p;
+    a.stream = c->stream;
+    a.A = c->A; a.B = c->B;
+    a.own_old = c->own_cur; a.own_new = c->own_nxt;
+    a.cls = c->cls; a.stamp = c->stamp; a.P = c->P; a.rm = c->rm;
+    a.part_first_blk = c->part_first_blk;
+    a.blk_cnt = c->blk_cnt; a.blk_off = c->blk_off; a.l_off = c->l_off;
+    a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.lft = c->lft;
+    a.special = c->special; a.cnt = c->cnt; a.iters = c->iters;
+    return a;
+}
+
+lbm_status check_device(lbm_ctx *c) {
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    Counters h;
+    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+    if (h.err & ERR_NONFINITE) return fail(LBM_E_DIVERGED, "a particle state became non-finite");
+    if (h.err & ERR_FAST_PARTICLE) return fail(LBM_E_DIVERGED, "a particle moved more than one lattice unit in a step");
+    if (h.err & ERR_LINK_OVERFLOW) return fail(LBM_E_NOMEM, "cut-link list exceeded its capacity (%d)", c->p.link_cap);
+    if (h.err & ERR_SPECIAL_OVERFLOW) return fail(LBM_E_NOMEM, "boundary-node list exceeded its capacity (%d)", c->p.special_cap);
+    return LBM_OK;
+}
+
+// Flags from scratch for the current poses into own_nxt, node classes against
+// own_cur, then links of the new flags; own_nxt becomes current.
+lbm_status reflag(lbm_ctx *c) {
+    launch_refresh_pose(c->p, c->P, c->stream);
+    launch_fill_i32(c->own_nxt, c->pl.N, FLUID, c->stream);
+    launch_fill_u8(c->cls, c->pl.N, 0, c->stream);
+    launch_reset_counters(c->cnt, c->stream);
+    StepArgs a = base_args(c);
+    a.tag = ++c->tag;
+    a.phase = PHASE_FLAGS;
+    a.move = 1;
+    launch_phase(a);
+    a.phase = PHASE_LINKBUILD;
+    launch_phase(a);
+    std::swap(c->own_cur, c->own_nxt);
+    c->pending_refill = true;
+    return LBM_OK;
+}
+
+lbm_status do_refill(lbm_ctx *c) {
+    StepArgs a = base_args(c);
+    a.phase = PHASE_SPECIAL;
+    a.in_place = 1;
+    a.B = c->A;                  // in place on the stored state
+    a.own_old = c->own_nxt;      // flags before the last re-flag
+    launch_phase(a);
+    c->pending_refill = false;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+static lbm_status prepare(const lbm_config *cfg, int32_t n_p, const lbm_particle *parts,
+                          std::vector<DevParticle> *hp, Plan *pl) {
+    lbm_status s = validate_config(cfg);
+    if (s) return s;
+    if (n_p < 0 || n_p > 65535) return fail(LBM_E_INVALID, "n_p must be 0..65535");
+    if (n_p > 0 && !parts) return fail(LBM_E_INVALID, "particles is NULL");
+    std::vector<double> rb(n_p);
+    hp->assign(n_p, DevParticle{});
+    const int L[3] = {cfg->nx, cfg->ny, cfg->nz};
+    for (int p = 0; p < n_p; ++p) {
+        const lbm_particle &q = parts[p];
+        if ((s = validate_particle(cfg, &q, p))) return s;
+        BodyProps bp;
+        if (!body_properties(q.n_cp, q.cp_xyz, q.cp_k, cfg->quad_h, bp))
+            return fail(LBM_E_INVALID, "particle %d has no volume at quad_h", p);
+        DevParticle &d = (*hp)[p];
+        d.n_cp = q.n_cp;
+        d.mode = q.mode;
+        const double qn = std::sqrt(q.quat[0] * q.quat[0] + q.quat[1] * q.quat[1] + q.quat[2] * q.quat[2] + q.quat[3] * q.quat[3]);
+        for (int a = 0; a < 4; ++a) d.q[a] = q.quat[a] / qn;
+        double R[9];
+        rot_of_quat(d.q, R);
+        for (int i = 0; i < q.n_cp; ++i) {
+            d.k[i] = q.cp_k[i];
+            for (int a = 0; a < 3; ++a) d.cpb[i][a] = q.cp_xyz[3 * i + a] - bp.c[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            d.X[a] = q.x[a] + R[3 * a] * bp.c[0] + R[3 * a + 1] * bp.c[1] + R[3 * a + 2] * bp.c[2];
+            d.v[a] = q.v[a];
+            d.w[a] = q.omega[a];
+        }
+        d.V = bp.V;
+        d.m = q.density * bp.V;
+        for (int a = 0; a < 9; ++a) d.I[a] = q.density * bp.I[a];
+        if (!invert3(d.I, d.Iinv)) {
+            if (q.mode == LBM_MODE_FREE) return fail(LBM_E_INVALID, "particle %d: singular inertia", p);
+            for (int a = 0; a < 9; ++a) d.Iinv[a] = 0;
+        }
+        d.rb = bounding_radius(q.n_cp, q.cp_xyz, q.cp_k, bp.c);
+        rb[p] = d.rb;
+        for (int a = 0; a < 3; ++a)
+            if (!((cfg->periodic >> a) & 1u) && (d.X[a] - d.rb < 0.0 || d.X[a] + d.rb > L[a] - 1.0))
+                return fail(LBM_E_INVALID, "particle %d: bounding sphere crosses a wall on axis %d", p, a);
+    }
+    if ((s = make_plan(cfg, n_p, rb, *pl))) return s;
+    for (int p = 0; p < n_p; ++p) {
+        DevParticle &d = (*hp)[p];
+        d.half = pl->half[p];
+        for (int a = 0; a < 3; ++a) d.full[a] = pl->dims[3 * p + a] == L[a] && ((cfg->periodic >> a) & 1u);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_arena_bytes(const lbm_config *cfg, int32_t n_p, const lbm_particle *p, size_t *bytes) {
+    if (!bytes) return fail(LBM_E_INVALID, "bytes is NULL");
+    std::vector<DevParticle> hp;
+    Plan pl;
+    lbm_status s = prepare(cfg, n_p, p, &hp, &pl);
+    if (s) return s;
+    *bytes = pl.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *parts, void *dev_arena,
+                    size_t arena_bytes, void *hip_stream, lbm_ctx **out) {
+    if (!out) return fail(LBM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::vector<DevParticle> hp;
+    Plan pl;
+    lbm_status s = prepare(cfg, n_p, parts, &hp, &pl);
+    if (s) return s;
+    if (!dev_arena) return fail(LBM_E_INVALID, "arena is NULL");
+    if (arena_bytes < pl.total) return fail(LBM_E_NOMEM, "arena holds %zu bytes, %zu needed", arena_bytes, pl.total);
+    if ((uintptr_t)dev_arena & 255) return fail(LBM_E_INVALID, "arena must be 256-byte aligned");
+
+    lbm_ctx *c = new lbm_ctx();
+    c->cfg = *cfg;
+    c->pl = pl;
+    c->stream = (hipStream_t)hip_stream;
+    c->arena = (char *)dev_arena;
+    char *b = c->arena;
+    c->A = b + pl.off_A; c->B = b + pl.off_B;
+    c->own_cur = (int32_t *)(b + pl.off_own0); c->own_nxt = (int32_t *)(b + pl.off_own1);
+    c->cls = (uint8_t *)(b + pl.off_cls);
+    c->stamp = (uint32_t *)(b + pl.off_stamp);
+    c->P = (DevParticle *)(b + pl.off_P);
+    c->rm.part = (const int *)(b + pl.off_part);
+    c->rm.first = (const int *)(b + pl.off_first);
+    c->rm.dims = (const int *)(b + pl.off_dims);
+    c->part_first_blk = (int *)(b + pl.off_pfb);
+    c->blk_cnt = (int *)(b + pl.off_bcnt); c->blk_off = (int *)(b + pl.off_boff);
+    c->l_off = (int *)(b + pl.off_loff);
+    c->l_node = (uint32_t *)(b + pl.off_lnode); c->l_do = (uint32_t *)(b + pl.off_ldo);
+    c->l_q = (double *)(b + pl.off_lq); c->lft = (double *)(b + pl.off_lft);
+    c->special = (uint32_t *)(b + pl.off_special);
+    c->cnt = (Counters *)(b + pl.off_cnt);
+    c->iters = (int *)(b + pl.off_iters);
+    c->tag = 0;
+    c->timing = false;
+    c->ev_used = 0;
+    c->timed_launches = 0;
+    c->timed_ms = 0;
+    c->steps = 0;
+
+    Params &p = c->p;
+    memset(&p, 0, sizeof p);
+    p.nx = cfg->nx; p.ny = cfg->ny; p.nz = cfg->nz;
+    p.periodic = cfg->periodic;
+    p.N = pl.N;
+    p.np = n_p;
+    p.bc = cfg->bc;
+    p.n_sub = cfg->n_sub;
+    p.storage = cfg->storage;
+    p.rho0 = cfg->rho0;
+    p.tau = cfg->tau;
+    p.rho0f = (float)cfg->rho0;
+    p.omega = (float)(1.0 / cfg->tau);
+    p.fcoef = (float)(1.0 - 0.5 / cfg->tau);
+    for (int a = 0; a < 3; ++a) { p.gfd[a] = cfg->g_fluid[a]; p.gp[a] = cfg->g_particle[a]; }
+    p.scale = 1.f; p.inv_scale = 1.f;
+    if (cfg->storage == 1) {
+        p.scale = cfg->fp16_scale != 0.f ? cfg->fp16_scale : 1024.f;
+        p.inv_scale = 1.f / p.scale;
+    }
+    p.link_cap = pl.link_cap;
+    p.special_cap = pl.special_cap;
+    p.region_blocks = pl.region_blocks;
+
+    auto bail = [&](lbm_status st) { delete c; return st; };
+#define HIPCHK_C(expr)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return bail(fail(LBM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+    if (n_p > 0) {
+        HIPCHK_C(hipMemcpyAsync(c->P, hp.data(), sizeof(DevParticle) * n_p, hipMemcpyHostToDevice, c->stream));
+        HIPCHK_C(hipMemcpyAsync((void *)c->rm.part, pl.part.data(), 4 * pl.part.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK_C(hipMemcpyAsync((void *)c->rm.first, pl.first.data(), 4 * pl.first.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK_C(hipMemcpyAsync((void *)c->rm.dims, pl.dims.data(), 4 * pl.dims.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK_C(hipMemcpyAsync(c->part_first_blk, pl.part_first_blk.data(), 4 * n_p, hipMemcpyHostToDevice, c->stream));
+    }
+    std::vector<int> zeros(n_p + 1, 0);
+    HIPCHK_C(hipMemcpyAsync(c->l_off, zeros.data(), 4 * (n_p + 1), hipMemcpyHostToDevice, c->stream));
+    Counters zc{};
+    HIPCHK_C(hipMemcpyAsync(c->cnt, &zc, sizeof zc, hipMemcpyHostToDevice, c->stream));
+    int zi[16] = {0};
+    HIPCHK_C(hipMemcpyAsync(c->iters, zi, sizeof zi, hipMemcpyHostToDevice, c->stream));
+    launch_fill_i32(c->own_cur, pl.N, FLUID, c->stream);
+    launch_fill_i32((int32_t *)c->stamp, pl.N, 0, c->stream);
+
+    // counter-force: the fluid carries minus the net weight of free bodies
+    if (cfg->counter_force && n_p > 0) {
+        // needs the fluid volume, i.e. the flags: flag first, then read back
+        reflag(c);
+        HIPCHK_C(hipStreamSynchronize(c->stream));
+        Counters h;
+        HIPCHK_C(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+        const double nf = (double)(pl.N - h.n_solid);
+        double W[3] = {0, 0, 0};
+        for (int q = 0; q < n_p; ++q)
+            if (hp[q].mode == LBM_MODE_FREE)
+                for (int a = 0; a < 3; ++a) W[a] += (hp[q].m - cfg->rho0 * hp[q].V) * cfg->g_particle[a];
+        for (int a = 0; a < 3; ++a) p.gfd[a] = cfg->g_fluid[a] - W[a] / (cfg->rho0 * nf);
+    } else {
+        reflag(c);
+    }
+    p.gx = (float)p.gfd[0]; p.gy = (float)p.gfd[1]; p.gz = (float)p.gfd[2];
+    c->pending_refill = false;
+    StepArgs a = base_args(c);
+    a.phase = PHASE_INIT_STATE;
+    a.own_old = c->own_cur;
+    launch_phase(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bail(fail(LBM_E_HIP, "kernel launch: %s", hipGetErrorString(e)));
+    lbm_status st = check_device(c);
+    if (st) return bail(st);
+#undef HIPCHK_C
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status metaball_flag(lbm_ctx *c, int64_t *n_solid, int64_t *n_links) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    if (c->pending_refill) do_refill(c);
+    reflag(c);
+    if (n_solid || n_links) {
+        lbm_status s = check_device(c);
+        if (s) return s;
+        Counters h;
+        HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+        if (n_solid) *n_solid = h.n_solid;
+        if (n_links) *n_links = h.n_links;
+    }
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status refill(lbm_ctx *c, int64_t *n_refilled) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    if (!c->pending_refill) {
+        if (n_refilled) *n_refilled = 0;
+        return LBM_OK;
+    }
+    do_refill(c);
+    if (n_refilled) {
+        lbm_status s = check_device(c);
+        if (s) return s;
+        Counters h;
+        HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+        *n_refilled = h.n_refill;
+    }
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    if (n_steps < 0) return fail(LBM_E_INVALID, "n_steps must be >= 0");
+    if (mode != LBM_STEP_COUPLED && mode != LBM_STEP_FLUID_ONLY) return fail(LBM_E_INVALID, "unknown step mode");
+    if (c->pending_refill) do_refill(c);
+    const bool move = mode == LBM_STEP_COUPLED;
+    for (int s = 0; s < n_steps; ++s) {
+        StepArgs a = base_args(c);
+        a.move = move;
+        if (!move) a.own_new = c->own_cur;  // geometry fixed
+        a.tag = ++c->tag;
+        a.phase = PHASE_LINKS;
+        launch_phase(a);
+        a.phase = PHASE_FLAGS;
+        launch_phase(a);
+        const bool t = c->timing && c->ev_used + 2 <= c->ev.size();
+        if (t) HIPCHK(hipEventRecord(c->ev[c->ev_used], c->stream));
+        a.phase = PHASE_BULK;
+        launch_phase(a);
+        if (t) {
+            HIPCHK(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+            c->ev_used += 2;
+        }
+        a.phase = PHASE_SPECIAL;
+        a.in_place = 0;
+        launch_phase(a);
+        if (move) {
+            a.phase = PHASE_LINKBUILD;
+            launch_phase(a);
+            std::swap(c->own_cur, c->own_nxt);
+        }
+        std::swap(c->A, c->B);
+        c->steps++;
+    }
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx *c) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    return check_device(c);
+}
+
+lbm_status particle_forces(lbm_ctx *c, double *F, double *T) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    std::vector<DevParticle> hp(c->p.np);
+    if (c->p.np) HIPCHK(hipMemcpy(hp.data(), c->P, sizeof(DevParticle) * c->p.np, hipMemcpyDeviceToHost));
+    for (int p = 0; p < c->p.np; ++p)
+        for (int a = 0; a < 3; ++a) {
+            if (F) F[3 * p + a] = hp[p].F[a];
+            if (T) T[3 * p + a] = hp[p].T[a];
+        }
+    return LBM_OK;
+}
+
+static lbm_status read_state(lbm_ctx *c, double *host) {
+    lbm_status s = check_device(c);
+    if (s) return s;
+    const long long N = c->pl.N;
+    const size_t sb = c->pl.storage_bytes;
+    std::vector<char> raw((size_t)Q * N * sb);
+    HIPCHK(hipMemcpy(raw.data(), c->A, raw.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < Q; ++i)
+        for (long long n = 0; n < N; ++n) {
+            const size_t k = (size_t)i * N + n;
+            double d;
+            if (sb == 4) {
+                d = ((const float *)raw.data())[k];
+            } else if (c->p.storage == 1) {
+                d = (double)(float)((const _Float16 *)raw.data())[k] * (double)c->p.inv_scale;
+            } else {
+                const uint32_t u = (uint32_t)((const uint16_t *)raw.data())[k] << 16;
+                float f;
+                memcpy(&f, &u, 4);
+                d = f;
+            }
+            host[k] = d + WD[i] * c->p.rho0;
+        }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx *c, double *f) {
+    if (!c || !f) return fail(LBM_E_INVALID, "NULL argument");
+    return read_state(c, f);
+}
+
+lbm_status lbm_set_populations(lbm_ctx *c, const double *f, int32_t post_collision) {
+    if (!c || !f) return fail(LBM_E_INVALID, "NULL argument");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    const long long N = c->pl.N;
+    for (long long k = 0; k < (long long)Q * N; ++k)
+        if (!std::isfinite(f[k])) return fail(LBM_E_INVALID, "non-finite population at %lld", k);
+    std::vector<char> raw((size_t)Q * N * c->pl.storage_bytes);
+    for (int i = 0; i < Q; ++i)
+        for (long long n = 0; n < N; ++n) {
+            const size_t k = (size_t)i * N + n;
+            const double d = f[k] - WD[i] * c->p.rho0;
+            if (c->pl.storage_bytes == 4) {
+                ((float *)raw.data())[k] = (float)d;
+            } else if (c->p.storage == 1) {
+                ((_Float16 *)raw.data())[k] = (_Float16)(float)(d * c->p.scale);
+            } else {
+                const float x = (float)d;
+                uint32_t u;
+                memcpy(&u, &x, 4);
+                u += 0x7fffu + ((u >> 16) & 1u);
+                ((uint16_t *)raw.data())[k] = (uint16_t)(u >> 16);
+            }
+        }
+    HIPCHK(hipMemcpy(c->A, raw.data(), raw.size(), hipMemcpyHostToDevice));
+    if (!post_collision) {
+        StepArgs a = base_args(c);
+        a.phase = PHASE_COLLIDE_STORED;
+        a.own_old = c->own_cur;
+        launch_phase(a);
+    }
+    c->pending_refill = false;
+    return check_device(c);
+}
+
+lbm_status lbm_get_macros(lbm_ctx *c, double *rho, double *u) {
+    if (!c || !rho || !u) return fail(LBM_E_INVALID, "NULL argument");
+    const long long N = c->pl.N;
+    std::vector<double> f((size_t)Q * N);
+    lbm_status s = read_state(c, f.data());
+    if (s) return s;
+    for (long long n = 0; n < N; ++n) {
+        double r = 0, j[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+            const double v = f[(size_t)i * N + n];
+            r += v;
+            j[0] += EX[i] * v; j[1] += EY[i] * v; j[2] += EZ[i] * v;
+        }
+        rho[n] = r;
+        for (int a = 0; a < 3; ++a) u[3 * n + a] = j[a] / r - 0.5 * c->p.gfd[a];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_flags(lbm_ctx *c, int32_t *owner) {
+    if (!c || !owner) return fail(LBM_E_INVALID, "NULL argument");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    HIPCHK(hipMemcpy(owner, c->own_cur, 4 * c->pl.N, hipMemcpyDeviceToHost));
+    for (long long n = 0; n < c->pl.N; ++n)
+        if (owner[n] == FLUID) owner[n] = -1;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_links(lbm_ctx *c, int64_t *n_links, uint32_t *node, int32_t *dir, int32_t *owner, double *q) {
+    if (!c || !n_links) return fail(LBM_E_INVALID, "NULL argument");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    Counters h;
+    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+    *n_links = h.n_links;
+    if (!node && !dir && !owner && !q) return LBM_OK;
+    const int nl = h.n_links;
+    std::vector<uint32_t> nd(nl), d(nl);
+    std::vector<double> qq(nl);
+    if (nl) {
+        HIPCHK(hipMemcpy(nd.data(), c->l_node, 4 * (size_t)nl, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(d.data(), c->l_do, 4 * (size_t)nl, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(qq.data(), c->l_q, 8 * (size_t)nl, hipMemcpyDeviceToHost));
+    }
+    for (int l = 0; l < nl; ++l) {
+        if (node) node[l] = nd[l];
+        if (dir) dir[l] = (int32_t)(d[l] & 31u);
+        if (owner) owner[l] = (int32_t)(d[l] >> 8);
+        if (q) q[l] = qq[l];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_particles(lbm_ctx *c, lbm_particle_state *out) {
+    if (!c || (!out && c->p.np)) return fail(LBM_E_INVALID, "NULL argument");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    std::vector<DevParticle> hp(c->p.np);
+    if (c->p.np) HIPCHK(hipMemcpy(hp.data(), c->P, sizeof(DevParticle) * c->p.np, hipMemcpyDeviceToHost));
+    for (int p = 0; p < c->p.np; ++p) {
+        lbm_particle_state &o = out[p];
+        const DevParticle &d = hp[p];
+        memcpy(o.x, d.X, sizeof o.x); memcpy(o.quat, d.q, sizeof o.quat);
+        memcpy(o.v, d.v, sizeof o.v); memcpy(o.omega, d.w, sizeof o.omega);
+        memcpy(o.F, d.F, sizeof o.F); memcpy(o.T, d.T, sizeof o.T);
+        o.mass = d.m; o.volume = d.V;
+        memcpy(o.inertia, d.I, sizeof o.inertia);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_particles(lbm_ctx *c, const lbm_particle_state *in) {
+    if (!c || (!in && c->p.np)) return fail(LBM_E_INVALID, "NULL argument");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    std::vector<DevParticle> hp(c->p.np);
+    if (c->p.np) HIPCHK(hipMemcpy(hp.data(), c->P, sizeof(DevParticle) * c->p.np, hipMemcpyDeviceToHost));
+    const int L[3] = {c->p.nx, c->p.ny, c->p.nz};
+    for (int p = 0; p < c->p.np; ++p) {
+        const lbm_particle_state &o = in[p];
+        if (!finite_all(o.x, 3) || !finite_all(o.quat, 4) || !finite_all(o.v, 3) || !finite_all(o.omega, 3))
+            return fail(LBM_E_INVALID, "particle %d: non-finite state", p);
+        DevParticle &d = hp[p];
+        const double qn = std::sqrt(o.quat[0] * o.quat[0] + o.quat[1] * o.quat[1] + o.quat[2] * o.quat[2] + o.quat[3] * o.quat[3]);
+        if (!(qn > 0)) return fail(LBM_E_INVALID, "particle %d: zero quaternion", p);
+        for (int a = 0; a < 3; ++a) {
+            d.X[a] = o.x[a]; d.v[a] = o.v[a]; d.w[a] = o.omega[a];
+            if (!((c->p.periodic >> a) & 1u) && (d.X[a] - d.rb < 0.0 || d.X[a] + d.rb > L[a] - 1.0))
+                return fail(LBM_E_INVALID, "particle %d: bounding sphere crosses a wall on axis %d", p, a);
+        }
+        for (int a = 0; a < 4; ++a) d.q[a] = o.quat[a] / qn;
+    }
+    if (c->p.np) HIPCHK(hipMemcpy(c->P, hp.data(), sizeof(DevParticle) * c->p.np, hipMemcpyHostToDevice));
+    launch_refresh_pose(c->p, c->P, c->stream);
+    return check_device(c);
+}
+
+lbm_status lbm_get_gfluid(lbm_ctx *c, double *g3) {
+    if (!c || !g3) return fail(LBM_E_INVALID, "NULL argument");
+    for (int a = 0; a < 3; ++a) g3[a] = c->p.gfd[a];
+    return LBM_OK;
+}
+
+lbm_status lbm_timing_enable(lbm_ctx *c, int32_t on) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    if (on && c->ev.empty()) {
+        c->ev.resize(2 * 1024);
+        for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
+    }
+    c->timing = on != 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_timing_read(lbm_ctx *c, double *ms, int64_t *launches, int64_t *nodes_per_launch) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double tot = 0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]));
+        tot += t;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = (int64_t)(c->ev_used / 2);
+    if (nodes_per_launch) *nodes_per_launch = c->pl.N;
+    c->ev_used = 0;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    for (auto &e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Device-side data layout shared by the kernels and the host launcher.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mdl {
+
+constexpr int Q = 19;
+constexpr int MAXCP = 20;
+constexpr int32_t FLUID = 0x7fffffff;  // owner value of a fluid node (atomicMin-friendly)
+constexpr int PAD = 4;                  // region margin beyond the bounding radius
+constexpr int BLK = 256;                // threads per block of the region kernels
+
+enum : uint8_t { CLS_SOLID_OLD = 1, CLS_SOLID_NEW = 2, CLS_LINKS_OLD = 4 };
+enum : int { ERR_LINK_OVERFLOW = 1, ERR_SPECIAL_OVERFLOW = 2, ERR_FAST_PARTICLE = 4,
+             ERR_NONFINITE = 8 };
+
+// D3Q19 velocities in the order documented in midelbm.h.
+constexpr int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int EY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int EZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+constexpr double WD[Q] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+// FP64 particle record (one per body) living in device memory.
+struct DevParticle {
+    double X[3], q[4], v[3], w[3];  // centroid, body->lab quaternion, velocity, spin (lab)
+    double m, V;
+    double I[9], Iinv[9];           // body frame, about the centroid
+    double F[3], T[3];              // hydrodynamic load of the last step
+    double cpb[MAXCP][3];           // control points, body frame (origin = centroid)
+    double k[MAXCP];
+    double cpl[MAXCP][3];           // control points, lab frame, current pose
+    double rb;                      // bounding radius about X
+    int n_cp, mode;
+    int half;                       // region half-width (ceil(rb) + PAD)
+    int lo[3];                      // region origin (unwrapped), set from X each pose change
+    int full[3];                    // 1: the region spans a whole periodic axis
+};
+
+// Small device-side counters, reset and read by the host at sync points.
+struct Counters {
+    int n_links;    // links of the current geometry
+    int n_special;  // boundary and uncovered nodes listed this step
+    int n_refill;   // uncovered nodes this step
+    int n_solid;    // solid nodes counted by the last classification
+    int err;        // ERR_* bits
+    int pad[3];
+};
+
+// Per-context constants, passed to kernels by value.
+struct Params {
+    int nx, ny, nz;
+    unsigned periodic;
+    long long N;
+    int np;
+    int bc;
+    int n_sub;
+    int storage;
+    float rho0f, omega, fcoef;  // 1/tau and 1 - 1/(2 tau)
+    float gx, gy, gz;           // fluid body acceleration
+    float scale, inv_scale;     // storage scale (FP16) and its inverse
+    double rho0, tau;
+    double gfd[3];              // fluid body acceleration, FP64
+    double gp[3];               // particle gravity
+    int link_cap, special_cap;
+    int region_blocks;          // blocks of the region kernels
+};
+
+// Region block map: block b of a region kernel works on particle part[b],
+// local region indices [first[b], first[b] + BLK).
+struct RegionMap {
+    const int *part;
+    const int *first;
+    const int *dims;  // [np][3] region extent per axis
+};
+
+}  // namespace mdl

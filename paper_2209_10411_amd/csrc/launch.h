@@ -1,0 +1,48 @@
+// Interface between the host-side C ABI (api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace mdl {
+
+enum Phase {
+    PHASE_LINKS = 0,       // bounce-back values + momentum exchange, force reduction, rigid body
+    PHASE_FLAGS = 1,       // region flags (when move) and node classes
+    PHASE_BULK = 2,        // stream-collide of plain fluid nodes
+    PHASE_SPECIAL = 3,     // boundary and uncovered nodes
+    PHASE_LINKBUILD = 4,   // cut links and q of the new geometry
+    PHASE_INIT_STATE = 5,     // collided rest state
+    PHASE_COLLIDE_STORED = 6  // collide the stored populations of fluid nodes in place
+};
+
+struct StepArgs {
+    Params p;
+    int phase;
+    int move;      // PHASE_LINKS: update particles; PHASE_FLAGS: re-flag
+    int in_place;  // PHASE_SPECIAL: refill in place
+    uint32_t tag;
+    hipStream_t stream;
+    void *A, *B;
+    int32_t *own_old, *own_new;
+    uint8_t *cls;
+    uint32_t *stamp;
+    DevParticle *P;
+    RegionMap rm;
+    const int *part_first_blk;
+    int *blk_cnt, *blk_off, *l_off;
+    uint32_t *l_node, *l_do;
+    double *l_q, *lft;
+    uint32_t *special;
+    Counters *cnt;
+    int *iters;
+};
+
+void launch_phase(const StepArgs &a);
+void launch_fill_i32(int32_t *a, long long n, int32_t v, hipStream_t s);
+void launch_fill_u8(uint8_t *a, long long n, uint8_t v, hipStream_t s);
+void launch_reset_counters(Counters *cnt, hipStream_t s);
+void launch_refresh_pose(const Params &p, DevParticle *P, hipStream_t s);
+
+}  // namespace mdl

@@ -1,0 +1,79 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/midelbm.h declares, and lbm_arena_bytes (host-only) validates its
+inputs with the documented status codes."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "midelbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:lbm_status|void|const char\s*\*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def mdl():
+    import paper_2209_10411_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2209_10411_amd import build
+        build.build()
+    return m
+
+
+def test_header_lists_the_hot_path_calls():
+    names = header_functions()
+    for n in ["lbm_init", "metaball_flag", "lbm_step", "particle_forces", "refill"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(mdl):
+    L = mdl.lib()
+    for n in header_functions():
+        assert hasattr(L, n), n
+    assert sorted(mdl.EXPORTS) == header_functions()
+
+
+def test_arena_bytes_counts_populations(mdl):
+    cfg = workloads.config1()
+    b32 = mdl.arena_bytes(cfg)
+    cfg.storage = workloads.STORE_F16
+    b16 = mdl.arena_bytes(cfg)
+    N = 64 ** 3
+    assert b32 >= 2 * 19 * 4 * N
+    assert b32 - b16 >= 2 * 19 * 2 * N - 1024
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda c: setattr(c, "tau", 0.5), -1),
+    (lambda c: setattr(c, "nx", 2), -1),
+    (lambda c: setattr(c, "storage", 7), -1),
+    (lambda c: setattr(c, "n_sub", 0), -1),
+    (lambda c: setattr(c, "g_fluid", np.array([np.nan, 0, 0])), -1),
+    (lambda c: c.particles[0].__setattr__("cp_k", np.array([-1.0])), -1),
+    (lambda c: (c.particles[0].__setattr__("cp_xyz", np.arange(63.0).reshape(21, 3) / 10),
+                c.particles[0].__setattr__("cp_k", np.ones(21))), -1),
+    (lambda c: c.particles[0].__setattr__("density", 0.0), -1),
+])
+def test_arena_bytes_rejects_bad_input(mdl, mutate, code):
+    cfg = workloads.config1()
+    mutate(cfg)
+    with pytest.raises(mdl.LbmError) as e:
+        mdl.arena_bytes(cfg)
+    assert e.value.status == code
+    assert mdl.lib().lbm_last_error()
+
+
+def test_particle_crossing_a_wall_is_rejected(mdl):
+    cfg = workloads.config2(scale=0.25)
+    cfg.particles[0].x = np.array([3.0, 16.0, 50.0])
+    with pytest.raises(mdl.LbmError) as e:
+        mdl.arena_bytes(cfg)
+    assert "wall" in str(e.value)
