@@ -1,0 +1,172 @@
+"""Benchmark of the coupled metaball / lattice Boltzmann step on one MI355X.
+
+Workload: the single settling particle case -- 128 x 128 x 384 lattice with
+no-slip walls, D3Q19 BGK tau = 0.6, one free metaball of 8 control points
+(R = 10, density ratio 1.5, gravity 2e-5), interpolated bounce-back, local
+refilling; synthetic inputs from workloads.config2().  One step is one full
+coupled step (cut-link bounce-back and momentum exchange, rigid body,
+flagging, stream-collide with refill, cut-link rebuild).
+
+Prints one JSON line: MLUPS over all lattice nodes with FP32 storage (the
+headline), the same with FP16 storage, the roofline of the dominant kernel
+(the stream-collide, timed with HIP events on the library's stream), and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+KERNEL_SRC = os.path.join(ROOT, "paper_2209_10411_amd", "csrc", "kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_bulk_settling_128x128x384_pmc.txt")
+
+
+def bytes_per_node(storage: int) -> int:
+    return 19 * 2 * (4 if storage == 0 else 2)
+
+
+def run_gpu(cfg, steps, warmup):
+    import torch
+
+    import paper_2209_10411_amd as mdl
+
+    sim = mdl.Simulation(cfg, device="cuda:0")
+    sim.step(warmup)
+    sim.sync()
+    sim.timing(True)
+    sim.timing_read()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_n, k_nodes = sim.timing_read()
+    x = sim.particles()[0]["x"]
+    nr = sim.nr_stats()
+    sim.close()
+    return dt, k_ms, k_n, k_nodes, x, nr
+
+
+def traffic_from_profile():
+    """FETCH/WRITE bytes per launch of the stream-collide kernel from the
+    committed rocprofv3 --pmc summary, if it was taken on this kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, budget_s):
+    import oracle
+
+    t0 = time.perf_counter()
+    o = oracle.Oracle(cfg)
+    t_init = time.perf_counter() - t0
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(cfg.n_nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} coupled steps of the same 128x128x384 settling case "
+                      f"(FP64, {oracle.threads()} OpenMP threads, {t_init:.1f} s setup excluded)"}
+
+
+def calib_copy(gib: float = 1.0):
+    """A plain copy of known size, for scaling the PMC byte counters."""
+    import torch
+    n = int(gib * (1 << 30))
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": n, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB copy (PMC calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by z-slabs across GPUs, which this build does not implement)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.calib_copy:
+        calib_copy()
+        return
+    import workloads
+
+    cfg = workloads.config2()
+    N = cfg.n_nodes
+    dt, k_ms, k_n, k_nodes, x, nr = run_gpu(cfg, args.steps, args.warmup)
+    mlups = N * args.steps / dt / 1e6
+    k_avg_s = k_ms / 1e3 / max(k_n, 1)
+    alg_bytes = k_nodes * bytes_per_node(0) + N  # populations of updated nodes + class byte of all
+    achieved = alg_bytes / k_avg_s / 1e9
+    traffic = traffic_from_profile()
+    out = {
+        "metric": "MLUPS with moving metaball boundaries (FP32 vs FP16-store) + % HBM peak",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "settling-particle 128x128x384 walls, D3Q19 BGK tau=0.6, "
+                               "1 metaball 8 cp R=10, density ratio 1.5, g=2e-5, IBB + refill, "
+                               "FP32 deviation storage",
+                   "nx": 128, "ny": 128, "nz": 384, "nodes": N, "storage": "f32",
+                   "step": "coupled (links+MEM, rigid body, flags, stream-collide+refill, links)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_bulk<f32>",
+                     "kernel_avg_ms": round(k_ms / max(k_n, 1), 5),
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "kernel_mlups": round(k_nodes / k_avg_s / 1e6, 1),
+        "particle_x_final": [round(v, 6) for v in x],
+        "link_fraction_newton": {"links": nr[0], "mean_iterations": round(nr[1] / max(nr[0], 1), 3)},
+    }
+    if not args.no_fp16:
+        cfg16 = workloads.config2()
+        cfg16.storage = workloads.STORE_F16
+        dt16, k16_ms, k16_n, k16_nodes, _, _ = run_gpu(cfg16, args.steps, args.warmup)
+        k16_s = k16_ms / 1e3 / max(k16_n, 1)
+        ach16 = (k16_nodes * bytes_per_node(1) + N) / k16_s / 1e9
+        out["fp16_store"] = {"value": round(N * args.steps / dt16 / 1e6, 1), "unit": "MLUPS",
+                             "ms_per_step": round(dt16 * 1e3 / args.steps, 5),
+                             "kernel_avg_ms": round(k16_ms / max(k16_n, 1), 5),
+                             "kernel_achieved_GBs": round(ach16, 1),
+                             "kernel_frac": round(ach16 / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -122,7 +122,8 @@ typedef struct {
 lbm_status lbm_arena_bytes(const lbm_config *cfg, int32_t n_p, const lbm_particle *p, size_t *bytes);
 
 /* Validates the configuration (tau > 0.5, sizes >= 3, 1..20 control points
- * with k > 0, finite inputs, particles clear of walls and of each other),
+ * with k > 0, finite inputs, each body's bounding sphere inside the walled
+ * faces; overlapping bodies are not rejected, see the owner rule above),
  * computes body properties, uploads the state, flags the nodes, builds the
  * cut links and sets every fluid node to the collided rest state
  * f = feq(rho0, 0).  dev_arena must hold arena_bytes >= lbm_arena_bytes();
@@ -177,11 +178,17 @@ lbm_status lbm_set_particles(lbm_ctx *ctx, const lbm_particle_state *in /* [n_p]
 lbm_status lbm_get_gfluid(lbm_ctx *ctx, double *g3);
 
 /* ---- measurement ---- */
-/* When enabled, the stream-collide kernel of every step is bracketed by HIP
- * events on the context's stream; lbm_timing_read returns the summed elapsed
- * milliseconds and launch count since the last reset (synchronises). */
+/* When enabled, the stream-collide kernel of every step (up to 4096 steps
+ * between reads) is bracketed by HIP events on the context's stream;
+ * lbm_timing_read returns the summed elapsed milliseconds and the launch
+ * count since the last read, and the number of nodes that kernel updated in
+ * the last step (all nodes but solid, boundary and uncovered ones); it
+ * synchronises. */
 lbm_status lbm_timing_enable(lbm_ctx *ctx, int32_t on);
 lbm_status lbm_timing_read(lbm_ctx *ctx, double *ms, int64_t *launches, int64_t *nodes_per_launch);
+/* Link fractions solved and Newton/bisection iterations spent on them since
+ * the last call (resets the counts; synchronises). */
+lbm_status lbm_nr_stats(lbm_ctx *ctx, int64_t *links, int64_t *iterations);
 /* Waits for the context's stream and reports device-side errors. */
 lbm_status lbm_sync(lbm_ctx *ctx);
 

@@ -56,7 +56,8 @@ class lbm_particle_state(C.Structure):
 EXPORTS = ["lbm_arena_bytes", "lbm_init", "metaball_flag", "lbm_step", "particle_forces", "refill",
            "lbm_get_macros", "lbm_get_populations", "lbm_set_populations", "lbm_get_flags",
            "lbm_get_links", "lbm_get_particles", "lbm_set_particles", "lbm_get_gfluid",
-           "lbm_timing_enable", "lbm_timing_read", "lbm_sync", "lbm_destroy", "lbm_last_error"]
+           "lbm_timing_enable", "lbm_timing_read", "lbm_nr_stats", "lbm_sync", "lbm_destroy",
+           "lbm_last_error"]
 
 _lib = None
 
@@ -89,6 +90,7 @@ def lib():
         L.lbm_get_gfluid.argtypes = [vp, dp]
         L.lbm_timing_enable.argtypes = [vp, C.c_int32]
         L.lbm_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.lbm_nr_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_sync.argtypes = [vp]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
@@ -272,6 +274,12 @@ class Simulation:
         return g
 
     # ---- measurement
+    def nr_stats(self):
+        """(link fractions solved, Newton/bisection iterations) since the last call."""
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(lib().lbm_nr_stats(self._ctx, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
+
     def timing(self, on: bool = True):
         _check(lib().lbm_timing_enable(self._ctx, int(bool(on))))
 

@@ -157,9 +157,9 @@ struct Plan {
     std::vector<int> part, first;     // [region_blocks]
     std::vector<int> part_first_blk;  // [np]
     std::vector<int> half;            // [np]
-    size_t off_A, off_B, off_own0, off_own1, off_cls, off_stamp, off_P, off_part, off_first, off_dims,
-        off_pfb, off_bcnt, off_boff, off_loff, off_lnode, off_ldo, off_lq, off_lft, off_special,
-        off_cnt, off_iters, total;
+    size_t off_A, off_B, off_own[3], off_skip[2], off_stamp, off_P, off_part, off_first, off_dims,
+        off_pfb, off_bcnt, off_boff, off_loff, off_lnode, off_ldo, off_lq, off_lpart, off_special,
+        off_cnt, total;
 };
 
 struct HostParticle {
@@ -258,9 +258,9 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     const size_t pop = (size_t)Q * pl.N * pl.storage_bytes;
     pl.off_A = take(pop);
     pl.off_B = take(pop);
-    pl.off_own0 = take(4 * pl.N);
-    pl.off_own1 = take(4 * pl.N);
-    pl.off_cls = take(pl.N);
+    for (int k = 0; k < 3; ++k) pl.off_own[k] = take(4 * pl.N);
+    pl.off_skip[0] = take(pl.N);
+    pl.off_skip[1] = take(pl.N);
     pl.off_stamp = take(4 * pl.N);
     pl.off_P = take(sizeof(DevParticle) * std::max(np, 1));
     pl.off_part = take(4 * std::max(pl.region_blocks, 1));
@@ -273,10 +273,10 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_lnode = take(4 * (size_t)std::max(pl.link_cap, 1));
     pl.off_ldo = take(4 * (size_t)std::max(pl.link_cap, 1));
     pl.off_lq = take(8 * (size_t)std::max(pl.link_cap, 1));
-    pl.off_lft = take(48 * (size_t)std::max(pl.link_cap, 1));
+    // per-chunk, per-body partial momentum sums: chunk + body < cap/256 + 1 + np
+    pl.off_lpart = take(48 * ((size_t)pl.link_cap / 256 + 2 + np));
     pl.off_special = take(4 * (size_t)std::max(pl.special_cap, 1));
     pl.off_cnt = take(sizeof(Counters));
-    pl.off_iters = take(64);
     pl.total = o;
     return LBM_OK;
 }
@@ -290,16 +290,19 @@ struct lbm_ctx {
     hipStream_t stream;
     char *arena;
     void *A, *B;
-    int32_t *own_cur, *own_nxt;
-    uint8_t *cls;
+    int32_t *own[3];
+    int ic, in, id;  // current flags, next (all FLUID), dead (previous)
+    uint8_t *skip[2];
+    int is;          // skip mask of the coming step
     uint32_t *stamp;
     DevParticle *P;
     RegionMap rm;
-    int *part_first_blk, *blk_cnt, *blk_off, *l_off, *iters;
+    int *part_first_blk, *blk_cnt, *blk_off, *l_off;
     uint32_t *l_node, *l_do, *special;
-    double *l_q, *lft;
+    double *l_q, *lpart;
     Counters *cnt;
-    uint32_t tag;
+    hipStream_t aux;              // second stream: link build overlapped with stream-collide
+    hipEvent_t ev_main, ev_flags, ev_links;
     bool pending_refill;
     bool timing;
     std::vector<hipEvent_t> ev;  // start/stop pairs
@@ -316,12 +319,13 @@ StepArgs base_args(lbm_ctx *c) {
     a.p = c->p;
     a.stream = c->stream;
     a.A = c->A; a.B = c->B;
-    a.own_old = c->own_cur; a.own_new = c->own_nxt;
-    a.cls = c->cls; a.stamp = c->stamp; a.P = c->P; a.rm = c->rm;
+    a.own_old = c->own[c->ic]; a.own_new = c->own[c->in]; a.own_dead = nullptr;
+    a.skip = c->skip[c->is]; a.skip_next = c->skip[1 - c->is];
+    a.stamp = c->stamp; a.P = c->P; a.rm = c->rm;
     a.part_first_blk = c->part_first_blk;
     a.blk_cnt = c->blk_cnt; a.blk_off = c->blk_off; a.l_off = c->l_off;
-    a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.lft = c->lft;
-    a.special = c->special; a.cnt = c->cnt; a.iters = c->iters;
+    a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.part = c->lpart;
+    a.special = c->special; a.cnt = c->cnt;
     return a;
 }
 
@@ -334,24 +338,29 @@ lbm_status check_device(lbm_ctx *c) {
     if (h.err & ERR_FAST_PARTICLE) return fail(LBM_E_DIVERGED, "a particle moved more than one lattice unit in a step");
     if (h.err & ERR_LINK_OVERFLOW) return fail(LBM_E_NOMEM, "cut-link list exceeded its capacity (%d)", c->p.link_cap);
     if (h.err & ERR_SPECIAL_OVERFLOW) return fail(LBM_E_NOMEM, "boundary-node list exceeded its capacity (%d)", c->p.special_cap);
+    if (h.err & ERR_BAD_INDEX) return fail(LBM_E_STATE, "an index list held an out-of-range entry (skipped)");
     return LBM_OK;
 }
 
-// Flags from scratch for the current poses into own_nxt, node classes against
-// own_cur, then links of the new flags; own_nxt becomes current.
+// Flags from scratch for the current poses into the next buffer, node
+// classes against the current one, then the links of the new flags.  The
+// old flags stay in the dead buffer until refill() has used them.
 lbm_status reflag(lbm_ctx *c) {
     launch_refresh_pose(c->p, c->P, c->stream);
-    launch_fill_i32(c->own_nxt, c->pl.N, FLUID, c->stream);
-    launch_fill_u8(c->cls, c->pl.N, 0, c->stream);
+    launch_fill_i32(c->own[c->in], c->pl.N, FLUID, c->stream);
+    launch_fill_i32(c->own[c->id], c->pl.N, FLUID, c->stream);
+    launch_fill_u8(c->skip[0], c->pl.N, 0, c->stream);
+    launch_fill_u8(c->skip[1], c->pl.N, 0, c->stream);
     launch_reset_counters(c->cnt, c->stream);
     StepArgs a = base_args(c);
-    a.tag = ++c->tag;
     a.phase = PHASE_FLAGS;
     a.move = 1;
     launch_phase(a);
     a.phase = PHASE_LINKBUILD;
     launch_phase(a);
-    std::swap(c->own_cur, c->own_nxt);
+    const int old = c->ic;
+    c->ic = c->in; c->in = c->id; c->id = old;
+    c->is = 1 - c->is;
     c->pending_refill = true;
     return LBM_OK;
 }
@@ -361,8 +370,9 @@ lbm_status do_refill(lbm_ctx *c) {
     a.phase = PHASE_SPECIAL;
     a.in_place = 1;
     a.B = c->A;                  // in place on the stored state
-    a.own_old = c->own_nxt;      // flags before the last re-flag
+    a.own_old = c->own[c->id];   // flags before the last re-flag
     launch_phase(a);
+    launch_fill_i32(c->own[c->id], c->pl.N, FLUID, c->stream);
     c->pending_refill = false;
     return LBM_OK;
 }
@@ -455,8 +465,11 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->arena = (char *)dev_arena;
     char *b = c->arena;
     c->A = b + pl.off_A; c->B = b + pl.off_B;
-    c->own_cur = (int32_t *)(b + pl.off_own0); c->own_nxt = (int32_t *)(b + pl.off_own1);
-    c->cls = (uint8_t *)(b + pl.off_cls);
+    for (int k = 0; k < 3; ++k) c->own[k] = (int32_t *)(b + pl.off_own[k]);
+    c->ic = 0; c->in = 1; c->id = 2;
+    c->skip[0] = (uint8_t *)(b + pl.off_skip[0]);
+    c->skip[1] = (uint8_t *)(b + pl.off_skip[1]);
+    c->is = 0;
     c->stamp = (uint32_t *)(b + pl.off_stamp);
     c->P = (DevParticle *)(b + pl.off_P);
     c->rm.part = (const int *)(b + pl.off_part);
@@ -466,11 +479,11 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->blk_cnt = (int *)(b + pl.off_bcnt); c->blk_off = (int *)(b + pl.off_boff);
     c->l_off = (int *)(b + pl.off_loff);
     c->l_node = (uint32_t *)(b + pl.off_lnode); c->l_do = (uint32_t *)(b + pl.off_ldo);
-    c->l_q = (double *)(b + pl.off_lq); c->lft = (double *)(b + pl.off_lft);
+    c->l_q = (double *)(b + pl.off_lq); c->lpart = (double *)(b + pl.off_lpart);
     c->special = (uint32_t *)(b + pl.off_special);
     c->cnt = (Counters *)(b + pl.off_cnt);
-    c->iters = (int *)(b + pl.off_iters);
-    c->tag = 0;
+    c->aux = nullptr;
+    c->ev_main = c->ev_flags = c->ev_links = nullptr;
     c->timing = false;
     c->ev_used = 0;
     c->timed_launches = 0;
@@ -501,7 +514,14 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     p.special_cap = pl.special_cap;
     p.region_blocks = pl.region_blocks;
 
-    auto bail = [&](lbm_status st) { delete c; return st; };
+    auto bail = [&](lbm_status st) {
+        if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+        if (c->ev_flags) (void)hipEventDestroy(c->ev_flags);
+        if (c->ev_links) (void)hipEventDestroy(c->ev_links);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        delete c;
+        return st;
+    };
 #define HIPCHK_C(expr)                                                                        \
     do {                                                                                      \
         hipError_t e_ = (expr);                                                               \
@@ -518,9 +538,11 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     HIPCHK_C(hipMemcpyAsync(c->l_off, zeros.data(), 4 * (n_p + 1), hipMemcpyHostToDevice, c->stream));
     Counters zc{};
     HIPCHK_C(hipMemcpyAsync(c->cnt, &zc, sizeof zc, hipMemcpyHostToDevice, c->stream));
-    int zi[16] = {0};
-    HIPCHK_C(hipMemcpyAsync(c->iters, zi, sizeof zi, hipMemcpyHostToDevice, c->stream));
-    launch_fill_i32(c->own_cur, pl.N, FLUID, c->stream);
+    HIPCHK_C(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK_C(hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming));
+    HIPCHK_C(hipEventCreateWithFlags(&c->ev_flags, hipEventDisableTiming));
+    HIPCHK_C(hipEventCreateWithFlags(&c->ev_links, hipEventDisableTiming));
+    for (int k = 0; k < 3; ++k) launch_fill_i32(c->own[k], pl.N, FLUID, c->stream);
     launch_fill_i32((int32_t *)c->stamp, pl.N, 0, c->stream);
 
     // counter-force: the fluid carries minus the net weight of free bodies
@@ -543,7 +565,6 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->pending_refill = false;
     StepArgs a = base_args(c);
     a.phase = PHASE_INIT_STATE;
-    a.own_old = c->own_cur;
     launch_phase(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bail(fail(LBM_E_HIP, "kernel launch: %s", hipGetErrorString(e)));
@@ -594,15 +615,28 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
     if (mode != LBM_STEP_COUPLED && mode != LBM_STEP_FLUID_ONLY) return fail(LBM_E_INVALID, "unknown step mode");
     if (c->pending_refill) do_refill(c);
     const bool move = mode == LBM_STEP_COUPLED;
+    // Per step: the stream-collide of plain nodes runs on the caller's stream
+    // while the second stream does bounce-back + momentum exchange, the
+    // rigid-body update, flagging, classification and the link build; the
+    // boundary/uncovered pass joins both.
     for (int s = 0; s < n_steps; ++s) {
         StepArgs a = base_args(c);
         a.move = move;
-        if (!move) a.own_new = c->own_cur;  // geometry fixed
-        a.tag = ++c->tag;
-        a.phase = PHASE_LINKS;
-        launch_phase(a);
-        a.phase = PHASE_FLAGS;
-        launch_phase(a);
+        if (!move) a.own_new = a.own_old;  // geometry fixed
+        HIPCHK(hipEventRecord(c->ev_main, c->stream));
+        HIPCHK(hipStreamWaitEvent(c->aux, c->ev_main, 0));
+        StepArgs b = a;
+        b.stream = c->aux;
+        b.phase = PHASE_LINKS;
+        launch_phase(b);
+        b.phase = PHASE_FLAGS;
+        launch_phase(b);
+        HIPCHK(hipEventRecord(c->ev_flags, c->aux));
+        if (move) {
+            b.phase = PHASE_LINKBUILD;
+            b.own_dead = c->own[c->id];  // flags of step n-1 are dead: cleared here
+            launch_phase(b);
+        }
         const bool t = c->timing && c->ev_used + 2 <= c->ev.size();
         if (t) HIPCHK(hipEventRecord(c->ev[c->ev_used], c->stream));
         a.phase = PHASE_BULK;
@@ -611,16 +645,21 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
             HIPCHK(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
             c->ev_used += 2;
         }
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_flags, 0));
         a.phase = PHASE_SPECIAL;
         a.in_place = 0;
         launch_phase(a);
         if (move) {
-            a.phase = PHASE_LINKBUILD;
-            launch_phase(a);
-            std::swap(c->own_cur, c->own_nxt);
+            const int old = c->ic;
+            c->ic = c->in; c->in = c->id; c->id = old;
         }
+        c->is = 1 - c->is;
         std::swap(c->A, c->B);
         c->steps++;
+    }
+    if (n_steps > 0) {  // everything on the second stream is done when the caller's stream is
+        HIPCHK(hipEventRecord(c->ev_links, c->aux));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_links, 0));
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -704,7 +743,6 @@ lbm_status lbm_set_populations(lbm_ctx *c, const double *f, int32_t post_collisi
     if (!post_collision) {
         StepArgs a = base_args(c);
         a.phase = PHASE_COLLIDE_STORED;
-        a.own_old = c->own_cur;
         launch_phase(a);
     }
     c->pending_refill = false;
@@ -734,7 +772,7 @@ lbm_status lbm_get_flags(lbm_ctx *c, int32_t *owner) {
     if (!c || !owner) return fail(LBM_E_INVALID, "NULL argument");
     lbm_status s = check_device(c);
     if (s) return s;
-    HIPCHK(hipMemcpy(owner, c->own_cur, 4 * c->pl.N, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(owner, c->own[c->ic], 4 * c->pl.N, hipMemcpyDeviceToHost));
     for (long long n = 0; n < c->pl.N; ++n)
         if (owner[n] == FLUID) owner[n] = -1;
     return LBM_OK;
@@ -818,7 +856,7 @@ lbm_status lbm_get_gfluid(lbm_ctx *c, double *g3) {
 lbm_status lbm_timing_enable(lbm_ctx *c, int32_t on) {
     if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
     if (on && c->ev.empty()) {
-        c->ev.resize(2 * 1024);
+        c->ev.resize(2 * 4096);
         for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
     }
     c->timing = on != 0;
@@ -836,14 +874,41 @@ lbm_status lbm_timing_read(lbm_ctx *c, double *ms, int64_t *launches, int64_t *n
     }
     if (ms) *ms = tot;
     if (launches) *launches = (int64_t)(c->ev_used / 2);
-    if (nodes_per_launch) *nodes_per_launch = c->pl.N;
+    if (nodes_per_launch) {
+        // nodes the stream-collide kernel updated in the last step: all but
+        // solid nodes and the boundary/uncovered nodes handled separately
+        Counters h;
+        HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+        *nodes_per_launch = c->pl.N - h.n_solid - std::min(h.n_special, c->p.special_cap);
+    }
     c->ev_used = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_nr_stats(lbm_ctx *c, int64_t *links, int64_t *iterations) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    Counters h;
+    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+    if (links) *links = (int64_t)h.nr_links;
+    if (iterations) *iterations = (int64_t)h.nr_iters;
+    const unsigned long long z[2] = {0ull, 0ull};
+    HIPCHK(hipMemcpy(&c->cnt->nr_iters, z, sizeof z, hipMemcpyHostToDevice));
     return LBM_OK;
 }
 
 void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
     for (auto &e : c->ev) (void)hipEventDestroy(e);
+    if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+    if (c->ev_flags) (void)hipEventDestroy(c->ev_flags);
+    if (c->ev_links) (void)hipEventDestroy(c->ev_links);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+    }
     delete c;
 }
 

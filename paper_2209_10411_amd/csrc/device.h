@@ -13,9 +13,8 @@ constexpr int32_t FLUID = 0x7fffffff;  // owner value of a fluid node (atomicMin
 constexpr int PAD = 4;                  // region margin beyond the bounding radius
 constexpr int BLK = 256;                // threads per block of the region kernels
 
-enum : uint8_t { CLS_SOLID_OLD = 1, CLS_SOLID_NEW = 2, CLS_LINKS_OLD = 4 };
 enum : int { ERR_LINK_OVERFLOW = 1, ERR_SPECIAL_OVERFLOW = 2, ERR_FAST_PARTICLE = 4,
-             ERR_NONFINITE = 8 };
+             ERR_NONFINITE = 8, ERR_BAD_INDEX = 16 };
 
 // D3Q19 velocities in the order documented in midelbm.h.
 constexpr int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
@@ -49,7 +48,10 @@ struct Counters {
     int n_refill;   // uncovered nodes this step
     int n_solid;    // solid nodes counted by the last classification
     int err;        // ERR_* bits
-    int pad[3];
+    uint32_t tag;   // classification pass number (stamps claimed nodes)
+    int pad[2];
+    unsigned long long nr_iters;  // Newton/bisection iterations of the link fractions
+    unsigned long long nr_links;  // link fractions solved
 };
 
 // Per-context constants, passed to kernels by value.

@@ -31,22 +31,28 @@ template <> struct Store<0> {
     using T = float;
     __device__ static float ld(const T *p, long long i, float) { return p[i]; }
     __device__ static void st(T *p, long long i, float v, float) { p[i] = v; }
+    __device__ static void st_nt(T *p, long long i, float v, float) { __builtin_nontemporal_store(v, p + i); }
 };
 template <> struct Store<1> {
     using T = _Float16;
     __device__ static float ld(const T *p, long long i, float inv) { return (float)p[i] * inv; }
     __device__ static void st(T *p, long long i, float v, float s) { p[i] = (_Float16)(v * s); }
+    __device__ static void st_nt(T *p, long long i, float v, float s) {
+        __builtin_nontemporal_store((_Float16)(v * s), p + i);
+    }
 };
 template <> struct Store<2> {
     using T = uint16_t;
     __device__ static float ld(const T *p, long long i, float) {
         return __uint_as_float((uint32_t)p[i] << 16);
     }
-    __device__ static void st(T *p, long long i, float v, float) {
+    __device__ static uint16_t rne(float v) {
         uint32_t u = __float_as_uint(v);
         u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-        p[i] = (uint16_t)(u >> 16);
+        return (uint16_t)(u >> 16);
     }
+    __device__ static void st(T *p, long long i, float v, float) { p[i] = rne(v); }
+    __device__ static void st_nt(T *p, long long i, float v, float) { __builtin_nontemporal_store(rne(v), p + i); }
 };
 
 // ------------------------------------------------------------- lattice ops
@@ -103,56 +109,94 @@ __device__ __forceinline__ void min_image(const Params &p, double d[3]) {
         if (p.periodic & (1u << a)) d[a] -= L[a] * floor(d[a] / L[a] + 0.5);
 }
 
-// Metaball function (Eq. metaballM) of one body at a lab point, minimum
-// image on periodic axes; a control point exactly on x gives +inf.
-__device__ double metaball(const Params &p, const DevParticle &P, const double x[3]) {
+// Control points of one body staged in LDS by the whole block, padded to a
+// multiple of 4 with weight-0 copies of the first point (they add exactly
+// zero) so that evaluation loops run 4 independent terms at a time.
+struct CPs {
+    double x[MAXCP + 3][3];
+    double k[MAXCP + 3];
+    int n;  // padded count
+};
+
+__device__ void stage_cps(CPs &c, const DevParticle &P) {
+    const int n4 = (P.n_cp + 3) & ~3;
+    for (int t = threadIdx.x; t < n4 * 4; t += blockDim.x) {
+        const int i = t >> 2, a = t & 3;
+        const int src = i < P.n_cp ? i : 0;
+        if (a < 3) c.x[i][a] = P.cpl[src][a];
+        else c.k[i] = i < P.n_cp ? P.k[i] : 0.0;
+    }
+    if (threadIdx.x == 0) c.n = n4;
+}
+
+// Metaball function (Eq. metaballM) at a lab point, minimum image on
+// periodic axes; a control point exactly on x gives +inf.  Terms k_i/r_i^2
+// are exact quotients summed in index order.
+__device__ double metaball(const Params &p, const CPs &P, const double x[3]) {
 #pragma clang fp contract(off)
     double C = 0.0;
-    for (int i = 0; i < P.n_cp; ++i) {
-        double d[3] = {x[0] - P.cpl[i][0], x[1] - P.cpl[i][1], x[2] - P.cpl[i][2]};
-        min_image(p, d);
-        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        if (r2 == 0.0) return __builtin_inf();
-        C += P.k[i] / r2;
+    for (int i0 = 0; i0 < P.n; i0 += 4) {
+        double term[4];
+        bool hit = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u;
+            double d[3] = {x[0] - P.x[i][0], x[1] - P.x[i][1], x[2] - P.x[i][2]};
+            min_image(p, d);
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            hit |= r2 == 0.0;
+            term[u] = P.k[i] / r2;
+        }
+        if (hit) return __builtin_inf();
+        C += term[0];
+        C += term[1];
+        C += term[2];
+        C += term[3];
     }
     return C;
 }
 
-// C and dC/ds along x(s) = xf - s e.
-__device__ void metaball_ds(const Params &p, const DevParticle &P, const double xf[3], const int e[3],
+// C and dC/ds along x(s) = xf - s e (one reciprocal per control point).
+__device__ void metaball_ds(const Params &p, const CPs &P, const double xf[3], const int e[3],
                             double s, double &C, double &dC) {
 #pragma clang fp contract(off)
     C = 0.0; dC = 0.0;
-    for (int i = 0; i < P.n_cp; ++i) {
-        double d[3] = {xf[0] - s * e[0] - P.cpl[i][0], xf[1] - s * e[1] - P.cpl[i][1],
-                       xf[2] - s * e[2] - P.cpl[i][2]};
-        min_image(p, d);
-        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        if (r2 == 0.0) { C = __builtin_inf(); dC = 0.0; return; }
-        const double kr = P.k[i] / r2;
-        C += kr;
-        dC += 2.0 * kr / r2 * (d[0] * e[0] + d[1] * e[1] + d[2] * e[2]);
+    const double xs[3] = {xf[0] - s * e[0], xf[1] - s * e[1], xf[2] - s * e[2]};
+    for (int i0 = 0; i0 < P.n; i0 += 4) {
+        double kr[4], g[4];
+        bool hit = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u;
+            double d[3] = {xs[0] - P.x[i][0], xs[1] - P.x[i][1], xs[2] - P.x[i][2]};
+            min_image(p, d);
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            hit |= r2 == 0.0;
+            const double inv = 1.0 / r2;
+            kr[u] = P.k[i] * inv;
+            g[u] = 2.0 * kr[u] * inv * (d[0] * e[0] + d[1] * e[1] + d[2] * e[2]);
+        }
+        if (hit) { C = __builtin_inf(); dC = 0.0; return; }
+        C += kr[0] + kr[1] + kr[2] + kr[3];
+        dC += g[0] + g[1] + g[2] + g[3];
     }
 }
 
 // Link fraction (sec. 2.3.2): first root of g(s) = C(xf - s e) - 1 on (0,1].
 // The root is bracketed in the first of 8 equal sub-intervals where g changes
-// sign, then refined by Newton steps that fall back to bisection whenever a
-// step leaves the bracket.  'guess' (in [0,1], or < 0 for none) replaces the
-// regula-falsi start.  Returns the number of Newton/bisection iterations.
-__device__ int link_fraction(const Params &p, const DevParticle &P, int x, int y, int z, int i,
-                             double guess, double &q) {
+// sign, then refined by Newton steps from the regula-falsi point (or from
+// 'guess' when it lies in the bracket); a step that would leave the bracket
+// or does not at least halve the last step is replaced by bisection.
+// Returns the number of iterations.
+__device__ int link_fraction(const Params &p, const CPs &P, int x, int y, int z, int i, double guess,
+                             double &q) {
     const double xf[3] = {(double)x, (double)y, (double)z};
     const int e[3] = {EX[i], EY[i], EZ[i]};
-    double lo = 0.0, hi = 1.0, glo = -1.0, ghi = 0.0;
-    {
-        double C, dC;
-        metaball_ds(p, P, xf, e, 0.0, C, dC);
-        glo = C - 1.0;
-    }
+    double lo = 0.0, hi = 1.0, glo, ghi = 0.0, C, dC;
+    metaball_ds(p, P, xf, e, 0.0, C, dC);
+    glo = C - 1.0;
     for (int k = 1; k <= 8; ++k) {
         const double s = (double)k / 8.0;
-        double C, dC;
         metaball_ds(p, P, xf, e, s, C, dC);
         if (C >= 1.0) { hi = s; ghi = C - 1.0; break; }
         lo = s; glo = C - 1.0;
@@ -162,20 +206,52 @@ __device__ int link_fraction(const Params &p, const DevParticle &P, int x, int y
     else if (ghi < __builtin_inf()) s = lo + (hi - lo) * (-glo) / (ghi - glo);
     else s = 0.5 * (lo + hi);
     if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+    double dxold = hi - lo, dx = dxold;
     int it = 0;
-    for (; it < 100; ++it) {
-        double C, dC;
+    while (it < 100) {
         metaball_ds(p, P, xf, e, s, C, dC);
+        ++it;
         const double g = C - 1.0;
         if (g >= 0.0) hi = s; else lo = s;
-        if (hi - lo <= 4e-16) break;
-        double sn = (dC != 0.0) ? s - g / dC : 0.5 * (lo + hi);
-        if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
-        if (fabs(sn - s) <= 1e-15) { s = sn; break; }
-        s = sn;
+        const double sn = s - g / dC;
+        if (!(dC != 0.0) || !(sn > lo && sn < hi) || fabs(2.0 * g) > fabs(dxold * dC)) {
+            dxold = dx;
+            dx = 0.5 * (hi - lo);
+            s = lo + dx;
+        } else {
+            dxold = dx;
+            dx = s - sn;
+            s = sn;
+        }
+        if (fabs(dx) < 1e-13) break;
     }
     q = s;
-    return it + 1;
+    return it;
+}
+
+// Wave-aggregated append: one atomic per wave; returns this lane's slot.
+__device__ __forceinline__ int wave_append(int *counter, bool pred) {
+    const unsigned long long m = __ballot(pred);
+    if (!m) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    const unsigned long long below = lane ? (m & ((1ull << lane) - 1ull)) : 0ull;
+    return pred ? base + __popcll(below) : -1;
+}
+
+// Sum over the lanes of a wave (all 64 lanes must take part).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
 __device__ __forceinline__ void cross3(const double a[3], const double b[3], double o[3]) {
@@ -184,29 +260,51 @@ __device__ __forceinline__ void cross3(const double a[3], const double b[3], dou
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-__device__ __forceinline__ double feq64(int i, double rho, const double u[3]) {
-    const double eu = EX[i] * u[0] + EY[i] * u[1] + EZ[i] * u[2];
+
+// D3Q19 tables indexable by a runtime lane number.
+__constant__ int c_ex[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__constant__ int c_ey[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__constant__ int c_ez[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+__constant__ int c_opp[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+__constant__ float c_w[Q] = {1.f / 3, 1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18, 1.f / 18,
+                             1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36,
+                             1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+__constant__ double c_wd[Q] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                               1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                               1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+// Second-order equilibrium of a runtime direction in FP64.
+__device__ __forceinline__ double feq64d(int i, double rho, const double u[3]) {
+    const double eu = c_ex[i] * u[0] + c_ey[i] * u[1] + c_ez[i] * u[2];
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    return WD[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    return c_wd[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
 }
 
-// Density and velocity of a stored (post-collision) node in FP64:
-// rho = rho0 + sum d, u = sum e d / rho - g/2 (the collision added F).
-template <int S>
-__device__ void moments64(const Params &p, const typename Store<S>::T *A, long long n, double &rho,
-                          double u[3]) {
-    double dr = 0.0, j[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double d = (double)Store<S>::ld(A, (long long)i * p.N + n, p.inv_scale);
-        dr += d;
-        j[0] += EX[i] * d; j[1] += EY[i] * d; j[2] += EZ[i] * d;
-    }
-    rho = p.rho0 + dr;
-    for (int a = 0; a < 3; ++a) u[a] = j[a] / rho - 0.5 * p.gfd[a];
+// BGK + Guo for the one direction i a lane owns, given the node's moments.
+__device__ __forceinline__ float collide_lane(float d, int i, float dr, float jx, float jy, float jz,
+                                              const Params &p) {
+    const float rho = p.rho0f + dr;
+    const float Fx = rho * p.gx, Fy = rho * p.gy, Fz = rho * p.gz;
+    const float inv = 1.0f / rho;
+    const float ux = (jx + 0.5f * Fx) * inv, uy = (jy + 0.5f * Fy) * inv, uz = (jz + 0.5f * Fz) * inv;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float uF = ux * Fx + uy * Fy + uz * Fz;
+    const float ex = (float)c_ex[i], ey = (float)c_ey[i], ez = (float)c_ez[i], w = c_w[i];
+    const float eu = ex * ux + ey * uy + ez * uz;
+    const float eF = ex * Fx + ey * Fy + ez * Fz;
+    const float deq = w * (dr + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+    const float Fi = p.fcoef * w * (3.f * (eF - uF) + 9.f * eu * eF);
+    return d + p.omega * (deq - d) + Fi;
 }
 
 // ------------------------------------------------------------------ kernels
+// One thread per cut link (links come particle-major).  The thread forms the
+// incoming population on the link -- simple bounce-back, or the paper's
+// interpolated rule with the moments of x_f and x_f + e_i in FP64 -- and
+// leaves it in B for the boundary-node pass, then the link's momentum
+// exchange  dP = (e_ib - u_w) f+_ib(x_f) - (e_i - u_w) f_i(x_f, t+1),
+// dT = (x_w - X) x dP.  Each chunk of 256 links sums its links per body
+// segment (fixed segmented tree) into part[chunk + body] (deterministic).
 template <int S>
 __global__ __launch_bounds__(256) void k_links(Params p, const typename Store<S>::T *__restrict__ A,
                                                typename Store<S>::T *__restrict__ B,
@@ -214,50 +312,94 @@ __global__ __launch_bounds__(256) void k_links(Params p, const typename Store<S>
                                                const DevParticle *__restrict__ P,
                                                const uint32_t *__restrict__ l_node,
                                                const uint32_t *__restrict__ l_do,
-                                               const double *__restrict__ l_q, double *__restrict__ lft,
-                                               const Counters *__restrict__ cnt) {
+                                               const double *__restrict__ l_q, double *__restrict__ part,
+                                               Counters *__restrict__ cnt) {
+    __shared__ double sv[6][256];
+    __shared__ int spid[256];
+    const int t = threadIdx.x;
     const int nl = cnt->n_links;
-    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < nl; l += gridDim.x * blockDim.x) {
-        const long long n = l_node[l];
-        const int i = (int)(l_do[l] & 31u), pi = (int)(l_do[l] >> 8);
-        const int ib = OPP[i];
-        const DevParticle &B0 = P[pi];
-        int x, y, z;
-        node_xyz(p, n, x, y, z);
-        long long ff = -1;
-        const bool ibb = p.bc == 1 && nbr(p, x, y, z, EX[i], EY[i], EZ[i], ff) && own[ff] == FLUID;
-        const double q = ibb ? l_q[l] : 0.5;
-        double r[3] = {x - q * EX[i] - B0.X[0], y - q * EY[i] - B0.X[1], z - q * EZ[i] - B0.X[2]};
-        min_image(p, r);
-        double uw[3];
-        cross3(B0.w, r, uw);
-        for (int a = 0; a < 3; ++a) uw[a] += B0.v[a];
-        const double w = WD[i];
-        const double fb = w * p.rho0 + (double)Store<S>::ld(A, (long long)ib * p.N + n, p.inv_scale);
-        const double mw = 6.0 * w * p.rho0 * (EX[i] * uw[0] + EY[i] * uw[1] + EZ[i] * uw[2]);
-        double val;
-        if (!ibb) {
-            val = fb + mw;
-        } else {
-            double rf, uf[3], rff, uff[3], ud[3];
-            moments64<S>(p, A, n, rf, uf);
-            moments64<S>(p, A, ff, rff, uff);
-            for (int a = 0; a < 3; ++a) {
-                const double us = q <= 0.5 ? 2.0 * q * uf[a] + (1.0 - 2.0 * q) * uff[a]
-                                           : (1.0 - q) / q * uf[a] + (2.0 * q - 1.0) / q * uw[a];
-                const double uss = (1.0 - q) / (1.0 + q) * uff[a] + 2.0 * q / (1.0 + q) * uw[a];
-                ud[a] = us / 3.0 + 2.0 * uss / 3.0;
+    const int nchunk = (nl + 255) >> 8;
+    for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int l = (ch << 8) + t;
+        double dP[3] = {0, 0, 0}, dT[3] = {0, 0, 0};
+        int pi = -1;
+        bool ok = l < nl;
+        long long n = 0;
+        int i = 1;
+        if (ok) {
+            n = l_node[l];
+            i = (int)(l_do[l] & 31u);
+            pi = (int)(l_do[l] >> 8);
+            if (n >= p.N || pi >= p.np || i < 1 || i >= Q) {  // never expected: report, do not touch memory
+                atomicOr(&cnt->err, ERR_BAD_INDEX);
+                ok = false;
+                pi = -1;
             }
-            val = feq64(ib, rf, ud) + fb - feq64(ib, rf, uf) + mw;
         }
-        Store<S>::st(B, (long long)i * p.N + n, (float)(val - w * p.rho0), p.scale);
-        double dP[3], dT[3];
-        dP[0] = (EX[ib] - uw[0]) * fb - (EX[i] - uw[0]) * val;
-        dP[1] = (EY[ib] - uw[1]) * fb - (EY[i] - uw[1]) * val;
-        dP[2] = (EZ[ib] - uw[2]) * fb - (EZ[i] - uw[2]) * val;
-        cross3(r, dP, dT);
-        double *o = lft + 6ll * l;
-        o[0] = dP[0]; o[1] = dP[1]; o[2] = dP[2]; o[3] = dT[0]; o[4] = dT[1]; o[5] = dT[2];
+        if (ok) {
+            const int ib = c_opp[i];
+            int x, y, z;
+            node_xyz(p, n, x, y, z);
+            long long ff = -1;
+            const bool ibb = p.bc == 1 && nbr(p, x, y, z, c_ex[i], c_ey[i], c_ez[i], ff) && own[ff] == FLUID;
+            const DevParticle &Bd = P[pi];
+            const double q = ibb ? l_q[l] : 0.5;
+            double r[3] = {x - q * c_ex[i] - Bd.X[0], y - q * c_ey[i] - Bd.X[1], z - q * c_ez[i] - Bd.X[2]};
+            min_image(p, r);
+            double uw[3];
+            cross3(Bd.w, r, uw);
+            for (int a = 0; a < 3; ++a) uw[a] += Bd.v[a];
+            const double w = c_wd[i];
+            const double fb = w * p.rho0 + (double)Store<S>::ld(A, (long long)ib * p.N + n, p.inv_scale);
+            const double mw = 6.0 * w * p.rho0 * (c_ex[i] * uw[0] + c_ey[i] * uw[1] + c_ez[i] * uw[2]);
+            double val;
+            if (!ibb) {
+                val = fb + mw;
+            } else {
+                double m0 = 0, m1 = 0, m2 = 0, m3 = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+#pragma unroll
+                for (int j = 0; j < Q; ++j) {
+                    const double d0 = (double)Store<S>::ld(A, (long long)j * p.N + n, p.inv_scale);
+                    const double d1 = (double)Store<S>::ld(A, (long long)j * p.N + ff, p.inv_scale);
+                    m0 += d0; m1 += EX[j] * d0; m2 += EY[j] * d0; m3 += EZ[j] * d0;
+                    k0 += d1; k1 += EX[j] * d1; k2 += EY[j] * d1; k3 += EZ[j] * d1;
+                }
+                const double rf = p.rho0 + m0, rff = p.rho0 + k0;
+                const double uf[3] = {m1 / rf - 0.5 * p.gfd[0], m2 / rf - 0.5 * p.gfd[1], m3 / rf - 0.5 * p.gfd[2]};
+                const double uff[3] = {k1 / rff - 0.5 * p.gfd[0], k2 / rff - 0.5 * p.gfd[1], k3 / rff - 0.5 * p.gfd[2]};
+                double ud[3];
+                for (int a = 0; a < 3; ++a) {
+                    const double us = q <= 0.5 ? 2.0 * q * uf[a] + (1.0 - 2.0 * q) * uff[a]
+                                               : (1.0 - q) / q * uf[a] + (2.0 * q - 1.0) / q * uw[a];
+                    const double uss = (1.0 - q) / (1.0 + q) * uff[a] + 2.0 * q / (1.0 + q) * uw[a];
+                    ud[a] = us / 3.0 + 2.0 * uss / 3.0;
+                }
+                val = feq64d(ib, rf, ud) + fb - feq64d(ib, rf, uf) + mw;
+            }
+            Store<S>::st(B, (long long)i * p.N + n, (float)(val - w * p.rho0), p.scale);
+            dP[0] = (c_ex[ib] - uw[0]) * fb - (c_ex[i] - uw[0]) * val;
+            dP[1] = (c_ey[ib] - uw[1]) * fb - (c_ey[i] - uw[1]) * val;
+            dP[2] = (c_ez[ib] - uw[2]) * fb - (c_ez[i] - uw[2]) * val;
+            cross3(r, dP, dT);
+        }
+        double v6[6] = {dP[0], dP[1], dP[2], dT[0], dT[1], dT[2]};
+        for (int c = 0; c < 6; ++c) sv[c][t] = v6[c];
+        spid[t] = pi;
+        __syncthreads();
+        // inclusive segmented scan (segments = runs of one body, contiguous)
+        for (int h = 1; h < 256; h <<= 1) {
+            const bool take = t >= h && spid[t - h] == pi;
+            double add[6];
+            for (int c = 0; c < 6; ++c) add[c] = take ? sv[c][t - h] : 0.0;
+            __syncthreads();
+            for (int c = 0; c < 6; ++c) { v6[c] += add[c]; sv[c][t] = v6[c]; }
+            __syncthreads();
+        }
+        if (pi >= 0 && (t == 255 || spid[t + 1] != pi)) {  // tail of a body segment
+            double *o = part + 6ll * (ch + pi);
+            for (int c = 0; c < 6; ++c) o[c] = v6[c];
+        }
+        __syncthreads();
     }
 }
 
@@ -291,10 +433,7 @@ __device__ void refresh_pose(const Params &p, DevParticle &P) {
     for (int i = 0; i < P.n_cp; ++i)
         for (int a = 0; a < 3; ++a)
             P.cpl[i][a] = P.X[a] + R[3 * a] * P.cpb[i][0] + R[3 * a + 1] * P.cpb[i][1] + R[3 * a + 2] * P.cpb[i][2];
-    const int L[3] = {p.nx, p.ny, p.nz};
-    for (int a = 0; a < 3; ++a)
-        P.lo[a] = P.full[a] ? 0 : (int)floor(P.X[a]) - P.half;
-    (void)L;
+    for (int a = 0; a < 3; ++a) P.lo[a] = P.full[a] ? 0 : (int)floor(P.X[a]) - P.half;
 }
 
 // Semi-implicit Euler over n_sub sub-steps with the hydrodynamic load held;
@@ -337,20 +476,26 @@ __device__ void rigid_update(const Params &p, DevParticle &P) {
     }
 }
 
-// One block per particle: fixed-order FP64 sum of the link momenta, then the
-// rigid-body update (move != 0).  Block 0 also clears the per-step counters.
+// One block per particle: fixed-order FP64 sum of the link momenta (chunk
+// partials from k_links), then the rigid-body update (move != 0) on an LDS
+// copy of the particle record.  Block 0 also clears the per-step counters and
+// advances the classification tag.
 __global__ __launch_bounds__(256) void k_reduce_rigid(Params p, DevParticle *__restrict__ P,
                                                       const int *__restrict__ l_off,
-                                                      const double *__restrict__ lft,
+                                                      const double *__restrict__ part,
                                                       Counters *__restrict__ cnt, int move) {
     __shared__ double red[6][256];
+    __shared__ DevParticle sp;
     const int pi = blockIdx.x, t = threadIdx.x;
-    if (pi == 0 && t == 0) { cnt->n_special = 0; cnt->n_refill = 0; cnt->n_solid = 0; }
+    if (pi == 0 && t == 0) { cnt->n_special = 0; cnt->n_refill = 0; cnt->n_solid = 0; cnt->tag += 1u; }
     if (pi >= p.np) return;
+    constexpr int W = sizeof(DevParticle) / 4;
+    for (int k = t; k < W; k += 256) ((int *)&sp)[k] = ((const int *)&P[pi])[k];
     double s[6] = {0, 0, 0, 0, 0, 0};
-    const int a = l_off[pi], b = l_off[pi + 1];
-    for (int l = a + t; l < b; l += 256)
-        for (int c = 0; c < 6; ++c) s[c] += lft[6ll * l + c];
+    const int a = max(0, l_off[pi]), b = min(l_off[pi + 1], p.link_cap);
+    if (b > a)  // chunks of 256 links holding this body's links; slot = chunk + body
+        for (int ch = (a >> 8) + t; ch <= ((b - 1) >> 8); ch += 256)
+            for (int c = 0; c < 6; ++c) s[c] += part[6ll * (ch + pi) + c];
     for (int c = 0; c < 6; ++c) red[c][t] = s[c];
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -358,28 +503,30 @@ __global__ __launch_bounds__(256) void k_reduce_rigid(Params p, DevParticle *__r
             for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + h];
         __syncthreads();
     }
-    if (t != 0) return;
-    DevParticle &B = P[pi];
-    for (int c = 0; c < 3; ++c) { B.F[c] = red[c][0]; B.T[c] = red[3 + c][0]; }
-    if (!move) return;
-    const double X0[3] = {B.X[0], B.X[1], B.X[2]};
-    rigid_update(p, B);
-    double d2 = 0.0;
-    bool finite = true;
-    for (int c = 0; c < 3; ++c) {
-        d2 += (B.X[c] - X0[c]) * (B.X[c] - X0[c]);
-        finite = finite && isfinite(B.X[c]) && isfinite(B.v[c]) && isfinite(B.w[c]);
-    }
-    if (!finite) atomicOr(&cnt->err, ERR_NONFINITE);
-    else if (d2 > 1.0) atomicOr(&cnt->err, ERR_FAST_PARTICLE);
-    // wrap the centroid into the box on periodic axes
-    const int L[3] = {p.nx, p.ny, p.nz};
-    for (int c = 0; c < 3; ++c)
-        if ((p.periodic >> c) & 1u) {
-            if (B.X[c] < 0.0) B.X[c] += L[c];
-            else if (B.X[c] >= L[c]) B.X[c] -= L[c];
+    if (t == 0) {
+        for (int c = 0; c < 3; ++c) { sp.F[c] = red[c][0]; sp.T[c] = red[3 + c][0]; }
+        if (move) {
+            const double X0[3] = {sp.X[0], sp.X[1], sp.X[2]};
+            rigid_update(p, sp);
+            double d2 = 0.0;
+            bool finite = true;
+            for (int c = 0; c < 3; ++c) {
+                d2 += (sp.X[c] - X0[c]) * (sp.X[c] - X0[c]);
+                finite = finite && isfinite(sp.X[c]) && isfinite(sp.v[c]) && isfinite(sp.w[c]);
+            }
+            if (!finite) atomicOr(&cnt->err, ERR_NONFINITE);
+            else if (d2 > 1.0) atomicOr(&cnt->err, ERR_FAST_PARTICLE);
+            const int L[3] = {p.nx, p.ny, p.nz};
+            for (int c = 0; c < 3; ++c)  // keep the centroid inside a periodic box
+                if ((p.periodic >> c) & 1u) {
+                    if (sp.X[c] < 0.0) sp.X[c] += L[c];
+                    else if (sp.X[c] >= L[c]) sp.X[c] -= L[c];
+                }
+            refresh_pose(p, sp);
         }
-    refresh_pose(p, B);
+    }
+    __syncthreads();
+    for (int k = t; k < W; k += 256) ((int *)&P[pi])[k] = ((const int *)&sp)[k];
 }
 
 __global__ void k_refresh_pose(Params p, DevParticle *P) {
@@ -411,75 +558,122 @@ __device__ __forceinline__ bool region_node(const Params &p, const RegionMap &rm
     return true;
 }
 
-__global__ __launch_bounds__(BLK) void k_region_clear(Params p, RegionMap rm, const DevParticle *P,
-                                                      int32_t *own_new) {
-    int pi, x, y, z;
-    long long n;
-    if (region_node(p, rm, P, pi, x, y, z, n)) own_new[n] = FLUID;
-}
-
+// Flags (sec. 2.1): C >= 1 is solid; the owner is the lowest body index
+// (atomicMin).  own_new must hold FLUID on the region beforehand.
 __global__ __launch_bounds__(BLK) void k_region_mark(Params p, RegionMap rm, const DevParticle *P,
                                                      int32_t *own_new) {
+    __shared__ CPs cps;
+    stage_cps(cps, P[rm.part[blockIdx.x]]);
+    __syncthreads();
     int pi, x, y, z;
     long long n;
     if (!region_node(p, rm, P, pi, x, y, z, n)) return;
     const double xp[3] = {(double)x, (double)y, (double)z};
-    if (metaball(p, P[pi], xp) >= 1.0) atomicMin(&own_new[n], pi);
+    if (metaball(p, cps, xp) >= 1.0) atomicMin(&own_new[n], pi);
 }
 
-// Node classes: solid before / after, and "has cut links before" (a fluid
-// node with an in-domain solid neighbour).  Fluid-after nodes that were solid
-// or had links go to the special list.  Each node is handled once per pass
-// (claimed through the stamp array) although regions may overlap.
+__device__ __forceinline__ int block_sum(int v, int *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int h = BLK / 2; h > 0; h >>= 1) {
+        if (t < h) sh[t] += sh[t + h];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// Cut-link mask of a node for body pi: directions i >= 1 whose source
+// x - e_i is an in-domain node owned by pi, for a fluid node x.
+__device__ __forceinline__ uint32_t link_mask(const Params &p, const int32_t *own, int pi, int x, int y,
+                                              int z, long long n) {
+    if (own[n] != FLUID) return 0u;
+    uint32_t m = 0u;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        long long s;
+        if (nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s) && own[s] == pi) m |= 1u << i;
+    }
+    return m;
+}
+
+// Node classification over the body regions, once per node (claimed through
+// the stamp array when several regions may overlap):
+//   - special list of this step: nodes fluid after the step that were solid
+//     before (uncovered: refill) or had an in-domain solid neighbour before
+//     (cut links: bounce-back);
+//   - skip mask of the NEXT step's stream-collide: solid after, or with an
+//     in-domain solid neighbour after (those nodes are left to the links and
+//     special passes);
+//   - with blk_cnt set, the block also counts the cut links of the new flags
+//     for its body (first pass of the link build).
 __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm, const DevParticle *P,
                                                          const int32_t *__restrict__ own_old,
                                                          const int32_t *__restrict__ own_new,
-                                                         uint8_t *__restrict__ cls, uint32_t *stamp,
-                                                         uint32_t tag, uint32_t *special,
-                                                         Counters *cnt) {
+                                                         uint8_t *__restrict__ skip_next, uint32_t *stamp,
+                                                         uint32_t *special, Counters *cnt, int *blk_cnt) {
+    __shared__ int sh[BLK];
     int pi, x, y, z;
     long long n;
-    if (!region_node(p, rm, P, pi, x, y, z, n)) return;
-    if (atomicExch(&stamp[n], tag) == tag) return;
-    const bool so = own_old[n] != FLUID, sn = own_new[n] != FLUID;
-    bool lo = false;
-    if (!so) {
+    const bool in = region_node(p, rm, P, pi, x, y, z, n);
+    bool nb_old = false, nb_new = false;
+    int c = 0;
+    bool so = false, sn = false;
+    if (in) {
+        so = own_old[n] != FLUID;
+        sn = own_new[n] != FLUID;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             long long s;
-            if (nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s) && own_old[s] != FLUID) lo = true;
+            if (nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s)) {
+                const int32_t vo = own_old[s], vn = own_new[s];
+                nb_old |= vo != FLUID;
+                nb_new |= vn != FLUID;
+                c += (vn == pi) ? 1 : 0;
+            }
         }
+        if (sn) c = 0;
     }
-    cls[n] = (uint8_t)((so ? CLS_SOLID_OLD : 0) | (sn ? CLS_SOLID_NEW : 0) | (lo ? CLS_LINKS_OLD : 0));
-    if (sn) atomicAdd(&cnt->n_solid, 1);
-    if (!sn && (so || lo)) {
-        const int k = atomicAdd(&cnt->n_special, 1);
+    if (blk_cnt) {
+        const int s = block_sum(c, sh);
+        if (threadIdx.x == 0) blk_cnt[blockIdx.x] = s;
+    }
+    if (!in) return;
+    if (p.np > 1) {  // regions of several bodies may overlap: first claimer classifies
+        const uint32_t tag = cnt->tag;
+        if (atomicExch(&stamp[n], tag) == tag) return;
+    }
+    skip_next[n] = (uint8_t)((sn || nb_new) ? 1 : 0);
+    const bool lo = !so && nb_old;
+    wave_append(&cnt->n_solid, sn);
+    wave_append(&cnt->n_refill, !sn && so);
+    const int k = wave_append(&cnt->n_special, !sn && (so || lo));
+    if (k >= 0) {
         if (k < p.special_cap) special[k] = (uint32_t)n;
         else atomicOr(&cnt->err, ERR_SPECIAL_OVERFLOW);
-        if (so) atomicAdd(&cnt->n_refill, 1);
     }
 }
 
-// Plain fluid nodes: pull-stream (periodic wrap, resting halfway walls) and
-// collide.  One wave covers 64 consecutive x of one (y, z) row; blocks are
-// remapped so that each XCD works through a contiguous slab of the lattice.
+// Plain fluid nodes (skip mask clear: fluid with no solid neighbour at the
+// start of the step): pull-stream (periodic wrap, resting halfway walls) and
+// collide.  One wave covers 64 consecutive x of one (y, z) row; a block of 8
+// waves takes consecutive rows in lattice order (the hardware spreads
+// consecutive blocks over the XCDs).  Results are written with
+// non-temporal stores: they are not read again within the step.
+constexpr int BULK_WAVES = 8;
 template <int S>
-__global__ __launch_bounds__(256) void k_bulk(Params p, const typename Store<S>::T *__restrict__ A,
-                                              typename Store<S>::T *__restrict__ B,
-                                              const uint8_t *__restrict__ cls, int nseg, int nblk,
-                                              int nblk8) {
+__global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typename Store<S>::T *__restrict__ A,
+                                                          typename Store<S>::T *__restrict__ B,
+                                                          const uint8_t *__restrict__ skip, int nseg) {
     using T = typename Store<S>::T;
-    const int b = blockIdx.x;
-    const int lb = (b & 7) * nblk8 + (b >> 3);
-    if (lb >= nblk) return;
-    const int wave = lb * 4 + (threadIdx.x >> 6);
+    const int wave = blockIdx.x * BULK_WAVES + (threadIdx.x >> 6);
     const int seg = wave % nseg, row = wave / nseg;
     if (row >= p.ny * p.nz) return;
     const int x = seg * 64 + (threadIdx.x & 63);
     if (x >= p.nx) return;
     const int y = row % p.ny, z = row / p.ny;
     const int n = row * p.nx + x;
-    if (cls[n]) return;
+    if (skip[n]) return;
     // source coordinates for e = -1, 0, +1 on each axis (wrapped), -1 = wall
     int sx[3], sy[3], sz[3];
     sx[1] = x; sy[1] = y; sz[1] = z;
@@ -503,67 +697,81 @@ __global__ __launch_bounds__(256) void k_bulk(Params p, const typename Store<S>:
     }
     collide(d, p);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Store<S>::st(B + (long long)i * p.N, n, d[i], p.scale);
+    for (int i = 0; i < Q; ++i) Store<S>::st_nt(B + (long long)i * p.N, n, d[i], p.scale);
 }
 
-// Boundary and uncovered nodes.  Boundary: a source inside a wall bounces off
-// the resting wall, a source inside a body takes the bounce-back value that
-// k_links left in B.  Uncovered (solid before): populations from fluid
-// sources are kept, a missing f_i becomes f_opp(i) + 6 w rho0 e_i.u_new if the
-// opposite came from a fluid node, else feq_i(rho0, u_new).  Then collide.
-// in_place (refill after an external re-flag): only uncovered nodes, A == B.
+// Boundary and uncovered nodes, one wave per node, lane i < 19 owning
+// direction i.  Boundary: a source inside a wall bounces off the resting
+// wall, a source inside a body takes the bounce-back value that k_links left
+// in B.  Uncovered (solid before): populations from fluid sources are kept, a
+// missing f_i becomes f_opp(i) + 6 w rho0 e_i.u_new if the opposite came from
+// a fluid node, else feq_i(rho0, u_new).  Then collide.  in_place (refill
+// after an external re-flag): only uncovered nodes, A == B.
 template <int S>
 __global__ __launch_bounds__(256) void k_special(Params p, const typename Store<S>::T *A,
                                                  typename Store<S>::T *B,
                                                  const int32_t *__restrict__ own_old,
                                                  const DevParticle *__restrict__ P,
                                                  const uint32_t *__restrict__ list,
-                                                 const Counters *__restrict__ cnt, int in_place) {
+                                                 Counters *__restrict__ cnt, int in_place) {
+    const int lane = threadIdx.x & 63;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
     const int ns = min(cnt->n_special, p.special_cap);
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += gridDim.x * blockDim.x) {
+    const int i = lane < Q ? lane : 0;
+    for (int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; k < ns; k += nw) {
         const long long n = list[k];
+        if (n >= p.N) {  // never expected: report, do not touch memory
+            if (lane == 0) atomicOr(&cnt->err, ERR_BAD_INDEX);
+            continue;
+        }
         const int own_n = own_old[n];
+        if (own_n != FLUID && (own_n < 0 || own_n >= p.np)) {
+            if (lane == 0) atomicOr(&cnt->err, ERR_BAD_INDEX);
+            continue;
+        }
         const bool unc = own_n != FLUID;
         if (in_place && !unc) continue;
         int x, y, z;
         node_xyz(p, n, x, y, z);
-        float d[Q];
-        uint32_t missing = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
+        float d = 0.f;
+        bool missing = false;
+        if (lane < Q) {
             long long s;
-            if (!nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s)) {
-                if (unc) missing |= 1u << i;
-                else d[i] = Store<S>::ld(A, (long long)OPP[i] * p.N + n, p.inv_scale);
+            if (!nbr(p, x, y, z, -c_ex[i], -c_ey[i], -c_ez[i], s)) {
+                if (unc) missing = true;
+                else d = Store<S>::ld(A, (long long)c_opp[i] * p.N + n, p.inv_scale);
             } else if (own_old[s] != FLUID) {
-                if (unc) missing |= 1u << i;
-                else d[i] = Store<S>::ld(B, (long long)i * p.N + n, p.inv_scale);
+                if (unc) missing = true;
+                else d = Store<S>::ld(B, (long long)i * p.N + n, p.inv_scale);
             } else {
-                d[i] = Store<S>::ld(A, (long long)i * p.N + s, p.inv_scale);
+                d = Store<S>::ld(A, (long long)i * p.N + s, p.inv_scale);
             }
         }
         if (unc) {
-            const DevParticle &Bd = P[own_n];
-            double r[3] = {x - Bd.X[0], y - Bd.X[1], z - Bd.X[2]};
-            min_image(p, r);
-            double un[3];
-            cross3(Bd.w, r, un);
-            for (int a = 0; a < 3; ++a) un[a] += Bd.v[a];
-            const double uu = un[0] * un[0] + un[1] * un[1] + un[2] * un[2];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                if (!((missing >> i) & 1u)) continue;
-                const double eu = EX[i] * un[0] + EY[i] * un[1] + EZ[i] * un[2];
+            const float dopp = __shfl(d, c_opp[i]);
+            if (missing) {
+                const DevParticle &Bd = P[own_n];
+                double r[3] = {x - Bd.X[0], y - Bd.X[1], z - Bd.X[2]};
+                min_image(p, r);
+                double un[3];
+                cross3(Bd.w, r, un);
+                for (int a = 0; a < 3; ++a) un[a] += Bd.v[a];
+                const double uu = un[0] * un[0] + un[1] * un[1] + un[2] * un[2];
+                const double eu = c_ex[i] * un[0] + c_ey[i] * un[1] + c_ez[i] * un[2];
+                const double w = c_wd[i];
                 long long s2;
-                if (nbr(p, x, y, z, EX[i], EY[i], EZ[i], s2) && own_old[s2] == FLUID)
-                    d[i] = (float)((double)d[OPP[i]] + 6.0 * WD[i] * p.rho0 * eu);
+                if (nbr(p, x, y, z, c_ex[i], c_ey[i], c_ez[i], s2) && own_old[s2] == FLUID)
+                    d = (float)((double)dopp + 6.0 * w * p.rho0 * eu);
                 else
-                    d[i] = (float)(WD[i] * p.rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+                    d = (float)(w * p.rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
             }
         }
-        collide(d, p);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) Store<S>::st(B, (long long)i * p.N + n, d[i], p.scale);
+        const float dv = lane < Q ? d : 0.f;
+        const float dr = wave_sum(dv);
+        const float jx = wave_sum(lane < Q ? c_ex[i] * dv : 0.f);
+        const float jy = wave_sum(lane < Q ? c_ey[i] * dv : 0.f);
+        const float jz = wave_sum(lane < Q ? c_ez[i] * dv : 0.f);
+        if (lane < Q) Store<S>::st(B, (long long)i * p.N + n, collide_lane(d, i, dr, jx, jy, jz, p), p.scale);
     }
 }
 
@@ -601,6 +809,7 @@ __global__ void k_reset_counters(Counters *cnt) {
     cnt->n_special = 0;
     cnt->n_refill = 0;
     cnt->n_solid = 0;
+    cnt->tag += 1u;
 }
 
 __global__ void k_fill_i32(int32_t *a, long long n, int32_t v) {
@@ -612,43 +821,8 @@ __global__ void k_fill_u8(uint8_t *a, long long n, uint8_t v) {
         a[i] = v;
 }
 
-// Cut links of the new geometry: pass 1 counts per block.
-__device__ __forceinline__ int links_of_node(const Params &p, const int32_t *own, int pi, int x, int y,
-                                             int z, long long n) {
-    if (own[n] != FLUID) return 0;
-    int c = 0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        long long s;
-        if (nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s) && own[s] == pi) ++c;
-    }
-    return c;
-}
-
-__device__ __forceinline__ int block_sum(int v, int *sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int h = BLK / 2; h > 0; h >>= 1) {
-        if (t < h) sh[t] += sh[t + h];
-        __syncthreads();
-    }
-    return sh[0];
-}
-
-__global__ __launch_bounds__(BLK) void k_link_count(Params p, RegionMap rm, const DevParticle *P,
-                                                    const int32_t *__restrict__ own, int *blk_cnt) {
-    __shared__ int sh[BLK];
-    int pi, x, y, z;
-    long long n;
-    int c = 0;
-    if (region_node(p, rm, P, pi, x, y, z, n)) c = links_of_node(p, own, pi, x, y, z, n);
-    const int s = block_sum(c, sh);
-    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = s;
-}
-
-// Pass 2: one block scans the block counts; per-particle offsets follow from
-// the first block of each particle.
+// Link build, pass 2: one block scans the per-block link counts; per-body
+// offsets follow from the first block of each body.
 __global__ __launch_bounds__(1024) void k_link_scan(Params p, const int *__restrict__ blk_cnt,
                                                     int *__restrict__ blk_off,
                                                     const int *__restrict__ part_first_blk,
@@ -674,26 +848,36 @@ __global__ __launch_bounds__(1024) void k_link_scan(Params p, const int *__restr
         const int total = sh[1023];
         if (total > p.link_cap) atomicOr(&cnt->err, ERR_LINK_OVERFLOW);
         cnt->n_links = min(total, p.link_cap);
+        l_off[p.np] = min(total, p.link_cap);
     }
     for (int q = t; q < p.np; q += 1024) l_off[q] = min(blk_off[part_first_blk[q]], p.link_cap);
-    if (t == 0) l_off[p.np] = min(sh[1023], p.link_cap);
 }
 
-// Pass 3: write the links in block order, thread order, direction order,
-// with q from the safeguarded Newton iteration.
+// Link build, pass 3: the block lists its links (thread order, then
+// direction order) in LDS and then solves one link per thread, with the
+// body's control points in LDS.  With clear set, the block also resets that
+// (no longer needed) flag buffer to FLUID on its region.
 __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const DevParticle *P,
                                                    const int32_t *__restrict__ own,
                                                    const int *__restrict__ blk_off,
                                                    uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
-                                                   double *__restrict__ l_q, int *iters) {
+                                                   double *__restrict__ l_q, Counters *cnt, int32_t *clear) {
+    __shared__ CPs cps;
     __shared__ int sh[BLK];
+    __shared__ int sxyz[BLK][3];
+    __shared__ uint32_t snode[BLK];
+    __shared__ uint16_t lk[BLK * 18];
+    const int t = threadIdx.x;
+    stage_cps(cps, P[rm.part[blockIdx.x]]);
     int pi, x, y, z;
     long long n;
-    int c = 0;
     const bool in = region_node(p, rm, P, pi, x, y, z, n);
-    if (in) c = links_of_node(p, own, pi, x, y, z, n);
-    const int t = threadIdx.x;
+    const uint32_t m = in ? link_mask(p, own, pi, x, y, z, n) : 0u;
+    if (in && clear) clear[n] = FLUID;
+    const int c = __popc(m);
     sh[t] = c;
+    sxyz[t][0] = x; sxyz[t][1] = y; sxyz[t][2] = z;
+    snode[t] = (uint32_t)n;
     __syncthreads();
     for (int h = 1; h < BLK; h <<= 1) {
         const int v = t >= h ? sh[t - h] : 0;
@@ -701,24 +885,30 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
         sh[t] += v;
         __syncthreads();
     }
-    if (!c) return;
-    int o = blk_off[blockIdx.x] + sh[t] - c;
-    const DevParticle &B = P[pi];
+    int o = sh[t] - c;
+    for (int i = 1; i < Q; ++i)
+        if ((m >> i) & 1u) lk[o++] = (uint16_t)((t << 5) | i);
+    __syncthreads();
+    const int total = sh[BLK - 1];
+    const int base = blk_off[blockIdx.x];
+    const int pid = rm.part[blockIdx.x];
     int it_sum = 0;
-#pragma unroll 1
-    for (int i = 1; i < Q; ++i) {
-        long long s;
-        if (!(nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s) && own[s] == pi)) continue;
-        if (o < p.link_cap) {
-            double q;
-            it_sum += link_fraction(p, B, x, y, z, i, -1.0, q);
-            l_node[o] = (uint32_t)n;
-            l_do[o] = (uint32_t)i | ((uint32_t)pi << 8);
-            l_q[o] = q;
-        }
-        ++o;
+    for (int j = t; j < total; j += BLK) {
+        const int tt = lk[j] >> 5, i = lk[j] & 31;
+        const int oo = base + j;
+        if (oo >= p.link_cap) continue;
+        double q;
+        it_sum += link_fraction(p, cps, sxyz[tt][0], sxyz[tt][1], sxyz[tt][2], i, -1.0, q);
+        l_node[oo] = snode[tt];
+        l_do[oo] = (uint32_t)i | ((uint32_t)pid << 8);
+        l_q[oo] = q;
     }
-    if (iters) atomicAdd(iters, it_sum);
+    __syncthreads();  // every thread has read its scan values before sh is reused
+    const int its = block_sum(it_sum, sh);
+    if (t == 0 && total > 0) {
+        atomicAdd(&cnt->nr_iters, (unsigned long long)its);
+        atomicAdd(&cnt->nr_links, (unsigned long long)min(total, max(0, p.link_cap - base)));
+    }
 }
 
 // ------------------------------------------------------------ host launchers
@@ -729,39 +919,33 @@ static void launch_step_kernels_t(const StepArgs &a) {
     using T = typename Store<S>::T;
     const Params &p = a.p;
     T *A = (T *)a.A, *B = (T *)a.B;
-    const int link_grid = max(1, min(cdiv(p.link_cap, 256), 1024));
-    const int spec_grid = max(1, min(cdiv(p.special_cap, 256), 1024));
+    const int link_grid = max(1, min(cdiv(p.link_cap, 256), 2048));
+    const int spec_grid = max(1, min(cdiv(p.special_cap, 4), 2048));
     if (a.phase == PHASE_LINKS) {
         if (p.np > 0)
             k_links<S><<<link_grid, 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.l_node, a.l_do, a.l_q,
-                                                         a.lft, a.cnt);
-        k_reduce_rigid<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.lft, a.cnt, a.move);
+                                                         a.part, a.cnt);
+        k_reduce_rigid<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, a.move);
     } else if (a.phase == PHASE_FLAGS) {
         if (p.np > 0) {
-            if (a.move) {
-                k_region_clear<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new);
-                k_region_mark<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new);
-            }
+            if (a.move) k_region_mark<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new);
             k_region_classify<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_old, a.own_new,
-                                                                      a.cls, a.stamp, a.tag, a.special,
-                                                                      a.cnt);
+                                                                      a.skip_next, a.stamp, a.special,
+                                                                      a.cnt, a.move ? a.blk_cnt : nullptr);
         }
     } else if (a.phase == PHASE_BULK) {
         const int nseg = cdiv(p.nx, 64);
         const long long waves = (long long)nseg * p.ny * p.nz;
-        const int nblk = cdiv(waves, 4);
-        const int nblk8 = cdiv(nblk, 8);
-        k_bulk<S><<<nblk8 * 8, 256, 0, a.stream>>>(p, A, B, a.cls, nseg, nblk, nblk8);
+        k_bulk<S><<<cdiv(waves, BULK_WAVES), 64 * BULK_WAVES, 0, a.stream>>>(p, A, B, a.skip, nseg);
     } else if (a.phase == PHASE_SPECIAL) {
         if (p.np > 0)
             k_special<S><<<spec_grid, 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.special, a.cnt,
                                                            a.in_place);
     } else if (a.phase == PHASE_LINKBUILD) {
         if (p.np > 0) {
-            k_link_count<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new, a.blk_cnt);
             k_link_scan<<<1, 1024, 0, a.stream>>>(p, a.blk_cnt, a.blk_off, a.part_first_blk, a.l_off, a.cnt);
             k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new, a.blk_off,
-                                                                a.l_node, a.l_do, a.l_q, a.iters);
+                                                                a.l_node, a.l_do, a.l_q, a.cnt, a.own_dead);
         }
     } else if (a.phase == PHASE_INIT_STATE) {
         k_init_state<S><<<2048, 256, 0, a.stream>>>(p, A, a.own_old);

@@ -22,21 +22,21 @@ struct StepArgs {
     int phase;
     int move;      // PHASE_LINKS: update particles; PHASE_FLAGS: re-flag
     int in_place;  // PHASE_SPECIAL: refill in place
-    uint32_t tag;
     hipStream_t stream;
     void *A, *B;
     int32_t *own_old, *own_new;
-    uint8_t *cls;
+    int32_t *own_dead;  // PHASE_LINKBUILD: flag buffer to reset to FLUID on the regions, or NULL
+    uint8_t *skip;       // PHASE_BULK: skip mask of this step
+    uint8_t *skip_next;  // PHASE_FLAGS: skip mask of the next step
     uint32_t *stamp;
     DevParticle *P;
     RegionMap rm;
     const int *part_first_blk;
     int *blk_cnt, *blk_off, *l_off;
     uint32_t *l_node, *l_do;
-    double *l_q, *lft;
+    double *l_q, *part;
     uint32_t *special;
     Counters *cnt;
-    int *iters;
 };
 
 void launch_phase(const StepArgs &a);
