@@ -78,6 +78,16 @@ def lib():
         L.orc_feq.argtypes = [C.c_double, _dp, _dp]
         L.orc_collide_node.argtypes = [_dp, _dp, C.c_double, _dp]
         L.orc_lattice.argtypes = [_i32p, _dp, _i32p]
+        L.orc_set_contact.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_pair_geometry.restype = C.c_int
+        L.orc_pair_geometry.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_wall_geometry.restype = C.c_int
+        L.orc_wall_geometry.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.orc_dem_only.argtypes = [C.c_void_p, C.c_int]
+        L.orc_n_contacts.restype = C.c_long
+        L.orc_n_contacts.argtypes = [C.c_void_p]
+        L.orc_n_contact_fail.restype = C.c_long
+        L.orc_n_contact_fail.argtypes = [C.c_void_p]
         L.orc_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -146,6 +156,8 @@ class Oracle:
                                     int(p.mode), float(cfg.quad_h))
             if rc < 0:
                 raise ValueError("oracle rejected a particle")
+        L.orc_set_contact(self._h, float(cfg.contact_rs), float(cfg.contact_kn),
+                          float(cfg.contact_en), float(cfg.contact_mu))
         L.orc_init(self._h)
 
     def __del__(self):
@@ -225,3 +237,26 @@ class Oracle:
 
     def link_q(self, p: int, x: int, y: int, z: int, i: int) -> float:
         return lib().orc_link_q(self._h, p, x, y, z, i)
+
+    def pair_geometry(self, i: int, j: int):
+        """(status, x_m, x_c0, x_c1, x_cp, n, delta) of bodies i, j."""
+        xm, xc0, xc1, xcp, n, d = [np.zeros(3) for _ in range(5)] + [np.zeros(1)]
+        r = lib().orc_pair_geometry(self._h, i, j, xm, xc0, xc1, xcp, n, d)
+        return r, xm, xc0, xc1, xcp, n, float(d[0])
+
+    def wall_geometry(self, p: int, axis: int, side: int):
+        """(status, x_cw, x_cm, x_cp, n, delta) of body p and a walled face."""
+        xcw, xcm, xcp, n, d = [np.zeros(3) for _ in range(4)] + [np.zeros(1)]
+        r = lib().orc_wall_geometry(self._h, p, axis, side, xcw, xcm, xcp, n, d)
+        return r, xcw, xcm, xcp, n, float(d[0])
+
+    def dem_only(self, n: int):
+        lib().orc_dem_only(self._h, int(n))
+
+    @property
+    def n_contacts(self) -> int:
+        return lib().orc_n_contacts(self._h)
+
+    @property
+    def n_contact_fail(self) -> int:
+        return lib().orc_n_contact_fail(self._h)

@@ -39,6 +39,7 @@
 
 #define Q 19
 #define MAX_CP 20
+#define PI_D 3.14159265358979323846
 
 /* D3Q19 velocities: rest, the six faces, the twelve edges; opposites are
  * adjacent (1/2, 3/4, ...). */
@@ -76,6 +77,12 @@ typedef struct orc_ctx {
     unsigned periodic;
     double tau, rho0, gf[3], gp[3];
     int bc, n_sub, counter_force;
+    /* contact (sec. 2.3.1): sphere radius R_s of the sphero-metaball, normal
+     * stiffness k_n (0 disables contact), restitution e, friction mu_s */
+    double c_rs, c_kn, c_en, c_mu;
+    double *xi_pair; /* [np][np][3] tangential springs of body pairs (i < j) */
+    double *xi_wall; /* [np][6][3] tangential springs against the six faces */
+    long n_contacts, n_contact_fail;
     int np, cap;
     orc_particle *P;
     double *f;      /* [Q][N] post-stream populations (the state) */
@@ -321,7 +328,7 @@ void orc_destroy(orc_ctx *c) {
     if (!c) return;
     free(c->f); free(c->fp); free(c->rho); free(c->u); free(c->own); free(c->own2);
     free(c->l_start); free(c->l_cnt); free(c->l_node); free(c->l_dir); free(c->l_own);
-    free(c->l_q); free(c->P); free(c);
+    free(c->l_q); free(c->P); free(c->xi_pair); free(c->xi_wall); free(c);
 }
 
 /* Adds a body.  cp_xyz are in a body frame whose origin sits at x; the
@@ -359,6 +366,10 @@ int orc_add_particle(orc_ctx *c, int n_cp, const double *cp_xyz, const double *c
         P->v[a] = v[a]; P->w[a] = w[a];
     }
     P->rb = rmax + sqrt(sk);
+    free(c->xi_pair);
+    free(c->xi_wall);
+    c->xi_pair = (double *)calloc(3 * (size_t)(c->np + 1) * (c->np + 1), sizeof(double));
+    c->xi_wall = (double *)calloc(3 * 6 * (size_t)(c->np + 1), sizeof(double));
     P->V = V; P->m = density * V; P->mode = mode;
     for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) P->I[a][b] = density * I[3 * a + b];
     if (mode == 0 && inv3(P->I, P->Iinv)) return -1;
@@ -630,53 +641,349 @@ static void momentum_exchange(orc_ctx *c) {
     }
 }
 
-/* Newton-Euler update (sec. 2.3.1) over one lattice time unit split into
- * n_sub sub-steps with the hydrodynamic load held: semi-implicit Euler for
- * v and X; body-frame Euler equation I dw_b/dt = T_b - w_b x I w_b for the
- * spin; the attitude advances by the exact rotation of w_b over the
- * sub-step.  Weight minus buoyancy (m - rho0 V) g acts on free bodies.
- * Kinematic bodies move with their given v and w. */
-static void rigid_body(orc_ctx *c, orc_particle *P, const double Fh[3], const double Th[3]) {
-    double dt = 1.0 / c->n_sub;
-    for (int s = 0; s < c->n_sub; ++s) {
-        if (P->mode == 1) {
-            double phi[3] = {P->w[0] * dt, P->w[1] * dt, P->w[2] * dt}, dq[4];
-            for (int a = 0; a < 3; ++a) P->X[a] += P->v[a] * dt;
-            quat_exp(phi, dq);
-            quat_mul(dq, P->q, P->q);
-        } else {
-            double R[3][3], Tb[3], wb[3], Iw[3], g[3], rhs[3], dw[3];
-            for (int a = 0; a < 3; ++a) {
-                double Ft = Fh[a] + (P->m - c->rho0 * P->V) * c->gp[a];
-                P->v[a] += Ft / P->m * dt;
-                P->X[a] += P->v[a] * dt;
-            }
-            quat_to_rot(P->q, R);
-            for (int a = 0; a < 3; ++a) {
-                Tb[a] = R[0][a] * Th[0] + R[1][a] * Th[1] + R[2][a] * Th[2];
-                wb[a] = R[0][a] * P->w[0] + R[1][a] * P->w[1] + R[2][a] * P->w[2];
-            }
-            for (int a = 0; a < 3; ++a) Iw[a] = P->I[a][0] * wb[0] + P->I[a][1] * wb[1] + P->I[a][2] * wb[2];
-            cross(wb, Iw, g);
-            for (int a = 0; a < 3; ++a) rhs[a] = Tb[a] - g[a];
-            for (int a = 0; a < 3; ++a) dw[a] = P->Iinv[a][0] * rhs[0] + P->Iinv[a][1] * rhs[1] + P->Iinv[a][2] * rhs[2];
-            for (int a = 0; a < 3; ++a) wb[a] += dw[a] * dt;
-            for (int a = 0; a < 3; ++a) P->w[a] = R[a][0] * wb[0] + R[a][1] * wb[1] + R[a][2] * wb[2];
-            double phi[3] = {wb[0] * dt, wb[1] * dt, wb[2] * dt}, dq[4];
-            quat_exp(phi, dq);
-            quat_mul(P->q, dq, P->q);
+/* One sub-step dt of the Newton-Euler update (sec. 2.3.1) of one body
+ * under total force F and torque T (lab frame, hydrodynamic + contact):
+ * semi-implicit Euler for v and X; body-frame Euler equation
+ * I dw_b/dt = T_b - w_b x I w_b for the spin; the attitude advances by the
+ * exact rotation of w_b over the sub-step.  Weight minus buoyancy
+ * (m - rho0 V) g acts on free bodies.  Kinematic bodies move with their given
+ * v and w. */
+static void body_substep(orc_ctx *c, orc_particle *P, const double F[3], const double T[3], double dt) {
+    if (P->mode == 1) {
+        double phi[3] = {P->w[0] * dt, P->w[1] * dt, P->w[2] * dt}, dq[4];
+        for (int a = 0; a < 3; ++a) P->X[a] += P->v[a] * dt;
+        quat_exp(phi, dq);
+        quat_mul(dq, P->q, P->q);
+    } else {
+        double R[3][3], Tb[3], wb[3], Iw[3], g[3], rhs[3], dw[3];
+        for (int a = 0; a < 3; ++a) {
+            double Ft = F[a] + (P->m - c->rho0 * P->V) * c->gp[a];
+            P->v[a] += Ft / P->m * dt;
+            P->X[a] += P->v[a] * dt;
         }
-        double nq = sqrt(P->q[0] * P->q[0] + P->q[1] * P->q[1] + P->q[2] * P->q[2] + P->q[3] * P->q[3]);
-        for (int a = 0; a < 4; ++a) P->q[a] /= nq;
+        quat_to_rot(P->q, R);
+        for (int a = 0; a < 3; ++a) {
+            Tb[a] = R[0][a] * T[0] + R[1][a] * T[1] + R[2][a] * T[2];
+            wb[a] = R[0][a] * P->w[0] + R[1][a] * P->w[1] + R[2][a] * P->w[2];
+        }
+        for (int a = 0; a < 3; ++a) Iw[a] = P->I[a][0] * wb[0] + P->I[a][1] * wb[1] + P->I[a][2] * wb[2];
+        cross(wb, Iw, g);
+        for (int a = 0; a < 3; ++a) rhs[a] = Tb[a] - g[a];
+        for (int a = 0; a < 3; ++a) dw[a] = P->Iinv[a][0] * rhs[0] + P->Iinv[a][1] * rhs[1] + P->Iinv[a][2] * rhs[2];
+        for (int a = 0; a < 3; ++a) wb[a] += dw[a] * dt;
+        for (int a = 0; a < 3; ++a) P->w[a] = R[a][0] * wb[0] + R[a][1] * wb[1] + R[a][2] * wb[2];
+        double phi[3] = {wb[0] * dt, wb[1] * dt, wb[2] * dt}, dq[4];
+        quat_exp(phi, dq);
+        quat_mul(P->q, dq, P->q);
     }
+    double nq = sqrt(P->q[0] * P->q[0] + P->q[1] * P->q[1] + P->q[2] * P->q[2] + P->q[3] * P->q[3]);
+    for (int a = 0; a < 4; ++a) P->q[a] /= nq;
     update_lab_cps(P);
 }
 
+/* ------------------------------------------------------ contact (sec. 2.3.1) */
+/* Zoomed internal metaball of the sphero-metaball: the body scaled by
+ * s = 1 - R_s / sqrt(sum k) about its centroid (control points
+ * X + s (p - X), weights s^2 k), which is the same shape shrunk; dilating it
+ * by a sphere of radius R_s approximates the body.  'shift' moves it to a
+ * periodic image. */
+static int inner_metaball(const orc_ctx *c, const orc_particle *P, const double shift[3],
+                          double cp[][3], double k[]) {
+    double sk = 0.0;
+    for (int i = 0; i < P->n_cp; ++i) sk += P->k[i];
+    double s = 1.0 - c->c_rs / sqrt(sk);
+    if (!(s > 0.0)) return -1;
+    for (int i = 0; i < P->n_cp; ++i) {
+        for (int a = 0; a < 3; ++a) cp[i][a] = P->X[a] + shift[a] + s * (P->cpl[i][a] - P->X[a]);
+        k[i] = s * s * P->k[i];
+    }
+    return P->n_cp;
+}
+
+/* f = sum k/r^2, its gradient sum -2 k d/r^4 and Hessian
+ * sum 2 k (4 d d^T / r^6 - I / r^4) at x (d = x - p). */
+static void mb_eval(int n, double cp[][3], const double k[], const double x[3], double *f, double g[3],
+                    double H[3][3]) {
+    *f = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        g[a] = 0.0;
+        for (int b = 0; b < 3; ++b) H[a][b] = 0.0;
+    }
+    for (int i = 0; i < n; ++i) {
+        double d[3] = {x[0] - cp[i][0], x[1] - cp[i][1], x[2] - cp[i][2]};
+        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double r4 = r2 * r2, r6 = r4 * r2;
+        *f += k[i] / r2;
+        for (int a = 0; a < 3; ++a) {
+            g[a] += -2.0 * k[i] * d[a] / r4;
+            for (int b = 0; b < 3; ++b) H[a][b] += 2.0 * k[i] * (4.0 * d[a] * d[b] / r6 - (a == b ? 1.0 : 0.0) / r4);
+        }
+    }
+}
+
+/* Contact geometry of two bodies (Eqs. CM_coreF, eq:grad, eq:cp,
+ * eq:contactprop): Newton-Raphson for the stationary point x_m of
+ * f0 + f1 between the inner metaballs, started on the centroid segment at
+ * the point dividing it in the ratio (K0/K1)^(1/3) (exact for single points);
+ * Taylor projections x_c0 = x_m + q0 grad f0 with q0 = (1 - f0)/|grad f0|^2
+ * (and likewise x_c1); n = (x_c0 - x_c1)/|x_c0 - x_c1| points from body 1 to
+ * body 0; delta = 2 R_s - |x_c0 - x_c1|; the contact point is the middle of
+ * the overlap on the line, x_cp = x_c0 - (R_s - delta/2) n.  Returns 1 for a
+ * contact, 0 for none, -1 if the iteration failed. */
+int orc_pair_geometry(orc_ctx *c, int i0, int i1, double xm[3], double xc0[3], double xc1[3],
+                      double xcp[3], double nrm[3], double *delta) {
+    const orc_particle *P0 = &c->P[i0], *P1 = &c->P[i1];
+    double sh0[3] = {0, 0, 0}, sh1[3], d01[3];
+    for (int a = 0; a < 3; ++a) d01[a] = P1->X[a] - P0->X[a];
+    min_image(c, d01);
+    for (int a = 0; a < 3; ++a) sh1[a] = P0->X[a] + d01[a] - P1->X[a];
+    double cp0[MAX_CP][3], k0[MAX_CP], cp1[MAX_CP][3], k1[MAX_CP];
+    int n0 = inner_metaball(c, P0, sh0, cp0, k0), n1 = inner_metaball(c, P1, sh1, cp1, k1);
+    if (n0 < 0 || n1 < 0) return -1;
+    double K0 = 0, K1 = 0;
+    for (int i = 0; i < n0; ++i) K0 += k0[i];
+    for (int i = 0; i < n1; ++i) K1 += k1[i];
+    double rho = cbrt(K0 / K1);
+    for (int a = 0; a < 3; ++a) xm[a] = P0->X[a] + d01[a] * rho / (1.0 + rho);
+    double L = sqrt(d01[0] * d01[0] + d01[1] * d01[1] + d01[2] * d01[2]);
+    int ok = 0;
+    for (int it = 0; it < 60; ++it) {
+        double f0, g0[3], H0[3][3], f1, g1[3], H1[3][3], H[3][3], Hi[3][3], dx[3];
+        mb_eval(n0, cp0, k0, xm, &f0, g0, H0);
+        mb_eval(n1, cp1, k1, xm, &f1, g1, H1);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) H[a][b] = H0[a][b] + H1[a][b];
+        if (inv3(H, Hi)) break;
+        double st = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            dx[a] = -(Hi[a][0] * (g0[0] + g1[0]) + Hi[a][1] * (g0[1] + g1[1]) + Hi[a][2] * (g0[2] + g1[2]));
+            st += dx[a] * dx[a];
+        }
+        st = sqrt(st);
+        if (st > 0.25 * L) for (int a = 0; a < 3; ++a) dx[a] *= 0.25 * L / st;
+        for (int a = 0; a < 3; ++a) xm[a] += dx[a];
+        if (st < 1e-12 * (1.0 + L)) { ok = 1; break; }
+    }
+    if (!ok) return -1;
+    double f0, g0[3], H0[3][3], f1, g1[3], H1[3][3];
+    mb_eval(n0, cp0, k0, xm, &f0, g0, H0);
+    mb_eval(n1, cp1, k1, xm, &f1, g1, H1);
+    if (!(f0 < 1.0 && f1 < 1.0)) return -1; /* the inner bodies overlap */
+    double q0 = (1.0 - f0) / (g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2]);
+    double q1 = (1.0 - f1) / (g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
+    double d = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        xc0[a] = xm[a] + q0 * g0[a];
+        xc1[a] = xm[a] + q1 * g1[a];
+        d += (xc0[a] - xc1[a]) * (xc0[a] - xc1[a]);
+    }
+    d = sqrt(d);
+    *delta = 2.0 * c->c_rs - d;
+    for (int a = 0; a < 3; ++a) {
+        nrm[a] = (xc0[a] - xc1[a]) / d;
+        xcp[a] = xc0[a] - (c->c_rs - 0.5 * *delta) * nrm[a];
+    }
+    return *delta > 0.0;
+}
+
+/* Contact of a body with the halfway wall normal to axis ax (side 0: the
+ * wall at -1/2, side 1: at L - 1/2) (Eqs. metawallcp, contactprop2): the
+ * point x_cw of the wall plane where grad f is normal to the plane (2-D
+ * Newton-Raphson on the in-plane gradient, from the centroid's projection),
+ * x_cm = x_cw + q grad f with q = (1 - f)/|grad f|^2, n = (x_cm - x_cw)/|...|
+ * (into the domain), delta = R_s - |x_cm - x_cw|, x_cp = x_cw + delta/2 n. */
+int orc_wall_geometry(orc_ctx *c, int ip, int ax, int side, double xcw[3], double xcm[3], double xcp[3],
+                      double nrm[3], double *delta) {
+    const orc_particle *P = &c->P[ip];
+    int L = ax == 0 ? c->nx : (ax == 1 ? c->ny : c->nz);
+    double wpos = side ? L - 0.5 : -0.5;
+    if (fabs(P->X[ax] - wpos) > P->rb + c->c_rs) return 0;
+    double sh[3] = {0, 0, 0}, cp[MAX_CP][3], k[MAX_CP];
+    int n = inner_metaball(c, P, sh, cp, k);
+    if (n < 0) return -1;
+    int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+    for (int a = 0; a < 3; ++a) xcw[a] = P->X[a];
+    xcw[ax] = wpos;
+    int ok = 0;
+    for (int it = 0; it < 60; ++it) {
+        double f, g[3], H[3][3];
+        mb_eval(n, cp, k, xcw, &f, g, H);
+        double h11 = H[a1][a1], h12 = H[a1][a2], h22 = H[a2][a2];
+        double det = h11 * h22 - h12 * h12;
+        if (!(fabs(det) > 0)) break;
+        double d1 = -(h22 * g[a1] - h12 * g[a2]) / det, d2 = -(-h12 * g[a1] + h11 * g[a2]) / det;
+        double st = sqrt(d1 * d1 + d2 * d2);
+        if (st > 0.25 * P->rb) { d1 *= 0.25 * P->rb / st; d2 *= 0.25 * P->rb / st; }
+        xcw[a1] += d1;
+        xcw[a2] += d2;
+        if (st < 1e-12 * (1.0 + P->rb)) { ok = 1; break; }
+    }
+    if (!ok) return -1;
+    double f, g[3], H[3][3];
+    mb_eval(n, cp, k, xcw, &f, g, H);
+    if (!(f < 1.0)) return -1;
+    double q = (1.0 - f) / (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double d = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        xcm[a] = xcw[a] + q * g[a];
+        d += (xcm[a] - xcw[a]) * (xcm[a] - xcw[a]);
+    }
+    d = sqrt(d);
+    *delta = c->c_rs - d;
+    for (int a = 0; a < 3; ++a) {
+        nrm[a] = (xcm[a] - xcw[a]) / d;
+        xcp[a] = xcw[a] + 0.5 * *delta * nrm[a];
+    }
+    return *delta > 0.0;
+}
+
+/* Linear spring-dashpot with a Coulomb-capped tangential spring (sec. 2.3.1):
+ * F_n = k_n delta + eta_n (v_j - v_i).n while delta > 0, eta_n from the
+ * restitution e and the effective mass; tangential spring xi advanced by the
+ * tangential relative velocity u_t (kept in the tangent plane), F_t =
+ * k_t xi + eta_t u_t with k_t = 2/7 k_n, eta_t = eta_n, capped at mu_s F_n.
+ * Returns the force on body i (along +n from j to i) in F. */
+static void spring_dashpot(const orc_ctx *c, double meff, const double n[3], double delta,
+                           const double vrel[3], double xi[3], double dt, double F[3]) {
+    double le = log(c->c_en);
+    double zeta = -le / sqrt(PI_D * PI_D + le * le);
+    double etan = 2.0 * zeta * sqrt(meff * c->c_kn), kt = 2.0 / 7.0 * c->c_kn, etat = etan;
+    double vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    double Fn = c->c_kn * delta + etan * vn;
+    double ut[3], xn = xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2], Ft[3], ftn = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        ut[a] = vrel[a] - vn * n[a];
+        xi[a] = xi[a] - xn * n[a] + ut[a] * dt;
+        Ft[a] = kt * xi[a] + etat * ut[a];
+        ftn += Ft[a] * Ft[a];
+    }
+    ftn = sqrt(ftn);
+    double cap = c->c_mu * fabs(Fn);
+    if (ftn > cap && ftn > 0.0) {
+        for (int a = 0; a < 3; ++a) {
+            Ft[a] *= cap / ftn;
+            xi[a] = Ft[a] / kt;
+        }
+    }
+    for (int a = 0; a < 3; ++a) F[a] = Fn * n[a] + Ft[a];
+}
+
+static void point_velocity(const orc_ctx *c, const orc_particle *P, const double x[3], double v[3]) {
+    double r[3] = {x[0] - P->X[0], x[1] - P->X[1], x[2] - P->X[2]}, wr[3];
+    min_image(c, r);
+    cross(P->w, r, wr);
+    for (int a = 0; a < 3; ++a) v[a] = P->v[a] + wr[a];
+}
+
+/* Contact forces and torques on every body at the current poses: body
+ * pairs whose bounding spheres overlap and bodies near walled faces.  Sums
+ * in a fixed order (pairs by i then j). */
+static void contact_forces(orc_ctx *c, double (*Fc)[3], double (*Tc)[3], double dt) {
+    int np = c->np;
+    for (int p = 0; p < np; ++p)
+        for (int a = 0; a < 3; ++a) Fc[p][a] = Tc[p][a] = 0.0;
+    if (!(c->c_kn > 0.0)) return;
+    for (int i = 0; i < np; ++i)
+        for (int j = i + 1; j < np; ++j) {
+            orc_particle *Pi = &c->P[i], *Pj = &c->P[j];
+            double *xi = c->xi_pair + 3 * ((long)i * np + j);
+            if (Pi->mode == 1 && Pj->mode == 1) continue;
+            double d[3] = {Pj->X[0] - Pi->X[0], Pj->X[1] - Pi->X[1], Pj->X[2] - Pi->X[2]};
+            min_image(c, d);
+            if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) > Pi->rb + Pj->rb) {
+                xi[0] = xi[1] = xi[2] = 0.0;
+                continue;
+            }
+            double xm[3], xc0[3], xc1[3], xcp[3], n[3], delta;
+            int r = orc_pair_geometry(c, i, j, xm, xc0, xc1, xcp, n, &delta);
+            if (r < 0) c->n_contact_fail++;
+            if (r <= 0) { xi[0] = xi[1] = xi[2] = 0.0; continue; }
+            c->n_contacts++;
+            double vi[3], vj[3], vrel[3], F[3], ri[3], rj[3], Ti[3], Tj[3];
+            point_velocity(c, Pi, xcp, vi);
+            point_velocity(c, Pj, xcp, vj);
+            for (int a = 0; a < 3; ++a) vrel[a] = vj[a] - vi[a];
+            double meff = Pi->mode == 1 ? Pj->m : (Pj->mode == 1 ? Pi->m : Pi->m * Pj->m / (Pi->m + Pj->m));
+            spring_dashpot(c, meff, n, delta, vrel, xi, dt, F);
+            for (int a = 0; a < 3; ++a) { ri[a] = xcp[a] - Pi->X[a]; rj[a] = xcp[a] - Pj->X[a]; }
+            min_image(c, ri);
+            min_image(c, rj);
+            double Fm[3] = {-F[0], -F[1], -F[2]};
+            cross(ri, F, Ti);
+            cross(rj, Fm, Tj);
+            for (int a = 0; a < 3; ++a) {
+                Fc[i][a] += F[a]; Tc[i][a] += Ti[a];
+                Fc[j][a] += Fm[a]; Tc[j][a] += Tj[a];
+            }
+        }
+    for (int i = 0; i < np; ++i) {
+        orc_particle *Pi = &c->P[i];
+        if (Pi->mode == 1) continue;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (c->periodic & (1u << ax)) continue;
+            for (int side = 0; side < 2; ++side) {
+                double *xi = c->xi_wall + 3 * ((long)i * 6 + 2 * ax + side);
+                double xcw[3], xcm[3], xcp[3], n[3], delta;
+                int r = orc_wall_geometry(c, i, ax, side, xcw, xcm, xcp, n, &delta);
+                if (r < 0) c->n_contact_fail++;
+                if (r <= 0) { xi[0] = xi[1] = xi[2] = 0.0; continue; }
+                c->n_contacts++;
+                double vi[3], vrel[3], F[3], ri[3], Ti[3];
+                point_velocity(c, Pi, xcp, vi);
+                for (int a = 0; a < 3; ++a) vrel[a] = -vi[a];
+                spring_dashpot(c, Pi->m, n, delta, vrel, xi, dt, F);
+                for (int a = 0; a < 3; ++a) ri[a] = xcp[a] - Pi->X[a];
+                cross(ri, F, Ti);
+                for (int a = 0; a < 3; ++a) { Fc[i][a] += F[a]; Tc[i][a] += Ti[a]; }
+            }
+        }
+    }
+}
+
+/* Rigid-body update of all bodies over one lattice time unit: n_sub
+ * sub-steps, each with contact forces recomputed at the sub-step's poses and
+ * the hydrodynamic load of the lattice step held. */
+static void rigid_update_all(orc_ctx *c) {
+    double dt = 1.0 / c->n_sub;
+    int np = c->np;
+    double (*Fc)[3] = malloc(sizeof(double[3]) * (np ? np : 1));
+    double (*Tc)[3] = malloc(sizeof(double[3]) * (np ? np : 1));
+    for (int s = 0; s < c->n_sub; ++s) {
+        contact_forces(c, Fc, Tc, dt);
+        for (int p = 0; p < np; ++p) {
+            double F[3], T[3];
+            for (int a = 0; a < 3; ++a) { F[a] = c->P[p].F[a] + Fc[p][a]; T[a] = c->P[p].T[a] + Tc[p][a]; }
+            body_substep(c, &c->P[p], F, T, dt);
+        }
+    }
+    free(Fc);
+    free(Tc);
+}
+
+/* One lattice time unit of body p alone under a given hydrodynamic load (no
+ * contact); used by tests. */
 int orc_rigid_body_step(orc_ctx *c, int p, const double *F, const double *T) {
     if (p < 0 || p >= c->np) return -1;
-    rigid_body(c, &c->P[p], F, T);
+    double dt = 1.0 / c->n_sub;
+    for (int s = 0; s < c->n_sub; ++s) body_substep(c, &c->P[p], F, T, dt);
     return 0;
 }
+
+/* Bodies only (no fluid): n lattice time units of contact dynamics with the
+ * hydrodynamic load set to zero; used by tests. */
+int orc_dem_only(orc_ctx *c, int nsteps) {
+    for (int p = 0; p < c->np; ++p)
+        for (int a = 0; a < 3; ++a) c->P[p].F[a] = c->P[p].T[a] = 0.0;
+    for (int t = 0; t < nsteps; ++t) rigid_update_all(c);
+    return 0;
+}
+
+void orc_set_contact(orc_ctx *c, double rs, double kn, double en, double mu) {
+    c->c_rs = rs; c->c_kn = kn; c->c_en = en; c->c_mu = mu;
+}
+
+long orc_n_contacts(const orc_ctx *c) { return c->n_contacts; }
+long orc_n_contact_fail(const orc_ctx *c) { return c->n_contact_fail; }
 
 /* Local refilling (sec. 2.3.2): a node solid at n and fluid at n+1 keeps the
  * populations that streamed in from nodes that were fluid; a missing f_i
@@ -716,11 +1023,7 @@ int orc_step(orc_ctx *c, int nsteps) {
         collide_all(c, c->fp);
         stream_all(c);                     /* 2 */
         momentum_exchange(c);              /* 3 */
-        for (int p = 0; p < c->np; ++p) {  /* 4 */
-            double F[3], T[3];
-            memcpy(F, c->P[p].F, sizeof F); memcpy(T, c->P[p].T, sizeof T);
-            rigid_body(c, &c->P[p], F, T);
-        }
+        rigid_update_all(c);               /* 4 */
         flag_all(c, c->own2);              /* 5 */
         refill(c, c->own, c->own2);        /* 6 */
         int32_t *t2 = c->own; c->own = c->own2; c->own2 = t2;

@@ -68,6 +68,11 @@ class Config:
     counter_force: int = 0
     quad_h: float = 0.125
     storage: int = STORE_F32
+    # contact (sphero-metaball, linear spring-dashpot); contact_kn = 0 disables it
+    contact_rs: float = 1.0
+    contact_kn: float = 0.0
+    contact_en: float = 0.5
+    contact_mu: float = 0.5
     particles: List[Particle] = dataclasses.field(default_factory=list)
     name: str = ""
     steps: int = 0
