@@ -95,6 +95,13 @@ typedef struct {
     float fp16_scale;     /* FP16 storage multiplies deviations by this power of
                              two (0 selects 1024); ignored for FP32 and BF16       */
     int32_t reserved;
+    /* contact (sec. 2.3.1): sphero-metaball of sphere radius contact_rs around
+     * the body shrunk by 1 - contact_rs/sqrt(sum k); linear spring-dashpot with
+     * stiffness contact_kn (0 disables contact), damping from the restitution
+     * contact_en, tangential spring 2/7 contact_kn capped by contact_mu times
+     * the normal force; recomputed every rigid-body sub-step.  Enabled contact
+     * supports at most 1024 particles.                                       */
+    double contact_rs, contact_kn, contact_en, contact_mu;
 } lbm_config;
 
 typedef struct {
@@ -189,6 +196,10 @@ lbm_status lbm_timing_read(lbm_ctx *ctx, double *ms, int64_t *launches, int64_t 
 /* Link fractions solved and Newton/bisection iterations spent on them since
  * the last call (resets the counts; synchronises). */
 lbm_status lbm_nr_stats(lbm_ctx *ctx, int64_t *links, int64_t *iterations);
+/* Contacts resolved (body pairs and walls, counted per rigid-body sub-step)
+ * and contact iterations that did not converge, since lbm_init
+ * (synchronises). */
+lbm_status lbm_contact_stats(lbm_ctx *ctx, int64_t *contacts, int64_t *failures);
 /* Waits for the context's stream and reports device-side errors. */
 lbm_status lbm_sync(lbm_ctx *ctx);
 

@@ -622,7 +622,8 @@ static void stream_all(orc_ctx *c) {
 /* Momentum exchange over the cut links (sec. 2.3.2, MEM paragraph), in the
  * Galilean-invariant per-link form
  *   dP = (e_ib - u_w) f+_ib(x_f, t) - (e_i - u_w) f_i(x_f, t+1),
- *   dT = (x_w - X) x dP.  Serial, link order. */
+ *   dT = (x_w - X) x dP,
+ * with both populations counted relative to w rho0.  Serial, link order. */
 static void momentum_exchange(orc_ctx *c) {
     for (int p = 0; p < c->np; ++p)
         for (int a = 0; a < 3; ++a) c->P[p].F[a] = c->P[p].T[a] = 0.0;
@@ -632,8 +633,13 @@ static void momentum_exchange(orc_ctx *c) {
         int i = c->l_dir[l], ib = opp(i), p = c->l_own[l];
         int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long)c->nx * c->ny));
         double xw[3], uw[3], r[3];
-        double fin = bounce(c, n, x, y, z, i, p, c->l_q[l], xw, uw, r);
-        double fout = c->fp[(long)ib * N + n];
+        /* exchanged populations taken relative to the rest state w rho0: the
+         * uniform reference pressure then exerts no force, also on a body whose
+         * surface touches a wall or another body and has no cut links there
+         * (over a closed surface its per-link terms -2 w rho0 e_i cancel
+         * exactly, since cut links come in opposite pairs of equal count) */
+        double fin = bounce(c, n, x, y, z, i, p, c->l_q[l], xw, uw, r) - WT[i] * c->rho0;
+        double fout = c->fp[(long)ib * N + n] - WT[ib] * c->rho0;
         double dP[3], dT[3];
         for (int a = 0; a < 3; ++a) dP[a] = (EV[ib][a] - uw[a]) * fout - (EV[i][a] - uw[a]) * fin;
         cross(r, dP, dT);
@@ -727,9 +733,10 @@ static void mb_eval(int n, double cp[][3], const double k[], const double x[3], 
  * the point dividing it in the ratio (K0/K1)^(1/3) (exact for single points);
  * Taylor projections x_c0 = x_m + q0 grad f0 with q0 = (1 - f0)/|grad f0|^2
  * (and likewise x_c1); n = (x_c0 - x_c1)/|x_c0 - x_c1| points from body 1 to
- * body 0; delta = 2 R_s - |x_c0 - x_c1|; the contact point is the middle of
- * the overlap on the line, x_cp = x_c0 - (R_s - delta/2) n.  Returns 1 for a
- * contact, 0 for none, -1 if the iteration failed. */
+ * body 0; delta = 2 R_s - |x_c0 - x_c1| (in signed form, see below); the
+ * contact point is the middle of the overlap on the line,
+ * x_cp = x_c0 - (R_s - delta/2) n.  Returns 1 for a contact, 0 for none, -1
+ * if the iteration failed. */
 int orc_pair_geometry(orc_ctx *c, int i0, int i1, double xm[3], double xc0[3], double xc1[3],
                       double xcp[3], double nrm[3], double *delta) {
     const orc_particle *P0 = &c->P[i0], *P1 = &c->P[i1];
@@ -768,19 +775,20 @@ int orc_pair_geometry(orc_ctx *c, int i0, int i1, double xm[3], double xc0[3], d
     double f0, g0[3], H0[3][3], f1, g1[3], H1[3][3];
     mb_eval(n0, cp0, k0, xm, &f0, g0, H0);
     mb_eval(n1, cp1, k1, xm, &f1, g1, H1);
-    if (!(f0 < 1.0 && f1 < 1.0)) return -1; /* the inner bodies overlap */
-    double q0 = (1.0 - f0) / (g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2]);
-    double q1 = (1.0 - f1) / (g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
-    double d = 0.0;
+    double G0 = sqrt(g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2]);
+    double G1 = sqrt(g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
+    if (!(G0 > 0.0 && G1 > 0.0)) return -1;
+    double q0 = (1.0 - f0) / (G0 * G0), q1 = (1.0 - f1) / (G1 * G1);
+    /* At the stationary point grad f0 = -grad f1, so x_c0 - x_c1 lies along
+     * n = grad f0/|grad f0| (from body 1 towards body 0) and its signed length
+     * is s = (1 - f0)/|grad f0| + (1 - f1)/|grad f1|, which stays meaningful
+     * when the inner bodies overlap (s < 0). */
+    double sgap = (1.0 - f0) / G0 + (1.0 - f1) / G1;
+    *delta = 2.0 * c->c_rs - sgap;
     for (int a = 0; a < 3; ++a) {
         xc0[a] = xm[a] + q0 * g0[a];
         xc1[a] = xm[a] + q1 * g1[a];
-        d += (xc0[a] - xc1[a]) * (xc0[a] - xc1[a]);
-    }
-    d = sqrt(d);
-    *delta = 2.0 * c->c_rs - d;
-    for (int a = 0; a < 3; ++a) {
-        nrm[a] = (xc0[a] - xc1[a]) / d;
+        nrm[a] = g0[a] / G0;
         xcp[a] = xc0[a] - (c->c_rs - 0.5 * *delta) * nrm[a];
     }
     return *delta > 0.0;
@@ -789,7 +797,8 @@ int orc_pair_geometry(orc_ctx *c, int i0, int i1, double xm[3], double xc0[3], d
 /* Contact of a body with the halfway wall normal to axis ax (side 0: the
  * wall at -1/2, side 1: at L - 1/2) (Eqs. metawallcp, contactprop2): the
  * point x_cw of the wall plane where grad f is normal to the plane (2-D
- * Newton-Raphson on the in-plane gradient, from the centroid's projection),
+ * Newton-Raphson on the in-plane gradient, started at the projection of the
+ * control point where f on the plane is largest),
  * x_cm = x_cw + q grad f with q = (1 - f)/|grad f|^2, n = (x_cm - x_cw)/|...|
  * (into the domain), delta = R_s - |x_cm - x_cw|, x_cp = x_cw + delta/2 n. */
 int orc_wall_geometry(orc_ctx *c, int ip, int ax, int side, double xcw[3], double xcm[3], double xcp[3],
@@ -802,8 +811,18 @@ int orc_wall_geometry(orc_ctx *c, int ip, int ax, int side, double xcw[3], doubl
     int n = inner_metaball(c, P, sh, cp, k);
     if (n < 0) return -1;
     int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
-    for (int a = 0; a < 3; ++a) xcw[a] = P->X[a];
-    xcw[ax] = wpos;
+    /* start: the projection onto the plane of the control point where f on
+     * the plane is largest (near the maximum of f over the plane) */
+    double best = -1.0;
+    for (int i = 0; i < n; ++i) {
+        double y[3] = {cp[i][0], cp[i][1], cp[i][2]}, fy, gy[3], Hy[3][3];
+        y[ax] = wpos;
+        mb_eval(n, cp, k, y, &fy, gy, Hy);
+        if (fy > best) {
+            best = fy;
+            for (int a = 0; a < 3; ++a) xcw[a] = y[a];
+        }
+    }
     int ok = 0;
     for (int it = 0; it < 60; ++it) {
         double f, g[3], H[3][3];
@@ -821,17 +840,16 @@ int orc_wall_geometry(orc_ctx *c, int ip, int ax, int side, double xcw[3], doubl
     if (!ok) return -1;
     double f, g[3], H[3][3];
     mb_eval(n, cp, k, xcw, &f, g, H);
-    if (!(f < 1.0)) return -1;
-    double q = (1.0 - f) / (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-    double d = 0.0;
+    double G = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (!(G > 0.0)) return -1;
+    double q = (1.0 - f) / (G * G);
+    /* grad f is normal to the plane at x_cw and points into the body, so
+     * x_cm - x_cw = q grad f has the signed length (1 - f)/|grad f| along
+     * n = grad f/|grad f| (negative when the inner body crosses the plane). */
+    *delta = c->c_rs - (1.0 - f) / G;
     for (int a = 0; a < 3; ++a) {
         xcm[a] = xcw[a] + q * g[a];
-        d += (xcm[a] - xcw[a]) * (xcm[a] - xcw[a]);
-    }
-    d = sqrt(d);
-    *delta = c->c_rs - d;
-    for (int a = 0; a < 3; ++a) {
-        nrm[a] = (xcm[a] - xcw[a]) / d;
+        nrm[a] = g[a] / G;
         xcp[a] = xcw[a] + 0.5 * *delta * nrm[a];
     }
     return *delta > 0.0;

@@ -38,7 +38,9 @@ class lbm_config(C.Structure):
                 ("tau", C.c_double), ("rho0", C.c_double), ("g_fluid", C.c_double * 3),
                 ("g_particle", C.c_double * 3), ("storage", C.c_int32), ("bc", C.c_int32),
                 ("n_sub", C.c_int32), ("counter_force", C.c_int32), ("quad_h", C.c_double),
-                ("fp16_scale", C.c_float), ("reserved", C.c_int32)]
+                ("fp16_scale", C.c_float), ("reserved", C.c_int32),
+                ("contact_rs", C.c_double), ("contact_kn", C.c_double), ("contact_en", C.c_double),
+                ("contact_mu", C.c_double)]
 
 
 class lbm_particle(C.Structure):
@@ -56,7 +58,8 @@ class lbm_particle_state(C.Structure):
 EXPORTS = ["lbm_arena_bytes", "lbm_init", "metaball_flag", "lbm_step", "particle_forces", "refill",
            "lbm_get_macros", "lbm_get_populations", "lbm_set_populations", "lbm_get_flags",
            "lbm_get_links", "lbm_get_particles", "lbm_set_particles", "lbm_get_gfluid",
-           "lbm_timing_enable", "lbm_timing_read", "lbm_nr_stats", "lbm_sync", "lbm_destroy",
+           "lbm_timing_enable", "lbm_timing_read", "lbm_nr_stats", "lbm_contact_stats", "lbm_sync",
+           "lbm_destroy",
            "lbm_last_error"]
 
 _lib = None
@@ -91,6 +94,7 @@ def lib():
         L.lbm_timing_enable.argtypes = [vp, C.c_int32]
         L.lbm_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_nr_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.lbm_contact_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_sync.argtypes = [vp]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
@@ -121,6 +125,10 @@ def make_config(cfg) -> lbm_config:
     c.counter_force = int(cfg.counter_force)
     c.quad_h = float(cfg.quad_h)
     c.fp16_scale = float(getattr(cfg, "fp16_scale", 0.0))
+    c.contact_rs = float(getattr(cfg, "contact_rs", 1.0))
+    c.contact_kn = float(getattr(cfg, "contact_kn", 0.0))
+    c.contact_en = float(getattr(cfg, "contact_en", 0.5))
+    c.contact_mu = float(getattr(cfg, "contact_mu", 0.5))
     return c
 
 
@@ -278,6 +286,12 @@ class Simulation:
         """(link fractions solved, Newton/bisection iterations) since the last call."""
         a, b = C.c_int64(0), C.c_int64(0)
         _check(lib().lbm_nr_stats(self._ctx, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
+
+    def contact_stats(self):
+        """(contacts resolved, failed contact iterations) since initialisation."""
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(lib().lbm_contact_stats(self._ctx, C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)
 
     def timing(self, on: bool = True):

@@ -160,6 +160,8 @@ struct Plan {
     size_t off_A, off_B, off_own[3], off_skip[2], off_stamp, off_P, off_part, off_first, off_dims,
         off_pfb, off_bcnt, off_boff, off_loff, off_lnode, off_ldo, off_lq, off_lpart, off_special,
         off_cnt, total;
+    bool contact;
+    size_t off_pairF, off_pairTi, off_pairTj, off_wallF, off_wallT, off_xiP, off_xiW;
 };
 
 struct HostParticle {
@@ -179,6 +181,12 @@ lbm_status validate_config(const lbm_config *c) {
     if (c->bc < 0 || c->bc > 1) return fail(LBM_E_INVALID, "unknown boundary rule %d", c->bc);
     if (c->n_sub < 1) return fail(LBM_E_INVALID, "n_sub must be >= 1");
     if (!(c->quad_h > 0) || !std::isfinite(c->quad_h)) return fail(LBM_E_INVALID, "quad_h must be > 0");
+    if (c->contact_kn < 0.0 || !std::isfinite(c->contact_kn)) return fail(LBM_E_INVALID, "contact_kn must be >= 0");
+    if (c->contact_kn > 0.0) {
+        if (!(c->contact_rs > 0.0) || !std::isfinite(c->contact_rs)) return fail(LBM_E_INVALID, "contact_rs must be > 0");
+        if (!(c->contact_en > 0.0 && c->contact_en <= 1.0)) return fail(LBM_E_INVALID, "contact_en must be in (0, 1]");
+        if (!(c->contact_mu >= 0.0) || !std::isfinite(c->contact_mu)) return fail(LBM_E_INVALID, "contact_mu must be >= 0");
+    }
     if (c->storage == 1 && c->fp16_scale != 0.f) {
         int e;
         const float m = std::frexp(c->fp16_scale, &e);
@@ -276,6 +284,15 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     // per-chunk, per-body partial momentum sums: chunk + body < cap/256 + 1 + np
     pl.off_lpart = take(48 * ((size_t)pl.link_cap / 256 + 2 + np));
     pl.off_special = take(4 * (size_t)std::max(pl.special_cap, 1));
+    pl.contact = c->contact_kn > 0.0 && np > 0;
+    const size_t npp = pl.contact ? (size_t)np * np : 1, npw = pl.contact ? (size_t)np * 6 : 1;
+    pl.off_pairF = take(24 * npp);
+    pl.off_pairTi = take(24 * npp);
+    pl.off_pairTj = take(24 * npp);
+    pl.off_wallF = take(24 * npw);
+    pl.off_wallT = take(24 * npw);
+    pl.off_xiP = take(24 * npp);
+    pl.off_xiW = take(24 * npw);
     pl.off_cnt = take(sizeof(Counters));
     pl.total = o;
     return LBM_OK;
@@ -301,6 +318,7 @@ struct lbm_ctx {
     uint32_t *l_node, *l_do, *special;
     double *l_q, *lpart;
     Counters *cnt;
+    ContactBufs cb;
     hipStream_t aux;              // second stream: link build overlapped with stream-collide
     hipEvent_t ev_main, ev_flags, ev_links;
     bool pending_refill;
@@ -325,7 +343,7 @@ StepArgs base_args(lbm_ctx *c) {
     a.part_first_blk = c->part_first_blk;
     a.blk_cnt = c->blk_cnt; a.blk_off = c->blk_off; a.l_off = c->l_off;
     a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.part = c->lpart;
-    a.special = c->special; a.cnt = c->cnt;
+    a.special = c->special; a.cnt = c->cnt; a.cb = c->cb;
     return a;
 }
 
@@ -427,6 +445,14 @@ static lbm_status prepare(const lbm_config *cfg, int32_t n_p, const lbm_particle
             if (!((cfg->periodic >> a) & 1u) && (d.X[a] - d.rb < 0.0 || d.X[a] + d.rb > L[a] - 1.0))
                 return fail(LBM_E_INVALID, "particle %d: bounding sphere crosses a wall on axis %d", p, a);
     }
+    if (cfg->contact_kn > 0.0) {
+        if (n_p > 1024) return fail(LBM_E_INVALID, "contact supports at most 1024 particles");
+        for (int p = 0; p < n_p; ++p) {
+            double sk = 0;
+            for (int i = 0; i < parts[p].n_cp; ++i) sk += parts[p].cp_k[i];
+            if (!(cfg->contact_rs < std::sqrt(sk))) return fail(LBM_E_INVALID, "particle %d: contact_rs >= sqrt(sum k)", p);
+        }
+    }
     if ((s = make_plan(cfg, n_p, rb, *pl))) return s;
     for (int p = 0; p < n_p; ++p) {
         DevParticle &d = (*hp)[p];
@@ -482,6 +508,10 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->l_q = (double *)(b + pl.off_lq); c->lpart = (double *)(b + pl.off_lpart);
     c->special = (uint32_t *)(b + pl.off_special);
     c->cnt = (Counters *)(b + pl.off_cnt);
+    c->cb.pairF = (double *)(b + pl.off_pairF); c->cb.pairTi = (double *)(b + pl.off_pairTi);
+    c->cb.pairTj = (double *)(b + pl.off_pairTj); c->cb.wallF = (double *)(b + pl.off_wallF);
+    c->cb.wallT = (double *)(b + pl.off_wallT); c->cb.xiP = (double *)(b + pl.off_xiP);
+    c->cb.xiW = (double *)(b + pl.off_xiW);
     c->aux = nullptr;
     c->ev_main = c->ev_flags = c->ev_links = nullptr;
     c->timing = false;
@@ -510,6 +540,8 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
         p.scale = cfg->fp16_scale != 0.f ? cfg->fp16_scale : 1024.f;
         p.inv_scale = 1.f / p.scale;
     }
+    p.contact = pl.contact ? 1 : 0;
+    p.c_rs = cfg->contact_rs; p.c_kn = cfg->contact_kn; p.c_en = cfg->contact_en; p.c_mu = cfg->contact_mu;
     p.link_cap = pl.link_cap;
     p.special_cap = pl.special_cap;
     p.region_blocks = pl.region_blocks;
@@ -538,6 +570,12 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     HIPCHK_C(hipMemcpyAsync(c->l_off, zeros.data(), 4 * (n_p + 1), hipMemcpyHostToDevice, c->stream));
     Counters zc{};
     HIPCHK_C(hipMemcpyAsync(c->cnt, &zc, sizeof zc, hipMemcpyHostToDevice, c->stream));
+    if (pl.contact) {  // tangential springs start relaxed
+        std::vector<double> z((size_t)n_p * n_p * 3, 0.0);
+        HIPCHK_C(hipMemcpyAsync(c->cb.xiP, z.data(), 24 * (size_t)n_p * n_p, hipMemcpyHostToDevice, c->stream));
+        HIPCHK_C(hipMemcpyAsync(c->cb.xiW, z.data(), 24 * (size_t)n_p * 6, hipMemcpyHostToDevice, c->stream));
+        HIPCHK_C(hipStreamSynchronize(c->stream));
+    }
     HIPCHK_C(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIPCHK_C(hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming));
     HIPCHK_C(hipEventCreateWithFlags(&c->ev_flags, hipEventDisableTiming));
@@ -895,6 +933,17 @@ lbm_status lbm_nr_stats(lbm_ctx *c, int64_t *links, int64_t *iterations) {
     if (iterations) *iterations = (int64_t)h.nr_iters;
     const unsigned long long z[2] = {0ull, 0ull};
     HIPCHK(hipMemcpy(&c->cnt->nr_iters, z, sizeof z, hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status lbm_contact_stats(lbm_ctx *c, int64_t *contacts, int64_t *failures) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    Counters h;
+    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+    if (contacts) *contacts = (int64_t)h.n_contacts;
+    if (failures) *failures = (int64_t)h.n_contact_fail;
     return LBM_OK;
 }
 

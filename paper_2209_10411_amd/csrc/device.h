@@ -39,6 +39,7 @@ struct DevParticle {
     int half;                       // region half-width (ceil(rb) + PAD)
     int lo[3];                      // region origin (unwrapped), set from X each pose change
     int full[3];                    // 1: the region spans a whole periodic axis
+    double X0[3];                   // centroid at the start of the current step
 };
 
 // Small device-side counters, reset and read by the host at sync points.
@@ -52,6 +53,8 @@ struct Counters {
     int pad[2];
     unsigned long long nr_iters;  // Newton/bisection iterations of the link fractions
     unsigned long long nr_links;  // link fractions solved
+    unsigned long long n_contacts;      // contacts resolved (pairs + walls, per sub-step)
+    unsigned long long n_contact_fail;  // contact iterations that did not converge
 };
 
 // Per-context constants, passed to kernels by value.
@@ -71,6 +74,20 @@ struct Params {
     double gp[3];               // particle gravity
     int link_cap, special_cap;
     int region_blocks;          // blocks of the region kernels
+    int contact;                // contact enabled
+    double c_rs, c_kn, c_en, c_mu;
+};
+
+// Per-sub-step contact results and tangential springs (arena), for bodies
+// i < j at index i * np + j and walls at 6 * i + 2 * axis + side.
+struct ContactBufs {
+    double *pairF;   // [np*np][3] force on i
+    double *pairTi;  // [np*np][3] torque on i
+    double *pairTj;  // [np*np][3] torque on j
+    double *wallF;   // [np*6][3]
+    double *wallT;   // [np*6][3]
+    double *xiP;     // [np*np][3] tangential springs, pairs
+    double *xiW;     // [np*6][3] tangential springs, walls
 };
 
 // Region block map: block b of a region kernel works on particle part[b],

@@ -4,8 +4,10 @@
 //   k_links          one thread per cut link: bounce-back value (simple or the
 //                    paper's interpolated rule, sec. 2.3.2 Eqs. eqneq1-neqd)
 //                    and the link's momentum exchange in FP64
-//   k_reduce_rigid   one block per particle: fixed-order FP64 sum of the link
-//                    momenta, then the Newton-Euler update (sec. 2.3.1)
+//   k_reduce         one block per particle: fixed-order FP64 sum of the link
+//                    momenta
+//   k_rigid          one block: sphero-metaball contacts and the Newton-Euler
+//                    update of all particles over the sub-steps (sec. 2.3.1)
 //   k_region_*       per-particle cubes: metaball flags (sec. 2.1), node
 //                    classes and the list of nodes needing the slow path
 //   k_bulk           every plain fluid node: pull-stream + BGK/Guo collide,
@@ -302,8 +304,8 @@ __device__ __forceinline__ float collide_lane(float d, int i, float dr, float jx
 // incoming population on the link -- simple bounce-back, or the paper's
 // interpolated rule with the moments of x_f and x_f + e_i in FP64 -- and
 // leaves it in B for the boundary-node pass, then the link's momentum
-// exchange  dP = (e_ib - u_w) f+_ib(x_f) - (e_i - u_w) f_i(x_f, t+1),
-// dT = (x_w - X) x dP.  Each chunk of 256 links sums its links per body
+// exchange  dP = (e_ib - u_w) f+_ib(x_f) - (e_i - u_w) f_i(x_f, t+1) with
+// both populations relative to w rho0, dT = (x_w - X) x dP.  Each chunk of 256 links sums its links per body
 // segment (fixed segmented tree) into part[chunk + body] (deterministic).
 template <int S>
 __global__ __launch_bounds__(256) void k_links(Params p, const typename Store<S>::T *__restrict__ A,
@@ -377,9 +379,13 @@ __global__ __launch_bounds__(256) void k_links(Params p, const typename Store<S>
                 val = feq64d(ib, rf, ud) + fb - feq64d(ib, rf, uf) + mw;
             }
             Store<S>::st(B, (long long)i * p.N + n, (float)(val - w * p.rho0), p.scale);
-            dP[0] = (c_ex[ib] - uw[0]) * fb - (c_ex[i] - uw[0]) * val;
-            dP[1] = (c_ey[ib] - uw[1]) * fb - (c_ey[i] - uw[1]) * val;
-            dP[2] = (c_ez[ib] - uw[2]) * fb - (c_ez[i] - uw[2]) * val;
+            // exchanged populations relative to w rho0: the uniform reference
+            // pressure exerts no force (its per-link terms cancel over a closed
+            // surface; a surface touching a wall has no links there)
+            const double fbd = fb - w * p.rho0, vald = val - w * p.rho0;
+            dP[0] = (c_ex[ib] - uw[0]) * fbd - (c_ex[i] - uw[0]) * vald;
+            dP[1] = (c_ey[ib] - uw[1]) * fbd - (c_ey[i] - uw[1]) * vald;
+            dP[2] = (c_ez[ib] - uw[2]) * fbd - (c_ez[i] - uw[2]) * vald;
             cross3(r, dP, dT);
         }
         double v6[6] = {dP[0], dP[1], dP[2], dT[0], dT[1], dT[2]};
@@ -436,61 +442,18 @@ __device__ void refresh_pose(const Params &p, DevParticle &P) {
     for (int a = 0; a < 3; ++a) P.lo[a] = P.full[a] ? 0 : (int)floor(P.X[a]) - P.half;
 }
 
-// Semi-implicit Euler over n_sub sub-steps with the hydrodynamic load held;
-// spin by the body-frame Euler equation with the full inertia tensor; the
-// attitude advances by the exact rotation of the sub-step's spin.
-__device__ void rigid_update(const Params &p, DevParticle &P) {
-    const double dt = 1.0 / p.n_sub;
-    for (int s = 0; s < p.n_sub; ++s) {
-        if (P.mode == 1) {
-            const double phi[3] = {P.w[0] * dt, P.w[1] * dt, P.w[2] * dt};
-            double dq[4];
-            for (int a = 0; a < 3; ++a) P.X[a] += P.v[a] * dt;
-            quat_of_rotvec(phi, dq);
-            quat_mul(dq, P.q, P.q);
-        } else {
-            for (int a = 0; a < 3; ++a) {
-                const double Ft = P.F[a] + (P.m - p.rho0 * P.V) * p.gp[a];
-                P.v[a] += Ft / P.m * dt;
-                P.X[a] += P.v[a] * dt;
-            }
-            double R[9], Tb[3], wb[3], Iw[3], gy[3];
-            quat_rot(P.q, R);
-            for (int a = 0; a < 3; ++a) {
-                Tb[a] = R[a] * P.T[0] + R[3 + a] * P.T[1] + R[6 + a] * P.T[2];
-                wb[a] = R[a] * P.w[0] + R[3 + a] * P.w[1] + R[6 + a] * P.w[2];
-            }
-            for (int a = 0; a < 3; ++a) Iw[a] = P.I[3 * a] * wb[0] + P.I[3 * a + 1] * wb[1] + P.I[3 * a + 2] * wb[2];
-            cross3(wb, Iw, gy);
-            const double rhs[3] = {Tb[0] - gy[0], Tb[1] - gy[1], Tb[2] - gy[2]};
-            for (int a = 0; a < 3; ++a)
-                wb[a] += dt * (P.Iinv[3 * a] * rhs[0] + P.Iinv[3 * a + 1] * rhs[1] + P.Iinv[3 * a + 2] * rhs[2]);
-            for (int a = 0; a < 3; ++a) P.w[a] = R[3 * a] * wb[0] + R[3 * a + 1] * wb[1] + R[3 * a + 2] * wb[2];
-            const double phi[3] = {wb[0] * dt, wb[1] * dt, wb[2] * dt};
-            double dq[4];
-            quat_of_rotvec(phi, dq);
-            quat_mul(P.q, dq, P.q);
-        }
-        const double nq = sqrt(P.q[0] * P.q[0] + P.q[1] * P.q[1] + P.q[2] * P.q[2] + P.q[3] * P.q[3]);
-        for (int a = 0; a < 4; ++a) P.q[a] /= nq;
-    }
-}
-
 // One block per particle: fixed-order FP64 sum of the link momenta (chunk
-// partials from k_links), then the rigid-body update (move != 0) on an LDS
-// copy of the particle record.  Block 0 also clears the per-step counters and
-// advances the classification tag.
-__global__ __launch_bounds__(256) void k_reduce_rigid(Params p, DevParticle *__restrict__ P,
-                                                      const int *__restrict__ l_off,
-                                                      const double *__restrict__ part,
-                                                      Counters *__restrict__ cnt, int move) {
+// partials from k_links) into the particle's hydrodynamic force and torque.
+// Block 0 also clears the per-step counters and advances the classification
+// tag.
+__global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restrict__ P,
+                                                const int *__restrict__ l_off,
+                                                const double *__restrict__ part,
+                                                Counters *__restrict__ cnt) {
     __shared__ double red[6][256];
-    __shared__ DevParticle sp;
     const int pi = blockIdx.x, t = threadIdx.x;
     if (pi == 0 && t == 0) { cnt->n_special = 0; cnt->n_refill = 0; cnt->n_solid = 0; cnt->tag += 1u; }
     if (pi >= p.np) return;
-    constexpr int W = sizeof(DevParticle) / 4;
-    for (int k = t; k < W; k += 256) ((int *)&sp)[k] = ((const int *)&P[pi])[k];
     double s[6] = {0, 0, 0, 0, 0, 0};
     const int a = max(0, l_off[pi]), b = min(l_off[pi + 1], p.link_cap);
     if (b > a)  // chunks of 256 links holding this body's links; slot = chunk + body
@@ -503,30 +466,368 @@ __global__ __launch_bounds__(256) void k_reduce_rigid(Params p, DevParticle *__r
             for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + h];
         __syncthreads();
     }
-    if (t == 0) {
-        for (int c = 0; c < 3; ++c) { sp.F[c] = red[c][0]; sp.T[c] = red[3 + c][0]; }
-        if (move) {
-            const double X0[3] = {sp.X[0], sp.X[1], sp.X[2]};
-            rigid_update(p, sp);
-            double d2 = 0.0;
-            bool finite = true;
-            for (int c = 0; c < 3; ++c) {
-                d2 += (sp.X[c] - X0[c]) * (sp.X[c] - X0[c]);
-                finite = finite && isfinite(sp.X[c]) && isfinite(sp.v[c]) && isfinite(sp.w[c]);
-            }
-            if (!finite) atomicOr(&cnt->err, ERR_NONFINITE);
-            else if (d2 > 1.0) atomicOr(&cnt->err, ERR_FAST_PARTICLE);
-            const int L[3] = {p.nx, p.ny, p.nz};
-            for (int c = 0; c < 3; ++c)  // keep the centroid inside a periodic box
-                if ((p.periodic >> c) & 1u) {
-                    if (sp.X[c] < 0.0) sp.X[c] += L[c];
-                    else if (sp.X[c] >= L[c]) sp.X[c] -= L[c];
-                }
-            refresh_pose(p, sp);
+    if (t == 0)
+        for (int c = 0; c < 3; ++c) { P[pi].F[c] = red[c][0]; P[pi].T[c] = red[3 + c][0]; }
+}
+
+// ------------------------------------------------------ contact (sec. 2.3.1)
+__device__ bool inv3d(const double A[9], double B[9]) {
+    const double d = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(fabs(d) > 0.0)) return false;
+    B[0] = (A[4] * A[8] - A[5] * A[7]) / d; B[1] = (A[2] * A[7] - A[1] * A[8]) / d;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) / d; B[3] = (A[5] * A[6] - A[3] * A[8]) / d;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) / d; B[5] = (A[2] * A[3] - A[0] * A[5]) / d;
+    B[6] = (A[3] * A[7] - A[4] * A[6]) / d; B[7] = (A[1] * A[6] - A[0] * A[7]) / d;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) / d;
+    return true;
+}
+
+// Zoomed internal metaball of the sphero-metaball: the body shrunk about its
+// centroid by s = 1 - R_s / sqrt(sum k) (points X + s (p - X), weights
+// s^2 k), translated by 'shift' (periodic image).
+__device__ int inner_metaball(const Params &p, const DevParticle &P, const double shift[3],
+                              double cp[MAXCP][3], double k[MAXCP]) {
+    double sk = 0.0;
+    for (int i = 0; i < P.n_cp; ++i) sk += P.k[i];
+    const double s = 1.0 - p.c_rs / sqrt(sk);
+    if (!(s > 0.0)) return -1;
+    for (int i = 0; i < P.n_cp; ++i) {
+        for (int a = 0; a < 3; ++a) cp[i][a] = P.X[a] + shift[a] + s * (P.cpl[i][a] - P.X[a]);
+        k[i] = s * s * P.k[i];
+    }
+    return P.n_cp;
+}
+
+// f = sum k/r^2, gradient sum -2k d/r^4, Hessian sum 2k (4 d d^T/r^6 - I/r^4).
+__device__ void mb_eval3(int n, const double cp[MAXCP][3], const double k[MAXCP], const double x[3],
+                         double &f, double g[3], double H[9]) {
+    f = 0.0;
+    for (int a = 0; a < 3; ++a) g[a] = 0.0;
+    for (int a = 0; a < 9; ++a) H[a] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double d[3] = {x[0] - cp[i][0], x[1] - cp[i][1], x[2] - cp[i][2]};
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const double r4 = r2 * r2, r6 = r4 * r2;
+        f += k[i] / r2;
+        for (int a = 0; a < 3; ++a) {
+            g[a] += -2.0 * k[i] * d[a] / r4;
+            for (int b = 0; b < 3; ++b) H[3 * a + b] += 2.0 * k[i] * (4.0 * d[a] * d[b] / r6 - (a == b ? 1.0 : 0.0) / r4);
         }
     }
+}
+
+// Contact of two bodies (Eqs. CM_coreF, eq:grad, eq:cp, eq:contactprop):
+// Newton-Raphson for the stationary point x_m of f0 + f1 between the inner
+// metaballs from the point of the centroid segment dividing it in the ratio
+// (K0/K1)^(1/3); Taylor projections x_c = x_m + q grad f, q = (1 - f)/|grad f|^2;
+// n from body 1 to body 0; delta = 2 R_s - |x_c0 - x_c1| (signed form); contact
+// point in the middle of the overlap.  1 = contact, 0 = none, -1 = iteration
+// failed.
+__device__ int pair_geometry(const Params &p, const DevParticle &P0, const DevParticle &P1, double xcp[3],
+                             double nrm[3], double &delta) {
+    double d01[3] = {P1.X[0] - P0.X[0], P1.X[1] - P0.X[1], P1.X[2] - P0.X[2]};
+    min_image(p, d01);
+    const double sh0[3] = {0.0, 0.0, 0.0};
+    const double sh1[3] = {P0.X[0] + d01[0] - P1.X[0], P0.X[1] + d01[1] - P1.X[1], P0.X[2] + d01[2] - P1.X[2]};
+    double cp0[MAXCP][3], k0[MAXCP], cp1[MAXCP][3], k1[MAXCP];
+    const int n0 = inner_metaball(p, P0, sh0, cp0, k0), n1 = inner_metaball(p, P1, sh1, cp1, k1);
+    if (n0 < 0 || n1 < 0) return -1;
+    double K0 = 0.0, K1 = 0.0;
+    for (int i = 0; i < n0; ++i) K0 += k0[i];
+    for (int i = 0; i < n1; ++i) K1 += k1[i];
+    const double rho = cbrt(K0 / K1);
+    double xm[3];
+    for (int a = 0; a < 3; ++a) xm[a] = P0.X[a] + d01[a] * rho / (1.0 + rho);
+    const double L = sqrt(d01[0] * d01[0] + d01[1] * d01[1] + d01[2] * d01[2]);
+    bool ok = false;
+    for (int it = 0; it < 60; ++it) {
+        double f0, g0[3], H0[9], f1, g1[3], H1[9], H[9], Hi[9], dx[3];
+        mb_eval3(n0, cp0, k0, xm, f0, g0, H0);
+        mb_eval3(n1, cp1, k1, xm, f1, g1, H1);
+        for (int a = 0; a < 9; ++a) H[a] = H0[a] + H1[a];
+        if (!inv3d(H, Hi)) break;
+        double st = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            dx[a] = -(Hi[3 * a] * (g0[0] + g1[0]) + Hi[3 * a + 1] * (g0[1] + g1[1]) + Hi[3 * a + 2] * (g0[2] + g1[2]));
+            st += dx[a] * dx[a];
+        }
+        st = sqrt(st);
+        if (st > 0.25 * L)
+            for (int a = 0; a < 3; ++a) dx[a] *= 0.25 * L / st;
+        for (int a = 0; a < 3; ++a) xm[a] += dx[a];
+        if (st < 1e-12 * (1.0 + L)) { ok = true; break; }
+    }
+    if (!ok) return -1;
+    double f0, g0[3], H0[9], f1, g1[3], H1[9];
+    mb_eval3(n0, cp0, k0, xm, f0, g0, H0);
+    mb_eval3(n1, cp1, k1, xm, f1, g1, H1);
+    const double G0 = sqrt(g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2]);
+    const double G1 = sqrt(g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
+    if (!(G0 > 0.0 && G1 > 0.0)) return -1;
+    // grad f0 = -grad f1 at x_m: x_c0 - x_c1 lies along n = grad f0/|grad f0|
+    // with signed length (1 - f0)/|grad f0| + (1 - f1)/|grad f1| (< 0 when the
+    // inner bodies overlap)
+    const double q0 = (1.0 - f0) / (G0 * G0);
+    delta = 2.0 * p.c_rs - ((1.0 - f0) / G0 + (1.0 - f1) / G1);
+    for (int a = 0; a < 3; ++a) {
+        nrm[a] = g0[a] / G0;
+        xcp[a] = xm[a] + q0 * g0[a] - (p.c_rs - 0.5 * delta) * nrm[a];
+    }
+    return delta > 0.0 ? 1 : 0;
+}
+
+// Contact with the halfway wall normal to axis ax (side 0 at -1/2, side 1 at
+// L - 1/2) (Eqs. metawallcp, contactprop2): stationary point x_cw of f on the
+// wall plane by 2-D Newton-Raphson from the projection of the control point
+// where f on the plane is largest, x_cm =
+// x_cw + q grad f, n = (x_cm - x_cw)/|...|, delta = R_s - |x_cm - x_cw|,
+// x_cp = x_cw + delta/2 n.
+__device__ int wall_geometry(const Params &p, const DevParticle &P, int ax, int side, double xcp[3],
+                             double nrm[3], double &delta) {
+    const int L = ax == 0 ? p.nx : (ax == 1 ? p.ny : p.nz);
+    const double wpos = side ? L - 0.5 : -0.5;
+    if (fabs(P.X[ax] - wpos) > P.rb + p.c_rs) return 0;
+    const double sh[3] = {0.0, 0.0, 0.0};
+    double cp[MAXCP][3], k[MAXCP];
+    const int n = inner_metaball(p, P, sh, cp, k);
+    if (n < 0) return -1;
+    const int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+    // start at the projection of the control point where f on the plane is largest
+    double xcw[3] = {P.X[0], P.X[1], P.X[2]};
+    double best = -1.0;
+    for (int i = 0; i < n; ++i) {
+        double y[3] = {cp[i][0], cp[i][1], cp[i][2]}, fy, gy[3], Hy[9];
+        y[ax] = wpos;
+        mb_eval3(n, cp, k, y, fy, gy, Hy);
+        if (fy > best) {
+            best = fy;
+            for (int a = 0; a < 3; ++a) xcw[a] = y[a];
+        }
+    }
+    bool ok = false;
+    for (int it = 0; it < 60; ++it) {
+        double f, g[3], H[9];
+        mb_eval3(n, cp, k, xcw, f, g, H);
+        const double h11 = H[3 * a1 + a1], h12 = H[3 * a1 + a2], h22 = H[3 * a2 + a2];
+        const double det = h11 * h22 - h12 * h12;
+        if (!(fabs(det) > 0.0)) break;
+        double d1 = -(h22 * g[a1] - h12 * g[a2]) / det, d2 = -(-h12 * g[a1] + h11 * g[a2]) / det;
+        const double st = sqrt(d1 * d1 + d2 * d2);
+        if (st > 0.25 * P.rb) { d1 *= 0.25 * P.rb / st; d2 *= 0.25 * P.rb / st; }
+        xcw[a1] += d1;
+        xcw[a2] += d2;
+        if (st < 1e-12 * (1.0 + P.rb)) { ok = true; break; }
+    }
+    if (!ok) return -1;
+    double f, g[3], H[9];
+    mb_eval3(n, cp, k, xcw, f, g, H);
+    const double G = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (!(G > 0.0)) return -1;
+    // grad f is normal to the plane at x_cw and points into the body: signed
+    // length of x_cm - x_cw along n = grad f/|grad f| is (1 - f)/|grad f|
+    delta = p.c_rs - (1.0 - f) / G;
+    for (int a = 0; a < 3; ++a) {
+        nrm[a] = g[a] / G;
+        xcp[a] = xcw[a] + 0.5 * delta * nrm[a];
+    }
+    return delta > 0.0 ? 1 : 0;
+}
+
+// Linear spring-dashpot (sec. 2.3.1): F_n = k_n delta + eta_n (v_j - v_i).n,
+// eta_n = 2 zeta sqrt(m_eff k_n) with zeta from the restitution; tangential
+// spring xi (kept in the tangent plane) advanced by the tangential relative
+// velocity, F_t = k_t xi + eta_n u_t, k_t = 2/7 k_n, capped at mu |F_n|.
+__device__ void spring_dashpot(const Params &p, double meff, const double n[3], double delta,
+                               const double vrel[3], double xi[3], double dt, double F[3]) {
+    const double le = log(p.c_en);
+    const double zeta = -le / sqrt(M_PI * M_PI + le * le);
+    const double etan = 2.0 * zeta * sqrt(meff * p.c_kn), kt = 2.0 / 7.0 * p.c_kn;
+    const double vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    const double Fn = p.c_kn * delta + etan * vn;
+    const double xn = xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2];
+    double Ft[3], ftn = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double ut = vrel[a] - vn * n[a];
+        xi[a] = xi[a] - xn * n[a] + ut * dt;
+        Ft[a] = kt * xi[a] + etan * ut;
+        ftn += Ft[a] * Ft[a];
+    }
+    ftn = sqrt(ftn);
+    const double cap = p.c_mu * fabs(Fn);
+    if (ftn > cap && ftn > 0.0)
+        for (int a = 0; a < 3; ++a) {
+            Ft[a] *= cap / ftn;
+            xi[a] = Ft[a] / kt;
+        }
+    for (int a = 0; a < 3; ++a) F[a] = Fn * n[a] + Ft[a];
+}
+
+__device__ void point_velocity(const Params &p, const DevParticle &P, const double x[3], double v[3],
+                               double r[3]) {
+    r[0] = x[0] - P.X[0]; r[1] = x[1] - P.X[1]; r[2] = x[2] - P.X[2];
+    min_image(p, r);
+    double wr[3];
+    cross3(P.w, r, wr);
+    for (int a = 0; a < 3; ++a) v[a] = P.v[a] + wr[a];
+}
+
+// One sub-step dt of the Newton-Euler update of a body under total force F
+// and torque T (hydrodynamic + contact): semi-implicit Euler for v, X;
+// body-frame Euler equation with the full inertia tensor for the spin; exact
+// rotation of the sub-step spin for the attitude.  Kinematic bodies move with
+// their given v, w.
+__device__ void body_substep(const Params &p, DevParticle &P, const double F[3], const double T[3], double dt) {
+    if (P.mode == 1) {
+        const double phi[3] = {P.w[0] * dt, P.w[1] * dt, P.w[2] * dt};
+        double dq[4];
+        for (int a = 0; a < 3; ++a) P.X[a] += P.v[a] * dt;
+        quat_of_rotvec(phi, dq);
+        quat_mul(dq, P.q, P.q);
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            const double Ft = F[a] + (P.m - p.rho0 * P.V) * p.gp[a];
+            P.v[a] += Ft / P.m * dt;
+            P.X[a] += P.v[a] * dt;
+        }
+        double R[9], Tb[3], wb[3], Iw[3], gy[3];
+        quat_rot(P.q, R);
+        for (int a = 0; a < 3; ++a) {
+            Tb[a] = R[a] * T[0] + R[3 + a] * T[1] + R[6 + a] * T[2];
+            wb[a] = R[a] * P.w[0] + R[3 + a] * P.w[1] + R[6 + a] * P.w[2];
+        }
+        for (int a = 0; a < 3; ++a) Iw[a] = P.I[3 * a] * wb[0] + P.I[3 * a + 1] * wb[1] + P.I[3 * a + 2] * wb[2];
+        cross3(wb, Iw, gy);
+        const double rhs[3] = {Tb[0] - gy[0], Tb[1] - gy[1], Tb[2] - gy[2]};
+        for (int a = 0; a < 3; ++a)
+            wb[a] += dt * (P.Iinv[3 * a] * rhs[0] + P.Iinv[3 * a + 1] * rhs[1] + P.Iinv[3 * a + 2] * rhs[2]);
+        for (int a = 0; a < 3; ++a) P.w[a] = R[3 * a] * wb[0] + R[3 * a + 1] * wb[1] + R[3 * a + 2] * wb[2];
+        const double phi[3] = {wb[0] * dt, wb[1] * dt, wb[2] * dt};
+        double dq[4];
+        quat_of_rotvec(phi, dq);
+        quat_mul(P.q, dq, P.q);
+    }
+    const double nq = sqrt(P.q[0] * P.q[0] + P.q[1] * P.q[1] + P.q[2] * P.q[2] + P.q[3] * P.q[3]);
+    for (int a = 0; a < 4; ++a) P.q[a] /= nq;
+    refresh_pose(p, P);
+}
+
+// All bodies over one lattice time unit in one block: n_sub sub-steps, each
+// with the contact forces of every body pair (threads over pairs) and every
+// walled face at the sub-step's poses, then each body advanced by its
+// hydrodynamic load (held) plus its contacts summed in a fixed order
+// (partners by index, then faces).  Finally end-of-step checks, periodic
+// wrap of the centroid and the region origin.
+__global__ __launch_bounds__(256) void k_rigid(Params p, DevParticle *__restrict__ P, ContactBufs cb,
+                                               Counters *__restrict__ cnt) {
+    const int t = threadIdx.x, np = p.np;
+    for (int q = t; q < np; q += 256)
+        for (int a = 0; a < 3; ++a) P[q].X0[a] = P[q].X[a];
     __syncthreads();
-    for (int k = t; k < W; k += 256) ((int *)&P[pi])[k] = ((const int *)&sp)[k];
+    const double dt = 1.0 / p.n_sub;
+    for (int s = 0; s < p.n_sub; ++s) {
+        if (p.contact) {
+            for (int q = t; q < np * np; q += 256) {
+                const int i = q / np, j = q - i * np;
+                if (j <= i) continue;
+                double F[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, Tj[3] = {0, 0, 0};
+                double *xi = cb.xiP + 3ll * q;
+                const DevParticle &Pi = P[i], &Pj = P[j];
+                if (!(Pi.mode == 1 && Pj.mode == 1)) {
+                    double d[3] = {Pj.X[0] - Pi.X[0], Pj.X[1] - Pi.X[1], Pj.X[2] - Pi.X[2]};
+                    min_image(p, d);
+                    int r = 0;
+                    double xcp[3], n[3], delta = 0.0;
+                    if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) <= Pi.rb + Pj.rb)
+                        r = pair_geometry(p, Pi, Pj, xcp, n, delta);
+                    if (r < 0) atomicAdd(&cnt->n_contact_fail, 1ull);
+                    if (r <= 0) {
+                        xi[0] = xi[1] = xi[2] = 0.0;
+                    } else {
+                        atomicAdd(&cnt->n_contacts, 1ull);
+                        double vi[3], vj[3], ri[3], rj[3], vrel[3];
+                        point_velocity(p, Pi, xcp, vi, ri);
+                        point_velocity(p, Pj, xcp, vj, rj);
+                        for (int a = 0; a < 3; ++a) vrel[a] = vj[a] - vi[a];
+                        const double meff = Pi.mode == 1 ? Pj.m : (Pj.mode == 1 ? Pi.m : Pi.m * Pj.m / (Pi.m + Pj.m));
+                        spring_dashpot(p, meff, n, delta, vrel, xi, dt, F);
+                        const double Fm[3] = {-F[0], -F[1], -F[2]};
+                        cross3(ri, F, Ti);
+                        cross3(rj, Fm, Tj);
+                    }
+                }
+                for (int a = 0; a < 3; ++a) {
+                    cb.pairF[3ll * q + a] = F[a];
+                    cb.pairTi[3ll * q + a] = Ti[a];
+                    cb.pairTj[3ll * q + a] = Tj[a];
+                }
+            }
+            for (int q = t; q < np * 6; q += 256) {
+                const int i = q / 6, w = q - 6 * i, ax = w >> 1, side = w & 1;
+                double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+                double *xi = cb.xiW + 3ll * q;
+                const DevParticle &Pi = P[i];
+                if (Pi.mode != 1 && !((p.periodic >> ax) & 1u)) {
+                    double xcp[3], n[3], delta = 0.0;
+                    const int r = wall_geometry(p, Pi, ax, side, xcp, n, delta);
+                    if (r < 0) atomicAdd(&cnt->n_contact_fail, 1ull);
+                    if (r <= 0) {
+                        xi[0] = xi[1] = xi[2] = 0.0;
+                    } else {
+                        atomicAdd(&cnt->n_contacts, 1ull);
+                        double vi[3], ri[3], vrel[3];
+                        point_velocity(p, Pi, xcp, vi, ri);
+                        for (int a = 0; a < 3; ++a) vrel[a] = -vi[a];
+                        spring_dashpot(p, Pi.m, n, delta, vrel, xi, dt, F);
+                        for (int a = 0; a < 3; ++a) ri[a] = xcp[a] - Pi.X[a];
+                        cross3(ri, F, T);
+                    }
+                }
+                for (int a = 0; a < 3; ++a) { cb.wallF[3ll * q + a] = F[a]; cb.wallT[3ll * q + a] = T[a]; }
+            }
+            __syncthreads();
+        }
+        for (int q = t; q < np; q += 256) {
+            DevParticle &B = P[q];
+            double F[3] = {B.F[0], B.F[1], B.F[2]}, T[3] = {B.T[0], B.T[1], B.T[2]};
+            if (p.contact) {
+                double Fc[3] = {0, 0, 0}, Tc[3] = {0, 0, 0};
+                for (int j = 0; j < np; ++j) {
+                    if (j == q) continue;
+                    if (j < q) {
+                        const long long k = (long long)j * np + q;
+                        for (int a = 0; a < 3; ++a) { Fc[a] -= cb.pairF[3 * k + a]; Tc[a] += cb.pairTj[3 * k + a]; }
+                    } else {
+                        const long long k = (long long)q * np + j;
+                        for (int a = 0; a < 3; ++a) { Fc[a] += cb.pairF[3 * k + a]; Tc[a] += cb.pairTi[3 * k + a]; }
+                    }
+                }
+                for (int w = 0; w < 6; ++w)
+                    for (int a = 0; a < 3; ++a) { Fc[a] += cb.wallF[3ll * (6 * q + w) + a]; Tc[a] += cb.wallT[3ll * (6 * q + w) + a]; }
+                for (int a = 0; a < 3; ++a) { F[a] += Fc[a]; T[a] += Tc[a]; }
+            }
+            body_substep(p, B, F, T, dt);
+        }
+        __syncthreads();
+    }
+    for (int q = t; q < np; q += 256) {
+        DevParticle &B = P[q];
+        double d2 = 0.0;
+        bool finite = true;
+        for (int c = 0; c < 3; ++c) {
+            d2 += (B.X[c] - B.X0[c]) * (B.X[c] - B.X0[c]);
+            finite = finite && isfinite(B.X[c]) && isfinite(B.v[c]) && isfinite(B.w[c]);
+        }
+        if (!finite) atomicOr(&cnt->err, ERR_NONFINITE);
+        else if (d2 > 1.0) atomicOr(&cnt->err, ERR_FAST_PARTICLE);
+        const int L[3] = {p.nx, p.ny, p.nz};
+        for (int c = 0; c < 3; ++c)  // keep the centroid inside a periodic box
+            if ((p.periodic >> c) & 1u) {
+                if (B.X[c] < 0.0) B.X[c] += L[c];
+                else if (B.X[c] >= L[c]) B.X[c] -= L[c];
+            }
+        refresh_pose(p, B);
+    }
 }
 
 __global__ void k_refresh_pose(Params p, DevParticle *P) {
@@ -925,7 +1226,8 @@ static void launch_step_kernels_t(const StepArgs &a) {
         if (p.np > 0)
             k_links<S><<<link_grid, 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.l_node, a.l_do, a.l_q,
                                                          a.part, a.cnt);
-        k_reduce_rigid<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, a.move);
+        k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt);
+        if (a.move && p.np > 0) k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
     } else if (a.phase == PHASE_FLAGS) {
         if (p.np > 0) {
             if (a.move) k_region_mark<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new);

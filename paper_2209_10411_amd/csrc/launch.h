@@ -37,6 +37,7 @@ struct StepArgs {
     double *l_q, *part;
     uint32_t *special;
     Counters *cnt;
+    ContactBufs cb;
 };
 
 void launch_phase(const StepArgs &a);

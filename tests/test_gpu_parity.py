@@ -239,3 +239,62 @@ def test_half_storage_error_vs_oracle(mdl, storage, tol):
     dx = np.abs(sim.particles()[0]["x"] - ref.particle(0)["x"]).max()
     print(f"storage {storage}: max|du|/U = {du:.2e}, |dx| = {dx:.2e}", flush=True)
     assert du < tol and dx < 1e-3
+
+
+def _compare_particles(sim, ref, cfg, tol_x, tol_v):
+    L = np.array([cfg.nx, cfg.ny, cfg.nz], float)
+    per = np.array([(cfg.periodic >> a) & 1 for a in range(3)], bool)
+    gs = sim.particles()
+    for j in range(len(cfg.particles)):
+        po = ref.particle(j)
+        dx = gs[j]["x"] - po["x"]
+        dx[per] -= L[per] * np.round(dx[per] / L[per])  # the library keeps periodic centroids in the box
+        assert np.abs(dx).max() < tol_x, (j, dx)
+        assert np.abs(gs[j]["v"] - po["v"]).max() < tol_v, (j, gs[j]["v"], po["v"])
+        assert np.abs(gs[j]["omega"] - po["omega"]).max() < tol_v
+    return max(np.abs(gs[j]["x"] - ref.particle(j)["x"]).max() for j in range(len(cfg.particles)))
+
+
+def test_contact_pair_collision(mdl):
+    """Two dense spheres driven into each other: sphero-metaball contact
+    (stationary point, Taylor projection, spring-dashpot with friction) on
+    the GPU against the oracle, through the collision and rebound."""
+    cfg = workloads.contact_pair()
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    for k in range(6):
+        sim.step(10)
+        ref.step(10)
+        compare_fields(sim, ref, du_tol=1e-4, drho_tol=1e-6, label=f"contact pair step {10 * (k + 1)}")
+        _compare_particles(sim, ref, cfg, 1e-5, 1e-5)
+    nc, nf = sim.contact_stats()
+    assert nc == ref.n_contacts and nc > 0 and nf == 0
+
+
+def test_body_lands_on_floor(mdl):
+    cfg = workloads.settle_on_floor()
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    for k in range(5):
+        sim.step(40)
+        ref.step(40)
+        compare_fields(sim, ref, du_tol=1e-4, drho_tol=1e-6, label=f"floor step {40 * (k + 1)}")
+        _compare_particles(sim, ref, cfg, 1e-5, 1e-5)
+    nc, nf = sim.contact_stats()
+    assert nc > 0 and nf == 0
+    assert abs(nc - ref.n_contacts) <= 2
+
+
+def test_periodic_suspension_small(mdl):
+    """Six bodies in a periodic box with the fluid counter-force: multi-body
+    flags (lowest index owns shared nodes), links, refills and minimum-image
+    geometry across the periodic faces."""
+    cfg = workloads.suspension_small()
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    assert np.allclose(sim.g_fluid(), ref.g_fluid, rtol=1e-12, atol=1e-18)
+    for k in range(3):
+        sim.step(20)
+        ref.step(20)
+        compare_fields(sim, ref, label=f"suspension step {20 * (k + 1)}")
+        _compare_particles(sim, ref, cfg, 1e-6, 1e-7)

@@ -257,3 +257,54 @@ def two_body(seed: int = 31, n: int = 48, nz: int = 80, bc: int = BC_IBB) -> Con
     return Config(nx=n, ny=n, nz=nz, periodic=0, tau=0.65, rho0=1.0,
                   g_particle=np.array([0.0, 0.0, -1e-4]), bc=bc, particles=bodies,
                   name=f"twobody-{n}x{n}x{nz}")
+
+
+def contact_pair(n: int = 40, v: float = 0.05, bc: int = BC_IBB) -> Config:
+    """Two dense free spheres (R = 5) driven head-on in a periodic box, contact on."""
+    bodies = []
+    for j, (x, vx) in enumerate(((n / 2 - 5.2, v), (n / 2 + 5.2, -v))):
+        bodies.append(Particle(cp_xyz=np.zeros((1, 3)), cp_k=np.array([25.0]),
+                               x=np.array([x, n / 2 + 0.6 * j, n / 2 - 0.2]),
+                               v=np.array([vx, 0.0, 0.0]), density=8.0))
+    return Config(nx=n, ny=n, nz=n, periodic=7, tau=0.7, bc=bc, n_sub=10, particles=bodies,
+                  contact_rs=1.0, contact_kn=20.0, contact_en=0.5, contact_mu=0.4, quad_h=0.25,
+                  name=f"contact-pair-{n}")
+
+
+def settle_on_floor(seed: int = 41, n: int = 32, nz: int = 28, bc: int = BC_IBB) -> Config:
+    """A 7-point body dropped just above the floor of a walled box, contact on."""
+    off, k = random_body(_rng(seed), 7, 5.0)
+    p = Particle(cp_xyz=off, cp_k=k, x=np.zeros(3), density=2.5,
+                 omega=np.array([0.0, 0.003, 0.0]), v=np.array([0.004, 0.0, -0.03]))
+    rb = p.bounding_radius()
+    p.x = np.array([n / 2, n / 2 + 0.4, rb + 0.2])
+    return Config(nx=n, ny=n, nz=nz, periodic=PERIODIC_X | PERIODIC_Y, tau=0.8, bc=bc, n_sub=5,
+                  g_particle=np.array([0.0, 0.0, -3e-3]), particles=[p], contact_rs=1.0,
+                  contact_kn=20.0, contact_en=0.5, contact_mu=0.5, quad_h=0.25, name="settle-floor")
+
+
+def suspension_small(n_bodies: int = 6, box: int = 48, seed: int = 51, bc: int = BC_IBB) -> Config:
+    """Small periodic suspension (bodies of 4..8 points, R 3.5..5, tightly
+    packed by random sequential addition), counter-force, contact on."""
+    rng = _rng(seed)
+    bodies, centers, radii = [], [], []
+    while len(bodies) < n_bodies:
+        n_cp = int(rng.integers(4, 9))
+        R = float(rng.uniform(3.5, 5.0))
+        off, k = random_body(rng, n_cp, R)
+        p = Particle(cp_xyz=off, cp_k=k, x=np.zeros(3), density=6.0,
+                     v=rng.uniform(-0.05, 0.05, 3))
+        rb = p.bounding_radius()
+        for _ in range(100000):
+            c = rng.uniform(0.0, box, size=3)
+            if all(np.linalg.norm((c - c2) - box * np.floor((c - c2) / box + 0.5)) > 0.7 * (rb + r2)
+                   for c2, r2 in zip(centers, radii)):
+                break
+        p.x = c
+        centers.append(c)
+        radii.append(rb)
+        bodies.append(p)
+    return Config(nx=box, ny=box, nz=box, periodic=7, tau=0.7, bc=bc, n_sub=4, counter_force=1,
+                  g_particle=np.array([0.0, 0.0, -2e-4]), particles=bodies, contact_rs=1.0,
+                  contact_kn=20.0, contact_en=0.5, contact_mu=0.5, quad_h=0.25,
+                  name=f"suspension-{box}-{n_bodies}")
