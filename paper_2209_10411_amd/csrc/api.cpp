@@ -158,9 +158,10 @@ struct Plan {
     std::vector<int> part_first_blk;  // [np]
     std::vector<int> half;            // [np]
     size_t off_A, off_B, off_own[3], off_skip[2], off_stamp, off_P, off_part, off_first, off_dims,
-        off_pfb, off_bcnt, off_boff, off_loff, off_lnode, off_ldo, off_lq, off_lpart, off_special,
+        off_pfb, off_bcnt, off_loff, off_lnode, off_ldo, off_lq, off_lpart, off_special,
         off_cnt, total;
     bool contact;
+    size_t off_lmask;
     size_t off_pairF, off_pairTi, off_pairTj, off_wallF, off_wallT, off_xiP, off_xiW;
 };
 
@@ -276,7 +277,7 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_dims = take(4 * 3 * std::max(np, 1));
     pl.off_pfb = take(4 * std::max(np, 1));
     pl.off_bcnt = take(4 * std::max(pl.region_blocks, 1));
-    pl.off_boff = take(4 * std::max(pl.region_blocks, 1));
+    pl.off_lmask = take(4 * (size_t)BLK * std::max(pl.region_blocks, 1));
     pl.off_loff = take(4 * (np + 1));
     pl.off_lnode = take(4 * (size_t)std::max(pl.link_cap, 1));
     pl.off_ldo = take(4 * (size_t)std::max(pl.link_cap, 1));
@@ -314,7 +315,8 @@ struct lbm_ctx {
     uint32_t *stamp;
     DevParticle *P;
     RegionMap rm;
-    int *part_first_blk, *blk_cnt, *blk_off, *l_off;
+    int *part_first_blk, *blk_cnt, *l_off;
+    uint32_t *lmask;
     uint32_t *l_node, *l_do, *special;
     double *l_q, *lpart;
     Counters *cnt;
@@ -341,7 +343,7 @@ StepArgs base_args(lbm_ctx *c) {
     a.skip = c->skip[c->is]; a.skip_next = c->skip[1 - c->is];
     a.stamp = c->stamp; a.P = c->P; a.rm = c->rm;
     a.part_first_blk = c->part_first_blk;
-    a.blk_cnt = c->blk_cnt; a.blk_off = c->blk_off; a.l_off = c->l_off;
+    a.blk_cnt = c->blk_cnt; a.l_off = c->l_off; a.lmask = c->lmask;
     a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.part = c->lpart;
     a.special = c->special; a.cnt = c->cnt; a.cb = c->cb;
     return a;
@@ -502,7 +504,8 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->rm.first = (const int *)(b + pl.off_first);
     c->rm.dims = (const int *)(b + pl.off_dims);
     c->part_first_blk = (int *)(b + pl.off_pfb);
-    c->blk_cnt = (int *)(b + pl.off_bcnt); c->blk_off = (int *)(b + pl.off_boff);
+    c->blk_cnt = (int *)(b + pl.off_bcnt);
+    c->lmask = (uint32_t *)(b + pl.off_lmask);
     c->l_off = (int *)(b + pl.off_loff);
     c->l_node = (uint32_t *)(b + pl.off_lnode); c->l_do = (uint32_t *)(b + pl.off_ldo);
     c->l_q = (double *)(b + pl.off_lq); c->lpart = (double *)(b + pl.off_lpart);

@@ -5,17 +5,19 @@
 //                    paper's interpolated rule, sec. 2.3.2 Eqs. eqneq1-neqd)
 //                    and the link's momentum exchange in FP64
 //   k_reduce         one block per particle: fixed-order FP64 sum of the link
-//                    momenta
-//   k_rigid          one block: sphero-metaball contacts and the Newton-Euler
-//                    update of all particles over the sub-steps (sec. 2.3.1)
+//                    momenta and, without contact, the body's rigid-body
+//                    update (sec. 2.3.1)
+//   k_rigid          one block (contact): sphero-metaball contacts and the
+//                    Newton-Euler update of all particles over the sub-steps
 //   k_region_*       per-particle cubes: metaball flags (sec. 2.1), node
 //                    classes and the list of nodes needing the slow path
 //   k_bulk           every plain fluid node: pull-stream + BGK/Guo collide,
 //                    branch-free apart from the one class byte (HBM-bound)
 //   k_special        boundary and uncovered nodes: pull with bounce-back or
 //                    refill (sec. 2.3.2, refilling equation), then collide
-//   k_link_*         cut-link list of the new geometry, link fractions q by
-//                    a safeguarded Newton iteration in FP64
+//   k_link_emit      cut-link list of the new geometry (masks and counts from
+//                    the classification), link fractions q by a safeguarded
+//                    Newton iteration in FP64
 // Populations are deviations f_i - w_i rho0 in FP32, FP16 or BF16 storage;
 // collisions run in FP32, everything geometric or mechanical in FP64.
 #include <hip/hip_runtime.h>
@@ -443,17 +445,21 @@ __device__ void refresh_pose(const Params &p, DevParticle &P) {
 }
 
 // One block per particle: fixed-order FP64 sum of the link momenta (chunk
-// partials from k_links) into the particle's hydrodynamic force and torque.
-// Block 0 also clears the per-step counters and advances the classification
-// tag.
-__global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restrict__ P,
-                                                const int *__restrict__ l_off,
-                                                const double *__restrict__ part,
-                                                Counters *__restrict__ cnt) {
-    __shared__ double red[6][256];
-    const int pi = blockIdx.x, t = threadIdx.x;
-    if (pi == 0 && t == 0) { cnt->n_special = 0; cnt->n_refill = 0; cnt->n_solid = 0; cnt->tag += 1u; }
-    if (pi >= p.np) return;
+// partials from k_links) into the particle's hydrodynamic force and torque;
+// with 'update' (no contact: bodies move independently) also the body's
+// rigid-body update on an LDS copy of its record.  Block 0 also clears the
+// per-step counters and advances the classification tag.
+__device__ void body_substep(const Params &p, DevParticle &P, const double F[3], const double T[3], double dt);
+__device__ void end_of_step(const Params &p, DevParticle &B, Counters *cnt);
+
+// Fixed-order FP64 sum of the chunk partials of body pi (from k_links) into
+// its hydrodynamic force and torque; with 'update' (no contact: bodies move
+// independently) also its rigid-body update on an LDS copy of its record.
+// Whole block, 256 threads; red and sp are LDS scratch.
+__device__ void reduce_body(const Params &p, DevParticle *__restrict__ P, int pi, const int *__restrict__ l_off,
+                            const double *__restrict__ part, Counters *__restrict__ cnt, int update,
+                            double (*red)[256], DevParticle &sp) {
+    const int t = threadIdx.x;
     double s[6] = {0, 0, 0, 0, 0, 0};
     const int a = max(0, l_off[pi]), b = min(l_off[pi + 1], p.link_cap);
     if (b > a)  // chunks of 256 links holding this body's links; slot = chunk + body
@@ -466,9 +472,47 @@ __global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restric
             for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + h];
         __syncthreads();
     }
-    if (t == 0)
-        for (int c = 0; c < 3; ++c) { P[pi].F[c] = red[c][0]; P[pi].T[c] = red[3 + c][0]; }
+    if (!update) {
+        if (t == 0)
+            for (int c = 0; c < 3; ++c) { P[pi].F[c] = red[c][0]; P[pi].T[c] = red[3 + c][0]; }
+        __syncthreads();
+        return;
+    }
+    constexpr int W = sizeof(DevParticle) / 4;
+    for (int k = t; k < W; k += 256) ((int *)&sp)[k] = ((const int *)&P[pi])[k];
+    __syncthreads();
+    if (t == 0) {
+        for (int c = 0; c < 3; ++c) { sp.F[c] = red[c][0]; sp.T[c] = red[3 + c][0]; sp.X0[c] = sp.X[c]; }
+        const double dt = 1.0 / p.n_sub;
+        for (int s2 = 0; s2 < p.n_sub; ++s2) body_substep(p, sp, sp.F, sp.T, dt);
+        end_of_step(p, sp, cnt);
+    }
+    __syncthreads();
+    for (int k = t; k < W; k += 256) ((int *)&P[pi])[k] = ((const int *)&sp)[k];
+    __syncthreads();
 }
+
+__device__ void reset_step_counters(Counters *cnt) {
+    cnt->n_special = 0;
+    cnt->n_refill = 0;
+    cnt->n_solid = 0;
+    cnt->tag += 1u;
+}
+
+// One block per particle: reduce_body.  Block 0 also clears the per-step
+// counters and advances the classification tag.
+__global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restrict__ P,
+                                                const int *__restrict__ l_off,
+                                                const double *__restrict__ part,
+                                                Counters *__restrict__ cnt, int update) {
+    __shared__ double red[6][256];
+    __shared__ DevParticle sp;
+    const int pi = blockIdx.x;
+    if (pi == 0 && threadIdx.x == 0) reset_step_counters(cnt);
+    if (pi >= p.np) return;
+    reduce_body(p, P, pi, l_off, part, cnt, update, red, sp);
+}
+
 
 // ------------------------------------------------------ contact (sec. 2.3.1)
 __device__ bool inv3d(const double A[9], double B[9]) {
@@ -718,9 +762,17 @@ __device__ void body_substep(const Params &p, DevParticle &P, const double F[3],
 // hydrodynamic load (held) plus its contacts summed in a fixed order
 // (partners by index, then faces).  Finally end-of-step checks, periodic
 // wrap of the centroid and the region origin.
-__global__ __launch_bounds__(256) void k_rigid(Params p, DevParticle *__restrict__ P, ContactBufs cb,
+constexpr int RIGID_LDS = 32;
+__global__ __launch_bounds__(256) void k_rigid(Params p, DevParticle *__restrict__ Pg, ContactBufs cb,
                                                Counters *__restrict__ cnt) {
+    __shared__ DevParticle sP[RIGID_LDS];
     const int t = threadIdx.x, np = p.np;
+    const bool lds = np <= RIGID_LDS;
+    DevParticle *P = lds ? sP : Pg;
+    constexpr int W = sizeof(DevParticle) / 4;
+    if (lds)
+        for (int k = t; k < W * np; k += 256) ((int *)sP)[k] = ((const int *)Pg)[k];
+    __syncthreads();
     for (int q = t; q < np; q += 256)
         for (int a = 0; a < 3; ++a) P[q].X0[a] = P[q].X[a];
     __syncthreads();
@@ -810,24 +862,30 @@ __global__ __launch_bounds__(256) void k_rigid(Params p, DevParticle *__restrict
         }
         __syncthreads();
     }
-    for (int q = t; q < np; q += 256) {
-        DevParticle &B = P[q];
-        double d2 = 0.0;
-        bool finite = true;
-        for (int c = 0; c < 3; ++c) {
-            d2 += (B.X[c] - B.X0[c]) * (B.X[c] - B.X0[c]);
-            finite = finite && isfinite(B.X[c]) && isfinite(B.v[c]) && isfinite(B.w[c]);
-        }
-        if (!finite) atomicOr(&cnt->err, ERR_NONFINITE);
-        else if (d2 > 1.0) atomicOr(&cnt->err, ERR_FAST_PARTICLE);
-        const int L[3] = {p.nx, p.ny, p.nz};
-        for (int c = 0; c < 3; ++c)  // keep the centroid inside a periodic box
-            if ((p.periodic >> c) & 1u) {
-                if (B.X[c] < 0.0) B.X[c] += L[c];
-                else if (B.X[c] >= L[c]) B.X[c] -= L[c];
-            }
-        refresh_pose(p, B);
+    for (int q = t; q < np; q += 256) end_of_step(p, P[q], cnt);
+    __syncthreads();
+    if (lds)
+        for (int k = t; k < W * np; k += 256) ((int *)Pg)[k] = ((const int *)sP)[k];
+}
+
+// End of a lattice step for one body: error checks (non-finite state, more
+// than one lattice unit moved), periodic wrap of the centroid, pose refresh.
+__device__ void end_of_step(const Params &p, DevParticle &B, Counters *cnt) {
+    double d2 = 0.0;
+    bool finite = true;
+    for (int c = 0; c < 3; ++c) {
+        d2 += (B.X[c] - B.X0[c]) * (B.X[c] - B.X0[c]);
+        finite = finite && isfinite(B.X[c]) && isfinite(B.v[c]) && isfinite(B.w[c]);
     }
+    if (!finite) atomicOr(&cnt->err, ERR_NONFINITE);
+    else if (d2 > 1.0) atomicOr(&cnt->err, ERR_FAST_PARTICLE);
+    const int L[3] = {p.nx, p.ny, p.nz};
+    for (int c = 0; c < 3; ++c)  // keep the centroid inside a periodic box
+        if ((p.periodic >> c) & 1u) {
+            if (B.X[c] < 0.0) B.X[c] += L[c];
+            else if (B.X[c] >= L[c]) B.X[c] -= L[c];
+        }
+    refresh_pose(p, B);
 }
 
 __global__ void k_refresh_pose(Params p, DevParticle *P) {
@@ -884,20 +942,6 @@ __device__ __forceinline__ int block_sum(int v, int *sh) {
     return sh[0];
 }
 
-// Cut-link mask of a node for body pi: directions i >= 1 whose source
-// x - e_i is an in-domain node owned by pi, for a fluid node x.
-__device__ __forceinline__ uint32_t link_mask(const Params &p, const int32_t *own, int pi, int x, int y,
-                                              int z, long long n) {
-    if (own[n] != FLUID) return 0u;
-    uint32_t m = 0u;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        long long s;
-        if (nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s) && own[s] == pi) m |= 1u << i;
-    }
-    return m;
-}
-
 // Node classification over the body regions, once per node (claimed through
 // the stamp array when several regions may overlap):
 //   - special list of this step: nodes fluid after the step that were solid
@@ -912,13 +956,14 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
                                                          const int32_t *__restrict__ own_old,
                                                          const int32_t *__restrict__ own_new,
                                                          uint8_t *__restrict__ skip_next, uint32_t *stamp,
-                                                         uint32_t *special, Counters *cnt, int *blk_cnt) {
+                                                         uint32_t *special, Counters *cnt, int *blk_cnt,
+                                                         uint32_t *lmask) {
     __shared__ int sh[BLK];
     int pi, x, y, z;
     long long n;
     const bool in = region_node(p, rm, P, pi, x, y, z, n);
     bool nb_old = false, nb_new = false;
-    int c = 0;
+    uint32_t m = 0u;
     bool so = false, sn = false;
     if (in) {
         so = own_old[n] != FLUID;
@@ -930,29 +975,32 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
                 const int32_t vo = own_old[s], vn = own_new[s];
                 nb_old |= vo != FLUID;
                 nb_new |= vn != FLUID;
-                c += (vn == pi) ? 1 : 0;
+                if (vn == pi) m |= 1u << i;
             }
         }
-        if (sn) c = 0;
+        if (sn) m = 0u;
     }
-    if (blk_cnt) {
-        const int s = block_sum(c, sh);
-        if (threadIdx.x == 0) blk_cnt[blockIdx.x] = s;
-    }
-    if (!in) return;
-    if (p.np > 1) {  // regions of several bodies may overlap: first claimer classifies
+    bool act = in;
+    if (act && p.np > 1) {  // regions of several bodies may overlap: first claimer classifies
         const uint32_t tag = cnt->tag;
-        if (atomicExch(&stamp[n], tag) == tag) return;
+        if (atomicExch(&stamp[n], tag) == tag) act = false;
     }
-    skip_next[n] = (uint8_t)((sn || nb_new) ? 1 : 0);
-    const bool lo = !so && nb_old;
-    wave_append(&cnt->n_solid, sn);
-    wave_append(&cnt->n_refill, !sn && so);
-    const int k = wave_append(&cnt->n_special, !sn && (so || lo));
-    if (k >= 0) {
-        if (k < p.special_cap) special[k] = (uint32_t)n;
-        else atomicOr(&cnt->err, ERR_SPECIAL_OVERFLOW);
+    if (act) {
+        skip_next[n] = (uint8_t)((sn || nb_new) ? 1 : 0);
+        const bool lo = !so && nb_old;
+        wave_append(&cnt->n_solid, sn);
+        wave_append(&cnt->n_refill, !sn && so);
+        const int k = wave_append(&cnt->n_special, !sn && (so || lo));
+        if (k >= 0) {
+            if (k < p.special_cap) special[k] = (uint32_t)n;
+            else atomicOr(&cnt->err, ERR_SPECIAL_OVERFLOW);
+        }
     }
+    if (!blk_cnt) return;
+    // first pass of the link build: this body's cut links of the new flags
+    lmask[blockIdx.x * BLK + threadIdx.x] = m;
+    const int s = block_sum(__popc(m), sh);
+    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = s;
 }
 
 // Plain fluid nodes (skip mask clear: fluid with no solid neighbour at the
@@ -1106,12 +1154,7 @@ __global__ void k_collide_stored(Params p, typename Store<S>::T *A, const int32_
     }
 }
 
-__global__ void k_reset_counters(Counters *cnt) {
-    cnt->n_special = 0;
-    cnt->n_refill = 0;
-    cnt->n_solid = 0;
-    cnt->tag += 1u;
-}
+__global__ void k_reset_counters(Counters *cnt) { reset_step_counters(cnt); }
 
 __global__ void k_fill_i32(int32_t *a, long long n, int32_t v) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -1122,45 +1165,16 @@ __global__ void k_fill_u8(uint8_t *a, long long n, uint8_t v) {
         a[i] = v;
 }
 
-// Link build, pass 2: one block scans the per-block link counts; per-body
-// offsets follow from the first block of each body.
-__global__ __launch_bounds__(1024) void k_link_scan(Params p, const int *__restrict__ blk_cnt,
-                                                    int *__restrict__ blk_off,
-                                                    const int *__restrict__ part_first_blk,
-                                                    int *__restrict__ l_off, Counters *cnt) {
-    __shared__ int sh[1024];
-    const int t = threadIdx.x, nb = p.region_blocks;
-    const int per = (nb + 1023) / 1024;
-    const int a = t * per, b = min(a + per, nb);
-    int s = 0;
-    for (int i = a; i < b; ++i) s += blk_cnt[i];
-    sh[t] = s;
-    __syncthreads();
-    for (int h = 1; h < 1024; h <<= 1) {  // inclusive Hillis-Steele scan
-        const int v = t >= h ? sh[t - h] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
-    }
-    int run = sh[t] - s;
-    for (int i = a; i < b; ++i) { blk_off[i] = run; run += blk_cnt[i]; }
-    __syncthreads();
-    if (t == 0) {
-        const int total = sh[1023];
-        if (total > p.link_cap) atomicOr(&cnt->err, ERR_LINK_OVERFLOW);
-        cnt->n_links = min(total, p.link_cap);
-        l_off[p.np] = min(total, p.link_cap);
-    }
-    for (int q = t; q < p.np; q += 1024) l_off[q] = min(blk_off[part_first_blk[q]], p.link_cap);
-}
-
-// Link build, pass 3: the block lists its links (thread order, then
-// direction order) in LDS and then solves one link per thread, with the
-// body's control points in LDS.  With clear set, the block also resets that
-// (no longer needed) flag buffer to FLUID on its region.
+// Link build, second pass: each block finds its offset in the particle-major
+// list by summing the counts of the blocks before it (the first block of a
+// body also records the body's offset, the last block the total), lists its
+// links in LDS (masks from the classification; thread order, then direction
+// order) and solves one link per thread with the body's control points in
+// LDS.
 __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const DevParticle *P,
-                                                   const int32_t *__restrict__ own,
-                                                   const int *__restrict__ blk_off,
+                                                   const uint32_t *__restrict__ lmask,
+                                                   const int *__restrict__ blk_cnt,
+                                                   const int *__restrict__ part_first_blk, int *__restrict__ l_off,
                                                    uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
                                                    double *__restrict__ l_q, Counters *cnt, int32_t *clear) {
     __shared__ CPs cps;
@@ -1170,10 +1184,24 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
     __shared__ uint16_t lk[BLK * 18];
     const int t = threadIdx.x;
     stage_cps(cps, P[rm.part[blockIdx.x]]);
+    int before = 0;
+    for (int b = t; b < (int)blockIdx.x; b += BLK) before += blk_cnt[b];
+    const int base = block_sum(before, sh);
+    __syncthreads();  // every thread has read the sum before sh is reused
+    const int pid = rm.part[blockIdx.x];
+    if (t == 0) {
+        if (part_first_blk[pid] == (int)blockIdx.x) l_off[pid] = min(base, p.link_cap);
+        if (blockIdx.x == gridDim.x - 1) {
+            const int total = base + blk_cnt[blockIdx.x];
+            if (total > p.link_cap) atomicOr(&cnt->err, ERR_LINK_OVERFLOW);
+            cnt->n_links = min(total, p.link_cap);
+            l_off[p.np] = min(total, p.link_cap);
+        }
+    }
     int pi, x, y, z;
     long long n;
     const bool in = region_node(p, rm, P, pi, x, y, z, n);
-    const uint32_t m = in ? link_mask(p, own, pi, x, y, z, n) : 0u;
+    const uint32_t m = in ? lmask[blockIdx.x * BLK + t] : 0u;
     if (in && clear) clear[n] = FLUID;
     const int c = __popc(m);
     sh[t] = c;
@@ -1191,8 +1219,6 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
         if ((m >> i) & 1u) lk[o++] = (uint16_t)((t << 5) | i);
     __syncthreads();
     const int total = sh[BLK - 1];
-    const int base = blk_off[blockIdx.x];
-    const int pid = rm.part[blockIdx.x];
     int it_sum = 0;
     for (int j = t; j < total; j += BLK) {
         const int tt = lk[j] >> 5, i = lk[j] & 31;
@@ -1223,17 +1249,19 @@ static void launch_step_kernels_t(const StepArgs &a) {
     const int link_grid = max(1, min(cdiv(p.link_cap, 256), 2048));
     const int spec_grid = max(1, min(cdiv(p.special_cap, 4), 2048));
     if (a.phase == PHASE_LINKS) {
+        const int update = a.move && !p.contact;
         if (p.np > 0)
             k_links<S><<<link_grid, 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.l_node, a.l_do, a.l_q,
                                                          a.part, a.cnt);
-        k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt);
-        if (a.move && p.np > 0) k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
+        k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, update);
+        if (a.move && p.contact && p.np > 0) k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
     } else if (a.phase == PHASE_FLAGS) {
         if (p.np > 0) {
             if (a.move) k_region_mark<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new);
             k_region_classify<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_old, a.own_new,
                                                                       a.skip_next, a.stamp, a.special,
-                                                                      a.cnt, a.move ? a.blk_cnt : nullptr);
+                                                                      a.cnt, a.move ? a.blk_cnt : nullptr,
+                                                                      a.lmask);
         }
     } else if (a.phase == PHASE_BULK) {
         const int nseg = cdiv(p.nx, 64);
@@ -1245,8 +1273,8 @@ static void launch_step_kernels_t(const StepArgs &a) {
                                                            a.in_place);
     } else if (a.phase == PHASE_LINKBUILD) {
         if (p.np > 0) {
-            k_link_scan<<<1, 1024, 0, a.stream>>>(p, a.blk_cnt, a.blk_off, a.part_first_blk, a.l_off, a.cnt);
-            k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new, a.blk_off,
+            k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt,
+                                                                a.part_first_blk, a.l_off,
                                                                 a.l_node, a.l_do, a.l_q, a.cnt, a.own_dead);
         }
     } else if (a.phase == PHASE_INIT_STATE) {

@@ -32,7 +32,8 @@ struct StepArgs {
     DevParticle *P;
     RegionMap rm;
     const int *part_first_blk;
-    int *blk_cnt, *blk_off, *l_off;
+    int *blk_cnt, *l_off;
+    uint32_t *lmask;  // per region thread: cut-link mask of the new flags
     uint32_t *l_node, *l_do;
     double *l_q, *part;
     uint32_t *special;
