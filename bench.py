@@ -9,8 +9,10 @@ flagging, stream-collide with refill, cut-link rebuild).
 
 Prints one JSON line: MLUPS over all lattice nodes with FP32 storage (the
 headline), the same with FP16 storage, the roofline of the dominant kernel
-(the stream-collide, timed with HIP events on the library's stream), and the
-CPU oracle timed on a bounded sample of the same workload.
+(the stream-collide, timed with HIP events on the library's stream), the
+64-case ensemble (batched, graph-replayed) beside the same systems stepped
+one by one, and the CPU oracle timed on a bounded sample of the headline
+workload.
 """
 import argparse
 import hashlib
@@ -52,6 +54,46 @@ def run_gpu(cfg, steps, warmup):
     nr = sim.nr_stats()
     sim.close()
     return dt, k_ms, k_n, k_nodes, x, nr
+
+
+def run_ensemble(n_cases, steps, warmup):
+    """The 64-case settling ensemble (random sizes 64..128 x 64..128 x 64..256,
+    tau, density ratio, 4..16 control points; walls; FP32): autotuned tiles,
+    batched launches with six-step graph replays, against the same systems
+    stepped one after another with lbm_step."""
+    import torch
+
+    import paper_2209_10411_amd as mdl
+    import workloads
+
+    cfgs = workloads.config4(n_cases)
+    nodes = sum(c.n_nodes for c in cfgs)
+    ens = mdl.Ensemble(cfgs, device="cuda:0")
+    t0 = time.perf_counter()
+    tiles, bw = ens.autotune(budget_ms=5000.0)
+    t_tune = time.perf_counter() - t0
+    ens.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # the same systems, one lbm_step call each (two streams per system, no batching)
+    t0 = time.perf_counter()
+    for sim in ens.cases:
+        sim.step(steps)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    hist = {f"{64 >> (6 - t)}x{64 >> t}": tiles.count(t) for t in (6, 5, 4)}
+    ens.close()
+    return {"workload": f"{n_cases}-case settling ensemble, walls, FP32, 64..128 x 64..128 x 64..256, "
+                        "tau U[0.55,1], density ratio U[1.1,2.5], 4..16 cp",
+            "cases": n_cases, "nodes": nodes, "steps": steps,
+            "value": round(nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(dt * 1e3 / steps, 4),
+            "unbatched_value": round(nodes * steps / dt_seq / 1e6, 1),
+            "unbatched_ms_per_step": round(dt_seq * 1e3 / steps, 4),
+            "tiles": hist, "waves_per_block": bw, "autotune_s": round(t_tune, 2)}
 
 
 def traffic_from_profile():
@@ -112,6 +154,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-case ensemble run")
+    ap.add_argument("--ensemble-steps", type=int, default=60)
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB copy (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -163,6 +207,8 @@ def main():
                              "kernel_avg_ms": round(k16_ms / max(k16_n, 1), 5),
                              "kernel_achieved_GBs": round(ach16, 1),
                              "kernel_frac": round(ach16 / HBM_PEAK_GBS, 4)}
+    if not args.no_ensemble:
+        out["ensemble"] = run_ensemble(64, args.ensemble_steps, 12)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)

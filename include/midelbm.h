@@ -62,6 +62,7 @@ extern "C" {
 #endif
 
 typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
 
 typedef enum {
     LBM_OK = 0,
@@ -205,6 +206,47 @@ lbm_status lbm_sync(lbm_ctx *ctx);
 
 void lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(void);
+
+/* ---- ensemble of independent systems ----
+ * n_cases systems (each as lbm_init would set it up: configs cfgs[i],
+ * particles parts[n_p[0] + ... + n_p[i-1] ...] concatenated) stepped
+ * together: the stream-collide of all systems runs as one launch over a table
+ * of equal tiles (a wave covers a tile of 64x1, 32x2 or 16x4 nodes, chosen
+ * per system by lbm_autotune), the boundary kernels of each system run around
+ * it on two streams owned by the batch, and six consecutive coupled steps
+ * (the period of the library's buffer rotation) are captured once into a HIP
+ * graph and replayed.  Every system computes exactly what lbm_step computes
+ * for it alone (same kernels, same per-system order).  All systems must use
+ * one storage type.  The arena layout is the library's: one 256-byte-aligned
+ * device block of lbm_batch_arena_bytes bytes, owned by the caller.
+ * Errors: LBM_E_INVALID for a bad case (the message names it), LBM_E_NOMEM
+ * for a short arena, LBM_E_HIP for runtime failures. */
+lbm_status lbm_batch_arena_bytes(int32_t n_cases, const lbm_config *cfgs, const int32_t *n_p,
+                                 const lbm_particle *parts, size_t *bytes);
+lbm_status lbm_batch_init(int32_t n_cases, const lbm_config *cfgs, const int32_t *n_p,
+                          const lbm_particle *parts, void *dev_arena, size_t arena_bytes,
+                          void *hip_stream, lbm_batch **out);
+/* n_steps coupled steps of every system, enqueued after the caller's stream's
+ * earlier work; the caller's stream waits for them.  use_graph = 1 replays
+ * the captured graph for each whole block of six steps (captured on first
+ * use and again whenever a system's buffers were rotated from outside, e.g.
+ * by lbm_step on its context); the rest runs as plain launches. */
+lbm_status lbm_batch_step(lbm_batch *b, int32_t n_steps, int32_t use_graph);
+/* Context of system i, for the getters and setters above; owned by the batch
+ * (do not destroy it). */
+lbm_status lbm_batch_case(lbm_batch *b, int32_t i, lbm_ctx **ctx);
+/* Chooses each system's wave tile (one launch per candidate, timed with HIP
+ * events) and the waves per block of the batched launch (4 or 8), within
+ * about budget_ms of host time (systems not reached keep 64x1).  Systems of
+ * equal sizes, storage and periodicity share one choice.  With a cache path,
+ * a complete cache file is read instead of measuring, and the choices are
+ * written to it otherwise (a small JSON object).  Synchronises; the results
+ * of the next step are unchanged by the tiles (only the launch shape is). */
+lbm_status lbm_autotune(lbm_batch *b, double budget_ms, const char *cache_path /* nullable */);
+/* Current choices: tw_log2[i] = log2 of the tile width of system i (6, 5 or
+ * 4), and the waves per block. */
+lbm_status lbm_batch_tiles(lbm_batch *b, int32_t *tw_log2 /* [n_cases] */, int32_t *waves_per_block);
+void lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus
 }

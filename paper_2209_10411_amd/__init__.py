@@ -60,7 +60,9 @@ EXPORTS = ["lbm_arena_bytes", "lbm_init", "metaball_flag", "lbm_step", "particle
            "lbm_get_links", "lbm_get_particles", "lbm_set_particles", "lbm_get_gfluid",
            "lbm_timing_enable", "lbm_timing_read", "lbm_nr_stats", "lbm_contact_stats", "lbm_sync",
            "lbm_destroy",
-           "lbm_last_error"]
+           "lbm_last_error",
+           "lbm_batch_arena_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_case", "lbm_autotune",
+           "lbm_batch_tiles", "lbm_batch_destroy"]
 
 _lib = None
 
@@ -99,8 +101,19 @@ def lib():
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         L.lbm_last_error.restype = C.c_char_p
+        ip = C.POINTER(C.c_int32)
+        L.lbm_batch_arena_bytes.argtypes = [C.c_int32, C.POINTER(lbm_config), ip, C.POINTER(lbm_particle),
+                                            C.POINTER(C.c_size_t)]
+        L.lbm_batch_init.argtypes = [C.c_int32, C.POINTER(lbm_config), ip, C.POINTER(lbm_particle), vp,
+                                     C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_batch_step.argtypes = [vp, C.c_int32, C.c_int32]
+        L.lbm_batch_case.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+        L.lbm_autotune.argtypes = [vp, C.c_double, C.c_char_p]
+        L.lbm_batch_tiles.argtypes = [vp, ip, ip]
+        L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_batch_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("lbm_destroy", "lbm_last_error"):
+            if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -184,7 +197,18 @@ class Simulation:
                           self.arena.numel(), C.c_void_p(self.stream.cuda_stream),
                           C.byref(self._ctx)))
 
+    @classmethod
+    def _view(cls, ctx: C.c_void_p, cfg, owner):
+        """A system owned by an Ensemble (not destroyed by this object)."""
+        self = cls.__new__(cls)
+        self.cfg, self.N, self.np = cfg, cfg.nx * cfg.ny * cfg.nz, len(cfg.particles)
+        self._ctx, self._owner = ctx, owner
+        return self
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self._ctx = C.c_void_p()
+            return
         if getattr(self, "_ctx", None) and self._ctx.value:
             lib().lbm_destroy(self._ctx)
             self._ctx = C.c_void_p()
@@ -301,3 +325,65 @@ class Simulation:
         ms, n, nodes = C.c_double(0), C.c_int64(0), C.c_int64(0)
         _check(lib().lbm_timing_read(self._ctx, C.byref(ms), C.byref(n), C.byref(nodes)))
         return float(ms.value), int(n.value), int(nodes.value)
+
+
+class Ensemble:
+    """Independent systems (a list of ``workloads.Config``) stepped together:
+    one batched stream-collide launch over all of them, per-system boundary
+    kernels, six-step HIP graph replays (include/midelbm.h, ensemble)."""
+
+    def __init__(self, cfgs, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.cfgs = list(cfgs)
+        n = len(self.cfgs)
+        L = lib()
+        self._c = (lbm_config * n)(*[make_config(c) for c in self.cfgs])
+        allp = [p for c in self.cfgs for p in c.particles]
+        self._parts, self._keep = make_particles(allp)
+        self._np = (C.c_int32 * n)(*[len(c.particles) for c in self.cfgs])
+        nb = C.c_size_t(0)
+        _check(L.lbm_batch_arena_bytes(n, self._c, self._np, self._parts, C.byref(nb)))
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._b = C.c_void_p()
+        _check(L.lbm_batch_init(n, self._c, self._np, self._parts, C.c_void_p(self.arena.data_ptr()),
+                                self.arena.numel(), C.c_void_p(self.stream.cuda_stream), C.byref(self._b)))
+        self.cases = []
+        for i, cfg in enumerate(self.cfgs):
+            ctx = C.c_void_p()
+            _check(L.lbm_batch_case(self._b, i, C.byref(ctx)))
+            self.cases.append(Simulation._view(ctx, cfg, self))
+
+    def step(self, n: int = 1, graph: bool = True):
+        _check(lib().lbm_batch_step(self._b, int(n), int(bool(graph))))
+
+    def autotune(self, budget_ms: float = 2000.0, cache: str | None = None):
+        _check(lib().lbm_autotune(self._b, float(budget_ms), cache.encode() if cache else None))
+        return self.tiles()
+
+    def tiles(self):
+        """(per-system tile width log2, waves per block)."""
+        t = (C.c_int32 * len(self.cfgs))()
+        w = C.c_int32(0)
+        _check(lib().lbm_batch_tiles(self._b, t, C.byref(w)))
+        return list(t), int(w.value)
+
+    def sync(self):
+        for c in self.cases:
+            c.sync()
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            for c in self.cases:
+                c._ctx = C.c_void_p()
+            lib().lbm_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <thread>
 #include <vector>
@@ -658,8 +660,12 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
     const bool move = mode == LBM_STEP_COUPLED;
     // Per step: the stream-collide of plain nodes runs on the caller's stream
     // while the second stream does bounce-back + momentum exchange, the
-    // rigid-body update, flagging, classification and the link build; the
-    // boundary/uncovered pass joins both.
+    // rigid-body update, flagging, classification, the boundary/uncovered
+    // node pass and the link build.  The boundary pass writes other nodes of
+    // the destination buffer than the stream-collide, so the two overlap; the
+    // next step's stream-collide (which pulls from those nodes) waits for it,
+    // and the next step's second-stream work starts after this step's
+    // stream-collide (it overwrites the buffer that one reads).
     for (int s = 0; s < n_steps; ++s) {
         StepArgs a = base_args(c);
         a.move = move;
@@ -671,6 +677,9 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
         b.phase = PHASE_LINKS;
         launch_phase(b);
         b.phase = PHASE_FLAGS;
+        launch_phase(b);
+        b.phase = PHASE_SPECIAL;
+        b.in_place = 0;
         launch_phase(b);
         HIPCHK(hipEventRecord(c->ev_flags, c->aux));
         if (move) {
@@ -687,9 +696,6 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
             c->ev_used += 2;
         }
         HIPCHK(hipStreamWaitEvent(c->stream, c->ev_flags, 0));
-        a.phase = PHASE_SPECIAL;
-        a.in_place = 0;
-        launch_phase(a);
         if (move) {
             const int old = c->ic;
             c->ic = c->in; c->in = c->id; c->id = old;
@@ -963,5 +969,493 @@ void lbm_destroy(lbm_ctx *c) {
     }
     delete c;
 }
+
+
+// ------------------------------------------------------------------ ensemble
+// A batch of independent systems stepped together: one batched stream-collide
+// launch over a table of equal tiles for all systems, the per-system boundary
+// kernels around it, and six consecutive steps (the period of the buffer
+// rotation: A/B 2, flags 3) captured once into a HIP graph and replayed.
+
+}  // extern "C"
+
+namespace {
+constexpr int GRAPH_PERIOD = 6;
+constexpr int TW_CANDIDATES[3] = {6, 5, 4};  // wave tiles 64x1, 32x2, 16x4
+}  // namespace
+
+struct lbm_batch {
+    int n = 0;
+    std::vector<lbm_ctx *> cs;
+    hipStream_t caller = nullptr, main = nullptr, aux = nullptr;
+    hipEvent_t ev_in = nullptr, ev_main = nullptr, ev_flags = nullptr, ev_links = nullptr, ev_out = nullptr;
+    int storage = 0, bw = 8;
+    std::vector<int> tw;  // tile width log2 per system
+    BulkCase *d_cases = nullptr;  // [n + 1]: the table, plus one slot for tuning runs
+    int *d_blk = nullptr;         // [blk_cap]: block -> system
+    int *d_blk1 = nullptr;        // [blk1_cap]: tuning runs of one system
+    size_t blk_cap = 0, blk1_cap = 0;
+    std::vector<BulkCase> h_cases;
+    std::vector<int> h_blk;
+    int nblocks = 0;
+    int parity = 0;  // parity of the next step relative to the table
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> graph_key;
+};
+
+namespace {
+
+long long tile_blocks(const lbm_config &c, int twl, int bw) {
+    const long long nsx = (c.nx + (1 << twl) - 1) >> twl, th = 64 >> twl;
+    const long long nsy = (c.ny + th - 1) / th;
+    return (nsx * nsy * c.nz + bw - 1) / bw;
+}
+
+BulkCase bulk_case(const lbm_ctx *c, int twl, int bw, int first_block) {
+    BulkCase b{};
+    const Params &p = c->p;
+    b.nx = p.nx; b.ny = p.ny; b.nz = p.nz; b.periodic = p.periodic; b.N = p.N;
+    b.rho0f = p.rho0f; b.omega = p.omega; b.fcoef = p.fcoef;
+    b.gx = p.gx; b.gy = p.gy; b.gz = p.gz; b.scale = p.scale; b.inv_scale = p.inv_scale;
+    b.tw_log2 = twl;
+    b.nsx = (p.nx + (1 << twl) - 1) >> twl;
+    b.nsy = (p.ny + (64 >> twl) - 1) / (64 >> twl);
+    b.first_block = first_block;
+    b.n_blocks = (int)tile_blocks(c->cfg, twl, bw);
+    b.A[0] = c->A; b.B[0] = c->B; b.A[1] = c->B; b.B[1] = c->A;
+    b.skip[0] = c->skip[c->is]; b.skip[1] = c->skip[1 - c->is];
+    return b;
+}
+
+lbm_status write_table(lbm_batch *b) {
+    b->h_cases.resize(b->n);
+    b->h_blk.clear();
+    int first = 0;
+    for (int i = 0; i < b->n; ++i) {
+        b->h_cases[i] = bulk_case(b->cs[i], b->tw[i], b->bw, first);
+        for (int k = 0; k < b->h_cases[i].n_blocks; ++k) b->h_blk.push_back(i);
+        first += b->h_cases[i].n_blocks;
+    }
+    if (b->h_blk.size() > b->blk_cap) return fail(LBM_E_NOMEM, "ensemble block table overflow");
+    b->nblocks = first;
+    HIPCHK(hipMemcpyAsync(b->d_cases, b->h_cases.data(), sizeof(BulkCase) * b->n, hipMemcpyHostToDevice, b->main));
+    HIPCHK(hipMemcpyAsync(b->d_blk, b->h_blk.data(), 4 * b->h_blk.size(), hipMemcpyHostToDevice, b->main));
+    HIPCHK(hipStreamSynchronize(b->main));
+    b->parity = 0;
+    return LBM_OK;
+}
+
+bool table_valid(const lbm_batch *b) {
+    if ((int)b->h_cases.size() != b->n) return false;
+    for (int i = 0; i < b->n; ++i) {
+        const BulkCase &h = b->h_cases[i];
+        const lbm_ctx *c = b->cs[i];
+        if (h.A[b->parity] != c->A || h.skip[b->parity] != c->skip[c->is] || h.tw_log2 != b->tw[i]) return false;
+    }
+    return true;
+}
+
+void drop_graph(lbm_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_key.clear();
+}
+
+std::vector<uintptr_t> state_key(const lbm_batch *b) {
+    std::vector<uintptr_t> k;
+    k.push_back((uintptr_t)b->parity);
+    for (auto *c : b->cs) {
+        k.push_back((uintptr_t)c->A);
+        k.push_back((uintptr_t)c->is);
+        k.push_back((uintptr_t)c->ic);
+    }
+    return k;
+}
+
+// One coupled step of every system, enqueued on b->main / b->aux: the
+// batched stream-collide on the first stream; bounce-back, rigid bodies,
+// flags, classification, boundary pass and link build of every system on the
+// second, which starts after the first stream's previous work.  The next
+// step's stream-collide waits for every system's boundary pass.
+lbm_status enqueue_batch_step(lbm_batch *b) {
+    HIPCHK(hipEventRecord(b->ev_main, b->main));
+    HIPCHK(hipStreamWaitEvent(b->aux, b->ev_main, 0));
+    std::vector<StepArgs> as(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        StepArgs a = base_args(b->cs[i]);
+        a.move = 1;
+        a.stream = b->aux;
+        a.phase = PHASE_LINKS;
+        launch_phase(a);
+        a.phase = PHASE_FLAGS;
+        launch_phase(a);
+        as[i] = a;
+    }
+    for (int i = 0; i < b->n; ++i) {
+        StepArgs a = as[i];
+        a.phase = PHASE_SPECIAL;
+        a.in_place = 0;
+        launch_phase(a);
+    }
+    HIPCHK(hipEventRecord(b->ev_flags, b->aux));
+    for (int i = 0; i < b->n; ++i) {
+        StepArgs a = as[i];
+        a.phase = PHASE_LINKBUILD;
+        a.own_dead = b->cs[i]->own[b->cs[i]->id];
+        launch_phase(a);
+    }
+    launch_bulk_batch(b->storage, b->bw, b->d_cases, b->d_blk, b->nblocks, b->parity, b->main);
+    HIPCHK(hipStreamWaitEvent(b->main, b->ev_flags, 0));
+    for (int i = 0; i < b->n; ++i) {
+        lbm_ctx *c = b->cs[i];
+        const int old = c->ic;
+        c->ic = c->in; c->in = c->id; c->id = old;
+        c->is = 1 - c->is;
+        std::swap(c->A, c->B);
+        c->steps++;
+    }
+    b->parity ^= 1;
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status join_aux(lbm_batch *b) {
+    HIPCHK(hipEventRecord(b->ev_links, b->aux));
+    HIPCHK(hipStreamWaitEvent(b->main, b->ev_links, 0));
+    return LBM_OK;
+}
+
+lbm_status capture_graph(lbm_batch *b) {
+    drop_graph(b);
+    std::vector<long long> steps0;
+    for (auto *c : b->cs) steps0.push_back(c->steps);
+    const std::vector<uintptr_t> key = state_key(b);
+    HIPCHK(hipStreamBeginCapture(b->main, hipStreamCaptureModeThreadLocal));
+    lbm_status st = LBM_OK;
+    for (int s = 0; s < GRAPH_PERIOD && st == LBM_OK; ++s) st = enqueue_batch_step(b);
+    if (st == LBM_OK) st = join_aux(b);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->main, &g);
+    // the capture executed nothing: the host-side rotation has come full circle
+    for (int i = 0; i < b->n; ++i) b->cs[i]->steps = steps0[i];
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(LBM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (state_key(b) != key) {
+        (void)hipGraphDestroy(g);
+        return fail(LBM_E_STATE, "ensemble state did not return to its start after %d steps", GRAPH_PERIOD);
+    }
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_key = key;
+    return LBM_OK;
+}
+
+void free_batch(lbm_batch *b) {
+    if (!b) return;
+    if (b->main) (void)hipStreamSynchronize(b->main);
+    if (b->aux) (void)hipStreamSynchronize(b->aux);
+    drop_graph(b);
+    for (auto *c : b->cs) lbm_destroy(c);
+    for (hipEvent_t e : {b->ev_in, b->ev_main, b->ev_flags, b->ev_links, b->ev_out})
+        if (e) (void)hipEventDestroy(e);
+    if (b->main) (void)hipStreamDestroy(b->main);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
+    delete b;
+}
+
+struct BatchLayout {
+    std::vector<size_t> off, bytes;
+    size_t off_cases, off_blk, off_blk1, blk_cap, blk1_cap, total;
+};
+
+lbm_status batch_layout(int32_t n, const lbm_config *cfgs, const int32_t *n_p, const lbm_particle *parts,
+                        BatchLayout &L) {
+    if (n < 1) return fail(LBM_E_INVALID, "n_cases must be >= 1");
+    if (!cfgs || !n_p) return fail(LBM_E_INVALID, "cfgs and n_p must not be NULL");
+    size_t o = 0;
+    long long pofs = 0, cap = 0, cap1 = 0;
+    for (int i = 0; i < n; ++i) {
+        if (n_p[i] < 0) return fail(LBM_E_INVALID, "case %d: n_p < 0", i);
+        if (cfgs[i].storage != cfgs[0].storage) return fail(LBM_E_INVALID, "all cases must use one storage type");
+        size_t by = 0;
+        lbm_status s = lbm_arena_bytes(&cfgs[i], n_p[i], parts ? parts + pofs : nullptr, &by);
+        if (s) {
+            const std::string m = g_err;
+            return fail(s, "case %d: %s", i, m.c_str());
+        }
+        L.off.push_back(o);
+        L.bytes.push_back(by);
+        o = align256(o + by);
+        pofs += n_p[i];
+        long long mx = 0;
+        for (int t : TW_CANDIDATES) mx = std::max(mx, tile_blocks(cfgs[i], t, 4));
+        cap += mx;
+        cap1 = std::max(cap1, mx);
+    }
+    if (cap > 0x7fffffffll) return fail(LBM_E_INVALID, "ensemble too large for one launch");
+    L.blk_cap = (size_t)cap;
+    L.blk1_cap = (size_t)cap1;
+    L.off_cases = o; o = align256(o + sizeof(BulkCase) * (n + 1));
+    L.off_blk = o; o = align256(o + 4 * L.blk_cap);
+    L.off_blk1 = o; o = align256(o + 4 * L.blk1_cap);
+    L.total = o;
+    return LBM_OK;
+}
+
+// tiny reader of the tuning cache written by lbm_autotune: {"bw": B, "tiles": {"key": t, ...}}
+bool cache_int(const std::string &txt, const std::string &key, int &v) {
+    const std::string pat = "\"" + key + "\":";
+    const size_t at = txt.find(pat);
+    if (at == std::string::npos) return false;
+    return std::sscanf(txt.c_str() + at + pat.size(), " %d", &v) == 1;
+}
+
+std::string case_key(const lbm_ctx *c) {
+    char k[96];
+    std::snprintf(k, sizeof k, "%dx%dx%d/s%d/p%u", c->p.nx, c->p.ny, c->p.nz, c->p.storage, c->p.periodic);
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_arena_bytes(int32_t n_cases, const lbm_config *cfgs, const int32_t *n_p,
+                                 const lbm_particle *parts, size_t *bytes) {
+    if (!bytes) return fail(LBM_E_INVALID, "bytes is NULL");
+    BatchLayout L;
+    lbm_status s = batch_layout(n_cases, cfgs, n_p, parts, L);
+    if (s) return s;
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_init(int32_t n_cases, const lbm_config *cfgs, const int32_t *n_p, const lbm_particle *parts,
+                          void *dev_arena, size_t arena_bytes, void *hip_stream, lbm_batch **out) {
+    if (!out) return fail(LBM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    BatchLayout L;
+    lbm_status s = batch_layout(n_cases, cfgs, n_p, parts, L);
+    if (s) return s;
+    if (!dev_arena) return fail(LBM_E_INVALID, "arena is NULL");
+    if ((uintptr_t)dev_arena & 255) return fail(LBM_E_INVALID, "arena must be 256-byte aligned");
+    if (arena_bytes < L.total) return fail(LBM_E_NOMEM, "arena holds %zu bytes, %zu needed", arena_bytes, L.total);
+    lbm_batch *b = new lbm_batch();
+    b->n = n_cases;
+    b->caller = (hipStream_t)hip_stream;
+    b->storage = cfgs[0].storage;
+    b->tw.assign(n_cases, 6);
+    char *base = (char *)dev_arena;
+    b->d_cases = (BulkCase *)(base + L.off_cases);
+    b->d_blk = (int *)(base + L.off_blk);
+    b->d_blk1 = (int *)(base + L.off_blk1);
+    b->blk_cap = L.blk_cap;
+    b->blk1_cap = L.blk1_cap;
+    long long pofs = 0;
+    for (int i = 0; i < n_cases; ++i) {
+        lbm_ctx *c = nullptr;
+        s = lbm_init(&cfgs[i], n_p[i], parts ? parts + pofs : nullptr, base + L.off[i], L.bytes[i], hip_stream, &c);
+        if (s) {
+            const std::string m = g_err;
+            free_batch(b);
+            return fail(s, "case %d: %s", i, m.c_str());
+        }
+        b->cs.push_back(c);
+        pofs += n_p[i];
+    }
+    auto bail = [&](hipError_t e, const char *what) {
+        free_batch(b);
+        return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    if ((e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    for (hipEvent_t *ev : {&b->ev_in, &b->ev_main, &b->ev_flags, &b->ev_links, &b->ev_out})
+        if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+    // the systems were initialised on the caller's stream
+    if ((e = hipStreamSynchronize(b->caller)) != hipSuccess) return bail(e, "hipStreamSynchronize");
+    s = write_table(b);
+    if (s) {
+        const std::string m = g_err;
+        free_batch(b);
+        return fail(s, "%s", m.c_str());
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_case(lbm_batch *b, int32_t i, lbm_ctx **ctx) {
+    if (!b || !ctx) return fail(LBM_E_INVALID, "batch and ctx must not be NULL");
+    if (i < 0 || i >= b->n) return fail(LBM_E_INVALID, "case %d out of range", i);
+    *ctx = b->cs[i];
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int32_t n_steps, int32_t use_graph) {
+    if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+    if (n_steps < 0) return fail(LBM_E_INVALID, "n_steps must be >= 0");
+    if (n_steps == 0) return LBM_OK;
+    for (auto *c : b->cs)
+        if (c->pending_refill) do_refill(c);
+    // the ensemble's streams follow the caller's
+    HIPCHK(hipEventRecord(b->ev_in, b->caller));
+    HIPCHK(hipStreamWaitEvent(b->main, b->ev_in, 0));
+    if (!table_valid(b)) {
+        lbm_status s = write_table(b);
+        if (s) return s;
+    }
+    while (n_steps > 0) {
+        if (use_graph && n_steps >= GRAPH_PERIOD) {
+            if (!b->exec || state_key(b) != b->graph_key) {
+                lbm_status s = capture_graph(b);
+                if (s) return s;
+            }
+            HIPCHK(hipGraphLaunch(b->exec, b->main));
+            for (auto *c : b->cs) c->steps += GRAPH_PERIOD;
+            n_steps -= GRAPH_PERIOD;
+        } else {
+            lbm_status s = enqueue_batch_step(b);
+            if (s) return s;
+            n_steps -= 1;
+        }
+    }
+    lbm_status s = join_aux(b);
+    if (s) return s;
+    HIPCHK(hipEventRecord(b->ev_out, b->main));
+    HIPCHK(hipStreamWaitEvent(b->caller, b->ev_out, 0));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_tiles(lbm_batch *b, int32_t *tw_log2, int32_t *waves_per_block) {
+    if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+    if (tw_log2)
+        for (int i = 0; i < b->n; ++i) tw_log2[i] = b->tw[i];
+    if (waves_per_block) *waves_per_block = b->bw;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_batch *b, double budget_ms, const char *cache_path) {
+    if (!b) return fail(LBM_E_INVALID, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->caller));
+    HIPCHK(hipStreamSynchronize(b->main));
+    drop_graph(b);
+    std::string txt;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "rb")) {
+            char buf[4096];
+            size_t r;
+            while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, r);
+            std::fclose(f);
+        }
+    }
+    bool complete = !txt.empty();
+    if (complete) {
+        int bw = 8;
+        if (!cache_int(txt, "bw", bw) || (bw != 4 && bw != 8)) complete = false;
+        std::vector<int> tw(b->n, 6);
+        for (int i = 0; i < b->n && complete; ++i)
+            if (!cache_int(txt, case_key(b->cs[i]), tw[i]) || tw[i] < 4 || tw[i] > 6) complete = false;
+        if (complete) {
+            b->bw = bw;
+            b->tw = tw;
+            return write_table(b);
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const auto t_start = std::chrono::steady_clock::now();
+    auto elapsed_ms = [&] {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    auto time_launch = [&](const BulkCase *cases, const int *blk, int nblk, int bw, float &best) -> lbm_status {
+        best = 1e30f;
+        launch_bulk_batch(b->storage, bw, cases, blk, nblk, 0, b->main);  // warm-up
+        for (int r = 0; r < 3; ++r) {
+            HIPCHK(hipEventRecord(e0, b->main));
+            launch_bulk_batch(b->storage, bw, cases, blk, nblk, 0, b->main);
+            HIPCHK(hipEventRecord(e1, b->main));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        return LBM_OK;
+    };
+    // per system: the wave tile (one system per launch; the result buffer is
+    // overwritten by the next step at every node the kernel touches)
+    std::vector<int> blk1;
+    lbm_status st = LBM_OK;
+    std::map<std::string, int> seen;
+    for (int i = 0; i < b->n && st == LBM_OK; ++i) {
+        const std::string key = case_key(b->cs[i]);
+        if (seen.count(key)) { b->tw[i] = seen[key]; continue; }
+        if (elapsed_ms() > budget_ms) break;
+        float best_ms = 1e30f;
+        int best_t = b->tw[i];
+        for (int t : TW_CANDIDATES) {
+            BulkCase h = bulk_case(b->cs[i], t, 8, 0);
+            blk1.assign(h.n_blocks, b->n);
+            if (blk1.size() > b->blk1_cap) continue;
+            st = hipMemcpy(b->d_cases + b->n, &h, sizeof h, hipMemcpyHostToDevice) == hipSuccess ? LBM_OK
+                 : fail(LBM_E_HIP, "hipMemcpy");
+            if (st) break;
+            st = hipMemcpy(b->d_blk1, blk1.data(), 4 * blk1.size(), hipMemcpyHostToDevice) == hipSuccess ? LBM_OK
+                 : fail(LBM_E_HIP, "hipMemcpy");
+            if (st) break;
+            float ms;
+            st = time_launch(b->d_cases, b->d_blk1, h.n_blocks, 8, ms);
+            if (st) break;
+            if (ms < best_ms) { best_ms = ms; best_t = t; }
+        }
+        b->tw[i] = best_t;
+        seen[key] = best_t;
+    }
+    // whole ensemble: waves per block
+    if (st == LBM_OK && elapsed_ms() <= budget_ms) {
+        float best_ms = 1e30f;
+        int best_bw = b->bw;
+        for (int bw : {8, 4}) {
+            b->bw = bw;
+            st = write_table(b);
+            if (st) break;
+            float ms;
+            st = time_launch(b->d_cases, b->d_blk, b->nblocks, bw, ms);
+            if (st) break;
+            if (ms < best_ms) { best_ms = ms; best_bw = bw; }
+        }
+        b->bw = best_bw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    st = write_table(b);
+    if (st) return st;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "wb")) {
+            std::fprintf(f, "{\"bw\": %d, \"tiles\": {", b->bw);
+            std::map<std::string, int> all;
+            for (int i = 0; i < b->n; ++i) all[case_key(b->cs[i])] = b->tw[i];
+            bool first = true;
+            for (auto &kv : all) {
+                std::fprintf(f, "%s\"%s\": %d", first ? "" : ", ", kv.first.c_str(), kv.second);
+                first = false;
+            }
+            std::fprintf(f, "}}\n");
+            std::fclose(f);
+        } else {
+            return fail(LBM_E_INVALID, "cannot write %s", cache_path);
+        }
+    }
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b) { free_batch(b); }
 
 }  // extern "C"

@@ -90,6 +90,22 @@ struct ContactBufs {
     double *xiW;     // [np*6][3] tangential springs, walls
 };
 
+// One system of an ensemble as seen by the batched stream-collide: sizes,
+// collision constants, tile shape and block range, and the buffers of a step
+// of either parity (parity 0: the assignment when the table was written).
+struct BulkCase {
+    int nx, ny, nz;
+    unsigned periodic;
+    long long N;
+    float rho0f, omega, fcoef, gx, gy, gz, scale, inv_scale;
+    int tw_log2;      // wave tile: 2^tw_log2 consecutive x by 64 >> tw_log2 rows of y
+    int nsx, nsy;     // tiles along x and along y per z plane
+    int first_block;  // first block of this system in the launch
+    int n_blocks;     // blocks of this system
+    void *A[2], *B[2];
+    const uint8_t *skip[2];
+};
+
 // Region block map: block b of a region kernel works on particle part[b],
 // local region indices [first[b], first[b] + BLK).
 struct RegionMap {

@@ -16,7 +16,8 @@
 //   k_special        boundary and uncovered nodes: pull with bounce-back or
 //                    refill (sec. 2.3.2, refilling equation), then collide
 //   k_link_emit      cut-link list of the new geometry (masks and counts from
-//                    the classification), link fractions q by a safeguarded
+//                    the classification)
+//   k_link_q         link fractions q, eight lanes per link, by a safeguarded
 //                    Newton iteration in FP64
 // Populations are deviations f_i - w_i rho0 in FP32, FP16 or BF16 storage;
 // collisions run in FP32, everything geometric or mechanical in FP64.
@@ -160,60 +161,73 @@ __device__ double metaball(const Params &p, const CPs &P, const double x[3]) {
     return C;
 }
 
-// C and dC/ds along x(s) = xf - s e (one reciprocal per control point).
-__device__ void metaball_ds(const Params &p, const CPs &P, const double xf[3], const int e[3],
-                            double s, double &C, double &dC) {
+// C and dC/ds at x_f - s e_i for one link held by an aligned group of eight
+// lanes: lane j sums control points j, j + 8, ... and the group adds its
+// partial sums by a butterfly, which leaves the same bits in every lane.
+__device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], const int e[3], double s,
+                             double &C, double &dC) {
 #pragma clang fp contract(off)
-    C = 0.0; dC = 0.0;
     const double xs[3] = {xf[0] - s * e[0], xf[1] - s * e[1], xf[2] - s * e[2]};
-    for (int i0 = 0; i0 < P.n; i0 += 4) {
-        double kr[4], g[4];
-        bool hit = false;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u;
-            double d[3] = {xs[0] - P.x[i][0], xs[1] - P.x[i][1], xs[2] - P.x[i][2]};
-            min_image(p, d);
-            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            hit |= r2 == 0.0;
-            const double inv = 1.0 / r2;
-            kr[u] = P.k[i] * inv;
-            g[u] = 2.0 * kr[u] * inv * (d[0] * e[0] + d[1] * e[1] + d[2] * e[2]);
+    double c = 0.0, g = 0.0;
+    for (int i = threadIdx.x & 7; i < P.n; i += 8) {
+        double d[3] = {xs[0] - P.x[i][0], xs[1] - P.x[i][1], xs[2] - P.x[i][2]};
+        min_image(p, d);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 == 0.0) {
+            c = __builtin_inf();
+            continue;
         }
-        if (hit) { C = __builtin_inf(); dC = 0.0; return; }
-        C += kr[0] + kr[1] + kr[2] + kr[3];
-        dC += g[0] + g[1] + g[2] + g[3];
+        const double inv = 1.0 / r2;
+        const double kr = P.k[i] * inv;
+        c += kr;
+        g += 2.0 * kr * inv * (d[0] * e[0] + d[1] * e[1] + d[2] * e[2]);
     }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+        c += __shfl_xor(c, o);
+        g += __shfl_xor(g, o);
+    }
+    C = c;
+    dC = g;
 }
 
-// Link fraction (sec. 2.3.2): first root of g(s) = C(xf - s e) - 1 on (0,1].
-// The root is bracketed in the first of 8 equal sub-intervals where g changes
-// sign, then refined by Newton steps from the regula-falsi point (or from
-// 'guess' when it lies in the bracket); a step that would leave the bracket
-// or does not at least halve the last step is replaced by bisection.
-// Returns the number of iterations.
-__device__ int link_fraction(const Params &p, const CPs &P, int x, int y, int z, int i, double guess,
-                             double &q) {
+// Link fraction q (sec. 2.3.2): the first root of C(x_f - s e_i) = 1 on
+// (0,1], for one link by an aligned group of eight lanes (all active).
+// Bracket: lane j evaluates C at s = (j + 1)/8 with the flagging's
+// arithmetic, and the first of the eight sub-interval ends with C >= 1 closes
+// the bracket (none: q = 1).  Then a safeguarded Newton iteration
+// (rtsafe-style: a Newton step that leaves the bracket or does not halve the
+// step falls back to bisection) to |step| < 1e-13, started at the guess when
+// it lies inside the bracket, else by regula falsi on the bracket ends.
+// Every lane returns the same q; the return value is the number of
+// evaluations of the iteration.
+__device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z, int i, double guess,
+                              double &q) {
+    const int lane = threadIdx.x & 63, j = lane & 7, base = lane & 56;
     const double xf[3] = {(double)x, (double)y, (double)z};
     const int e[3] = {EX[i], EY[i], EZ[i]};
-    double lo = 0.0, hi = 1.0, glo, ghi = 0.0, C, dC;
-    metaball_ds(p, P, xf, e, 0.0, C, dC);
-    glo = C - 1.0;
-    for (int k = 1; k <= 8; ++k) {
-        const double s = (double)k / 8.0;
-        metaball_ds(p, P, xf, e, s, C, dC);
-        if (C >= 1.0) { hi = s; ghi = C - 1.0; break; }
-        lo = s; glo = C - 1.0;
+    const double sj = (double)(j + 1) / 8.0;
+    const double xj[3] = {xf[0] - sj * e[0], xf[1] - sj * e[1], xf[2] - sj * e[2]};
+    const double Cj = metaball(p, P, xj);
+    const unsigned grp = (unsigned)((__ballot(Cj >= 1.0) >> base) & 0xffull);
+    const int k0 = grp ? __ffs(grp) - 1 : 7;
+    const double Chi = __shfl(Cj, base + k0), Clo = __shfl(Cj, base + (k0 > 0 ? k0 - 1 : 0));
+    if (!grp) {
+        q = 1.0;
+        return 0;
     }
+    double lo = k0 / 8.0, hi = (k0 + 1) / 8.0;
+    const double ghi = Chi - 1.0, glo = Clo - 1.0;
     double s;
     if (guess > lo && guess < hi) s = guess;
-    else if (ghi < __builtin_inf()) s = lo + (hi - lo) * (-glo) / (ghi - glo);
+    else if (k0 > 0 && ghi < __builtin_inf()) s = lo + (hi - lo) * (-glo) / (ghi - glo);
     else s = 0.5 * (lo + hi);
     if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
     double dxold = hi - lo, dx = dxold;
     int it = 0;
     while (it < 100) {
-        metaball_ds(p, P, xf, e, s, C, dC);
+        double C, dC;
+        metaball_ds8(p, P, xf, e, s, C, dC);
         ++it;
         const double g = C - 1.0;
         if (g >= 0.0) hi = s; else lo = s;
@@ -1003,26 +1017,14 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     if (threadIdx.x == 0) blk_cnt[blockIdx.x] = s;
 }
 
-// Plain fluid nodes (skip mask clear: fluid with no solid neighbour at the
+// Plain fluid node (skip mask clear: fluid with no solid neighbour at the
 // start of the step): pull-stream (periodic wrap, resting halfway walls) and
-// collide.  One wave covers 64 consecutive x of one (y, z) row; a block of 8
-// waves takes consecutive rows in lattice order (the hardware spreads
-// consecutive blocks over the XCDs).  Results are written with
-// non-temporal stores: they are not read again within the step.
-constexpr int BULK_WAVES = 8;
+// collide.  Results are written with non-temporal stores: they are not read
+// again within the step.
 template <int S>
-__global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typename Store<S>::T *__restrict__ A,
-                                                          typename Store<S>::T *__restrict__ B,
-                                                          const uint8_t *__restrict__ skip, int nseg) {
+__device__ __forceinline__ void bulk_update(const Params &p, const typename Store<S>::T *__restrict__ A,
+                                            typename Store<S>::T *__restrict__ B, int x, int y, int z, int n) {
     using T = typename Store<S>::T;
-    const int wave = blockIdx.x * BULK_WAVES + (threadIdx.x >> 6);
-    const int seg = wave % nseg, row = wave / nseg;
-    if (row >= p.ny * p.nz) return;
-    const int x = seg * 64 + (threadIdx.x & 63);
-    if (x >= p.nx) return;
-    const int y = row % p.ny, z = row / p.ny;
-    const int n = row * p.nx + x;
-    if (skip[n]) return;
     // source coordinates for e = -1, 0, +1 on each axis (wrapped), -1 = wall
     int sx[3], sy[3], sz[3];
     sx[1] = x; sy[1] = y; sz[1] = z;
@@ -1047,6 +1049,54 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typena
     collide(d, p);
 #pragma unroll
     for (int i = 0; i < Q; ++i) Store<S>::st_nt(B + (long long)i * p.N, n, d[i], p.scale);
+}
+
+// One system: one wave covers 64 consecutive x of one (y, z) row; a block of
+// 8 waves takes consecutive rows in lattice order (the hardware spreads
+// consecutive blocks over the XCDs).
+constexpr int BULK_WAVES = 8;
+template <int S>
+__global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typename Store<S>::T *__restrict__ A,
+                                                          typename Store<S>::T *__restrict__ B,
+                                                          const uint8_t *__restrict__ skip, int nseg) {
+    const int wave = blockIdx.x * BULK_WAVES + (threadIdx.x >> 6);
+    const int seg = wave % nseg, row = wave / nseg;
+    if (row >= p.ny * p.nz) return;
+    const int x = seg * 64 + (threadIdx.x & 63);
+    if (x >= p.nx) return;
+    const int y = row % p.ny, z = row / p.ny;
+    const int n = row * p.nx + x;
+    if (skip[n]) return;
+    bulk_update<S>(p, A, B, x, y, z, n);
+}
+
+// An ensemble of systems in one launch: the block table names each block's
+// system; within a system a wave covers a tile of 2^tw_log2 consecutive x by
+// 64 / 2^tw_log2 rows of y (the tile shape is chosen per system by the
+// autotuner), BW waves per block, tiles in lattice order.
+template <int S, int BW>
+__global__ __launch_bounds__(64 * BW) void k_bulk_batch(const BulkCase *__restrict__ cases,
+                                                        const int *__restrict__ blk_case, int parity) {
+    using T = typename Store<S>::T;
+    const BulkCase &c = cases[blk_case[blockIdx.x]];
+    const int wave = ((int)blockIdx.x - c.first_block) * BW + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int per_plane = c.nsx * c.nsy;
+    const int z = wave / per_plane;
+    if (z >= c.nz) return;
+    const int r = wave - z * per_plane;
+    const int ty = r / c.nsx, tx = r - ty * c.nsx;
+    const int x = (tx << c.tw_log2) + (lane & ((1 << c.tw_log2) - 1));
+    const int y = ty * (64 >> c.tw_log2) + (lane >> c.tw_log2);
+    if (x >= c.nx || y >= c.ny) return;
+    const int n = (z * c.ny + y) * c.nx + x;
+    if (c.skip[parity][n]) return;
+    Params p;
+    p.nx = c.nx; p.ny = c.ny; p.nz = c.nz; p.periodic = c.periodic; p.N = c.N;
+    p.rho0f = c.rho0f; p.omega = c.omega; p.fcoef = c.fcoef;
+    p.gx = c.gx; p.gy = c.gy; p.gz = c.gz;
+    p.scale = c.scale; p.inv_scale = c.inv_scale;
+    bulk_update<S>(p, (const T *)c.A[parity], (T *)c.B[parity], x, y, z, n);
 }
 
 // Boundary and uncovered nodes, one wave per node, lane i < 19 owning
@@ -1167,23 +1217,17 @@ __global__ void k_fill_u8(uint8_t *a, long long n, uint8_t v) {
 
 // Link build, second pass: each block finds its offset in the particle-major
 // list by summing the counts of the blocks before it (the first block of a
-// body also records the body's offset, the last block the total), lists its
-// links in LDS (masks from the classification; thread order, then direction
-// order) and solves one link per thread with the body's control points in
-// LDS.
+// body also records the body's offset, the last block the total) and lists
+// its links (masks from the classification; thread order, then direction
+// order).  The link fractions follow in k_link_q.
 __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const DevParticle *P,
                                                    const uint32_t *__restrict__ lmask,
                                                    const int *__restrict__ blk_cnt,
                                                    const int *__restrict__ part_first_blk, int *__restrict__ l_off,
                                                    uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
-                                                   double *__restrict__ l_q, Counters *cnt, int32_t *clear) {
-    __shared__ CPs cps;
+                                                   Counters *cnt, int32_t *clear) {
     __shared__ int sh[BLK];
-    __shared__ int sxyz[BLK][3];
-    __shared__ uint32_t snode[BLK];
-    __shared__ uint16_t lk[BLK * 18];
     const int t = threadIdx.x;
-    stage_cps(cps, P[rm.part[blockIdx.x]]);
     int before = 0;
     for (int b = t; b < (int)blockIdx.x; b += BLK) before += blk_cnt[b];
     const int base = block_sum(before, sh);
@@ -1205,8 +1249,6 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
     if (in && clear) clear[n] = FLUID;
     const int c = __popc(m);
     sh[t] = c;
-    sxyz[t][0] = x; sxyz[t][1] = y; sxyz[t][2] = z;
-    snode[t] = (uint32_t)n;
     __syncthreads();
     for (int h = 1; h < BLK; h <<= 1) {
         const int v = t >= h ? sh[t - h] : 0;
@@ -1214,27 +1256,74 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
         sh[t] += v;
         __syncthreads();
     }
-    int o = sh[t] - c;
+    int o = base + sh[t] - c;
     for (int i = 1; i < Q; ++i)
-        if ((m >> i) & 1u) lk[o++] = (uint16_t)((t << 5) | i);
-    __syncthreads();
-    const int total = sh[BLK - 1];
-    int it_sum = 0;
-    for (int j = t; j < total; j += BLK) {
-        const int tt = lk[j] >> 5, i = lk[j] & 31;
-        const int oo = base + j;
-        if (oo >= p.link_cap) continue;
-        double q;
-        it_sum += link_fraction(p, cps, sxyz[tt][0], sxyz[tt][1], sxyz[tt][2], i, -1.0, q);
-        l_node[oo] = snode[tt];
-        l_do[oo] = (uint32_t)i | ((uint32_t)pid << 8);
-        l_q[oo] = q;
+        if ((m >> i) & 1u) {
+            if (o < p.link_cap) {
+                l_node[o] = (uint32_t)n;
+                l_do[o] = (uint32_t)i | ((uint32_t)pid << 8);
+            }
+            ++o;
+        }
+}
+
+// Link build, third pass: the link fractions of the whole list, eight lanes
+// per link (32 links per block, blocks stride over the list), each group
+// with its body's control points staged in its own LDS slot.
+__global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__restrict__ P,
+                                                const uint32_t *__restrict__ l_node,
+                                                const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
+                                                Counters *cnt) {
+    __shared__ CPs cps[32];
+    __shared__ int sh[256];
+    const int t = threadIdx.x, g = t >> 3, j = t & 7;
+    const int nl = min(cnt->n_links, p.link_cap);
+    int it_sum = 0, links = 0;
+    for (int l0 = blockIdx.x * 32; l0 < nl; l0 += gridDim.x * 32) {  // block-uniform trip count
+        const int l = l0 + g;
+        const bool ok = l < nl;
+        int pid = 0, i = 1;
+        long long n = 0;
+        if (ok) {
+            n = l_node[l];
+            i = (int)(l_do[l] & 31u);
+            pid = (int)(l_do[l] >> 8);
+            if (n >= p.N || pid >= p.np || i < 1 || i >= Q) {  // never expected: report, solve nothing
+                if (j == 0) atomicOr(&cnt->err, ERR_BAD_INDEX);
+                pid = -1;
+            }
+        }
+        if (ok && pid >= 0) {  // stage this group's control points (padded to a multiple of 4, weight 0)
+            const DevParticle &B = P[pid];
+            const int n4 = (B.n_cp + 3) & ~3;
+            for (int e = j; e < n4 * 4; e += 8) {
+                const int k = e >> 2, a = e & 3;
+                const int src = k < B.n_cp ? k : 0;
+                if (a < 3) cps[g].x[k][a] = B.cpl[src][a];
+                else cps[g].k[k] = k < B.n_cp ? B.k[k] : 0.0;
+            }
+            if (j == 0) cps[g].n = n4;
+        }
+        __syncthreads();
+        if (ok && pid >= 0) {
+            int x, y, z;
+            node_xyz(p, n, x, y, z);
+            double q;
+            const int its = link_fraction8(p, cps[g], x, y, z, i, -1.0, q);
+            if (j == 0) {
+                l_q[l] = q;
+                it_sum += its;
+                ++links;
+            }
+        }
+        __syncthreads();  // the group slots are restaged in the next round
     }
-    __syncthreads();  // every thread has read its scan values before sh is reused
     const int its = block_sum(it_sum, sh);
-    if (t == 0 && total > 0) {
+    __syncthreads();
+    const int nls = block_sum(links, sh);
+    if (t == 0 && nls > 0) {
         atomicAdd(&cnt->nr_iters, (unsigned long long)its);
-        atomicAdd(&cnt->nr_links, (unsigned long long)min(total, max(0, p.link_cap - base)));
+        atomicAdd(&cnt->nr_links, (unsigned long long)nls);
     }
 }
 
@@ -1275,7 +1364,9 @@ static void launch_step_kernels_t(const StepArgs &a) {
         if (p.np > 0) {
             k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt,
                                                                 a.part_first_blk, a.l_off,
-                                                                a.l_node, a.l_do, a.l_q, a.cnt, a.own_dead);
+                                                                a.l_node, a.l_do, a.cnt, a.own_dead);
+            k_link_q<<<max(1, min(cdiv(p.link_cap, 32), 2048)), 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do,
+                                                                                    a.l_q, a.cnt);
         }
     } else if (a.phase == PHASE_INIT_STATE) {
         k_init_state<S><<<2048, 256, 0, a.stream>>>(p, A, a.own_old);
@@ -1298,6 +1389,21 @@ void launch_fill_i32(int32_t *a, long long n, int32_t v, hipStream_t s) {
 void launch_fill_u8(uint8_t *a, long long n, uint8_t v, hipStream_t s) {
     k_fill_u8<<<2048, 256, 0, s>>>(a, n, v);
 }
+template <int S>
+static void launch_bulk_batch_t(int bw, const BulkCase *cases, const int *blk_case, int nblocks, int parity,
+                                hipStream_t s) {
+    if (nblocks <= 0) return;
+    if (bw == 4) k_bulk_batch<S, 4><<<nblocks, 256, 0, s>>>(cases, blk_case, parity);
+    else k_bulk_batch<S, 8><<<nblocks, 512, 0, s>>>(cases, blk_case, parity);
+}
+
+void launch_bulk_batch(int storage, int bw, const BulkCase *cases, const int *blk_case, int nblocks, int parity,
+                       hipStream_t s) {
+    if (storage == 1) launch_bulk_batch_t<1>(bw, cases, blk_case, nblocks, parity, s);
+    else if (storage == 2) launch_bulk_batch_t<2>(bw, cases, blk_case, nblocks, parity, s);
+    else launch_bulk_batch_t<0>(bw, cases, blk_case, nblocks, parity, s);
+}
+
 void launch_reset_counters(Counters *cnt, hipStream_t s) { k_reset_counters<<<1, 1, 0, s>>>(cnt); }
 void launch_refresh_pose(const Params &p, DevParticle *P, hipStream_t s) {
     if (p.np > 0) k_refresh_pose<<<cdiv(p.np, 64), 64, 0, s>>>(p, P);

@@ -45,6 +45,9 @@ void launch_phase(const StepArgs &a);
 void launch_fill_i32(int32_t *a, long long n, int32_t v, hipStream_t s);
 void launch_fill_u8(uint8_t *a, long long n, uint8_t v, hipStream_t s);
 void launch_reset_counters(Counters *cnt, hipStream_t s);
+// Batched stream-collide of an ensemble (bw: waves per block, 4 or 8).
+void launch_bulk_batch(int storage, int bw, const BulkCase *cases, const int *blk_case, int nblocks, int parity,
+                       hipStream_t s);
 void launch_refresh_pose(const Params &p, DevParticle *P, hipStream_t s);
 
 }  // namespace mdl

@@ -153,7 +153,7 @@ def config4_case(b: int, ragged: bool = False) -> Config:
     off, k = random_body(rng, n_cp, R)
     p = Particle(cp_xyz=off, cp_k=k, x=np.zeros(3), density=ratio)
     rb = p.bounding_radius()
-    p.x = np.array([nx / 2, ny / 2, max(nz - rb - 4.0, nz / 2)])
+    p.x = np.array([nx / 2, ny / 2, max(nz - rb - 8.0, nz / 2)])
     return Config(nx=nx, ny=ny, nz=nz, periodic=0, tau=tau, rho0=1.0,
                   g_particle=np.array([0.0, 0.0, -2e-5]), bc=BC_IBB, particles=[p],
                   name=f"cfg4-case{b}", steps=1000)
@@ -161,6 +161,31 @@ def config4_case(b: int, ragged: bool = False) -> Config:
 
 def config4(n_cases: int = 64) -> List[Config]:
     return [config4_case(b) for b in range(n_cases)]
+
+
+def mini_ensemble(n_cases: int = 4, seed: int = 4100) -> List[Config]:
+    """Small walled settling systems of different sizes (one ragged, not a
+    multiple of 8), tau, density ratio and number of control points, with a
+    gravity large enough that each body covers and uncovers nodes within
+    tens of steps (ensemble tests)."""
+    rng = _rng(seed)
+    out = []
+    for b in range(n_cases):
+        nx, ny, nz = (int(v) for v in rng.integers(24, 41, size=3))
+        nz += 16
+        if b == 0:
+            nx, ny, nz = 37, 29, 45
+        n_cp = int(rng.integers(4, 12))
+        tau = float(rng.uniform(0.55, 1.0))
+        ratio = float(rng.uniform(1.1, 2.5))
+        R = 0.16 * min(nx, ny)
+        off, k = random_body(rng, n_cp, R)
+        p = Particle(cp_xyz=off, cp_k=k, x=np.array([nx / 2 + 0.3, ny / 2 - 0.2, nz * 0.6]),
+                     density=ratio, omega=np.array([0.001, 0.0, 0.002]))
+        out.append(Config(nx=nx, ny=ny, nz=nz, periodic=0, tau=tau, rho0=1.0,
+                          g_particle=np.array([0.0, 0.0, -4e-4]), bc=BC_IBB, particles=[p],
+                          name=f"mini{b}-{nx}x{ny}x{nz}"))
+    return out
 
 
 def config5(n_bodies: int = 200, box: int = 256, seed: int = 5,
