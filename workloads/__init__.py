@@ -333,3 +333,15 @@ def suspension_small(n_bodies: int = 6, box: int = 48, seed: int = 51, bc: int =
                   g_particle=np.array([0.0, 0.0, -2e-4]), particles=bodies, contact_rs=1.0,
                   contact_kn=20.0, contact_en=0.5, contact_mu=0.5, quad_h=0.25,
                   name=f"suspension-{box}-{n_bodies}")
+
+
+def mlp_init(seed: int = 7):
+    """Initial weights of the 87-64-64-4 warm-start MLP (parameter order
+    W1, b1, W2, b2, W3, b3): Xavier-uniform weights, zero biases."""
+    rng = _rng(seed)
+    parts = []
+    for fan_in, fan_out in ((87, 64), (64, 64), (64, 4)):
+        a = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(rng.uniform(-a, a, size=(fan_in, fan_out)).reshape(-1))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts)
