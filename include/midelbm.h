@@ -207,6 +207,65 @@ lbm_status lbm_sync(lbm_ctx *ctx);
 void lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(void);
 
+/* ---- warm start of the link fractions (spec form: an MLP trained on
+ * the method's own Newton solutions) ----
+ * The link fraction q of a cut link is the first root of C(x_f - s e_i) = 1
+ * on (0,1] (sec. 2.3.2), bracketed by eight samples and found by a
+ * safeguarded Newton iteration.  A small MLP (87 inputs -> 64 -> 64 -> 4,
+ * tanh hidden layers, linear output; FP16 weights and activations with FP32
+ * sums) can supply the starting point.  Inputs of a link: the fluid node
+ * relative to the centroid and the direction e_i, both in the body frame, the
+ * node scaled by 1/sqrt(sum k); a task bit (0: link fraction); the body's
+ * control points in the body frame sorted by weight (largest first), each
+ * (p/sqrt(sum k), k/sum k), zero-padded to 20.  Output 0 is the q guess
+ * (outputs 1..3 belong to a closest-point task, trained only when its bit
+ * is set).  The guess is used only when it lies inside the bracket, and a
+ * warm-started iteration not converged within 30 evaluations is redone from
+ * the plain start, so the root found is the plain one (within the Newton
+ * tolerance): the residual C - 1 judges the guess.
+ *
+ * Parameters: P = mlp_param_count() = 10052 FP32 values in the order
+ * W1 [87][64], b1 [64], W2 [64][64], b2 [64], W3 [64][4], b3 [4] (a layer
+ * computes z = h W + b).  A weights blob is caller-owned device memory of
+ * mlp_weights_bytes() bytes, 256-byte aligned: FP32 parameters, Adam
+ * moments and step count, the FP16 copy, and the training workspace. */
+size_t mlp_weights_bytes(void);
+int32_t mlp_param_count(void);
+/* Loads the FP32 parameters (host [P]) and resets the Adam state; syncs. */
+lbm_status mlp_init(void *dev_weights, const float *params, void *hip_stream);
+/* Copies the FP32 parameters to the host [P]; synchronises the stream. */
+lbm_status mlp_get_params(const void *dev_weights, float *params, void *hip_stream);
+/* Training samples from the context's current cut links: features
+ * dev_feat [n][87] FP16 and targets dev_target [n][4] FP32 (q, 0, 0, 0),
+ * n = min(n_max, links); synchronises. */
+lbm_status mlp_collect(lbm_ctx *ctx, int64_t n_max, void *dev_feat, void *dev_target, int64_t *n_out);
+/* Outputs [n][4] FP32 of the network for features [n][87]: precision 0 =
+ * FP16 features/weights/activations (the production form), 1 = FP32
+ * throughout (a test instantiation; features are then FP32).  Enqueued on
+ * the stream; uses the blob's workspace. */
+lbm_status mlp_forward(void *dev_weights, const void *dev_feat, int64_t n, int32_t precision, float *dev_out,
+                       void *hip_stream);
+/* Gradient (host [P], FP32) and loss of one batch of n <= 4096 samples:
+ * loss = (1/n) sum over samples of the squared errors of the targeted
+ * outputs (output 0 when the task bit is 0, outputs 1..3 otherwise);
+ * synchronises. */
+lbm_status mlp_grad(void *dev_weights, const void *dev_feat, const void *dev_target, int64_t n,
+                    int32_t precision, float *grad, double *loss, void *hip_stream);
+/* Adam over sequential minibatches of the n samples (in the order given),
+ * for the epochs given.  hparams_json: a flat object with any of "lr"
+ * (1e-3), "epochs" (1), "batch" (256, at most 4096), "beta1" (0.9), "beta2"
+ * (0.999), "eps" (1e-8), "precision" (0).  The step count persists in the
+ * blob across calls.  Synchronises. */
+lbm_status mlp_train(void *dev_feat, void *dev_target, int64_t n, const char *hparams_json, void *dev_weights,
+                     void *hip_stream);
+/* Warm-starts the link fractions of the context with the blob's FP16
+ * weights from now on (the blob must stay alive); NULL: plain Newton. */
+lbm_status lbm_set_warmstart(lbm_ctx *ctx, const void *dev_weights);
+/* Histogram of Newton evaluations per solved link since the last call
+ * (hist[65], last bin: 64 or more) and the largest |C - 1| at a link's last
+ * evaluation; resets both; synchronises. */
+lbm_status lbm_nr_histogram(lbm_ctx *ctx, int64_t *hist, double *resid_max);
+
 /* ---- ensemble of independent systems ----
  * n_cases systems (each as lbm_init would set it up: configs cfgs[i],
  * particles parts[n_p[0] + ... + n_p[i-1] ...] concatenated) stepped

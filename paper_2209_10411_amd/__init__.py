@@ -62,7 +62,9 @@ EXPORTS = ["lbm_arena_bytes", "lbm_init", "metaball_flag", "lbm_step", "particle
            "lbm_destroy",
            "lbm_last_error",
            "lbm_batch_arena_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_case", "lbm_autotune",
-           "lbm_batch_tiles", "lbm_batch_destroy"]
+           "lbm_batch_tiles", "lbm_batch_destroy",
+           "mlp_weights_bytes", "mlp_param_count", "mlp_init", "mlp_get_params", "mlp_collect", "mlp_forward",
+           "mlp_grad", "mlp_train", "lbm_set_warmstart", "lbm_nr_histogram"]
 
 _lib = None
 
@@ -112,8 +114,22 @@ def lib():
         L.lbm_batch_tiles.argtypes = [vp, ip, ip]
         L.lbm_batch_destroy.argtypes = [vp]
         L.lbm_batch_destroy.restype = None
+        L.mlp_weights_bytes.argtypes = []
+        L.mlp_weights_bytes.restype = C.c_size_t
+        L.mlp_param_count.argtypes = []
+        L.mlp_param_count.restype = C.c_int32
+        fp = C.POINTER(C.c_float)
+        L.mlp_init.argtypes = [vp, fp, vp]
+        L.mlp_get_params.argtypes = [vp, fp, vp]
+        L.mlp_collect.argtypes = [vp, C.c_int64, vp, vp, C.POINTER(C.c_int64)]
+        L.mlp_forward.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, vp]
+        L.mlp_grad.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, fp, dp, vp]
+        L.mlp_train.argtypes = [vp, vp, C.c_int64, C.c_char_p, vp, vp]
+        L.lbm_set_warmstart.argtypes = [vp, vp]
+        L.lbm_nr_histogram.argtypes = [vp, C.POINTER(C.c_int64), dp]
         for name in EXPORTS:
-            if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy"):
+            if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy", "mlp_weights_bytes",
+                            "mlp_param_count"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -318,6 +334,18 @@ class Simulation:
         _check(lib().lbm_contact_stats(self._ctx, C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)
 
+    def nr_histogram(self):
+        """(histogram of Newton evaluations per link [65], largest final |C - 1|) since the last call."""
+        h = np.zeros(65, dtype=np.int64)
+        r = C.c_double(0)
+        _check(lib().lbm_nr_histogram(self._ctx, h.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(r)))
+        return h, float(r.value)
+
+    def set_warmstart(self, mlp):
+        """Warm-start the link fractions with an ``Mlp`` (None: plain Newton)."""
+        self._warm = mlp
+        _check(lib().lbm_set_warmstart(self._ctx, C.c_void_p(mlp.blob.data_ptr()) if mlp is not None else None))
+
     def timing(self, on: bool = True):
         _check(lib().lbm_timing_enable(self._ctx, int(bool(on))))
 
@@ -387,3 +415,73 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+class Mlp:
+    """Warm-start MLP parameters, Adam state and workspace in one device blob
+    (include/midelbm.h, warm start)."""
+
+    N_IN, N_OUT = 87, 4
+
+    def __init__(self, params, device: str = "cuda:0", stream=None):
+        import torch
+
+        L = lib()
+        self.P = int(L.mlp_param_count())
+        self.device = torch.device(device)
+        self.blob = torch.empty(int(L.mlp_weights_bytes()), dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.load(params)
+
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def load(self, params):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != self.P:
+            raise ValueError(f"expected {self.P} parameters")
+        _check(lib().mlp_init(C.c_void_p(self.blob.data_ptr()), a.ctypes.data_as(C.POINTER(C.c_float)), self._s()))
+
+    def params(self) -> np.ndarray:
+        a = np.zeros(self.P, dtype=np.float32)
+        _check(lib().mlp_get_params(C.c_void_p(self.blob.data_ptr()), a.ctypes.data_as(C.POINTER(C.c_float)),
+                                    self._s()))
+        return a
+
+    def forward(self, feat, precision: int = 0):
+        """feat: device tensor [n][87] (float16 for precision 0, float32 for 1)."""
+        import torch
+        n = feat.shape[0]
+        out = torch.empty((n, self.N_OUT), dtype=torch.float32, device=self.device)
+        _check(lib().mlp_forward(C.c_void_p(self.blob.data_ptr()), C.c_void_p(feat.data_ptr()), n, int(precision),
+                                 C.c_void_p(out.data_ptr()), self._s()))
+        return out
+
+    def grad(self, feat, target, precision: int = 0):
+        g = np.zeros(self.P, dtype=np.float32)
+        loss = C.c_double(0)
+        _check(lib().mlp_grad(C.c_void_p(self.blob.data_ptr()), C.c_void_p(feat.data_ptr()),
+                              C.c_void_p(target.data_ptr()), feat.shape[0], int(precision),
+                              g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss), self._s()))
+        return g, float(loss.value)
+
+    def train(self, feat, target, **hp):
+        import json
+        _check(lib().mlp_train(C.c_void_p(feat.data_ptr()), C.c_void_p(target.data_ptr()), feat.shape[0],
+                               json.dumps(hp).encode(), C.c_void_p(self.blob.data_ptr()), self._s()))
+
+
+def mlp_collect(sim, n_max: int | None = None):
+    """Training samples (features float16 [n][87], targets float32 [n][4])
+    from the current cut links of a Simulation."""
+    import torch
+    L = lib()
+    if n_max is None:
+        n_max = len(sim.links()[0])
+    feat = torch.empty((n_max, Mlp.N_IN), dtype=torch.float16, device="cuda:0")
+    target = torch.empty((n_max, Mlp.N_OUT), dtype=torch.float32, device="cuda:0")
+    n = C.c_int64(0)
+    _check(L.mlp_collect(sim._ctx, int(n_max), C.c_void_p(feat.data_ptr()), C.c_void_p(target.data_ptr()),
+                         C.byref(n)))
+    return feat[:n.value], target[:n.value]

@@ -4,7 +4,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "api.cpp")]
+SRC = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "mlp.hip"),
+       os.path.join(HERE, "csrc", "api.cpp")]
 LIB = os.path.join(HERE, "libmidelbm.so")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

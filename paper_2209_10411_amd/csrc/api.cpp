@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -17,6 +18,7 @@
 #include "../../include/midelbm.h"
 #include "device.h"
 #include "launch.h"
+#include "mlp_dev.h"
 
 using namespace mdl;
 
@@ -41,6 +43,20 @@ lbm_status fail(lbm_status s, const char *fmt, ...) {
     } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// value of "key": <number> in a small flat JSON text (false if absent)
+bool json_num(const std::string &txt, const char *key, double &v) {
+    const std::string pat = std::string("\"") + key + "\"";
+    size_t at = txt.find(pat);
+    if (at == std::string::npos) return false;
+    at = txt.find(':', at + pat.size());
+    if (at == std::string::npos) return false;
+    char *end = nullptr;
+    const double r = std::strtod(txt.c_str() + at + 1, &end);
+    if (end == txt.c_str() + at + 1) return false;
+    v = r;
+    return true;
+}
 
 // Body properties by midpoint quadrature: cells of size h on a grid centred
 // on the box [min p - sqrt(sum k), max p + sqrt(sum k)] (C >= 1 needs some
@@ -163,7 +179,7 @@ struct Plan {
         off_pfb, off_bcnt, off_loff, off_lnode, off_ldo, off_lq, off_lpart, off_special,
         off_cnt, total;
     bool contact;
-    size_t off_lmask;
+    size_t off_lmask, off_nrs, off_mlpb;
     size_t off_pairF, off_pairTi, off_pairTj, off_wallF, off_wallT, off_xiP, off_xiW;
 };
 
@@ -297,6 +313,8 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_xiP = take(24 * npp);
     pl.off_xiW = take(24 * npw);
     pl.off_cnt = take(sizeof(Counters));
+    pl.off_nrs = take(sizeof(NrStats));
+    pl.off_mlpb = take(4 * (size_t)MLP_BODY * std::max(np, 1));
     pl.total = o;
     return LBM_OK;
 }
@@ -323,6 +341,9 @@ struct lbm_ctx {
     double *l_q, *lpart;
     Counters *cnt;
     ContactBufs cb;
+    NrStats *nrs;
+    float *mlp_body;            // [np][80] constant warm-start inputs of each body
+    const _Float16 *warm;       // warm-start MLP parameters, or NULL
     hipStream_t aux;              // second stream: link build overlapped with stream-collide
     hipEvent_t ev_main, ev_flags, ev_links;
     bool pending_refill;
@@ -348,6 +369,7 @@ StepArgs base_args(lbm_ctx *c) {
     a.blk_cnt = c->blk_cnt; a.l_off = c->l_off; a.lmask = c->lmask;
     a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.part = c->lpart;
     a.special = c->special; a.cnt = c->cnt; a.cb = c->cb;
+    a.nrs = c->nrs; a.warm = c->warm; a.mlp_body = c->mlp_body;
     return a;
 }
 
@@ -404,6 +426,28 @@ lbm_status do_refill(lbm_ctx *c) {
 extern "C" {
 
 const char *lbm_last_error(void) { return g_err.c_str(); }
+
+// Constant warm-start inputs of each body: its control points in the body
+// frame sorted by weight (largest first, ties by index), each as
+// (p / sqrt(sum k), k / sum k), zero-padded to 20 points.
+static std::vector<float> mlp_body_blocks(const std::vector<DevParticle> &hp) {
+    std::vector<float> out(hp.size() * MLP_BODY, 0.f);
+    for (size_t q = 0; q < hp.size(); ++q) {
+        const DevParticle &d = hp[q];
+        double K = 0.0;
+        for (int i = 0; i < d.n_cp; ++i) K += d.k[i];
+        const double s = std::sqrt(K);
+        std::vector<int> order(d.n_cp);
+        for (int i = 0; i < d.n_cp; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d.k[a] > d.k[b]; });
+        for (int r = 0; r < d.n_cp; ++r) {
+            const int i = order[r];
+            for (int a = 0; a < 3; ++a) out[q * MLP_BODY + 4 * r + a] = (float)(d.cpb[i][a] / s);
+            out[q * MLP_BODY + 4 * r + 3] = (float)(d.k[i] / K);
+        }
+    }
+    return out;
+}
 
 static lbm_status prepare(const lbm_config *cfg, int32_t n_p, const lbm_particle *parts,
                           std::vector<DevParticle> *hp, Plan *pl) {
@@ -513,6 +557,9 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->l_q = (double *)(b + pl.off_lq); c->lpart = (double *)(b + pl.off_lpart);
     c->special = (uint32_t *)(b + pl.off_special);
     c->cnt = (Counters *)(b + pl.off_cnt);
+    c->nrs = (NrStats *)(b + pl.off_nrs);
+    c->mlp_body = (float *)(b + pl.off_mlpb);
+    c->warm = nullptr;
     c->cb.pairF = (double *)(b + pl.off_pairF); c->cb.pairTi = (double *)(b + pl.off_pairTi);
     c->cb.pairTj = (double *)(b + pl.off_pairTj); c->cb.wallF = (double *)(b + pl.off_wallF);
     c->cb.wallT = (double *)(b + pl.off_wallT); c->cb.xiP = (double *)(b + pl.off_xiP);
@@ -575,6 +622,12 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     HIPCHK_C(hipMemcpyAsync(c->l_off, zeros.data(), 4 * (n_p + 1), hipMemcpyHostToDevice, c->stream));
     Counters zc{};
     HIPCHK_C(hipMemcpyAsync(c->cnt, &zc, sizeof zc, hipMemcpyHostToDevice, c->stream));
+    NrStats zn{};
+    HIPCHK_C(hipMemcpyAsync(c->nrs, &zn, sizeof zn, hipMemcpyHostToDevice, c->stream));
+    std::vector<float> mb = mlp_body_blocks(hp);
+    if (n_p > 0)
+        HIPCHK_C(hipMemcpyAsync(c->mlp_body, mb.data(), 4 * mb.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK_C(hipStreamSynchronize(c->stream));  // host buffers above are released on return
     if (pl.contact) {  // tangential springs start relaxed
         std::vector<double> z((size_t)n_p * n_p * 3, 0.0);
         HIPCHK_C(hipMemcpyAsync(c->cb.xiP, z.data(), 24 * (size_t)n_p * n_p, hipMemcpyHostToDevice, c->stream));
@@ -942,6 +995,148 @@ lbm_status lbm_nr_stats(lbm_ctx *c, int64_t *links, int64_t *iterations) {
     if (iterations) *iterations = (int64_t)h.nr_iters;
     const unsigned long long z[2] = {0ull, 0ull};
     HIPCHK(hipMemcpy(&c->cnt->nr_iters, z, sizeof z, hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status lbm_nr_histogram(lbm_ctx *c, int64_t *hist, double *resid_max) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    NrStats h;
+    HIPCHK(hipMemcpy(&h, c->nrs, sizeof h, hipMemcpyDeviceToHost));
+    if (hist)
+        for (int b = 0; b < NR_HIST; ++b) hist[b] = (int64_t)h.hist[b];
+    if (resid_max) {
+        float r;
+        std::memcpy(&r, &h.resid_bits, 4);
+        *resid_max = r;
+    }
+    const NrStats z{};
+    HIPCHK(hipMemcpy(c->nrs, &z, sizeof z, hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_warmstart(lbm_ctx *c, const void *dev_weights) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    if (dev_weights && ((uintptr_t)dev_weights & 255)) return fail(LBM_E_INVALID, "weights must be 256-byte aligned");
+    c->warm = dev_weights ? mlp_blob(const_cast<void *>(dev_weights)).w16 : nullptr;
+    return LBM_OK;
+}
+
+size_t mlp_weights_bytes(void) { return mlp_blob_bytes(); }
+int32_t mlp_param_count(void) { return MLP_P; }
+
+lbm_status mlp_init(void *dev_weights, const float *params, void *hip_stream) {
+    if (!dev_weights || !params) return fail(LBM_E_INVALID, "NULL argument");
+    if ((uintptr_t)dev_weights & 255) return fail(LBM_E_INVALID, "weights must be 256-byte aligned");
+    for (int i = 0; i < MLP_P; ++i)
+        if (!std::isfinite(params[i])) return fail(LBM_E_INVALID, "parameter %d is not finite", i);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const MlpBlob b = mlp_blob(dev_weights);
+    HIPCHK(hipMemcpyAsync(b.theta, params, 4 * (size_t)MLP_P, hipMemcpyHostToDevice, st));
+    launch_mlp_init(b, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return LBM_OK;
+}
+
+lbm_status mlp_get_params(const void *dev_weights, float *params, void *hip_stream) {
+    if (!dev_weights || !params) return fail(LBM_E_INVALID, "NULL argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const MlpBlob b = mlp_blob(const_cast<void *>(dev_weights));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(params, b.theta, 4 * (size_t)MLP_P, hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+lbm_status mlp_collect(lbm_ctx *c, int64_t n_max, void *dev_feat, void *dev_target, int64_t *n_out) {
+    if (!c || !dev_feat || !dev_target || !n_out) return fail(LBM_E_INVALID, "NULL argument");
+    if (n_max < 0) return fail(LBM_E_INVALID, "n_max < 0");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    Counters h;
+    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+    const int n = (int)std::min<int64_t>(n_max, std::min(h.n_links, c->p.link_cap));
+    launch_mlp_collect(c->p, c->P, c->mlp_body, c->l_node, c->l_do, c->l_q, n, (_Float16 *)dev_feat,
+                       (float *)dev_target, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *n_out = n;
+    return LBM_OK;
+}
+
+lbm_status mlp_forward(void *dev_weights, const void *dev_feat, int64_t n, int32_t precision, float *dev_out,
+                       void *hip_stream) {
+    if (!dev_weights || !dev_feat || !dev_out) return fail(LBM_E_INVALID, "NULL argument");
+    if (n < 0 || (precision != 0 && precision != 1)) return fail(LBM_E_INVALID, "bad n or precision");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const MlpBlob b = mlp_blob(dev_weights);
+    const size_t xb = precision == 1 ? 4 : 2;
+    for (int64_t a = 0; a < n; a += MLP_MAX_BATCH) {
+        const int m = (int)std::min<int64_t>(MLP_MAX_BATCH, n - a);
+        launch_mlp_forward(b, (const char *)dev_feat + (size_t)a * MLP_IN * xb, m, precision, st);
+        HIPCHK(hipMemcpyAsync(dev_out + (size_t)a * MLP_OUT, b.out, 4 * (size_t)m * MLP_OUT, hipMemcpyDeviceToDevice,
+                              st));
+    }
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status mlp_grad(void *dev_weights, const void *dev_feat, const void *dev_target, int64_t n, int32_t precision,
+                    float *grad, double *loss, void *hip_stream) {
+    if (!dev_weights || !dev_feat || !dev_target) return fail(LBM_E_INVALID, "NULL argument");
+    if (n < 1 || n > MLP_MAX_BATCH) return fail(LBM_E_INVALID, "n must be 1..%d", MLP_MAX_BATCH);
+    if (precision != 0 && precision != 1) return fail(LBM_E_INVALID, "precision must be 0 or 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const MlpBlob b = mlp_blob(dev_weights);
+    launch_mlp_loss_grad(b, dev_feat, (const float *)dev_target, (int)n, precision, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    if (grad) HIPCHK(hipMemcpy(grad, b.g, 4 * (size_t)MLP_P, hipMemcpyDeviceToHost));
+    if (loss) {
+        float l;
+        HIPCHK(hipMemcpy(&l, b.loss, 4, hipMemcpyDeviceToHost));
+        *loss = l;
+    }
+    return LBM_OK;
+}
+
+lbm_status mlp_train(void *dev_feat, void *dev_target, int64_t n, const char *hparams_json, void *dev_weights,
+                     void *hip_stream) {
+    if (!dev_weights || !dev_feat || !dev_target) return fail(LBM_E_INVALID, "NULL argument");
+    if (n < 1) return fail(LBM_E_INVALID, "n must be >= 1");
+    const std::string txt = hparams_json ? hparams_json : "";
+    double lr = 1e-3, epochs = 1, batch = 256, b1 = 0.9, b2 = 0.999, eps = 1e-8, prec = 0;
+    json_num(txt, "lr", lr);
+    json_num(txt, "epochs", epochs);
+    json_num(txt, "batch", batch);
+    json_num(txt, "beta1", b1);
+    json_num(txt, "beta2", b2);
+    json_num(txt, "eps", eps);
+    json_num(txt, "precision", prec);
+    const int bs = (int)batch, ne = (int)epochs, pr = (int)prec;
+    if (bs < 1 || bs > MLP_MAX_BATCH || ne < 0 || !(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) ||
+        !(eps > 0) || (pr != 0 && pr != 1))
+        return fail(LBM_E_INVALID, "bad hyper-parameters (batch 1..%d, epochs >= 0, lr > 0, 0 <= beta < 1, "
+                                   "eps > 0, precision 0 or 1)", MLP_MAX_BATCH);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const MlpBlob b = mlp_blob(dev_weights);
+    long long t = 0;
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(&t, b.t, 8, hipMemcpyDeviceToHost));
+    const size_t xb = pr == 1 ? 4 : 2;
+    for (int e = 0; e < ne; ++e)
+        for (int64_t a = 0; a < n; a += bs) {
+            const int m = (int)std::min<int64_t>(bs, n - a);
+            launch_mlp_loss_grad(b, (const char *)dev_feat + (size_t)a * MLP_IN * xb,
+                                 (const float *)dev_target + (size_t)a * MLP_OUT, m, pr, st);
+            ++t;
+            const double bc1 = 1.0 - std::pow(b1, (double)t), bc2 = 1.0 - std::pow(b2, (double)t);
+            launch_mlp_adam(b, (float)lr, (float)b1, (float)b2, (float)eps, (float)bc1, (float)bc2, st);
+        }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(b.t, &t, 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     return LBM_OK;
 }
 

@@ -57,6 +57,16 @@ struct Counters {
     unsigned long long n_contact_fail;  // contact iterations that did not converge
 };
 
+// Link-fraction solver statistics since the last read: histogram of the
+// Newton evaluations per link (last bin: NR_HIST - 1 or more) and the
+// largest |C - 1| at a link's last evaluation (FP32 bits).
+constexpr int NR_HIST = 65;
+struct NrStats {
+    unsigned long long hist[NR_HIST];
+    unsigned int resid_bits;
+    unsigned int pad;
+};
+
 // Per-context constants, passed to kernels by value.
 struct Params {
     int nx, ny, nz;

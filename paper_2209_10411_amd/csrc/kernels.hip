@@ -27,6 +27,7 @@
 
 #include "device.h"
 #include "launch.h"
+#include "mlp_dev.h"
 
 namespace mdl {
 
@@ -198,11 +199,12 @@ __device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], 
 // the bracket (none: q = 1).  Then a safeguarded Newton iteration
 // (rtsafe-style: a Newton step that leaves the bracket or does not halve the
 // step falls back to bisection) to |step| < 1e-13, started at the guess when
-// it lies inside the bracket, else by regula falsi on the bracket ends.
-// Every lane returns the same q; the return value is the number of
-// evaluations of the iteration.
+// it lies inside the bracket, else by regula falsi on the bracket ends, for
+// at most it_max evaluations (conv: converged).  Every lane returns the same
+// q and resid = C - 1 at the last evaluation; the return value is the
+// number of evaluations of the iteration.
 __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z, int i, double guess,
-                              double &q) {
+                              int it_max, double &q, double &resid, bool &conv) {
     const int lane = threadIdx.x & 63, j = lane & 7, base = lane & 56;
     const double xf[3] = {(double)x, (double)y, (double)z};
     const int e[3] = {EX[i], EY[i], EZ[i]};
@@ -212,6 +214,8 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
     const unsigned grp = (unsigned)((__ballot(Cj >= 1.0) >> base) & 0xffull);
     const int k0 = grp ? __ffs(grp) - 1 : 7;
     const double Chi = __shfl(Cj, base + k0), Clo = __shfl(Cj, base + (k0 > 0 ? k0 - 1 : 0));
+    resid = 0.0;
+    conv = true;
     if (!grp) {
         q = 1.0;
         return 0;
@@ -225,11 +229,13 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
     if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
     double dxold = hi - lo, dx = dxold;
     int it = 0;
-    while (it < 100) {
+    conv = false;
+    while (it < it_max) {
         double C, dC;
         metaball_ds8(p, P, xf, e, s, C, dC);
         ++it;
         const double g = C - 1.0;
+        resid = g;
         if (g >= 0.0) hi = s; else lo = s;
         const double sn = s - g / dC;
         if (!(dC != 0.0) || !(sn > lo && sn < hi) || fabs(2.0 * g) > fabs(dxold * dC)) {
@@ -241,7 +247,10 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
             dx = s - sn;
             s = sn;
         }
-        if (fabs(dx) < 1e-13) break;
+        if (fabs(dx) < 1e-13) {
+            conv = true;
+            break;
+        }
     }
     q = s;
     return it;
@@ -1269,31 +1278,49 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
 
 // Link build, third pass: the link fractions of the whole list, eight lanes
 // per link (32 links per block, blocks stride over the list), each group
-// with its body's control points staged in its own LDS slot.
+// with its body's control points staged in its own LDS slot.  With WARM the
+// group first evaluates the warm-start MLP for its link (FP16 weights staged
+// in LDS once per block, FP16 activations, FP32 sums; lane j computes hidden
+// units 8j..8j+7) and starts the Newton iteration at its q guess; a
+// warm-started iteration that has not converged in NR_WARM_MAX evaluations
+// is replaced by the plain one.  Per block: iteration histogram and largest
+// final |C - 1|, added to the statistics.
+constexpr int NR_WARM_MAX = 30, NR_MAX = 100;
+template <bool WARM>
 __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__restrict__ P,
                                                 const uint32_t *__restrict__ l_node,
                                                 const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
-                                                Counters *cnt) {
+                                                Counters *cnt, NrStats *__restrict__ nrs,
+                                                const _Float16 *__restrict__ wts, const float *__restrict__ body) {
     __shared__ CPs cps[32];
     __shared__ int sh[256];
+    __shared__ unsigned hist[NR_HIST];
+    __shared__ unsigned rmax;
+    __shared__ _Float16 wsh[WARM ? MLP_P : 1];
+    __shared__ _Float16 act[WARM ? 32 : 1][WARM ? MLP_IN + 2 * MLP_H : 1];  // inputs, h1, h2
     const int t = threadIdx.x, g = t >> 3, j = t & 7;
+    for (int b = t; b < NR_HIST; b += 256) hist[b] = 0u;
+    if (t == 0) rmax = 0u;
+    if (WARM)
+        for (int k = t; k < MLP_P; k += 256) wsh[k] = wts[k];
     const int nl = min(cnt->n_links, p.link_cap);
     int it_sum = 0, links = 0;
     for (int l0 = blockIdx.x * 32; l0 < nl; l0 += gridDim.x * 32) {  // block-uniform trip count
         const int l = l0 + g;
-        const bool ok = l < nl;
+        const bool ok0 = l < nl;
         int pid = 0, i = 1;
         long long n = 0;
-        if (ok) {
+        if (ok0) {
             n = l_node[l];
             i = (int)(l_do[l] & 31u);
             pid = (int)(l_do[l] >> 8);
             if (n >= p.N || pid >= p.np || i < 1 || i >= Q) {  // never expected: report, solve nothing
                 if (j == 0) atomicOr(&cnt->err, ERR_BAD_INDEX);
-                pid = -1;
             }
         }
-        if (ok && pid >= 0) {  // stage this group's control points (padded to a multiple of 4, weight 0)
+        const bool ok = ok0 && n < p.N && pid < p.np && i >= 1 && i < Q;
+        int x = 0, y = 0, z = 0;
+        if (ok) {  // stage this group's control points (padded to a multiple of 4, weight 0)
             const DevParticle &B = P[pid];
             const int n4 = (B.n_cp + 3) & ~3;
             for (int e = j; e < n4 * 4; e += 8) {
@@ -1303,17 +1330,64 @@ __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__r
                 else cps[g].k[k] = k < B.n_cp ? B.k[k] : 0.0;
             }
             if (j == 0) cps[g].n = n4;
+            node_xyz(p, n, x, y, z);
+            if (WARM) {
+                if (j == 0) {
+                    const int e[3] = {c_ex[i], c_ey[i], c_ez[i]};
+                    double head[7];
+                    mlp_link_head(p, B, x, y, z, e, head);
+                    for (int a = 0; a < 7; ++a) act[g][a] = (_Float16)head[a];
+                }
+                for (int c = j; c < MLP_BODY; c += 8) act[g][7 + c] = (_Float16)body[pid * MLP_BODY + c];
+            }
         }
         __syncthreads();
-        if (ok && pid >= 0) {
-            int x, y, z;
-            node_xyz(p, n, x, y, z);
-            double q;
-            const int its = link_fraction8(p, cps[g], x, y, z, i, -1.0, q);
+        double guess = -1.0;
+        if (WARM) {
+            // hidden layer 1: units 8j .. 8j+7 of this group's link
+            if (ok) {
+                float zz[8];
+                for (int u = 0; u < 8; ++u) zz[u] = (float)wsh[MLP_OFF_B1 + 8 * j + u];
+                for (int k = 0; k < MLP_IN; ++k) {
+                    const float xk = (float)act[g][k];
+                    for (int u = 0; u < 8; ++u) zz[u] += xk * (float)wsh[MLP_OFF_W1 + k * MLP_H + 8 * j + u];
+                }
+                for (int u = 0; u < 8; ++u) act[g][MLP_IN + 8 * j + u] = (_Float16)tanhf(zz[u]);
+            }
+            __syncthreads();
+            if (ok) {  // hidden layer 2 (h1 occupies act[MLP_IN .. MLP_IN + 64))
+                float zz[8];
+                for (int u = 0; u < 8; ++u) zz[u] = (float)wsh[MLP_OFF_B2 + 8 * j + u];
+                for (int k = 0; k < MLP_H; ++k) {
+                    const float hk = (float)act[g][MLP_IN + k];
+                    for (int u = 0; u < 8; ++u) zz[u] += hk * (float)wsh[MLP_OFF_W2 + k * MLP_H + 8 * j + u];
+                }
+                for (int u = 0; u < 8; ++u) act[g][MLP_IN + MLP_H + 8 * j + u] = (_Float16)tanhf(zz[u]);
+            }
+            __syncthreads();
+            float o = 0.f;
+            if (ok && j < MLP_OUT) {  // output j (only q = output 0 is used)
+                o = (float)wsh[MLP_OFF_B3 + j];
+                for (int k = 0; k < MLP_H; ++k)
+                    o += (float)act[g][MLP_IN + MLP_H + k] * (float)wsh[MLP_OFF_W3 + k * MLP_OUT + j];
+            }
+            const float q0 = __shfl(o, (t & 63) & 56);
+            guess = (double)q0;
+        }
+        if (ok) {
+            double q, resid;
+            bool conv;
+            int its = link_fraction8(p, cps[g], x, y, z, i, guess, WARM ? NR_WARM_MAX : NR_MAX, q, resid,
+                                     conv);
+            if (WARM && !conv) {
+                its += link_fraction8(p, cps[g], x, y, z, i, -1.0, NR_MAX, q, resid, conv);
+            }
             if (j == 0) {
                 l_q[l] = q;
                 it_sum += its;
                 ++links;
+                atomicAdd(&hist[min(its, NR_HIST - 1)], 1u);
+                atomicMax(&rmax, __float_as_uint((float)fabs(resid)));
             }
         }
         __syncthreads();  // the group slots are restaged in the next round
@@ -1324,7 +1398,10 @@ __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__r
     if (t == 0 && nls > 0) {
         atomicAdd(&cnt->nr_iters, (unsigned long long)its);
         atomicAdd(&cnt->nr_links, (unsigned long long)nls);
+        atomicMax(&nrs->resid_bits, rmax);
     }
+    for (int b = t; b < NR_HIST; b += 256)
+        if (hist[b]) atomicAdd(&nrs->hist[b], (unsigned long long)hist[b]);
 }
 
 // ------------------------------------------------------------ host launchers
@@ -1365,8 +1442,13 @@ static void launch_step_kernels_t(const StepArgs &a) {
             k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt,
                                                                 a.part_first_blk, a.l_off,
                                                                 a.l_node, a.l_do, a.cnt, a.own_dead);
-            k_link_q<<<max(1, min(cdiv(p.link_cap, 32), 2048)), 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do,
-                                                                                    a.l_q, a.cnt);
+            const int qg = max(1, min(cdiv(p.link_cap, 32), 2048));
+            if (a.warm)
+                k_link_q<true><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm,
+                                                          a.mlp_body);
+            else
+                k_link_q<false><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, nullptr,
+                                                           nullptr);
         }
     } else if (a.phase == PHASE_INIT_STATE) {
         k_init_state<S><<<2048, 256, 0, a.stream>>>(p, A, a.own_old);

@@ -39,6 +39,9 @@ struct StepArgs {
     uint32_t *special;
     Counters *cnt;
     ContactBufs cb;
+    NrStats *nrs;           // link-fraction solver statistics
+    const _Float16 *warm;   // warm-start MLP parameters (FP16), or NULL: plain Newton
+    const float *mlp_body;  // [np][80] constant MLP inputs of each body
 };
 
 void launch_phase(const StepArgs &a);

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     src = open(os.path.join(ROOT, "include", "midelbm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:lbm_status|void|const char\s*\*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:lbm_status|void|size_t|int32_t|const char\s*\*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 

@@ -1,0 +1,166 @@
+"""Warm-start MLP on the GPU (through the C ABI) against the FP64 oracle of
+oracle/mlp.py: the features of the method's own links, the forward pass,
+the gradient (FP16 form: 2e-2 of the largest component; FP32 test
+instantiation: 1e-5) and Adam steps, and the warm-started link solver,
+which must find the plain solver's roots (the Newton tolerance judges the
+guess) -- also with an untrained network."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mdl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_10411_amd as m
+    m.lib()
+    return m
+
+
+def oracle_features(cfg, sim, node, d, owner):
+    parts = sim.particles()
+    body = []
+    for p in cfg.particles:
+        _, c, _, _ = oracle.body_properties(p.cp_xyz, p.cp_k, cfg.quad_h)
+        body.append((np.asarray(p.cp_xyz) - c, np.asarray(p.cp_k)))
+    lat = oracle.lattice()
+    E = lat[0] if isinstance(lat, tuple) else lat["e"]
+    out = []
+    for n, i, o in zip(node, d, owner):
+        x = np.array([n % cfg.nx, (n // cfg.nx) % cfg.ny, n // (cfg.nx * cfg.ny)], float)
+        cpb, k = body[o]
+        out.append(omlp.features(cpb, k, parts[o]["x"], parts[o]["quat"], x, np.asarray(E[i], float),
+                                 dims=(cfg.nx, cfg.ny, cfg.nz), periodic=cfg.periodic))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("which", ["walled", "periodic"])
+def test_link_features_match_oracle(mdl, which):
+    cfg = workloads.small_settling(n=32, nz=48, R=5.0) if which == "walled" else workloads.suspension_small()
+    sim = mdl.Simulation(cfg)
+    sim.step(3)
+    node, d, owner, q = sim.links()
+    feat, target = mdl.mlp_collect(sim)
+    f = feat.float().cpu().numpy()
+    t = target.cpu().numpy()
+    assert f.shape == (len(q), 87)
+    assert np.array_equal(t[:, 0], q.astype(np.float32)) and np.all(t[:, 1:] == 0)
+    sel = np.arange(0, len(q), max(1, len(q) // 400))
+    ref = oracle_features(cfg, sim, node[sel], d[sel], owner[sel]).astype(np.float16).astype(np.float64)
+    ulp = np.spacing(np.abs(ref).astype(np.float16)).astype(np.float64)
+    assert np.all(np.abs(f[sel] - ref) <= ulp), np.abs(f[sel] - ref).max()
+    sim.close()
+
+
+def rand_batch(rng, n=256):
+    X = rng.normal(0, 0.6, size=(n, 87))
+    X[:, 6] = (np.arange(n) % 4 == 0).astype(float)
+    T = rng.normal(0.4, 0.3, size=(n, 4))
+    return X, T
+
+
+def params(seed):
+    rng = np.random.default_rng(seed)
+    return workloads.mlp_init(seed) + rng.normal(0, 0.05, size=omlp.P)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forward_and_gradient_match_oracle(mdl, precision):
+    import torch
+    theta = params(11).astype(np.float32)
+    net = mdl.Mlp(theta)
+    X, T = rand_batch(np.random.default_rng(12))
+    if precision == 0:
+        Xd = torch.tensor(X, dtype=torch.float16, device="cuda:0")
+        Xr = X.astype(np.float16).astype(np.float64)
+        th = theta.astype(np.float16).astype(np.float64)
+        tol = 2e-2
+    else:
+        Xd = torch.tensor(X, dtype=torch.float32, device="cuda:0")
+        Xr = X.astype(np.float32).astype(np.float64)
+        th = theta.astype(np.float64)
+        tol = 1e-5
+    Td = torch.tensor(T, dtype=torch.float32, device="cuda:0")
+    Tr = T.astype(np.float32).astype(np.float64)
+    out = net.forward(Xd, precision).cpu().numpy()
+    ref, _ = omlp.forward(th, Xr)
+    assert np.abs(out - ref).max() <= tol * np.abs(ref).max()
+    g, loss = net.grad(Xd, Td, precision)
+    gr = omlp.grad(th, Xr, Tr)
+    assert np.abs(g - gr).max() <= tol * np.abs(gr).max(), np.abs(g - gr).max() / np.abs(gr).max()
+    assert loss == pytest.approx(omlp.loss(th, Xr, Tr), rel=tol)
+
+
+def test_adam_steps_match_oracle(mdl):
+    """FP32 instantiation, two minibatches; eps large enough that tiny
+    gradients do not make the step sign-sensitive to rounding."""
+    import torch
+    theta = params(13)
+    net = mdl.Mlp(theta.astype(np.float32))
+    X, T = rand_batch(np.random.default_rng(14), n=512)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda:0")
+    Td = torch.tensor(T, dtype=torch.float32, device="cuda:0")
+    hp = dict(lr=1e-3, epochs=1, batch=256, eps=1e-3, precision=1)
+    net.train(Xd, Td, **hp)
+    ref = omlp.train(theta.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64),
+                     T.astype(np.float32).astype(np.float64), epochs=1, batch=256, lr=1e-3, eps=1e-3)
+    assert np.abs(net.params() - ref).max() <= 1e-6
+
+
+def shuffled_samples(mdl, sim, seed=0):
+    import torch
+    feat, target = mdl.mlp_collect(sim)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    perm = torch.randperm(feat.shape[0], generator=g).to(feat.device)
+    return feat[perm].contiguous(), target[perm].contiguous()
+
+
+def test_training_on_the_methods_links_reduces_the_loss(mdl):
+    cfg = workloads.small_settling(n=32, nz=48, R=5.0)
+    sim = mdl.Simulation(cfg)
+    feat, target = shuffled_samples(mdl, sim)
+    net = mdl.Mlp(workloads.mlp_init(15).astype(np.float32))
+    _, l0 = net.grad(feat[:4096], target[:4096])
+    net.train(feat, target, lr=3e-3, epochs=200, batch=64)
+    _, l1 = net.grad(feat[:4096], target[:4096])
+    print(f"links {feat.shape[0]}: loss {l0:.4e} -> {l1:.4e}", flush=True)
+    assert l1 < 0.2 * l0
+    sim.close()
+
+
+@pytest.mark.parametrize("trained", [True, False])
+def test_warm_start_finds_the_plain_roots(mdl, trained):
+    cfg = workloads.small_settling(n=32, nz=48, R=5.0)
+    net = mdl.Mlp(workloads.mlp_init(16).astype(np.float32))
+    if trained:
+        s0 = mdl.Simulation(cfg)
+        feat, target = shuffled_samples(mdl, s0)
+        net.train(feat, target, lr=3e-3, epochs=200, batch=64)
+        s0.close()
+    plain, warm = mdl.Simulation(cfg), mdl.Simulation(cfg)
+    warm.set_warmstart(net)
+    plain.nr_histogram()
+    warm.nr_histogram()
+    plain.step(10)
+    warm.step(10)
+    n0, d0, o0, q0 = plain.links()
+    n1, d1, o1, q1 = warm.links()
+    assert np.array_equal(n0, n1) and np.array_equal(d0, d1)
+    dq = np.abs(q1 - q0)
+    h0, r0 = plain.nr_histogram()
+    h1, r1 = warm.nr_histogram()
+    it = np.arange(65)
+    print(f"trained={trained}: |dq| median {np.median(dq):.2e} max {dq.max():.2e}; "
+          f"mean iterations plain {(h0 * it).sum() / h0.sum():.2f} warm {(h1 * it).sum() / h1.sum():.2f}; "
+          f"residual plain {r0:.1e} warm {r1:.1e}", flush=True)
+    assert np.median(dq) <= 1e-13 and dq.max() <= 2e-7 and np.mean(dq > 1e-11) < 0.01
+    assert r1 <= 1e-10 and r0 <= 1e-10
+    plain.close()
+    warm.close()
