@@ -11,8 +11,9 @@ Prints one JSON line: MLUPS over all lattice nodes with FP32 storage (the
 headline), the same with FP16 storage, the roofline of the dominant kernel
 (the stream-collide, timed with HIP events on the library's stream), the
 64-case ensemble (batched, graph-replayed) beside the same systems stepped
-one by one, and the CPU oracle timed on a bounded sample of the headline
-workload.
+one by one, the link-fraction warm start (MLP trained on the method's own
+Newton solutions) against plain Newton on the 200-body suspension, and the
+CPU oracle timed on a bounded sample of the headline workload.
 """
 import argparse
 import hashlib
@@ -96,6 +97,74 @@ def run_ensemble(n_cases, steps, warmup):
             "tiles": hist, "waves_per_block": bw, "autotune_s": round(t_tune, 2)}
 
 
+def nr_summary(hist, resid):
+    import numpy as np
+    it = np.arange(len(hist))
+    tot = max(int(hist.sum()), 1)
+    p99 = int(np.searchsorted(np.cumsum(hist), 0.99 * tot))
+    return {"links": int(hist.sum()), "mean_iterations": round(float((hist * it).sum()) / tot, 3),
+            "p99_iterations": p99, "max_final_residual": resid}
+
+
+def run_mlp_warmstart(steps, epochs):
+    """Link-fraction warm start on the 256^3 periodic suspension of 200
+    bodies (FP32): the MLP is trained on the link fractions the method
+    solved at the initial geometries of seeds 5, 6 and 7, then seed 5 runs
+    with plain and with warm-started Newton iterations."""
+    import torch
+
+    import paper_2209_10411_amd as mdl
+    import workloads
+
+    feats, targets = [], []
+    sim5 = None
+    t0 = time.perf_counter()
+    for seed in (5, 6, 7):
+        sim = mdl.Simulation(workloads.config5(seed=seed), device="cuda:0")
+        f, t = mdl.mlp_collect(sim)
+        feats.append(f.clone())
+        targets.append(t.clone())
+        if seed == 5:
+            sim5 = sim
+        else:
+            sim.close()
+    t_setup = time.perf_counter() - t0
+    feat, target = torch.cat(feats), torch.cat(targets)
+    perm = torch.randperm(feat.shape[0], generator=torch.Generator().manual_seed(0)).to(feat.device)
+    feat, target = feat[perm].contiguous(), target[perm].contiguous()
+    net = mdl.Mlp(workloads.mlp_init(5))
+    _, loss0 = net.grad(feat[:4096], target[:4096])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.train(feat, target, lr=1e-3, epochs=epochs, batch=1024)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    _, loss1 = net.grad(feat[:4096], target[:4096])
+    cfg = sim5.cfg
+    res = {}
+    for mode in ("plain", "mlp"):
+        sim5.set_warmstart(net if mode == "mlp" else None)
+        sim5.step(5)
+        sim5.sync()
+        sim5.nr_histogram()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim5.step(steps)
+        sim5.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h, r = sim5.nr_histogram()
+        res[mode] = dict(nr_summary(h, r), mlups=round(cfg.n_nodes * steps / dt / 1e6, 1),
+                         ms_per_step=round(dt * 1e3 / steps, 4))
+    sim5.close()
+    return {"workload": "256^3 periodic suspension, 200 bodies (6..20 cp, R 6..12), density ratio 1.5, "
+                        "counter-force, FP32, IBB",
+            "training_samples": int(feat.shape[0]), "epochs": epochs, "batch": 1024,
+            "train_s": round(t_train, 2), "setup_s": round(t_setup, 1),
+            "loss_before": round(loss0, 5), "loss_after": round(loss1, 5), "steps": steps,
+            "plain": res["plain"], "mlp": res["mlp"]}
+
+
 def traffic_from_profile():
     """FETCH/WRITE bytes per launch of the stream-collide kernel from the
     committed rocprofv3 --pmc summary, if it was taken on this kernel source."""
@@ -156,6 +225,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-case ensemble run")
     ap.add_argument("--ensemble-steps", type=int, default=60)
+    ap.add_argument("--no-mlp", action="store_true", help="skip the warm-start (MLP) run")
+    ap.add_argument("--mlp-steps", type=int, default=100)
+    ap.add_argument("--mlp-epochs", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB copy (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -209,6 +281,8 @@ def main():
                              "kernel_frac": round(ach16 / HBM_PEAK_GBS, 4)}
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(64, args.ensemble_steps, 12)
+    if not args.no_mlp:
+        out["warm_start"] = run_mlp_warmstart(args.mlp_steps, args.mlp_epochs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)

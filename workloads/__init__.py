@@ -188,42 +188,59 @@ def mini_ensemble(n_cases: int = 4, seed: int = 4100) -> List[Config]:
     return out
 
 
+def extent_radius(p: "Particle", n_dir: int = 256, dr: float = 0.25) -> float:
+    """Largest distance from the control-point origin of a point with
+    C >= 1 (rays in n_dir Fibonacci directions sampled every dr), at most
+    the bounding radius."""
+    i = np.arange(n_dir) + 0.5
+    phi = np.arccos(1 - 2 * i / n_dir)
+    th = np.pi * (1 + 5 ** 0.5) * i
+    dirs = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
+    r = np.arange(dr, p.bounding_radius() + dr, dr)
+    pts = dirs[:, None, :] * r[None, :, None]
+    d2 = ((pts[:, :, None, :] - p.cp_xyz[None, None, :, :]) ** 2).sum(-1)
+    C = (p.cp_k / np.maximum(d2, 1e-300)).sum(-1)
+    inside = C >= 1.0
+    far = np.where(inside.any(axis=1), (inside * r[None, :]).max(axis=1), 0.0)
+    return float(min(far.max() + dr, p.bounding_radius()))
+
+
 def config5(n_bodies: int = 200, box: int = 256, seed: int = 5,
-            max_tries: int = 200000) -> Config:
+            max_tries: int = 2000000) -> Config:
     """256^3 periodic suspension: bodies with 6..20 control points and
-    R ~ U[6, 12], placed by random sequential addition with bounding spheres
-    and a 1 lu gap, density ratio 1.5, gravity 2e-5, fluid counter-force."""
+    R ~ U[6, 12], placed by random sequential addition with a 1 lu gap
+    between the spheres that enclose each body's C >= 1 region about its
+    control-point origin (the looser bounding spheres max|p| + sqrt(sum k)
+    would fill 38 % of the box, at the jamming limit of the placement),
+    density ratio 1.5, gravity 2e-5, fluid counter-force; body-property
+    quadrature cell 1/4."""
     rng = _rng(seed)
     bodies: List[Particle] = []
-    centers, radii = [], []
+    centers = np.zeros((0, 3))
+    radii = np.zeros(0)
     tries = 0
     while len(bodies) < n_bodies:
         n_cp = int(rng.integers(6, 21))
         R = float(rng.uniform(6.0, 12.0))
         off, k = random_body(rng, n_cp, R)
         p = Particle(cp_xyz=off, cp_k=k, x=np.zeros(3), density=1.5)
-        rb = p.bounding_radius()
+        re = extent_radius(p)
         while True:
             tries += 1
             if tries > max_tries:
                 raise RuntimeError("random sequential placement did not finish")
             c = rng.uniform(0.0, box, size=3)
-            ok = True
-            for c2, r2 in zip(centers, radii):
-                d = c - c2
-                d -= box * np.floor(d / box + 0.5)
-                if np.linalg.norm(d) < rb + r2 + 1.0:
-                    ok = False
-                    break
-            if ok:
+            d = c[None, :] - centers
+            d -= box * np.floor(d / box + 0.5)
+            if not np.any(np.linalg.norm(d, axis=1) < re + radii + 1.0):
                 break
         p.x = c
-        centers.append(c)
-        radii.append(rb)
+        centers = np.vstack([centers, c])
+        radii = np.append(radii, re)
         bodies.append(p)
     return Config(nx=box, ny=box, nz=box, periodic=7, tau=0.6, rho0=1.0,
-                  g_particle=np.array([0.0, 0.0, -2e-5]), bc=BC_IBB, counter_force=1,
-                  particles=bodies, name=f"cfg5-{box}^3-{n_bodies}", steps=200)
+                  g_particle=np.array([0.0, 0.0, -2e-5]), bc=BC_IBB, counter_force=1, quad_h=0.25,
+                  particles=bodies, name=f"cfg5-{box}^3-{n_bodies}-seed{seed}", steps=200)
 
 
 # ------------------------------------------------------- validation cases
