@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--mlp-steps", type=int, default=100)
     ap.add_argument("--mlp-epochs", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB copy (PMC calibration)")
+    ap.add_argument("--only", choices=["ensemble", "warm-start"],
+                    help="run only this part and print its JSON object (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -237,6 +239,12 @@ def main():
         sys.exit(2)
     if args.calib_copy:
         calib_copy()
+        return
+    if args.only == "ensemble":
+        print(json.dumps(run_ensemble(64, args.ensemble_steps, 12)), flush=True)
+        return
+    if args.only == "warm-start":
+        print(json.dumps(run_mlp_warmstart(args.mlp_steps, args.mlp_epochs)), flush=True)
         return
     import workloads
 
