@@ -64,6 +64,7 @@ bool json_num(const std::string &txt, const char *key, double &v) {
 // and inertia tensor per unit density about the centroid.
 struct BodyProps {
     double V, c[3], I[9];
+    double re;  // radius about the centroid enclosing the inside cells, plus a cell diagonal and 1/2 lu
 };
 
 bool body_properties(int n_cp, const double *cp, const double *k, double h, BodyProps &out) {
@@ -110,10 +111,11 @@ bool body_properties(int n_cp, const double *cp, const double *k, double h, Body
     for (int t = 0; t < nth; ++t) { C += cnt[t]; S[0] += sx[t]; S[1] += sy[t]; S[2] += sz[t]; }
     if (C == 0) return false;
     for (int a = 0; a < 3; ++a) out.c[a] = lo[a] + h * ((double)S[a] / (double)C + 0.5);
-    std::vector<double> J(6 * nth, 0.0);
+    std::vector<double> J(6 * nth, 0.0), R2(nth, 0.0);
     for (int t = 0; t < nth; ++t)
         th.emplace_back([&, t] {
             double *j = &J[6 * t];
+            double &rmax = R2[t];
             for (int kz = t; kz < n[2]; kz += nth)
                 for (int ky = 0; ky < n[1]; ++ky)
                     for (int kx = 0; kx < n[0]; ++kx) {
@@ -121,6 +123,7 @@ bool body_properties(int n_cp, const double *cp, const double *k, double h, Body
                                      z = lo[2] + (kz + 0.5) * h;
                         if (!inside(x, y, z)) continue;
                         const double r0 = x - out.c[0], r1 = y - out.c[1], r2 = z - out.c[2];
+                        rmax = std::max(rmax, r0 * r0 + r1 * r1 + r2 * r2);
                         j[0] += r0 * r0; j[1] += r1 * r1; j[2] += r2 * r2;
                         j[3] += r0 * r1; j[4] += r0 * r2; j[5] += r1 * r2;
                     }
@@ -129,6 +132,9 @@ bool body_properties(int n_cp, const double *cp, const double *k, double h, Body
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (int t = 0; t < nth; ++t)
         for (int c = 0; c < 6; ++c) s[c] += J[6 * t + c];
+    double rm = 0.0;
+    for (int t = 0; t < nth; ++t) rm = std::max(rm, R2[t]);
+    out.re = std::sqrt(rm) + h * std::sqrt(3.0) + 0.5;
     const double h3 = h * h * h;
     out.V = (double)C * h3;
     out.I[0] = (s[1] + s[2]) * h3; out.I[4] = (s[0] + s[2]) * h3; out.I[8] = (s[0] + s[1]) * h3;
@@ -244,7 +250,9 @@ double bounding_radius(int n_cp, const double *cp, const double *k, const double
     return rm + std::sqrt(sk);
 }
 
-lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb, Plan &pl) {
+// rb: bounding radius (capacities); re: extent of the C >= 1 set (regions).
+lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb, const std::vector<double> &re,
+                     Plan &pl) {
     pl.N = (long long)c->nx * c->ny * c->nz;
     pl.np = np;
     pl.storage_bytes = c->storage == 0 ? 4 : 2;
@@ -256,7 +264,7 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     const int L[3] = {c->nx, c->ny, c->nz};
     long long lcap = 0, scap = 0;
     for (int p = 0; p < np; ++p) {
-        const int half = (int)std::ceil(rb[p]) + PAD;
+        const int half = (int)std::ceil(std::min(re[p], rb[p])) + PAD;
         pl.half[p] = half;
         long long vol = 1;
         for (int a = 0; a < 3; ++a) {
@@ -313,7 +321,7 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_xiP = take(24 * npp);
     pl.off_xiW = take(24 * npw);
     pl.off_cnt = take(sizeof(Counters));
-    pl.off_nrs = take(sizeof(NrStats));
+    pl.off_nrs = take(4 * (size_t)NR_BLOCKS * NR_HIST + 16 * (size_t)NR_BLOCKS + 4 * (size_t)NR_BLOCKS);
     pl.off_mlpb = take(4 * (size_t)MLP_BODY * std::max(np, 1));
     pl.total = o;
     return LBM_OK;
@@ -341,7 +349,7 @@ struct lbm_ctx {
     double *l_q, *lpart;
     Counters *cnt;
     ContactBufs cb;
-    NrStats *nrs;
+    NrStats nrs;
     float *mlp_body;            // [np][80] constant warm-start inputs of each body
     const _Float16 *warm;       // warm-start MLP parameters, or NULL
     hipStream_t aux;              // second stream: link build overlapped with stream-collide
@@ -389,6 +397,22 @@ lbm_status check_device(lbm_ctx *c) {
 // Flags from scratch for the current poses into the next buffer, node
 // classes against the current one, then the links of the new flags.  The
 // old flags stay in the dead buffer until refill() has used them.
+// Expected lengths of the link and boundary-node lists from the current ones
+// (bodies are rigid: their surface changes little), with a margin; the list
+// kernels stride over whatever the lists hold.  Synchronises.
+lbm_status estimate_lists(lbm_ctx *c) {
+    Counters h;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+    c->p.est_links = std::min(c->p.link_cap, (int)std::min<long long>(0x3fffffff, 3ll * h.n_links / 2 + 1024));
+    // boundary nodes carry several cut links each (the special list is empty
+    // right after set-up, when no previous flags exist)
+    c->p.est_special = std::min(c->p.special_cap,
+                                (int)std::min<long long>(0x3fffffff, std::max<long long>(3ll * h.n_special / 2,
+                                                                                         h.n_links / 2) + 1024));
+    return LBM_OK;
+}
+
 lbm_status reflag(lbm_ctx *c) {
     launch_refresh_pose(c->p, c->P, c->stream);
     launch_fill_i32(c->own[c->in], c->pl.N, FLUID, c->stream);
@@ -455,7 +479,7 @@ static lbm_status prepare(const lbm_config *cfg, int32_t n_p, const lbm_particle
     if (s) return s;
     if (n_p < 0 || n_p > 65535) return fail(LBM_E_INVALID, "n_p must be 0..65535");
     if (n_p > 0 && !parts) return fail(LBM_E_INVALID, "particles is NULL");
-    std::vector<double> rb(n_p);
+    std::vector<double> rb(n_p), re(n_p);
     hp->assign(n_p, DevParticle{});
     const int L[3] = {cfg->nx, cfg->ny, cfg->nz};
     for (int p = 0; p < n_p; ++p) {
@@ -489,6 +513,7 @@ static lbm_status prepare(const lbm_config *cfg, int32_t n_p, const lbm_particle
         }
         d.rb = bounding_radius(q.n_cp, q.cp_xyz, q.cp_k, bp.c);
         rb[p] = d.rb;
+        re[p] = bp.re;
         for (int a = 0; a < 3; ++a)
             if (!((cfg->periodic >> a) & 1u) && (d.X[a] - d.rb < 0.0 || d.X[a] + d.rb > L[a] - 1.0))
                 return fail(LBM_E_INVALID, "particle %d: bounding sphere crosses a wall on axis %d", p, a);
@@ -501,7 +526,7 @@ static lbm_status prepare(const lbm_config *cfg, int32_t n_p, const lbm_particle
             if (!(cfg->contact_rs < std::sqrt(sk))) return fail(LBM_E_INVALID, "particle %d: contact_rs >= sqrt(sum k)", p);
         }
     }
-    if ((s = make_plan(cfg, n_p, rb, *pl))) return s;
+    if ((s = make_plan(cfg, n_p, rb, re, *pl))) return s;
     for (int p = 0; p < n_p; ++p) {
         DevParticle &d = (*hp)[p];
         d.half = pl->half[p];
@@ -557,7 +582,9 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->l_q = (double *)(b + pl.off_lq); c->lpart = (double *)(b + pl.off_lpart);
     c->special = (uint32_t *)(b + pl.off_special);
     c->cnt = (Counters *)(b + pl.off_cnt);
-    c->nrs = (NrStats *)(b + pl.off_nrs);
+    c->nrs.work = (unsigned long long *)(b + pl.off_nrs);
+    c->nrs.hist = (unsigned int *)(b + pl.off_nrs + 16 * (size_t)NR_BLOCKS);
+    c->nrs.resid = (unsigned int *)(b + pl.off_nrs + 16 * (size_t)NR_BLOCKS + 4 * (size_t)NR_BLOCKS * NR_HIST);
     c->mlp_body = (float *)(b + pl.off_mlpb);
     c->warm = nullptr;
     c->cb.pairF = (double *)(b + pl.off_pairF); c->cb.pairTi = (double *)(b + pl.off_pairTi);
@@ -622,8 +649,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     HIPCHK_C(hipMemcpyAsync(c->l_off, zeros.data(), 4 * (n_p + 1), hipMemcpyHostToDevice, c->stream));
     Counters zc{};
     HIPCHK_C(hipMemcpyAsync(c->cnt, &zc, sizeof zc, hipMemcpyHostToDevice, c->stream));
-    NrStats zn{};
-    HIPCHK_C(hipMemcpyAsync(c->nrs, &zn, sizeof zn, hipMemcpyHostToDevice, c->stream));
+    launch_fill_i32((int32_t *)c->nrs.work, (16 + 4 * (long long)NR_HIST + 4) * NR_BLOCKS / 4, 0, c->stream);
     std::vector<float> mb = mlp_body_blocks(hp);
     if (n_p > 0)
         HIPCHK_C(hipMemcpyAsync(c->mlp_body, mb.data(), 4 * mb.size(), hipMemcpyHostToDevice, c->stream));
@@ -666,6 +692,8 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     if (e != hipSuccess) return bail(fail(LBM_E_HIP, "kernel launch: %s", hipGetErrorString(e)));
     lbm_status st = check_device(c);
     if (st) return bail(st);
+    st = estimate_lists(c);
+    if (st) return bail(st);
 #undef HIPCHK_C
     *out = c;
     return LBM_OK;
@@ -682,6 +710,7 @@ lbm_status metaball_flag(lbm_ctx *c, int64_t *n_solid, int64_t *n_links) {
         HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
         if (n_solid) *n_solid = h.n_solid;
         if (n_links) *n_links = h.n_links;
+        if ((s = estimate_lists(c))) return s;
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -989,12 +1018,14 @@ lbm_status lbm_nr_stats(lbm_ctx *c, int64_t *links, int64_t *iterations) {
     if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
     lbm_status s = check_device(c);
     if (s) return s;
-    Counters h;
-    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
-    if (links) *links = (int64_t)h.nr_links;
-    if (iterations) *iterations = (int64_t)h.nr_iters;
-    const unsigned long long z[2] = {0ull, 0ull};
-    HIPCHK(hipMemcpy(&c->cnt->nr_iters, z, sizeof z, hipMemcpyHostToDevice));
+    std::vector<unsigned long long> w(2 * (size_t)NR_BLOCKS);
+    HIPCHK(hipMemcpy(w.data(), c->nrs.work, 16 * (size_t)NR_BLOCKS, hipMemcpyDeviceToHost));
+    unsigned long long it = 0, nl = 0;
+    for (int b = 0; b < NR_BLOCKS; ++b) { it += w[2 * b]; nl += w[2 * b + 1]; }
+    if (links) *links = (int64_t)nl;
+    if (iterations) *iterations = (int64_t)it;
+    launch_fill_i32((int32_t *)c->nrs.work, 4 * (long long)NR_BLOCKS, 0, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 
@@ -1002,17 +1033,24 @@ lbm_status lbm_nr_histogram(lbm_ctx *c, int64_t *hist, double *resid_max) {
     if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
     lbm_status s = check_device(c);
     if (s) return s;
-    NrStats h;
-    HIPCHK(hipMemcpy(&h, c->nrs, sizeof h, hipMemcpyDeviceToHost));
+    std::vector<unsigned int> h((size_t)NR_BLOCKS * NR_HIST), r(NR_BLOCKS);
+    HIPCHK(hipMemcpy(h.data(), c->nrs.hist, 4 * h.size(), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(r.data(), c->nrs.resid, 4 * r.size(), hipMemcpyDeviceToHost));
+    unsigned int rb = 0;
+    for (int b = 0; b < NR_BLOCKS; ++b) rb = std::max(rb, r[b]);
     if (hist)
-        for (int b = 0; b < NR_HIST; ++b) hist[b] = (int64_t)h.hist[b];
+        for (int k = 0; k < NR_HIST; ++k) {
+            long long t = 0;
+            for (int b = 0; b < NR_BLOCKS; ++b) t += h[(size_t)b * NR_HIST + k];
+            hist[k] = t;
+        }
     if (resid_max) {
-        float r;
-        std::memcpy(&r, &h.resid_bits, 4);
-        *resid_max = r;
+        float f;
+        std::memcpy(&f, &rb, 4);
+        *resid_max = f;
     }
-    const NrStats z{};
-    HIPCHK(hipMemcpy(c->nrs, &z, sizeof z, hipMemcpyHostToDevice));
+    launch_fill_i32((int32_t *)c->nrs.hist, (long long)NR_BLOCKS * NR_HIST + NR_BLOCKS, 0, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 

@@ -51,20 +51,20 @@ struct Counters {
     int err;        // ERR_* bits
     uint32_t tag;   // classification pass number (stamps claimed nodes)
     int pad[2];
-    unsigned long long nr_iters;  // Newton/bisection iterations of the link fractions
-    unsigned long long nr_links;  // link fractions solved
     unsigned long long n_contacts;      // contacts resolved (pairs + walls, per sub-step)
     unsigned long long n_contact_fail;  // contact iterations that did not converge
 };
 
-// Link-fraction solver statistics since the last read: histogram of the
-// Newton evaluations per link (last bin: NR_HIST - 1 or more) and the
-// largest |C - 1| at a link's last evaluation (FP32 bits).
+// Link-fraction solver statistics since the last read, one slot per block
+// of the solver (no shared counters): histogram of the Newton evaluations per
+// link (last bin: NR_HIST - 1 or more), evaluations and links, and the largest
+// |C - 1| at a link's last evaluation (FP32 bits).  Summed on reading.
 constexpr int NR_HIST = 65;
+constexpr int NR_BLOCKS = 16384;  // largest grid of the solver
 struct NrStats {
-    unsigned long long hist[NR_HIST];
-    unsigned int resid_bits;
-    unsigned int pad;
+    unsigned int *hist;        // [NR_BLOCKS][NR_HIST]
+    unsigned long long *work;  // [NR_BLOCKS][2]: evaluations, links
+    unsigned int *resid;       // [NR_BLOCKS]
 };
 
 // Per-context constants, passed to kernels by value.
@@ -84,6 +84,7 @@ struct Params {
     double gp[3];               // particle gravity
     int link_cap, special_cap;
     int region_blocks;          // blocks of the region kernels
+    int est_links, est_special; // expected list lengths (launch sizes of the list kernels; 0: capacities)
     int contact;                // contact enabled
     double c_rs, c_kn, c_en, c_mu;
 };

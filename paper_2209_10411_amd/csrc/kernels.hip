@@ -1290,7 +1290,7 @@ template <bool WARM>
 __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__restrict__ P,
                                                 const uint32_t *__restrict__ l_node,
                                                 const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
-                                                Counters *cnt, NrStats *__restrict__ nrs,
+                                                Counters *cnt, NrStats nrs,
                                                 const _Float16 *__restrict__ wts, const float *__restrict__ body) {
     __shared__ CPs cps[32];
     __shared__ int sh[256];
@@ -1395,13 +1395,14 @@ __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__r
     const int its = block_sum(it_sum, sh);
     __syncthreads();
     const int nls = block_sum(links, sh);
-    if (t == 0 && nls > 0) {
-        atomicAdd(&cnt->nr_iters, (unsigned long long)its);
-        atomicAdd(&cnt->nr_links, (unsigned long long)nls);
-        atomicMax(&nrs->resid_bits, rmax);
+    if (blockIdx.x >= NR_BLOCKS) return;  // never: the launcher caps the grid
+    if (t == 0 && nls > 0) {  // this block's own slot: plain read-modify-write
+        nrs.work[2 * blockIdx.x] += (unsigned long long)its;
+        nrs.work[2 * blockIdx.x + 1] += (unsigned long long)nls;
+        nrs.resid[blockIdx.x] = max(nrs.resid[blockIdx.x], rmax);
     }
     for (int b = t; b < NR_HIST; b += 256)
-        if (hist[b]) atomicAdd(&nrs->hist[b], (unsigned long long)hist[b]);
+        if (hist[b]) nrs.hist[blockIdx.x * NR_HIST + b] += hist[b];
 }
 
 // ------------------------------------------------------------ host launchers
@@ -1412,8 +1413,11 @@ static void launch_step_kernels_t(const StepArgs &a) {
     using T = typename Store<S>::T;
     const Params &p = a.p;
     T *A = (T *)a.A, *B = (T *)a.B;
-    const int link_grid = max(1, min(cdiv(p.link_cap, 256), 2048));
-    const int spec_grid = max(1, min(cdiv(p.special_cap, 4), 2048));
+    // list kernels stride over their lists; size their grids for the expected lengths
+    const int nlink = p.est_links > 0 ? min(p.est_links, p.link_cap) : p.link_cap;
+    const int nspec = p.est_special > 0 ? min(p.est_special, p.special_cap) : p.special_cap;
+    const int link_grid = max(1, min(cdiv(nlink, 256), 2048));
+    const int spec_grid = max(1, min(cdiv(nspec, 4), 2048));
     if (a.phase == PHASE_LINKS) {
         const int update = a.move && !p.contact;
         if (p.np > 0)
@@ -1442,7 +1446,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
             k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt,
                                                                 a.part_first_blk, a.l_off,
                                                                 a.l_node, a.l_do, a.cnt, a.own_dead);
-            const int qg = max(1, min(cdiv(p.link_cap, 32), 2048));
+            const int qg = max(1, min(cdiv(nlink, 32), NR_BLOCKS));
             if (a.warm)
                 k_link_q<true><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm,
                                                           a.mlp_body);

@@ -39,7 +39,7 @@ struct StepArgs {
     uint32_t *special;
     Counters *cnt;
     ContactBufs cb;
-    NrStats *nrs;           // link-fraction solver statistics
+    NrStats nrs;            // link-fraction solver statistics (per-block slots)
     const _Float16 *warm;   // warm-start MLP parameters (FP16), or NULL: plain Newton
     const float *mlp_body;  // [np][80] constant MLP inputs of each body
 };

@@ -35,6 +35,7 @@ size_t mlp_blob_bytes() {
     o = al(o + 4 * (size_t)MLP_MAX_BATCH * MLP_H);  // dz2
     o = al(o + 4 * (size_t)MLP_P);          // g
     o = al(o + 4);                          // loss
+    o = al(o + 4 * (size_t)16 * (MLP_IN + 1) * MLP_H);  // weight-gradient slices
     return o;
 }
 
@@ -56,6 +57,7 @@ MlpBlob mlp_blob(void *base) {
     r.dz2 = (float *)take(4 * (size_t)MLP_MAX_BATCH * MLP_H);
     r.g = (float *)take(4 * (size_t)MLP_P);
     r.loss = (float *)take(4);
+    r.part = (float *)take(4 * (size_t)16 * (MLP_IN + 1) * MLP_H);
     return r;
 }
 
@@ -125,21 +127,36 @@ __global__ void k_mlp_bwd_data(const float *__restrict__ dZ, int N, const TW *__
     dZp[idx] = s * (1.f - h * h);
 }
 
-// gW[k][n] = sum_b h[b][k] dZ[b][n] (k < K), gb[n] = sum_b dZ[b][n] (k = K)
+// Weight gradients in two fixed-order stages: slice s of the batch gives
+// part[s][k][n] = sum_{b in slice} h[b][k] dZ[b][n] (row k = K: the bias,
+// h = 1); then g = sum over the slices in order.
+constexpr int MLP_SLICES = 16;
 template <typename TA>
-__global__ void k_mlp_bwd_weight(const TA *__restrict__ Hin, int K, const float *__restrict__ dZ, int N, int B,
-                                 float *__restrict__ g, int offW, int offB) {
+__global__ void k_mlp_bwd_weight_part(const TA *__restrict__ Hin, int K, const float *__restrict__ dZ, int N, int B,
+                                      float *__restrict__ part) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (K + 1) * N) return;
-    const int k = idx / N, n = idx - k * N;
+    const int per = (K + 1) * N;
+    if (idx >= MLP_SLICES * per) return;
+    const int sl = idx / per, r = idx - sl * per, k = r / N, n = r - k * N;
+    const int b0 = (int)((long long)B * sl / MLP_SLICES), b1 = (int)((long long)B * (sl + 1) / MLP_SLICES);
     float s = 0.f;
-    if (k < K) {
-        for (int b = 0; b < B; ++b) s += (float)Hin[(long long)b * K + k] * dZ[(long long)b * N + n];
-        g[offW + k * N + n] = s;
-    } else {
-        for (int b = 0; b < B; ++b) s += dZ[(long long)b * N + n];
-        g[offB + n] = s;
-    }
+    if (k < K)
+        for (int b = b0; b < b1; ++b) s += (float)Hin[(long long)b * K + k] * dZ[(long long)b * N + n];
+    else
+        for (int b = b0; b < b1; ++b) s += dZ[(long long)b * N + n];
+    part[idx] = s;
+}
+
+__global__ void k_mlp_bwd_weight_sum(const float *__restrict__ part, int K, int N, float *__restrict__ g, int offW,
+                                     int offB) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = (K + 1) * N;
+    if (r >= per) return;
+    float s = 0.f;
+    for (int sl = 0; sl < MLP_SLICES; ++sl) s += part[sl * per + r];
+    const int k = r / N, n = r - k * N;
+    if (k < K) g[offW + k * N + n] = s;
+    else g[offB + n] = s;
 }
 
 __global__ void k_mlp_adam(float *__restrict__ theta, const float *__restrict__ g, float *__restrict__ m,
@@ -205,6 +222,14 @@ void launch_mlp_forward(const MlpBlob &b, const void *X, int n, int precision, h
     else forward_t<_Float16, _Float16>(b, (const _Float16 *)X, b.w16, n, s);
 }
 
+template <typename TA>
+static void bwd_weight(const MlpBlob &b, const TA *Hin, int K, const float *dZ, int N, int n, int offW, int offB,
+                       hipStream_t s) {
+    k_mlp_bwd_weight_part<TA><<<cdiv((long long)MLP_SLICES * (K + 1) * N, 256), 256, 0, s>>>(Hin, K, dZ, N, n,
+                                                                                            b.part);
+    k_mlp_bwd_weight_sum<<<cdiv((K + 1) * N, 256), 256, 0, s>>>(b.part, K, N, b.g, offW, offB);
+}
+
 template <typename TA, typename TW>
 static void grad_t(const MlpBlob &b, const TA *X, const TW *W, const float *T, int n, hipStream_t s) {
     forward_t<TA, TW>(b, X, W, n, s);
@@ -212,16 +237,13 @@ static void grad_t(const MlpBlob &b, const TA *X, const TW *W, const float *T, i
     float *sq = b.dz1;  // squared errors, consumed before dz1 is written
     k_mlp_out_grad<TA><<<cdiv((long long)n * MLP_OUT, 256), 256, 0, s>>>(X, b.out, T, n, b.dout, sq);
     k_mlp_loss<<<1, 256, 0, s>>>(sq, n * MLP_OUT, n, b.loss);
-    k_mlp_bwd_weight<TA><<<cdiv((MLP_H + 1) * MLP_OUT, 256), 256, 0, s>>>(h2, MLP_H, b.dout, MLP_OUT, n, b.g,
-                                                                          MLP_OFF_W3, MLP_OFF_B3);
+    bwd_weight<TA>(b, h2, MLP_H, b.dout, MLP_OUT, n, MLP_OFF_W3, MLP_OFF_B3, s);
     k_mlp_bwd_data<TA, TW><<<cdiv((long long)n * MLP_H, 256), 256, 0, s>>>(b.dout, MLP_OUT, W, MLP_OFF_W3, MLP_H,
                                                                            h2, n, b.dz2);
-    k_mlp_bwd_weight<TA><<<cdiv((MLP_H + 1) * MLP_H, 256), 256, 0, s>>>(h1, MLP_H, b.dz2, MLP_H, n, b.g,
-                                                                        MLP_OFF_W2, MLP_OFF_B2);
+    bwd_weight<TA>(b, h1, MLP_H, b.dz2, MLP_H, n, MLP_OFF_W2, MLP_OFF_B2, s);
     k_mlp_bwd_data<TA, TW><<<cdiv((long long)n * MLP_H, 256), 256, 0, s>>>(b.dz2, MLP_H, W, MLP_OFF_W2, MLP_H, h1,
                                                                            n, b.dz1);
-    k_mlp_bwd_weight<TA><<<cdiv((MLP_IN + 1) * MLP_H, 256), 256, 0, s>>>(X, MLP_IN, b.dz1, MLP_H, n, b.g,
-                                                                         MLP_OFF_W1, MLP_OFF_B1);
+    bwd_weight<TA>(b, X, MLP_IN, b.dz1, MLP_H, n, MLP_OFF_W1, MLP_OFF_B1, s);
 }
 
 void launch_mlp_loss_grad(const MlpBlob &b, const void *X, const float *T, int n, int precision, hipStream_t s) {

@@ -59,6 +59,7 @@ struct MlpBlob {
     float *dz1, *dz2;      // [B][64]
     float *g;              // [P] gradient
     float *loss;           // [1]
+    float *part;           // [16][88][64] weight-gradient slices
 };
 size_t mlp_blob_bytes();
 MlpBlob mlp_blob(void *base);
