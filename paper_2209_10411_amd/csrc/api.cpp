@@ -1214,14 +1214,16 @@ void lbm_destroy(lbm_ctx *c) {
 
 namespace {
 constexpr int GRAPH_PERIOD = 6;
+constexpr int BATCH_AUX = 3;  // streams for the systems' boundary kernels (with the first: 4 hardware queues)
 constexpr int TW_CANDIDATES[3] = {6, 5, 4};  // wave tiles 64x1, 32x2, 16x4
 }  // namespace
 
 struct lbm_batch {
     int n = 0;
     std::vector<lbm_ctx *> cs;
-    hipStream_t caller = nullptr, main = nullptr, aux = nullptr;
-    hipEvent_t ev_in = nullptr, ev_main = nullptr, ev_flags = nullptr, ev_links = nullptr, ev_out = nullptr;
+    hipStream_t caller = nullptr, main = nullptr, aux[BATCH_AUX] = {};
+    hipEvent_t ev_in = nullptr, ev_main = nullptr, ev_out = nullptr;
+    hipEvent_t ev_flags[BATCH_AUX] = {}, ev_links[BATCH_AUX] = {};
     int storage = 0, bw = 8;
     std::vector<int> tw;  // tile width log2 per system
     BulkCase *d_cases = nullptr;  // [n + 1]: the table, plus one slot for tuning runs
@@ -1308,32 +1310,30 @@ std::vector<uintptr_t> state_key(const lbm_batch *b) {
     return k;
 }
 
-// One coupled step of every system, enqueued on b->main / b->aux: the
-// batched stream-collide on the first stream; bounce-back, rigid bodies,
-// flags, classification, boundary pass and link build of every system on the
-// second, which starts after the first stream's previous work.  The next
-// step's stream-collide waits for every system's boundary pass.
+// One coupled step of every system, enqueued on b->main and the second
+// streams: the batched stream-collide on the first stream; bounce-back,
+// rigid bodies, flags, classification, boundary pass and link build of each
+// system on one of the second streams (systems dealt out in turn), which
+// start after the first stream's previous work.  The next step's
+// stream-collide waits for every system's boundary pass.
 lbm_status enqueue_batch_step(lbm_batch *b) {
     HIPCHK(hipEventRecord(b->ev_main, b->main));
-    HIPCHK(hipStreamWaitEvent(b->aux, b->ev_main, 0));
+    for (int k = 0; k < BATCH_AUX; ++k) HIPCHK(hipStreamWaitEvent(b->aux[k], b->ev_main, 0));
     std::vector<StepArgs> as(b->n);
     for (int i = 0; i < b->n; ++i) {
         StepArgs a = base_args(b->cs[i]);
         a.move = 1;
-        a.stream = b->aux;
+        a.stream = b->aux[i % BATCH_AUX];
         a.phase = PHASE_LINKS;
         launch_phase(a);
         a.phase = PHASE_FLAGS;
         launch_phase(a);
-        as[i] = a;
-    }
-    for (int i = 0; i < b->n; ++i) {
-        StepArgs a = as[i];
         a.phase = PHASE_SPECIAL;
         a.in_place = 0;
         launch_phase(a);
+        as[i] = a;
     }
-    HIPCHK(hipEventRecord(b->ev_flags, b->aux));
+    for (int k = 0; k < BATCH_AUX; ++k) HIPCHK(hipEventRecord(b->ev_flags[k], b->aux[k]));
     for (int i = 0; i < b->n; ++i) {
         StepArgs a = as[i];
         a.phase = PHASE_LINKBUILD;
@@ -1341,7 +1341,7 @@ lbm_status enqueue_batch_step(lbm_batch *b) {
         launch_phase(a);
     }
     launch_bulk_batch(b->storage, b->bw, b->d_cases, b->d_blk, b->nblocks, b->parity, b->main);
-    HIPCHK(hipStreamWaitEvent(b->main, b->ev_flags, 0));
+    for (int k = 0; k < BATCH_AUX; ++k) HIPCHK(hipStreamWaitEvent(b->main, b->ev_flags[k], 0));
     for (int i = 0; i < b->n; ++i) {
         lbm_ctx *c = b->cs[i];
         const int old = c->ic;
@@ -1356,8 +1356,10 @@ lbm_status enqueue_batch_step(lbm_batch *b) {
 }
 
 lbm_status join_aux(lbm_batch *b) {
-    HIPCHK(hipEventRecord(b->ev_links, b->aux));
-    HIPCHK(hipStreamWaitEvent(b->main, b->ev_links, 0));
+    for (int k = 0; k < BATCH_AUX; ++k) {
+        HIPCHK(hipEventRecord(b->ev_links[k], b->aux[k]));
+        HIPCHK(hipStreamWaitEvent(b->main, b->ev_links[k], 0));
+    }
     return LBM_OK;
 }
 
@@ -1392,13 +1394,19 @@ lbm_status capture_graph(lbm_batch *b) {
 void free_batch(lbm_batch *b) {
     if (!b) return;
     if (b->main) (void)hipStreamSynchronize(b->main);
-    if (b->aux) (void)hipStreamSynchronize(b->aux);
+    for (hipStream_t a : b->aux)
+        if (a) (void)hipStreamSynchronize(a);
     drop_graph(b);
     for (auto *c : b->cs) lbm_destroy(c);
-    for (hipEvent_t e : {b->ev_in, b->ev_main, b->ev_flags, b->ev_links, b->ev_out})
+    for (hipEvent_t e : {b->ev_in, b->ev_main, b->ev_out})
         if (e) (void)hipEventDestroy(e);
+    for (int k = 0; k < BATCH_AUX; ++k) {
+        if (b->ev_flags[k]) (void)hipEventDestroy(b->ev_flags[k]);
+        if (b->ev_links[k]) (void)hipEventDestroy(b->ev_links[k]);
+    }
     if (b->main) (void)hipStreamDestroy(b->main);
-    if (b->aux) (void)hipStreamDestroy(b->aux);
+    for (hipStream_t a : b->aux)
+        if (a) (void)hipStreamDestroy(a);
     delete b;
 }
 
@@ -1508,8 +1516,12 @@ lbm_status lbm_batch_init(int32_t n_cases, const lbm_config *cfgs, const int32_t
     };
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
-    if ((e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
-    for (hipEvent_t *ev : {&b->ev_in, &b->ev_main, &b->ev_flags, &b->ev_links, &b->ev_out})
+    for (int k = 0; k < BATCH_AUX; ++k) {
+        if ((e = hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+        if ((e = hipEventCreateWithFlags(&b->ev_flags[k], hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+        if ((e = hipEventCreateWithFlags(&b->ev_links[k], hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
+    }
+    for (hipEvent_t *ev : {&b->ev_in, &b->ev_main, &b->ev_out})
         if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return bail(e, "event");
     // the systems were initialised on the caller's stream
     if ((e = hipStreamSynchronize(b->caller)) != hipSuccess) return bail(e, "hipStreamSynchronize");

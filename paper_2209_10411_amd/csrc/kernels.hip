@@ -198,9 +198,10 @@ __device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], 
 // arithmetic, and the first of the eight sub-interval ends with C >= 1 closes
 // the bracket (none: q = 1).  Then a safeguarded Newton iteration
 // (rtsafe-style: a Newton step that leaves the bracket or does not halve the
-// step falls back to bisection) to |step| < 1e-13, started at the guess when
-// it lies inside the bracket, else by regula falsi on the bracket ends, for
-// at most it_max evaluations (conv: converged).  Every lane returns the same
+// step falls back to bisection) to |step| < 1e-13 or |C - 1| < 1e-15,
+// started at the guess when it lies inside the bracket, else by regula
+// falsi on the bracket ends, for at most it_max evaluations (conv:
+// converged).  Every lane returns the same
 // q and resid = C - 1 at the last evaluation; the return value is the
 // number of evaluations of the iteration.
 __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z, int i, double guess,
@@ -236,6 +237,10 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
         ++it;
         const double g = C - 1.0;
         resid = g;
+        if (fabs(g) < 1e-15) {  // C = 1 to a few ulps: nothing left to resolve (tangent links get here
+            conv = true;        // long before the step drops below 1e-13)
+            break;
+        }
         if (g >= 0.0) hi = s; else lo = s;
         const double sn = s - g / dC;
         if (!(dC != 0.0) || !(sn > lo && sn < hi) || fabs(2.0 * g) > fabs(dxold * dC)) {
