@@ -298,3 +298,48 @@ def test_periodic_suspension_small(mdl):
         ref.step(20)
         compare_fields(sim, ref, label=f"suspension step {20 * (k + 1)}")
         _compare_particles(sim, ref, cfg, 1e-6, 1e-7)
+
+
+_TR_STEPS = (50, 100, 200, 400)
+
+
+@pytest.fixture(scope="module")
+def drafting_oracle():
+    """FP64 oracle snapshots of the two-body drafting case at 0.4 scale
+    (64 x 64 x 256, bodies of 6 and 12 control points, gravity raised to
+    2e-4 so that they move within the compared steps)."""
+    cfg = workloads.config3(scale=0.4, storage=workloads.STORE_F32)
+    cfg.g_particle = np.array([0.0, 0.0, -2e-4])
+    ref = oracle.Oracle(cfg)
+    snaps, done = {}, 0
+    for s in _TR_STEPS:
+        ref.step(s - done)
+        done = s
+        rho, u = ref.macros()
+        snaps[s] = (ref.owner() < 0, u, [ref.particle(j)["x"].copy() for j in range(2)])
+    return cfg, snaps
+
+
+@pytest.mark.parametrize("storage,tol_u,tol_x", [(workloads.STORE_F32, 1e-5, 1e-5), (workloads.STORE_F16, 5e-3, 2e-3),
+                                                 (workloads.STORE_BF16, 5e-2, 2e-2)])
+def test_storage_error_time_resolved(mdl, drafting_oracle, storage, tol_u, tol_x):
+    """Error of each storage type against the FP64 oracle along the
+    trajectory (max |du|/U over fluid nodes, particle |dx|), printed per
+    checkpoint."""
+    cfg0, snaps = drafting_oracle
+    cfg = cfg0.copy()
+    cfg.storage = storage
+    sim = mdl.Simulation(cfg)
+    done = 0
+    for s in _TR_STEPS:
+        sim.step(s - done)
+        done = s
+        fl, u_o, xs = snaps[s]
+        _, u_g = sim.macros()
+        fl = fl & (sim.owner() < 0)
+        U = np.abs(u_o[fl]).max()
+        du = np.abs(u_g[fl] - u_o[fl]).max() / U
+        dx = max(np.abs(p["x"] - x).max() for p, x in zip(sim.particles(), xs))
+        print(f"storage {storage} step {s}: U={U:.3e} max|du|/U={du:.2e} |dx|={dx:.2e}", flush=True)
+        assert du < tol_u and dx < tol_x
+    sim.close()
