@@ -106,6 +106,30 @@ def nr_summary(hist, resid):
             "p99_iterations": p99, "max_final_residual": resid}
 
 
+def run_suspension(steps):
+    """The 256^3 periodic suspension of 200 bodies (seed 5), plain Newton."""
+    import torch
+
+    import paper_2209_10411_amd as mdl
+    import workloads
+
+    cfg = workloads.config5(seed=5)
+    sim = mdl.Simulation(cfg, device="cuda:0")
+    sim.step(5)
+    sim.sync()
+    sim.nr_histogram()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h, r = sim.nr_histogram()
+    sim.close()
+    return dict(nr_summary(h, r), workload="256^3 periodic suspension, 200 bodies, FP32, IBB", steps=steps,
+                mlups=round(cfg.n_nodes * steps / dt / 1e6, 1), ms_per_step=round(dt * 1e3 / steps, 4))
+
+
 def run_mlp_warmstart(steps, epochs):
     """Link-fraction warm start on the 256^3 periodic suspension of 200
     bodies (FP32): the MLP is trained on the link fractions the method
@@ -229,7 +253,7 @@ def main():
     ap.add_argument("--mlp-steps", type=int, default=100)
     ap.add_argument("--mlp-epochs", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB copy (PMC calibration)")
-    ap.add_argument("--only", choices=["ensemble", "warm-start"],
+    ap.add_argument("--only", choices=["ensemble", "warm-start", "suspension"],
                     help="run only this part and print its JSON object (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -242,6 +266,9 @@ def main():
         return
     if args.only == "ensemble":
         print(json.dumps(run_ensemble(64, args.ensemble_steps, 12)), flush=True)
+        return
+    if args.only == "suspension":
+        print(json.dumps(run_suspension(args.mlp_steps)), flush=True)
         return
     if args.only == "warm-start":
         print(json.dumps(run_mlp_warmstart(args.mlp_steps, args.mlp_epochs)), flush=True)

@@ -181,7 +181,7 @@ struct Plan {
     std::vector<int> part, first;     // [region_blocks]
     std::vector<int> part_first_blk;  // [np]
     std::vector<int> half;            // [np]
-    size_t off_A, off_B, off_own[3], off_skip[2], off_stamp, off_P, off_part, off_first, off_dims,
+    size_t off_A, off_B, off_own[3], off_skip[2], off_P, off_part, off_first, off_dims,
         off_pfb, off_bcnt, off_loff, off_lnode, off_ldo, off_lq, off_lpart, off_special,
         off_cnt, total;
     bool contact;
@@ -296,7 +296,6 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     for (int k = 0; k < 3; ++k) pl.off_own[k] = take(4 * pl.N);
     pl.off_skip[0] = take(pl.N);
     pl.off_skip[1] = take(pl.N);
-    pl.off_stamp = take(4 * pl.N);
     pl.off_P = take(sizeof(DevParticle) * std::max(np, 1));
     pl.off_part = take(4 * std::max(pl.region_blocks, 1));
     pl.off_first = take(4 * std::max(pl.region_blocks, 1));
@@ -340,7 +339,6 @@ struct lbm_ctx {
     int ic, in, id;  // current flags, next (all FLUID), dead (previous)
     uint8_t *skip[2];
     int is;          // skip mask of the coming step
-    uint32_t *stamp;
     DevParticle *P;
     RegionMap rm;
     int *part_first_blk, *blk_cnt, *l_off;
@@ -372,7 +370,7 @@ StepArgs base_args(lbm_ctx *c) {
     a.A = c->A; a.B = c->B;
     a.own_old = c->own[c->ic]; a.own_new = c->own[c->in]; a.own_dead = nullptr;
     a.skip = c->skip[c->is]; a.skip_next = c->skip[1 - c->is];
-    a.stamp = c->stamp; a.P = c->P; a.rm = c->rm;
+    a.P = c->P; a.rm = c->rm;
     a.part_first_blk = c->part_first_blk;
     a.blk_cnt = c->blk_cnt; a.l_off = c->l_off; a.lmask = c->lmask;
     a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.part = c->lpart;
@@ -569,7 +567,6 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->skip[0] = (uint8_t *)(b + pl.off_skip[0]);
     c->skip[1] = (uint8_t *)(b + pl.off_skip[1]);
     c->is = 0;
-    c->stamp = (uint32_t *)(b + pl.off_stamp);
     c->P = (DevParticle *)(b + pl.off_P);
     c->rm.part = (const int *)(b + pl.off_part);
     c->rm.first = (const int *)(b + pl.off_first);
@@ -665,7 +662,6 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     HIPCHK_C(hipEventCreateWithFlags(&c->ev_flags, hipEventDisableTiming));
     HIPCHK_C(hipEventCreateWithFlags(&c->ev_links, hipEventDisableTiming));
     for (int k = 0; k < 3; ++k) launch_fill_i32(c->own[k], pl.N, FLUID, c->stream);
-    launch_fill_i32((int32_t *)c->stamp, pl.N, 0, c->stream);
 
     // counter-force: the fluid carries minus the net weight of free bodies
     if (cfg->counter_force && n_p > 0) {

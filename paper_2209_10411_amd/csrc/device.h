@@ -49,7 +49,7 @@ struct Counters {
     int n_refill;   // uncovered nodes this step
     int n_solid;    // solid nodes counted by the last classification
     int err;        // ERR_* bits
-    uint32_t tag;   // classification pass number (stamps claimed nodes)
+    uint32_t pad0;
     int pad[2];
     unsigned long long n_contacts;      // contacts resolved (pairs + walls, per sub-step)
     unsigned long long n_contact_fail;  // contact iterations that did not converge

@@ -476,7 +476,7 @@ __device__ void refresh_pose(const Params &p, DevParticle &P) {
 // partials from k_links) into the particle's hydrodynamic force and torque;
 // with 'update' (no contact: bodies move independently) also the body's
 // rigid-body update on an LDS copy of its record.  Block 0 also clears the
-// per-step counters and advances the classification tag.
+// per-step counters.
 __device__ void body_substep(const Params &p, DevParticle &P, const double F[3], const double T[3], double dt);
 __device__ void end_of_step(const Params &p, DevParticle &B, Counters *cnt);
 
@@ -524,11 +524,10 @@ __device__ void reset_step_counters(Counters *cnt) {
     cnt->n_special = 0;
     cnt->n_refill = 0;
     cnt->n_solid = 0;
-    cnt->tag += 1u;
 }
 
 // One block per particle: reduce_body.  Block 0 also clears the per-step
-// counters and advances the classification tag.
+// counters.
 __global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restrict__ P,
                                                 const int *__restrict__ l_off,
                                                 const double *__restrict__ part,
@@ -932,6 +931,15 @@ __device__ __forceinline__ bool region_node(const Params &p, const RegionMap &rm
     if (local >= dx * dy * dz) return false;
     const int lx = local % dx, t = local / dx, ly = t % dy, lz = t / dy;
     const DevParticle &B = P[pi];
+    if (!(B.full[0] | B.full[1] | B.full[2])) {
+        // only the part of the cube within half + 2 of its centre floor(X):
+        // what flagging, classification and link build touch lies within the
+        // extent r_e of a centroid (at most two steps away, each step moving
+        // less than one node), plus a neighbour (sqrt 2) and the offset of X
+        // from the centre (sqrt 3): r_e + 5.15 < ceil(r_e) + 6 = half + 2
+        const int ax = lx - B.half, ay = ly - B.half, az = lz - B.half, rr = B.half + 2;
+        if (ax * ax + ay * ay + az * az > rr * rr) return false;
+    }
     int c[3] = {B.lo[0] + lx, B.lo[1] + ly, B.lo[2] + lz};
     const int L[3] = {p.nx, p.ny, p.nz};
     for (int a = 0; a < 3; ++a) {
@@ -970,8 +978,12 @@ __device__ __forceinline__ int block_sum(int v, int *sh) {
     return sh[0];
 }
 
-// Node classification over the body regions, once per node (claimed through
-// the stamp array when several regions may overlap):
+// Node classification over the body regions.  Where regions overlap, one
+// region decides each node without any claiming: a solid node by its owner
+// after the step, an uncovered node by its owner before, a fluid node next to
+// solid nodes by the lowest body index among those neighbours (old and new
+// flags), whose region always contains it; a plain fluid node (no solid
+// node around) only gets skip = 0, which any region may write.
 //   - special list of this step: nodes fluid after the step that were solid
 //     before (uncovered: refill) or had an in-domain solid neighbour before
 //     (cut links: bounce-back);
@@ -983,36 +995,35 @@ __device__ __forceinline__ int block_sum(int v, int *sh) {
 __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm, const DevParticle *P,
                                                          const int32_t *__restrict__ own_old,
                                                          const int32_t *__restrict__ own_new,
-                                                         uint8_t *__restrict__ skip_next, uint32_t *stamp,
+                                                         uint8_t *__restrict__ skip_next,
                                                          uint32_t *special, Counters *cnt, int *blk_cnt,
                                                          uint32_t *lmask) {
     __shared__ int sh[BLK];
     int pi, x, y, z;
     long long n;
     const bool in = region_node(p, rm, P, pi, x, y, z, n);
-    bool nb_old = false, nb_new = false;
     uint32_t m = 0u;
-    bool so = false, sn = false;
+    // owners before / after, lowest owner among the neighbours before / after
+    int32_t oo = FLUID, on = FLUID, mo = FLUID, mn = FLUID;
     if (in) {
-        so = own_old[n] != FLUID;
-        sn = own_new[n] != FLUID;
+        oo = own_old[n];
+        on = own_new[n];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             long long s;
             if (nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s)) {
                 const int32_t vo = own_old[s], vn = own_new[s];
-                nb_old |= vo != FLUID;
-                nb_new |= vn != FLUID;
+                mo = min(mo, vo);
+                mn = min(mn, vn);
                 if (vn == pi) m |= 1u << i;
             }
         }
-        if (sn) m = 0u;
     }
+    const bool so = oo != FLUID, sn = on != FLUID, nb_old = mo != FLUID, nb_new = mn != FLUID;
+    const int32_t onb = min(mo, mn);
+    if (sn) m = 0u;
     bool act = in;
-    if (act && p.np > 1) {  // regions of several bodies may overlap: first claimer classifies
-        const uint32_t tag = cnt->tag;
-        if (atomicExch(&stamp[n], tag) == tag) act = false;
-    }
+    if (act) act = sn ? on == pi : so ? oo == pi : onb == FLUID || onb == pi;
     if (act) {
         skip_next[n] = (uint8_t)((sn || nb_new) ? 1 : 0);
         const bool lo = !so && nb_old;
@@ -1434,7 +1445,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
         if (p.np > 0) {
             if (a.move) k_region_mark<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new);
             k_region_classify<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_old, a.own_new,
-                                                                      a.skip_next, a.stamp, a.special,
+                                                                      a.skip_next, a.special,
                                                                       a.cnt, a.move ? a.blk_cnt : nullptr,
                                                                       a.lmask);
         }

@@ -28,7 +28,6 @@ struct StepArgs {
     int32_t *own_dead;  // PHASE_LINKBUILD: flag buffer to reset to FLUID on the regions, or NULL
     uint8_t *skip;       // PHASE_BULK: skip mask of this step
     uint8_t *skip_next;  // PHASE_FLAGS: skip mask of the next step
-    uint32_t *stamp;
     DevParticle *P;
     RegionMap rm;
     const int *part_first_blk;
