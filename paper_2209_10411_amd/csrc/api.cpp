@@ -351,7 +351,7 @@ struct lbm_ctx {
     float *mlp_body;            // [np][80] constant warm-start inputs of each body
     const _Float16 *warm;       // warm-start MLP parameters, or NULL
     hipStream_t aux;              // second stream: link build overlapped with stream-collide
-    hipEvent_t ev_main, ev_flags, ev_links;
+    hipEvent_t ev_main, ev_flags, ev_links, ev_bulk;
     bool pending_refill;
     bool timing;
     std::vector<hipEvent_t> ev;  // start/stop pairs
@@ -589,7 +589,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->cb.wallT = (double *)(b + pl.off_wallT); c->cb.xiP = (double *)(b + pl.off_xiP);
     c->cb.xiW = (double *)(b + pl.off_xiW);
     c->aux = nullptr;
-    c->ev_main = c->ev_flags = c->ev_links = nullptr;
+    c->ev_main = c->ev_flags = c->ev_links = c->ev_bulk = nullptr;
     c->timing = false;
     c->ev_used = 0;
     c->timed_launches = 0;
@@ -626,6 +626,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
         if (c->ev_main) (void)hipEventDestroy(c->ev_main);
         if (c->ev_flags) (void)hipEventDestroy(c->ev_flags);
         if (c->ev_links) (void)hipEventDestroy(c->ev_links);
+        if (c->ev_bulk) (void)hipEventDestroy(c->ev_bulk);
         if (c->aux) (void)hipStreamDestroy(c->aux);
         delete c;
         return st;
@@ -659,7 +660,9 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     }
     HIPCHK_C(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIPCHK_C(hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming));
-    HIPCHK_C(hipEventCreateWithFlags(&c->ev_flags, hipEventDisableTiming));
+    // recorded with kernel dispatches (hipExtLaunchKernel): default flags
+    HIPCHK_C(hipEventCreate(&c->ev_flags));
+    HIPCHK_C(hipEventCreate(&c->ev_bulk));
     HIPCHK_C(hipEventCreateWithFlags(&c->ev_links, hipEventDisableTiming));
     for (int k = 0; k < 3; ++k) launch_fill_i32(c->own[k], pl.N, FLUID, c->stream);
 
@@ -744,12 +747,16 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
     // next step's stream-collide (which pulls from those nodes) waits for it,
     // and the next step's second-stream work starts after this step's
     // stream-collide (it overwrites the buffer that one reads).
+    // the second stream's first step follows everything earlier on the caller's
+    // stream; later steps follow the previous stream-collide (the event rides
+    // on its dispatch)
+    if (n_steps > 0) HIPCHK(hipEventRecord(c->ev_main, c->stream));
+    hipEvent_t after = c->ev_main;
     for (int s = 0; s < n_steps; ++s) {
         StepArgs a = base_args(c);
         a.move = move;
         if (!move) a.own_new = a.own_old;  // geometry fixed
-        HIPCHK(hipEventRecord(c->ev_main, c->stream));
-        HIPCHK(hipStreamWaitEvent(c->aux, c->ev_main, 0));
+        HIPCHK(hipStreamWaitEvent(c->aux, after, 0));
         StepArgs b = a;
         b.stream = c->aux;
         b.phase = PHASE_LINKS;
@@ -758,21 +765,21 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
         launch_phase(b);
         b.phase = PHASE_SPECIAL;
         b.in_place = 0;
+        b.ev_stop = c->ev_flags;
         launch_phase(b);
-        HIPCHK(hipEventRecord(c->ev_flags, c->aux));
+        b.ev_stop = nullptr;
         if (move) {
             b.phase = PHASE_LINKBUILD;
             b.own_dead = c->own[c->id];  // flags of step n-1 are dead: cleared here
             launch_phase(b);
         }
         const bool t = c->timing && c->ev_used + 2 <= c->ev.size();
-        if (t) HIPCHK(hipEventRecord(c->ev[c->ev_used], c->stream));
         a.phase = PHASE_BULK;
+        a.ev_start = t ? c->ev[c->ev_used] : nullptr;
+        a.ev_stop = t ? c->ev[c->ev_used + 1] : c->ev_bulk;
+        after = a.ev_stop;
         launch_phase(a);
-        if (t) {
-            HIPCHK(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
-            c->ev_used += 2;
-        }
+        if (t) c->ev_used += 2;
         HIPCHK(hipStreamWaitEvent(c->stream, c->ev_flags, 0));
         if (move) {
             const int old = c->ic;
@@ -1192,6 +1199,7 @@ void lbm_destroy(lbm_ctx *c) {
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
     if (c->ev_flags) (void)hipEventDestroy(c->ev_flags);
     if (c->ev_links) (void)hipEventDestroy(c->ev_links);
+    if (c->ev_bulk) (void)hipEventDestroy(c->ev_bulk);
     if (c->aux) {
         (void)hipStreamSynchronize(c->aux);
         (void)hipStreamDestroy(c->aux);

@@ -21,6 +21,7 @@
 //                    Newton iteration in FP64
 // Populations are deviations f_i - w_i rho0 in FP32, FP16 or BF16 storage;
 // collisions run in FP32, everything geometric or mechanical in FP64.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -1452,11 +1453,16 @@ static void launch_step_kernels_t(const StepArgs &a) {
     } else if (a.phase == PHASE_BULK) {
         const int nseg = cdiv(p.nx, 64);
         const long long waves = (long long)nseg * p.ny * p.nz;
-        k_bulk<S><<<cdiv(waves, BULK_WAVES), 64 * BULK_WAVES, 0, a.stream>>>(p, A, B, a.skip, nseg);
+        // events ride on the dispatch itself (no separate marker packets)
+        hipExtLaunchKernelGGL(k_bulk<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0, a.stream,
+                              a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip, nseg);
     } else if (a.phase == PHASE_SPECIAL) {
         if (p.np > 0)
-            k_special<S><<<spec_grid, 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.special, a.cnt,
-                                                           a.in_place);
+            hipExtLaunchKernelGGL(k_special<S>, dim3(spec_grid), dim3(256), 0, a.stream, a.ev_start, a.ev_stop, 0,
+                                  p, (const T *)A, B, (const int32_t *)a.own_old, (const DevParticle *)a.P,
+                                  (const uint32_t *)a.special, a.cnt, a.in_place);
+        else if (a.ev_stop)
+            (void)hipEventRecord(a.ev_stop, a.stream);
     } else if (a.phase == PHASE_LINKBUILD) {
         if (p.np > 0) {
             k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt,

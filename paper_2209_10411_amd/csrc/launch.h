@@ -41,6 +41,7 @@ struct StepArgs {
     NrStats nrs;            // link-fraction solver statistics (per-block slots)
     const _Float16 *warm;   // warm-start MLP parameters (FP16), or NULL: plain Newton
     const float *mlp_body;  // [np][80] constant MLP inputs of each body
+    hipEvent_t ev_start, ev_stop;  // PHASE_BULK / PHASE_SPECIAL: events recorded with the dispatch, or NULL
 };
 
 void launch_phase(const StepArgs &a);
