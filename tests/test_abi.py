@@ -77,3 +77,61 @@ def test_particle_crossing_a_wall_is_rejected(mdl):
     with pytest.raises(mdl.LbmError) as e:
         mdl.arena_bytes(cfg)
     assert "wall" in str(e.value)
+
+
+def _batch_args(mdl, cfgs):
+    import ctypes as C
+    n = len(cfgs)
+    cc = (mdl.lbm_config * n)(*[mdl.make_config(c) for c in cfgs])
+    parts, keep = mdl.make_particles([p for c in cfgs for p in c.particles])
+    npa = (C.c_int32 * n)(*[len(c.particles) for c in cfgs])
+    return n, cc, npa, parts, keep
+
+
+def test_batch_arena_bytes_sums_the_systems(mdl):
+    import ctypes as C
+    cfgs = workloads.mini_ensemble(3)
+    n, cc, npa, parts, keep = _batch_args(mdl, cfgs)
+    b = C.c_size_t(0)
+    assert mdl.lib().lbm_batch_arena_bytes(n, cc, npa, parts, C.byref(b)) == 0
+    assert b.value >= sum(mdl.arena_bytes(c) for c in cfgs)
+
+
+def test_batch_rejects_mixed_storage_and_bad_cases(mdl):
+    import ctypes as C
+    cfgs = workloads.mini_ensemble(2)
+    cfgs[1].storage = workloads.STORE_F16
+    n, cc, npa, parts, keep = _batch_args(mdl, cfgs)
+    b = C.c_size_t(0)
+    assert mdl.lib().lbm_batch_arena_bytes(n, cc, npa, parts, C.byref(b)) == -1
+    assert b"storage" in mdl.lib().lbm_last_error()
+    cfgs = workloads.mini_ensemble(2)
+    cfgs[1].tau = 0.5
+    n, cc, npa, parts, keep = _batch_args(mdl, cfgs)
+    assert mdl.lib().lbm_batch_arena_bytes(n, cc, npa, parts, C.byref(b)) == -1
+    assert b"case 1" in mdl.lib().lbm_last_error()
+    assert mdl.lib().lbm_batch_arena_bytes(0, cc, npa, parts, C.byref(b)) == -1
+
+
+def test_mlp_sizes_match_the_oracle(mdl):
+    from oracle import mlp
+    assert mdl.lib().mlp_param_count() == mlp.P == 10052
+    assert mdl.lib().mlp_weights_bytes() >= 4 * 3 * mlp.P + 2 * mlp.P
+
+
+@pytest.mark.parametrize("hp", ['{"batch": 0}', '{"batch": 5000}', '{"lr": -1}', '{"beta1": 1.0}',
+                                '{"precision": 2}', '{"eps": 0}'])
+def test_mlp_train_rejects_bad_hyperparameters(mdl, hp):
+    """Rejected before any device access (the pointers are never used)."""
+    import ctypes as C
+    dummy = C.c_void_p(256)
+    rc = mdl.lib().mlp_train(dummy, dummy, 10, hp.encode(), dummy, None)
+    assert rc == -1
+    assert b"hyper-parameters" in mdl.lib().lbm_last_error()
+
+
+def test_mlp_grad_rejects_oversized_batches(mdl):
+    import ctypes as C
+    dummy = C.c_void_p(256)
+    assert mdl.lib().mlp_grad(dummy, dummy, dummy, 5000, 0, None, None, None) == -1
+    assert mdl.lib().mlp_grad(dummy, dummy, dummy, 10, 3, None, None, None) == -1

@@ -104,3 +104,16 @@ def test_system_stepped_alone_inside_an_ensemble(mdl):
     for i, (sim, ref) in enumerate(zip(ens.cases, refs)):
         assert_same(sim, ref, f"case {i}")
     ens.close()
+
+
+def test_ensemble_with_a_system_without_bodies(mdl):
+    """A body-free system (channel flow) between two settling systems."""
+    mini = workloads.mini_ensemble(2)
+    chan = workloads.poiseuille(0.8, H=24, g=1e-5, nx=16, nz=8)
+    cfgs = [mini[0], chan, mini[1]]
+    refs = [alone(mdl, c, 13) for c in cfgs]
+    ens = mdl.Ensemble(cfgs)
+    ens.step(13)
+    for i, (sim, ref) in enumerate(zip(ens.cases, refs)):
+        assert_same(sim, ref, f"case {i} ({cfgs[i].name})")
+    ens.close()
