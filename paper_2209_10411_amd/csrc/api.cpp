@@ -741,8 +741,8 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
     const bool move = mode == LBM_STEP_COUPLED;
     // Per step: the stream-collide of plain nodes runs on the caller's stream
     // while the second stream does bounce-back + momentum exchange, the
-    // rigid-body update, flagging, classification, the boundary/uncovered
-    // node pass and the link build.  The boundary pass writes other nodes of
+    // rigid-body update, flagging, classification with the boundary/uncovered
+    // node update, and the link build.  The boundary pass writes other nodes of
     // the destination buffer than the stream-collide, so the two overlap; the
     // next step's stream-collide (which pulls from those nodes) waits for it,
     // and the next step's second-stream work starts after this step's
@@ -761,10 +761,8 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
         b.stream = c->aux;
         b.phase = PHASE_LINKS;
         launch_phase(b);
-        b.phase = PHASE_FLAGS;
-        launch_phase(b);
-        b.phase = PHASE_SPECIAL;
-        b.in_place = 0;
+        b.phase = PHASE_FLAGS;  // with the boundary/uncovered update
+        b.do_special = 1;
         b.ev_stop = c->ev_flags;
         launch_phase(b);
         b.ev_stop = nullptr;
@@ -1330,10 +1328,8 @@ lbm_status enqueue_batch_step(lbm_batch *b) {
         a.stream = b->aux[i % BATCH_AUX];
         a.phase = PHASE_LINKS;
         launch_phase(a);
-        a.phase = PHASE_FLAGS;
-        launch_phase(a);
-        a.phase = PHASE_SPECIAL;
-        a.in_place = 0;
+        a.phase = PHASE_FLAGS;  // with the boundary/uncovered update
+        a.do_special = 1;
         launch_phase(a);
         as[i] = a;
     }

@@ -979,31 +979,97 @@ __device__ __forceinline__ int block_sum(int v, int *sh) {
     return sh[0];
 }
 
+// Boundary or uncovered node n = (x, y, z), one thread: pull the 19
+// populations -- a source outside a wall bounces off the resting wall, a
+// source inside a body takes the bounce-back value that k_links left in B;
+// for an uncovered node (solid before) populations from fluid sources are
+// kept and a missing f_i becomes f_opp(i) + 6 w rho0 e_i.u_new if the
+// opposite came from a fluid node, else feq_i(rho0, u_new) (sec. 2.3.2,
+// refilling) -- then collide and store into B.  wall / solid: bit i set
+// when the source x - e_i (i >= 1) lies outside the domain / in a body
+// before the step; owner: the body that covered an uncovered node (FLUID
+// otherwise).
+template <int S>
+__device__ void special_update(const Params &p, const typename Store<S>::T *__restrict__ A,
+                               typename Store<S>::T *__restrict__ B, const DevParticle *__restrict__ P, int x,
+                               int y, int z, long long n, uint32_t wall, uint32_t solid, int32_t owner) {
+    const bool unc = owner != FLUID;
+    // the rest population's source is the node itself: solid before for an
+    // uncovered node
+    if (unc) solid |= 1u;
+    float d[Q];
+    uint32_t missing = 0u;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        d[i] = 0.f;
+        if ((wall >> i) & 1u) {
+            if (unc) missing |= 1u << i;
+            else d[i] = Store<S>::ld(A, (long long)OPP[i] * p.N + n, p.inv_scale);
+        } else if ((solid >> i) & 1u) {
+            if (unc) missing |= 1u << i;
+            else d[i] = Store<S>::ld(B, (long long)i * p.N + n, p.inv_scale);
+        } else {
+            long long src;
+            nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], src);
+            d[i] = Store<S>::ld(A, (long long)i * p.N + src, p.inv_scale);
+        }
+    }
+    if (missing) {
+        const DevParticle &Bd = P[owner];
+        double r[3] = {x - Bd.X[0], y - Bd.X[1], z - Bd.X[2]};
+        min_image(p, r);
+        double un[3];
+        cross3(Bd.w, r, un);
+        for (int a = 0; a < 3; ++a) un[a] += Bd.v[a];
+        const double uu = un[0] * un[0] + un[1] * un[1] + un[2] * un[2];
+        float f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = d[i];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (!((missing >> i) & 1u)) continue;
+            const double eu = EX[i] * un[0] + EY[i] * un[1] + EZ[i] * un[2];
+            const double w = WD[i];
+            // the opposite direction's source is x + e_i: kept if it was fluid
+            if (!((missing >> OPP[i]) & 1u))
+                d[i] = (float)((double)f[OPP[i]] + 6.0 * w * p.rho0 * eu);
+            else
+                d[i] = (float)(w * p.rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+        }
+    }
+    collide(d, p);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Store<S>::st(B, (long long)i * p.N + n, d[i], p.scale);
+}
+
 // Node classification over the body regions.  Where regions overlap, one
 // region decides each node without any claiming: a solid node by its owner
 // after the step, an uncovered node by its owner before, a fluid node next to
 // solid nodes by the lowest body index among those neighbours (old and new
 // flags), whose region always contains it; a plain fluid node (no solid
 // node around) only gets skip = 0, which any region may write.
-//   - special list of this step: nodes fluid after the step that were solid
-//     before (uncovered: refill) or had an in-domain solid neighbour before
-//     (cut links: bounce-back);
+//   - nodes fluid after the step that were solid before (uncovered: refill)
+//     or had an in-domain solid neighbour before (cut links: bounce-back)
+//     go to the special list and, with do_special, are updated right here
+//     (special_update);
 //   - skip mask of the NEXT step's stream-collide: solid after, or with an
 //     in-domain solid neighbour after (those nodes are left to the links and
 //     special passes);
 //   - with blk_cnt set, the block also counts the cut links of the new flags
 //     for its body (first pass of the link build).
+template <int S>
 __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm, const DevParticle *P,
                                                          const int32_t *__restrict__ own_old,
                                                          const int32_t *__restrict__ own_new,
                                                          uint8_t *__restrict__ skip_next,
                                                          uint32_t *special, Counters *cnt, int *blk_cnt,
-                                                         uint32_t *lmask) {
+                                                         uint32_t *lmask, const typename Store<S>::T *A,
+                                                         typename Store<S>::T *B, int do_special) {
     __shared__ int sh[BLK];
     int pi, x, y, z;
     long long n;
     const bool in = region_node(p, rm, P, pi, x, y, z, n);
-    uint32_t m = 0u;
+    uint32_t m = 0u, wall = 0u, solid = 0u;
     // owners before / after, lowest owner among the neighbours before / after
     int32_t oo = FLUID, on = FLUID, mo = FLUID, mn = FLUID;
     if (in) {
@@ -1016,7 +1082,10 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
                 const int32_t vo = own_old[s], vn = own_new[s];
                 mo = min(mo, vo);
                 mn = min(mn, vn);
+                if (vo != FLUID) solid |= 1u << i;
                 if (vn == pi) m |= 1u << i;
+            } else {
+                wall |= 1u << i;
             }
         }
     }
@@ -1028,12 +1097,17 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     if (act) {
         skip_next[n] = (uint8_t)((sn || nb_new) ? 1 : 0);
         const bool lo = !so && nb_old;
+        const bool spec = !sn && (so || lo);
         wave_append(&cnt->n_solid, sn);
         wave_append(&cnt->n_refill, !sn && so);
-        const int k = wave_append(&cnt->n_special, !sn && (so || lo));
+        const int k = wave_append(&cnt->n_special, spec);
         if (k >= 0) {
             if (k < p.special_cap) special[k] = (uint32_t)n;
             else atomicOr(&cnt->err, ERR_SPECIAL_OVERFLOW);
+        }
+        if (spec && do_special) {
+            if (so && (oo < 0 || oo >= p.np)) atomicOr(&cnt->err, ERR_BAD_INDEX);  // never expected
+            else special_update<S>(p, A, B, P, x, y, z, n, wall, solid, oo);
         }
     }
     if (!blk_cnt) return;
@@ -1445,10 +1519,12 @@ static void launch_step_kernels_t(const StepArgs &a) {
     } else if (a.phase == PHASE_FLAGS) {
         if (p.np > 0) {
             if (a.move) k_region_mark<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new);
-            k_region_classify<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_old, a.own_new,
-                                                                      a.skip_next, a.special,
-                                                                      a.cnt, a.move ? a.blk_cnt : nullptr,
-                                                                      a.lmask);
+            hipExtLaunchKernelGGL(k_region_classify<S>, dim3(p.region_blocks), dim3(BLK), 0, a.stream, nullptr,
+                                  a.ev_stop, 0, p, a.rm, (const DevParticle *)a.P, (const int32_t *)a.own_old,
+                                  (const int32_t *)a.own_new, a.skip_next, a.special, a.cnt,
+                                  a.move ? a.blk_cnt : (int *)nullptr, a.lmask, (const T *)A, B, a.do_special);
+        } else if (a.ev_stop) {
+            (void)hipEventRecord(a.ev_stop, a.stream);
         }
     } else if (a.phase == PHASE_BULK) {
         const int nseg = cdiv(p.nx, 64);

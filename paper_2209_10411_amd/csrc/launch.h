@@ -9,7 +9,7 @@ namespace mdl {
 
 enum Phase {
     PHASE_LINKS = 0,       // bounce-back values + momentum exchange, force reduction, rigid body
-    PHASE_FLAGS = 1,       // region flags (when move) and node classes
+    PHASE_FLAGS = 1,       // region flags (when move), node classes, optionally the boundary/uncovered update
     PHASE_BULK = 2,        // stream-collide of plain fluid nodes
     PHASE_SPECIAL = 3,     // boundary and uncovered nodes
     PHASE_LINKBUILD = 4,   // cut links and q of the new geometry
@@ -22,6 +22,7 @@ struct StepArgs {
     int phase;
     int move;      // PHASE_LINKS: update particles; PHASE_FLAGS: re-flag
     int in_place;  // PHASE_SPECIAL: refill in place
+    int do_special;  // PHASE_FLAGS: also update the boundary and uncovered nodes into B
     hipStream_t stream;
     void *A, *B;
     int32_t *own_old, *own_new;
