@@ -275,11 +275,30 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
             vol *= d;
         }
         if (vol > 0x7fffffffll) return fail(LBM_E_INVALID, "particle %d is too large", p);
+        // blocks are tiles of TILE_X x TILE_Y x TILE_Z nodes; tiles wholly
+        // outside the ball the kernels visit (radius half + 2 about the
+        // cube's centre) are left out unless the region spans a periodic axis
         pl.part_first_blk[p] = (int)pl.part.size();
-        for (long long f = 0; f < vol; f += BLK) {
-            pl.part.push_back(p);
-            pl.first.push_back((int)f);
-        }
+        const int *d = &pl.dims[3 * p];
+        const int nt[3] = {(d[0] + TILE_X - 1) / TILE_X, (d[1] + TILE_Y - 1) / TILE_Y, (d[2] + TILE_Z - 1) / TILE_Z};
+        const int ts[3] = {TILE_X, TILE_Y, TILE_Z};
+        bool full = false;
+        for (int a = 0; a < 3; ++a) full = full || d[a] != 2 * half + 1;
+        const long long rr = (long long)(half + 2) * (half + 2);
+        for (int tz = 0; tz < nt[2]; ++tz)
+            for (int ty = 0; ty < nt[1]; ++ty)
+                for (int tx = 0; tx < nt[0]; ++tx) {
+                    const int t3[3] = {tx, ty, tz};
+                    long long r2 = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        const int lo = t3[a] * ts[a], hi = lo + ts[a] - 1;
+                        const int q = std::min(std::max(half, lo), hi);
+                        r2 += (long long)(q - half) * (q - half);
+                    }
+                    if (!full && r2 > rr) continue;
+                    pl.part.push_back(p);
+                    pl.first.push_back(tx + nt[0] * (ty + nt[1] * tz));
+                }
         const double area = 4.0 * M_PI * (rb[p] + 2.0) * (rb[p] + 2.0);
         lcap += (long long)(12.0 * area) + 4096;
         scap += (long long)(4.0 * area) + 4096;

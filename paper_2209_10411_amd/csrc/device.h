@@ -12,6 +12,7 @@ constexpr int MAXCP = 20;
 constexpr int32_t FLUID = 0x7fffffff;  // owner value of a fluid node (atomicMin-friendly)
 constexpr int PAD = 4;                  // region margin beyond the bounding radius
 constexpr int BLK = 256;                // threads per block of the region kernels
+constexpr int TILE_X = 8, TILE_Y = 8, TILE_Z = 4;  // a region block is a tile of BLK nodes
 
 enum : int { ERR_LINK_OVERFLOW = 1, ERR_SPECIAL_OVERFLOW = 2, ERR_FAST_PARTICLE = 4,
              ERR_NONFINITE = 8, ERR_BAD_INDEX = 16 };
@@ -118,7 +119,8 @@ struct BulkCase {
 };
 
 // Region block map: block b of a region kernel works on particle part[b],
-// local region indices [first[b], first[b] + BLK).
+// tile first[b] of its region (tiles of TILE_X x TILE_Y x TILE_Z nodes, x
+// fastest, then y, then z).
 struct RegionMap {
     const int *part;
     const int *first;

@@ -923,14 +923,24 @@ __global__ void k_refresh_pose(Params p, DevParticle *P) {
 
 // Region node of a region kernel thread; false if outside the region or the
 // domain.
+// Local region coordinates of thread t of tile f (tiles of TILE_X x TILE_Y
+// x TILE_Z nodes over a region of dx x dy x ... nodes, x fastest).
+__device__ __forceinline__ void tile_local(int f, int dx, int dy, int t, int &lx, int &ly, int &lz) {
+    const int ntx = (dx + TILE_X - 1) / TILE_X, nty = (dy + TILE_Y - 1) / TILE_Y;
+    const int tx = f % ntx, ty = (f / ntx) % nty, tz = f / (ntx * nty);
+    lx = tx * TILE_X + (t % TILE_X);
+    ly = ty * TILE_Y + (t / TILE_X) % TILE_Y;
+    lz = tz * TILE_Z + t / (TILE_X * TILE_Y);
+}
+
 __device__ __forceinline__ bool region_node(const Params &p, const RegionMap &rm,
                                             const DevParticle *P, int &pi, int &x, int &y, int &z,
                                             long long &n) {
     pi = rm.part[blockIdx.x];
-    const int local = rm.first[blockIdx.x] + threadIdx.x;
     const int dx = rm.dims[3 * pi], dy = rm.dims[3 * pi + 1], dz = rm.dims[3 * pi + 2];
-    if (local >= dx * dy * dz) return false;
-    const int lx = local % dx, t = local / dx, ly = t % dy, lz = t / dy;
+    int lx, ly, lz;
+    tile_local(rm.first[blockIdx.x], dx, dy, threadIdx.x, lx, ly, lz);
+    if (lx >= dx || ly >= dy || lz >= dz) return false;
     const DevParticle &B = P[pi];
     if (!(B.full[0] | B.full[1] | B.full[2])) {
         // only the part of the cube within half + 2 of its centre floor(X):
@@ -1066,6 +1076,31 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
                                                          uint32_t *lmask, const typename Store<S>::T *A,
                                                          typename Store<S>::T *B, int do_special) {
     __shared__ int sh[BLK];
+    // owners before / after over the tile and a one-node halo (beyond a wall: OUTSIDE)
+    constexpr int HX = TILE_X + 2, HY = TILE_Y + 2, HN = HX * HY * (TILE_Z + 2);
+    constexpr int32_t OUTSIDE = -2;
+    __shared__ int32_t h_old[HN], h_new[HN];
+    {
+        const int bp = rm.part[blockIdx.x];
+        const int dx = rm.dims[3 * bp], dy = rm.dims[3 * bp + 1];
+        int bx, by, bz;
+        tile_local(rm.first[blockIdx.x], dx, dy, 0, bx, by, bz);
+        const DevParticle &Bp = P[bp];
+        const int L[3] = {p.nx, p.ny, p.nz};
+        for (int h = threadIdx.x; h < HN; h += BLK) {
+            int c[3] = {Bp.lo[0] + bx - 1 + h % HX, Bp.lo[1] + by - 1 + (h / HX) % HY, Bp.lo[2] + bz - 1 + h / (HX * HY)};
+            bool ok = true;
+            for (int a = 0; a < 3; ++a)
+                if (c[a] < 0 || c[a] >= L[a]) {
+                    if ((p.periodic >> a) & 1u) c[a] = ((c[a] % L[a]) + L[a]) % L[a];
+                    else ok = false;
+                }
+            const long long g = ok ? (long long)c[0] + (long long)p.nx * ((long long)c[1] + (long long)p.ny * c[2]) : 0;
+            h_old[h] = ok ? own_old[g] : OUTSIDE;
+            h_new[h] = ok ? own_new[g] : OUTSIDE;
+        }
+    }
+    __syncthreads();
     int pi, x, y, z;
     long long n;
     const bool in = region_node(p, rm, P, pi, x, y, z, n);
@@ -1073,19 +1108,21 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     // owners before / after, lowest owner among the neighbours before / after
     int32_t oo = FLUID, on = FLUID, mo = FLUID, mn = FLUID;
     if (in) {
-        oo = own_old[n];
-        on = own_new[n];
+        const int t = threadIdx.x;
+        const int hc = (t % TILE_X + 1) + HX * ((t / TILE_X) % TILE_Y + 1) + HX * HY * (t / (TILE_X * TILE_Y) + 1);
+        oo = h_old[hc];
+        on = h_new[hc];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            long long s;
-            if (nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], s)) {
-                const int32_t vo = own_old[s], vn = own_new[s];
+            const int hs = hc - EX[i] - HX * EY[i] - HX * HY * EZ[i];
+            const int32_t vo = h_old[hs], vn = h_new[hs];
+            if (vo == OUTSIDE) {
+                wall |= 1u << i;
+            } else {
                 mo = min(mo, vo);
                 mn = min(mn, vn);
                 if (vo != FLUID) solid |= 1u << i;
                 if (vn == pi) m |= 1u << i;
-            } else {
-                wall |= 1u << i;
             }
         }
     }
