@@ -182,7 +182,7 @@ struct Plan {
     std::vector<int> part_first_blk;  // [np]
     std::vector<int> half;            // [np]
     size_t off_A, off_B, off_own[3], off_skip[2], off_P, off_part, off_first, off_dims,
-        off_pfb, off_bcnt, off_loff, off_lnode, off_ldo, off_lq, off_lpart, off_special,
+        off_pfb, off_bcnt, off_blinks, off_loff, off_lnode, off_ldo, off_lq, off_lpart, off_special,
         off_cnt, total;
     bool contact;
     size_t off_lmask, off_nrs, off_mlpb;
@@ -321,6 +321,7 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_dims = take(4 * 3 * std::max(np, 1));
     pl.off_pfb = take(4 * std::max(np, 1));
     pl.off_bcnt = take(4 * std::max(pl.region_blocks, 1));
+    pl.off_blinks = take(4 * (size_t)std::max(np, 1));
     pl.off_lmask = take(4 * (size_t)BLK * std::max(pl.region_blocks, 1));
     pl.off_loff = take(4 * (np + 1));
     pl.off_lnode = take(4 * (size_t)std::max(pl.link_cap, 1));
@@ -360,7 +361,7 @@ struct lbm_ctx {
     int is;          // skip mask of the coming step
     DevParticle *P;
     RegionMap rm;
-    int *part_first_blk, *blk_cnt, *l_off;
+    int *part_first_blk, *blk_cnt, *body_links, *l_off;
     uint32_t *lmask;
     uint32_t *l_node, *l_do, *special;
     double *l_q, *lpart;
@@ -391,7 +392,7 @@ StepArgs base_args(lbm_ctx *c) {
     a.skip = c->skip[c->is]; a.skip_next = c->skip[1 - c->is];
     a.P = c->P; a.rm = c->rm;
     a.part_first_blk = c->part_first_blk;
-    a.blk_cnt = c->blk_cnt; a.l_off = c->l_off; a.lmask = c->lmask;
+    a.blk_cnt = c->blk_cnt; a.body_links = c->body_links; a.l_off = c->l_off; a.lmask = c->lmask;
     a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.part = c->lpart;
     a.special = c->special; a.cnt = c->cnt; a.cb = c->cb;
     a.nrs = c->nrs; a.warm = c->warm; a.mlp_body = c->mlp_body;
@@ -437,6 +438,7 @@ lbm_status reflag(lbm_ctx *c) {
     launch_fill_u8(c->skip[0], c->pl.N, 0, c->stream);
     launch_fill_u8(c->skip[1], c->pl.N, 0, c->stream);
     launch_reset_counters(c->cnt, c->stream);
+    if (c->p.np > 0) launch_fill_i32(c->body_links, c->p.np, 0, c->stream);
     StepArgs a = base_args(c);
     a.phase = PHASE_FLAGS;
     a.move = 1;
@@ -592,6 +594,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->rm.dims = (const int *)(b + pl.off_dims);
     c->part_first_blk = (int *)(b + pl.off_pfb);
     c->blk_cnt = (int *)(b + pl.off_bcnt);
+    c->body_links = (int *)(b + pl.off_blinks);
     c->lmask = (uint32_t *)(b + pl.off_lmask);
     c->l_off = (int *)(b + pl.off_loff);
     c->l_node = (uint32_t *)(b + pl.off_lnode); c->l_do = (uint32_t *)(b + pl.off_ldo);

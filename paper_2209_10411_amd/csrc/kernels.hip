@@ -532,12 +532,13 @@ __device__ void reset_step_counters(Counters *cnt) {
 __global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restrict__ P,
                                                 const int *__restrict__ l_off,
                                                 const double *__restrict__ part,
-                                                Counters *__restrict__ cnt, int update) {
+                                                Counters *__restrict__ cnt, int update, int *body_links) {
     __shared__ double red[6][256];
     __shared__ DevParticle sp;
     const int pi = blockIdx.x;
     if (pi == 0 && threadIdx.x == 0) reset_step_counters(cnt);
     if (pi >= p.np) return;
+    if (threadIdx.x == 0) body_links[pi] = 0;  // link totals of the coming classification
     reduce_body(p, P, pi, l_off, part, cnt, update, red, sp);
 }
 
@@ -1073,7 +1074,8 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
                                                          const int32_t *__restrict__ own_new,
                                                          uint8_t *__restrict__ skip_next,
                                                          uint32_t *special, Counters *cnt, int *blk_cnt,
-                                                         uint32_t *lmask, const typename Store<S>::T *A,
+                                                         uint32_t *lmask, int *body_links,
+                                                         const typename Store<S>::T *A,
                                                          typename Store<S>::T *B, int do_special) {
     __shared__ int sh[BLK];
     // owners before / after over the tile and a one-node halo (beyond a wall: OUTSIDE)
@@ -1151,7 +1153,10 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     // first pass of the link build: this body's cut links of the new flags
     lmask[blockIdx.x * BLK + threadIdx.x] = m;
     const int s = block_sum(__popc(m), sh);
-    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = s;
+    if (threadIdx.x == 0) {
+        blk_cnt[blockIdx.x] = s;
+        if (s) atomicAdd(&body_links[rm.part[blockIdx.x]], s);  // integer: order-free
+    }
 }
 
 // Plain fluid node (skip mask clear: fluid with no solid neighbour at the
@@ -1353,23 +1358,26 @@ __global__ void k_fill_u8(uint8_t *a, long long n, uint8_t v) {
 }
 
 // Link build, second pass: each block finds its offset in the particle-major
-// list by summing the counts of the blocks before it (the first block of a
-// body also records the body's offset, the last block the total) and lists
+// list from the link totals of the bodies before its own and the counts of
+// its body's earlier blocks (the first block of a body also records the
+// body's offset, the last block the total) and lists
 // its links (masks from the classification; thread order, then direction
 // order).  The link fractions follow in k_link_q.
 __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const DevParticle *P,
                                                    const uint32_t *__restrict__ lmask,
                                                    const int *__restrict__ blk_cnt,
+                                                   const int *__restrict__ body_links,
                                                    const int *__restrict__ part_first_blk, int *__restrict__ l_off,
                                                    uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
                                                    Counters *cnt, int32_t *clear) {
     __shared__ int sh[BLK];
     const int t = threadIdx.x;
+    const int pid = rm.part[blockIdx.x];
     int before = 0;
-    for (int b = t; b < (int)blockIdx.x; b += BLK) before += blk_cnt[b];
+    for (int q = t; q < pid; q += BLK) before += body_links[q];
+    for (int b = part_first_blk[pid] + t; b < (int)blockIdx.x; b += BLK) before += blk_cnt[b];
     const int base = block_sum(before, sh);
     __syncthreads();  // every thread has read the sum before sh is reused
-    const int pid = rm.part[blockIdx.x];
     if (t == 0) {
         if (part_first_blk[pid] == (int)blockIdx.x) l_off[pid] = min(base, p.link_cap);
         if (blockIdx.x == gridDim.x - 1) {
@@ -1551,7 +1559,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
         if (p.np > 0)
             k_links<S><<<link_grid, 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.l_node, a.l_do, a.l_q,
                                                          a.part, a.cnt);
-        k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, update);
+        k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, update, a.body_links);
         if (a.move && p.contact && p.np > 0) k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
     } else if (a.phase == PHASE_FLAGS) {
         if (p.np > 0) {
@@ -1559,7 +1567,8 @@ static void launch_step_kernels_t(const StepArgs &a) {
             hipExtLaunchKernelGGL(k_region_classify<S>, dim3(p.region_blocks), dim3(BLK), 0, a.stream, nullptr,
                                   a.ev_stop, 0, p, a.rm, (const DevParticle *)a.P, (const int32_t *)a.own_old,
                                   (const int32_t *)a.own_new, a.skip_next, a.special, a.cnt,
-                                  a.move ? a.blk_cnt : (int *)nullptr, a.lmask, (const T *)A, B, a.do_special);
+                                  a.move ? a.blk_cnt : (int *)nullptr, a.lmask, a.body_links, (const T *)A, B,
+                                  a.do_special);
         } else if (a.ev_stop) {
             (void)hipEventRecord(a.ev_stop, a.stream);
         }
@@ -1578,7 +1587,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
             (void)hipEventRecord(a.ev_stop, a.stream);
     } else if (a.phase == PHASE_LINKBUILD) {
         if (p.np > 0) {
-            k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt,
+            k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt, a.body_links,
                                                                 a.part_first_blk, a.l_off,
                                                                 a.l_node, a.l_do, a.cnt, a.own_dead);
             const int qg = max(1, min(cdiv(nlink, 32), NR_BLOCKS));
