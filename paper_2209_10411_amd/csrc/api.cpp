@@ -321,7 +321,7 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_dims = take(4 * 3 * std::max(np, 1));
     pl.off_pfb = take(4 * std::max(np, 1));
     pl.off_bcnt = take(4 * std::max(pl.region_blocks, 1));
-    pl.off_blinks = take(4 * (size_t)std::max(np, 1));
+    pl.off_blinks = take(16 * (size_t)std::max(np, 1));
     pl.off_lmask = take(4 * (size_t)BLK * std::max(pl.region_blocks, 1));
     pl.off_loff = take(4 * (np + 1));
     pl.off_lnode = take(4 * (size_t)std::max(pl.link_cap, 1));
@@ -361,7 +361,7 @@ struct lbm_ctx {
     int is;          // skip mask of the coming step
     DevParticle *P;
     RegionMap rm;
-    int *part_first_blk, *blk_cnt, *body_links, *l_off;
+    int *part_first_blk, *blk_cnt, *body_stats, *l_off;
     uint32_t *lmask;
     uint32_t *l_node, *l_do, *special;
     double *l_q, *lpart;
@@ -392,7 +392,7 @@ StepArgs base_args(lbm_ctx *c) {
     a.skip = c->skip[c->is]; a.skip_next = c->skip[1 - c->is];
     a.P = c->P; a.rm = c->rm;
     a.part_first_blk = c->part_first_blk;
-    a.blk_cnt = c->blk_cnt; a.body_links = c->body_links; a.l_off = c->l_off; a.lmask = c->lmask;
+    a.blk_cnt = c->blk_cnt; a.body_stats = c->body_stats; a.l_off = c->l_off; a.lmask = c->lmask;
     a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.part = c->lpart;
     a.special = c->special; a.cnt = c->cnt; a.cb = c->cb;
     a.nrs = c->nrs; a.warm = c->warm; a.mlp_body = c->mlp_body;
@@ -431,6 +431,22 @@ lbm_status estimate_lists(lbm_ctx *c) {
     return LBM_OK;
 }
 
+// Node counts of the last classification, summed over the bodies (solid,
+// uncovered, boundary + uncovered); synchronises.
+lbm_status body_counts(lbm_ctx *c, long long &solid, long long &refilled, long long &special) {
+    solid = refilled = special = 0;
+    if (c->p.np == 0) return LBM_OK;
+    std::vector<int> bs(4 * (size_t)c->p.np);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(bs.data(), c->body_stats, 4 * bs.size(), hipMemcpyDeviceToHost));
+    for (int q = 0; q < c->p.np; ++q) {
+        solid += bs[4 * q + 1];
+        refilled += bs[4 * q + 2];
+        special += bs[4 * q + 3];
+    }
+    return LBM_OK;
+}
+
 lbm_status reflag(lbm_ctx *c) {
     launch_refresh_pose(c->p, c->P, c->stream);
     launch_fill_i32(c->own[c->in], c->pl.N, FLUID, c->stream);
@@ -438,7 +454,7 @@ lbm_status reflag(lbm_ctx *c) {
     launch_fill_u8(c->skip[0], c->pl.N, 0, c->stream);
     launch_fill_u8(c->skip[1], c->pl.N, 0, c->stream);
     launch_reset_counters(c->cnt, c->stream);
-    if (c->p.np > 0) launch_fill_i32(c->body_links, c->p.np, 0, c->stream);
+    if (c->p.np > 0) launch_fill_i32(c->body_stats, 4ll * c->p.np, 0, c->stream);
     StepArgs a = base_args(c);
     a.phase = PHASE_FLAGS;
     a.move = 1;
@@ -594,7 +610,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->rm.dims = (const int *)(b + pl.off_dims);
     c->part_first_blk = (int *)(b + pl.off_pfb);
     c->blk_cnt = (int *)(b + pl.off_bcnt);
-    c->body_links = (int *)(b + pl.off_blinks);
+    c->body_stats = (int *)(b + pl.off_blinks);
     c->lmask = (uint32_t *)(b + pl.off_lmask);
     c->l_off = (int *)(b + pl.off_loff);
     c->l_node = (uint32_t *)(b + pl.off_lnode); c->l_do = (uint32_t *)(b + pl.off_ldo);
@@ -692,10 +708,9 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     if (cfg->counter_force && n_p > 0) {
         // needs the fluid volume, i.e. the flags: flag first, then read back
         reflag(c);
-        HIPCHK_C(hipStreamSynchronize(c->stream));
-        Counters h;
-        HIPCHK_C(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
-        const double nf = (double)(pl.N - h.n_solid);
+        long long n_solid, n_ref, n_spec;
+        if (lbm_status st0 = body_counts(c, n_solid, n_ref, n_spec)) return bail(st0);
+        const double nf = (double)(pl.N - n_solid);
         double W[3] = {0, 0, 0};
         for (int q = 0; q < n_p; ++q)
             if (hp[q].mode == LBM_MODE_FREE)
@@ -729,7 +744,9 @@ lbm_status metaball_flag(lbm_ctx *c, int64_t *n_solid, int64_t *n_links) {
         if (s) return s;
         Counters h;
         HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
-        if (n_solid) *n_solid = h.n_solid;
+        long long ns, nr, nsp;
+        if ((s = body_counts(c, ns, nr, nsp))) return s;
+        if (n_solid) *n_solid = ns;
         if (n_links) *n_links = h.n_links;
         if ((s = estimate_lists(c))) return s;
     }
@@ -747,9 +764,9 @@ lbm_status refill(lbm_ctx *c, int64_t *n_refilled) {
     if (n_refilled) {
         lbm_status s = check_device(c);
         if (s) return s;
-        Counters h;
-        HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
-        *n_refilled = h.n_refill;
+        long long ns, nr, nsp;
+        if ((s = body_counts(c, ns, nr, nsp))) return s;
+        *n_refilled = nr;
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -1029,9 +1046,9 @@ lbm_status lbm_timing_read(lbm_ctx *c, double *ms, int64_t *launches, int64_t *n
     if (nodes_per_launch) {
         // nodes the stream-collide kernel updated in the last step: all but
         // solid nodes and the boundary/uncovered nodes handled separately
-        Counters h;
-        HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
-        *nodes_per_launch = c->pl.N - h.n_solid - std::min(h.n_special, c->p.special_cap);
+        long long ns, nr, nsp;
+        if (lbm_status s = body_counts(c, ns, nr, nsp)) return s;
+        *nodes_per_launch = c->pl.N - ns - nsp;
     }
     c->ev_used = 0;
     return LBM_OK;

@@ -47,8 +47,7 @@ struct DevParticle {
 struct Counters {
     int n_links;    // links of the current geometry
     int n_special;  // boundary and uncovered nodes listed this step
-    int n_refill;   // uncovered nodes this step
-    int n_solid;    // solid nodes counted by the last classification
+    int pad1, pad2;
     int err;        // ERR_* bits
     uint32_t pad0;
     int pad[2];

@@ -523,8 +523,6 @@ __device__ void reduce_body(const Params &p, DevParticle *__restrict__ P, int pi
 
 __device__ void reset_step_counters(Counters *cnt) {
     cnt->n_special = 0;
-    cnt->n_refill = 0;
-    cnt->n_solid = 0;
 }
 
 // One block per particle: reduce_body.  Block 0 also clears the per-step
@@ -532,13 +530,13 @@ __device__ void reset_step_counters(Counters *cnt) {
 __global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restrict__ P,
                                                 const int *__restrict__ l_off,
                                                 const double *__restrict__ part,
-                                                Counters *__restrict__ cnt, int update, int *body_links) {
+                                                Counters *__restrict__ cnt, int update, int *body_stats) {
     __shared__ double red[6][256];
     __shared__ DevParticle sp;
     const int pi = blockIdx.x;
     if (pi == 0 && threadIdx.x == 0) reset_step_counters(cnt);
     if (pi >= p.np) return;
-    if (threadIdx.x == 0) body_links[pi] = 0;  // link totals of the coming classification
+    if (threadIdx.x < 4) body_stats[4 * pi + threadIdx.x] = 0;  // counts of the coming classification
     reduce_body(p, P, pi, l_off, part, cnt, update, red, sp);
 }
 
@@ -990,6 +988,22 @@ __device__ __forceinline__ int block_sum(int v, int *sh) {
     return sh[0];
 }
 
+// Three block-wide sums at once (all BLK threads; sh3 LDS scratch).
+__device__ __forceinline__ void block_sum3(int &a, int &b, int &c, int (*sh3)[BLK]) {
+    const int t = threadIdx.x;
+    sh3[0][t] = a; sh3[1][t] = b; sh3[2][t] = c;
+    __syncthreads();
+    for (int h = BLK / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            sh3[0][t] += sh3[0][t + h];
+            sh3[1][t] += sh3[1][t + h];
+            sh3[2][t] += sh3[2][t + h];
+        }
+        __syncthreads();
+    }
+    a = sh3[0][0]; b = sh3[1][0]; c = sh3[2][0];
+}
+
 // Boundary or uncovered node n = (x, y, z), one thread: pull the 19
 // populations -- a source outside a wall bounces off the resting wall, a
 // source inside a body takes the bounce-back value that k_links left in B;
@@ -1061,8 +1075,9 @@ __device__ void special_update(const Params &p, const typename Store<S>::T *__re
 // node around) only gets skip = 0, which any region may write.
 //   - nodes fluid after the step that were solid before (uncovered: refill)
 //     or had an in-domain solid neighbour before (cut links: bounce-back)
-//     go to the special list and, with do_special, are updated right here
-//     (special_update);
+//     are updated right here with do_special (special_update), else listed
+//     for the in-place refill;
+//   - per-body counts of solid, uncovered and special nodes and of cut links;
 //   - skip mask of the NEXT step's stream-collide: solid after, or with an
 //     in-domain solid neighbour after (those nodes are left to the links and
 //     special passes);
@@ -1074,10 +1089,11 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
                                                          const int32_t *__restrict__ own_new,
                                                          uint8_t *__restrict__ skip_next,
                                                          uint32_t *special, Counters *cnt, int *blk_cnt,
-                                                         uint32_t *lmask, int *body_links,
+                                                         uint32_t *lmask, int *body_stats,
                                                          const typename Store<S>::T *A,
                                                          typename Store<S>::T *B, int do_special) {
     __shared__ int sh[BLK];
+    __shared__ int sh3[3][BLK];
     // owners before / after over the tile and a one-node halo (beyond a wall: OUTSIDE)
     constexpr int HX = TILE_X + 2, HY = TILE_Y + 2, HN = HX * HY * (TILE_Z + 2);
     constexpr int32_t OUTSIDE = -2;
@@ -1133,21 +1149,33 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     if (sn) m = 0u;
     bool act = in;
     if (act) act = sn ? on == pi : so ? oo == pi : onb == FLUID || onb == pi;
+    int c_solid = 0, c_refill = 0, c_spec = 0;
     if (act) {
         skip_next[n] = (uint8_t)((sn || nb_new) ? 1 : 0);
         const bool lo = !so && nb_old;
         const bool spec = !sn && (so || lo);
-        wave_append(&cnt->n_solid, sn);
-        wave_append(&cnt->n_refill, !sn && so);
-        const int k = wave_append(&cnt->n_special, spec);
-        if (k >= 0) {
-            if (k < p.special_cap) special[k] = (uint32_t)n;
-            else atomicOr(&cnt->err, ERR_SPECIAL_OVERFLOW);
+        c_solid = sn;
+        c_refill = !sn && so;
+        c_spec = spec;
+        if (!do_special) {  // the list is for the in-place refill that follows a re-flag
+            const int k = wave_append(&cnt->n_special, spec);
+            if (k >= 0) {
+                if (k < p.special_cap) special[k] = (uint32_t)n;
+                else atomicOr(&cnt->err, ERR_SPECIAL_OVERFLOW);
+            }
         }
         if (spec && do_special) {
             if (so && (oo < 0 || oo >= p.np)) atomicOr(&cnt->err, ERR_BAD_INDEX);  // never expected
             else special_update<S>(p, A, B, P, x, y, z, n, wall, solid, oo);
         }
+    }
+    // per-body node counts (one atomic per block and count, integers: order-free)
+    block_sum3(c_solid, c_refill, c_spec, sh3);
+    if (threadIdx.x == 0) {
+        int *bs = body_stats + 4 * rm.part[blockIdx.x];
+        if (c_solid) atomicAdd(bs + 1, c_solid);
+        if (c_refill) atomicAdd(bs + 2, c_refill);
+        if (c_spec) atomicAdd(bs + 3, c_spec);
     }
     if (!blk_cnt) return;
     // first pass of the link build: this body's cut links of the new flags
@@ -1155,7 +1183,7 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     const int s = block_sum(__popc(m), sh);
     if (threadIdx.x == 0) {
         blk_cnt[blockIdx.x] = s;
-        if (s) atomicAdd(&body_links[rm.part[blockIdx.x]], s);  // integer: order-free
+        if (s) atomicAdd(body_stats + 4 * rm.part[blockIdx.x], s);
     }
 }
 
@@ -1366,7 +1394,7 @@ __global__ void k_fill_u8(uint8_t *a, long long n, uint8_t v) {
 __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const DevParticle *P,
                                                    const uint32_t *__restrict__ lmask,
                                                    const int *__restrict__ blk_cnt,
-                                                   const int *__restrict__ body_links,
+                                                   const int *__restrict__ body_stats,
                                                    const int *__restrict__ part_first_blk, int *__restrict__ l_off,
                                                    uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
                                                    Counters *cnt, int32_t *clear) {
@@ -1374,7 +1402,7 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
     const int t = threadIdx.x;
     const int pid = rm.part[blockIdx.x];
     int before = 0;
-    for (int q = t; q < pid; q += BLK) before += body_links[q];
+    for (int q = t; q < pid; q += BLK) before += body_stats[4 * q];
     for (int b = part_first_blk[pid] + t; b < (int)blockIdx.x; b += BLK) before += blk_cnt[b];
     const int base = block_sum(before, sh);
     __syncthreads();  // every thread has read the sum before sh is reused
@@ -1559,7 +1587,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
         if (p.np > 0)
             k_links<S><<<link_grid, 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.l_node, a.l_do, a.l_q,
                                                          a.part, a.cnt);
-        k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, update, a.body_links);
+        k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, update, a.body_stats);
         if (a.move && p.contact && p.np > 0) k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
     } else if (a.phase == PHASE_FLAGS) {
         if (p.np > 0) {
@@ -1567,7 +1595,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
             hipExtLaunchKernelGGL(k_region_classify<S>, dim3(p.region_blocks), dim3(BLK), 0, a.stream, nullptr,
                                   a.ev_stop, 0, p, a.rm, (const DevParticle *)a.P, (const int32_t *)a.own_old,
                                   (const int32_t *)a.own_new, a.skip_next, a.special, a.cnt,
-                                  a.move ? a.blk_cnt : (int *)nullptr, a.lmask, a.body_links, (const T *)A, B,
+                                  a.move ? a.blk_cnt : (int *)nullptr, a.lmask, a.body_stats, (const T *)A, B,
                                   a.do_special);
         } else if (a.ev_stop) {
             (void)hipEventRecord(a.ev_stop, a.stream);
@@ -1587,7 +1615,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
             (void)hipEventRecord(a.ev_stop, a.stream);
     } else if (a.phase == PHASE_LINKBUILD) {
         if (p.np > 0) {
-            k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt, a.body_links,
+            k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt, a.body_stats,
                                                                 a.part_first_blk, a.l_off,
                                                                 a.l_node, a.l_do, a.cnt, a.own_dead);
             const int qg = max(1, min(cdiv(nlink, 32), NR_BLOCKS));

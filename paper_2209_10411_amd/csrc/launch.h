@@ -33,7 +33,7 @@ struct StepArgs {
     RegionMap rm;
     const int *part_first_blk;
     int *blk_cnt, *l_off;
-    int *body_links;  // [np] cut links of each body in the coming link build
+    int *body_stats;  // [np][4] per body: cut links, solid, uncovered, special nodes of the classification
     uint32_t *lmask;  // per region thread: cut-link mask of the new flags
     uint32_t *l_node, *l_do;
     double *l_q, *part;
