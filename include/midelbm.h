@@ -271,11 +271,15 @@ lbm_status lbm_nr_histogram(lbm_ctx *ctx, int64_t *hist, double *resid_max);
  * particles parts[n_p[0] + ... + n_p[i-1] ...] concatenated) stepped
  * together: the stream-collide of all systems runs as one launch over a table
  * of equal tiles (a wave covers a tile of 64x1, 32x2 or 16x4 nodes, chosen
- * per system by lbm_autotune), the boundary kernels of each system run around
- * it on two streams owned by the batch, and six consecutive coupled steps
- * (the period of the library's buffer rotation) are captured once into a HIP
+ * per system by lbm_autotune), each kind of boundary kernel runs as one
+ * launch for all systems (a block finds its system in a block table) on a
+ * second stream owned by the batch, and six consecutive coupled steps (the
+ * period of the library's buffer rotation) are captured once into a HIP
  * graph and replayed.  Every system computes exactly what lbm_step computes
- * for it alone (same kernels, same per-system order).  All systems must use
+ * for it alone (same kernel code, same per-system order; a warm-started
+ * system, lbm_set_warmstart on its context, keeps its network).  The launch
+ * tables are rewritten, and the graph captured again, whenever a system's
+ * buffers, constants or warm start changed from outside.  All systems must use
  * one storage type.  The arena layout is the library's: one 256-byte-aligned
  * device block of lbm_batch_arena_bytes bytes, owned by the caller.
  * Errors: LBM_E_INVALID for a bad case (the message names it), LBM_E_NOMEM

@@ -357,8 +357,9 @@ class Simulation:
 
 class Ensemble:
     """Independent systems (a list of ``workloads.Config``) stepped together:
-    one batched stream-collide launch over all of them, per-system boundary
-    kernels, six-step HIP graph replays (include/midelbm.h, ensemble)."""
+    one batched stream-collide launch over all of them, one batched launch
+    per kind of boundary kernel, six-step HIP graph replays
+    (include/midelbm.h, ensemble)."""
 
     def __init__(self, cfgs, device: str = "cuda:0", stream=None):
         import torch

@@ -1247,15 +1247,16 @@ void lbm_destroy(lbm_ctx *c) {
 
 // ------------------------------------------------------------------ ensemble
 // A batch of independent systems stepped together: one batched stream-collide
-// launch over a table of equal tiles for all systems, the per-system boundary
-// kernels around it, and six consecutive steps (the period of the buffer
-// rotation: A/B 2, flags 3) captured once into a HIP graph and replayed.
+// launch over a table of equal tiles for all systems, one batched launch per
+// kind of boundary kernel for all systems around it, and six consecutive
+// steps (the period of the buffer rotation: A/B 2, flags 3) captured once
+// into a HIP graph and replayed.
 
 }  // extern "C"
 
 namespace {
 constexpr int GRAPH_PERIOD = 6;
-constexpr int BATCH_AUX = 3;  // streams for the systems' boundary kernels (with the first: 4 hardware queues)
+constexpr int BATCH_AUX = 1;  // stream of the batched boundary kernels
 constexpr int TW_CANDIDATES[3] = {6, 5, 4};  // wave tiles 64x1, 32x2, 16x4
 }  // namespace
 
@@ -1274,7 +1275,16 @@ struct lbm_batch {
     std::vector<BulkCase> h_cases;
     std::vector<int> h_blk;
     int nblocks = 0;
-    int parity = 0;  // parity of the next step relative to the table
+    int phase = 0;  // steps since the tables were written, modulo GRAPH_PERIOD
+    // batched boundary kernels: argument blocks of the systems for each step
+    // of a period from the tables' start, block -> system maps per kind
+    CaseArgs *d_args = nullptr;  // [GRAPH_PERIOD][n]
+    int *d_map = nullptr;
+    size_t map_cap = 0;
+    int map_off[BK_N] = {}, map_n[BK_N] = {};
+    std::vector<CaseArgs> h_args;
+    std::vector<Params> h_p;  // each system's constants when the tables were written (byte copies)
+    bool any_rigid = false, any_warm = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> graph_key;
@@ -1304,7 +1314,61 @@ BulkCase bulk_case(const lbm_ctx *c, int twl, int bw, int first_block) {
     return b;
 }
 
+// Block ranges of a system in the batched boundary launches (the one-system
+// launch sizes; systems without bodies take no blocks but the force
+// reduction's, whose block 0 clears the step counters).
+void case_blocks(const lbm_ctx *c, int nb[BK_N]) {
+    const Params &p = c->p;
+    const bool bodies = p.np > 0;
+    nb[BK_LINKS] = bodies ? link_grid(p) : 0;
+    nb[BK_REDUCE] = std::max(p.np, 1);
+    nb[BK_RIGID] = bodies && p.contact ? 1 : 0;
+    nb[BK_REGION] = bodies ? p.region_blocks : 0;
+    nb[BK_LINKQ] = bodies ? link_q_grid(p) : 0;
+}
+
+// Largest block ranges of a system (list grids at full capacity).
+long long case_blocks_cap(const Params &p) {
+    if (p.np <= 0) return 1;
+    Params q = p;
+    q.est_links = 0;  // 0: sized for the capacity
+    return (long long)link_grid(q) + p.np + 1 + p.region_blocks + link_q_grid(q);
+}
+
+// Argument block of system c, k steps after its current state (buffer
+// rotation: A/B swap each step, flag buffers old/new/dead cycle, skip masks
+// swap), for the batched kernels of a step that moves the bodies.
+CaseArgs case_args(const lbm_ctx *c, int k) {
+    CaseArgs a{};
+    int ic = c->ic, in = c->in, id = c->id, is = c->is;
+    for (int s = 0; s < k; ++s) {
+        const int old = ic;
+        ic = in; in = id; id = old;
+        is = 1 - is;
+    }
+    a.p = c->p;
+    a.rm = c->rm;
+    a.A = (k & 1) ? c->B : c->A;
+    a.B = (k & 1) ? c->A : c->B;
+    a.own_old = c->own[ic]; a.own_new = c->own[in]; a.own_dead = c->own[id];
+    a.skip_next = c->skip[1 - is];
+    a.P = c->P;
+    a.part_first_blk = c->part_first_blk;
+    a.blk_cnt = c->blk_cnt; a.l_off = c->l_off; a.body_stats = c->body_stats;
+    a.lmask = c->lmask; a.l_node = c->l_node; a.l_do = c->l_do; a.special = c->special;
+    a.l_q = c->l_q; a.part = c->lpart;
+    a.cnt = c->cnt; a.cb = c->cb; a.nrs = c->nrs;
+    a.warm = c->warm; a.mlp_body = c->mlp_body;
+    a.update = !c->p.contact;
+    return a;
+}
+
+void drop_graph(lbm_batch *b);
+
+// Writes the launch tables for the systems' current state.  A captured graph
+// holds launch sizes and table offsets of the old tables: it is dropped.
 lbm_status write_table(lbm_batch *b) {
+    drop_graph(b);
     b->h_cases.resize(b->n);
     b->h_blk.clear();
     int first = 0;
@@ -1315,24 +1379,74 @@ lbm_status write_table(lbm_batch *b) {
     }
     if (b->h_blk.size() > b->blk_cap) return fail(LBM_E_NOMEM, "ensemble block table overflow");
     b->nblocks = first;
+    // boundary kernels: block ranges, maps, argument blocks for a period
+    std::vector<int> nb((size_t)b->n * BK_N);
+    int tot[BK_N] = {};
+    b->any_rigid = b->any_warm = false;
+    for (int i = 0; i < b->n; ++i) {
+        case_blocks(b->cs[i], &nb[(size_t)i * BK_N]);
+        for (int k = 0; k < BK_N; ++k) tot[k] += nb[(size_t)i * BK_N + k];
+        b->any_rigid = b->any_rigid || nb[(size_t)i * BK_N + BK_RIGID] > 0;
+        b->any_warm = b->any_warm || b->cs[i]->warm != nullptr;
+    }
+    size_t need = 0;
+    for (int k = 0; k < BK_N; ++k) {
+        b->map_off[k] = (int)need;
+        b->map_n[k] = tot[k];
+        need += (size_t)tot[k];
+    }
+    if (need > b->map_cap) return fail(LBM_E_NOMEM, "ensemble boundary block map overflow");
+    std::vector<int> map(need);
+    int at[BK_N] = {};
+    std::vector<CaseArgs> base(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        for (int k = 0; k < BK_N; ++k) {
+            const int m = nb[(size_t)i * BK_N + k];
+            base[i].first[k] = at[k];
+            base[i].nblk[k] = m;
+            for (int j = 0; j < m; ++j) map[(size_t)b->map_off[k] + at[k] + j] = i;
+            at[k] += m;
+        }
+    }
+    b->h_args.resize((size_t)GRAPH_PERIOD * b->n);
+    b->h_p.resize(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        std::memcpy(&b->h_p[i], &b->cs[i]->p, sizeof(Params));
+        for (int k = 0; k < GRAPH_PERIOD; ++k) {
+            CaseArgs a = case_args(b->cs[i], k);
+            std::memcpy(a.first, base[i].first, sizeof a.first);
+            std::memcpy(a.nblk, base[i].nblk, sizeof a.nblk);
+            b->h_args[(size_t)k * b->n + i] = a;
+        }
+    }
     HIPCHK(hipMemcpyAsync(b->d_cases, b->h_cases.data(), sizeof(BulkCase) * b->n, hipMemcpyHostToDevice, b->main));
     HIPCHK(hipMemcpyAsync(b->d_blk, b->h_blk.data(), 4 * b->h_blk.size(), hipMemcpyHostToDevice, b->main));
+    HIPCHK(hipMemcpyAsync(b->d_args, b->h_args.data(), sizeof(CaseArgs) * b->h_args.size(), hipMemcpyHostToDevice,
+                          b->main));
+    if (need) HIPCHK(hipMemcpyAsync(b->d_map, map.data(), 4 * need, hipMemcpyHostToDevice, b->main));
     HIPCHK(hipStreamSynchronize(b->main));
-    b->parity = 0;
+    b->phase = 0;
     return LBM_OK;
 }
 
 bool table_valid(const lbm_batch *b) {
-    if ((int)b->h_cases.size() != b->n) return false;
+    if ((int)b->h_cases.size() != b->n || b->h_args.size() != (size_t)GRAPH_PERIOD * b->n) return false;
     for (int i = 0; i < b->n; ++i) {
         const BulkCase &h = b->h_cases[i];
         const lbm_ctx *c = b->cs[i];
-        if (h.A[b->parity] != c->A || h.skip[b->parity] != c->skip[c->is] || h.tw_log2 != b->tw[i]) return false;
+        const int par = b->phase & 1;
+        if (h.A[par] != c->A || h.skip[par] != c->skip[c->is] || h.tw_log2 != b->tw[i]) return false;
+        const CaseArgs &a = b->h_args[(size_t)b->phase * b->n + i];
+        if (a.A != c->A || a.own_old != c->own[c->ic] || a.own_new != c->own[c->in] || a.warm != c->warm)
+            return false;
+        if (std::memcmp(&b->h_p[i], &c->p, sizeof(Params)) != 0) return false;
     }
     return true;
 }
 
+// (after the stream has run any launch of the graph)
 void drop_graph(lbm_batch *b) {
+    if (b->exec && b->main) (void)hipStreamSynchronize(b->main);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
@@ -1342,7 +1456,7 @@ void drop_graph(lbm_batch *b) {
 
 std::vector<uintptr_t> state_key(const lbm_batch *b) {
     std::vector<uintptr_t> k;
-    k.push_back((uintptr_t)b->parity);
+    k.push_back((uintptr_t)b->phase);
     for (auto *c : b->cs) {
         k.push_back((uintptr_t)c->A);
         k.push_back((uintptr_t)c->is);
@@ -1351,36 +1465,30 @@ std::vector<uintptr_t> state_key(const lbm_batch *b) {
     return k;
 }
 
-// One coupled step of every system, enqueued on b->main and the second
-// streams: the batched stream-collide on the first stream; bounce-back,
-// rigid bodies, flags, classification, boundary pass and link build of each
-// system on one of the second streams (systems dealt out in turn), which
-// start after the first stream's previous work.  The next step's
-// stream-collide waits for every system's boundary pass.
+// One coupled step of every system, enqueued on b->main and b->aux[0]: the
+// batched stream-collide on the first stream; on the second, which starts
+// after the first stream's previous work, the batched bounce-back and
+// momentum exchange, force reduction (and rigid bodies), flags,
+// classification with the boundary pass, then the link build.  The next
+// step's stream-collide waits for the boundary pass.
 lbm_status enqueue_batch_step(lbm_batch *b) {
+    hipStream_t ax = b->aux[0];
     HIPCHK(hipEventRecord(b->ev_main, b->main));
-    for (int k = 0; k < BATCH_AUX; ++k) HIPCHK(hipStreamWaitEvent(b->aux[k], b->ev_main, 0));
-    std::vector<StepArgs> as(b->n);
-    for (int i = 0; i < b->n; ++i) {
-        StepArgs a = base_args(b->cs[i]);
-        a.move = 1;
-        a.stream = b->aux[i % BATCH_AUX];
-        a.phase = PHASE_LINKS;
-        launch_phase(a);
-        a.phase = PHASE_FLAGS;  // with the boundary/uncovered update
-        a.do_special = 1;
-        launch_phase(a);
-        as[i] = a;
-    }
-    for (int k = 0; k < BATCH_AUX; ++k) HIPCHK(hipEventRecord(b->ev_flags[k], b->aux[k]));
-    for (int i = 0; i < b->n; ++i) {
-        StepArgs a = as[i];
-        a.phase = PHASE_LINKBUILD;
-        a.own_dead = b->cs[i]->own[b->cs[i]->id];
-        launch_phase(a);
-    }
-    launch_bulk_batch(b->storage, b->bw, b->d_cases, b->d_blk, b->nblocks, b->parity, b->main);
-    for (int k = 0; k < BATCH_AUX; ++k) HIPCHK(hipStreamWaitEvent(b->main, b->ev_flags[k], 0));
+    HIPCHK(hipStreamWaitEvent(ax, b->ev_main, 0));
+    const CaseArgs *cs = b->d_args + (size_t)b->phase * b->n;
+    auto run = [&](BatchOp op, int kind) {
+        launch_case_batch(b->storage, op, cs, b->d_map + b->map_off[kind], b->map_n[kind], ax);
+    };
+    run(OP_LINKS, BK_LINKS);
+    run(OP_REDUCE, BK_REDUCE);
+    if (b->any_rigid) run(OP_RIGID, BK_RIGID);
+    run(OP_MARK, BK_REGION);
+    run(OP_CLASSIFY, BK_REGION);
+    HIPCHK(hipEventRecord(b->ev_flags[0], ax));
+    run(OP_EMIT, BK_REGION);
+    run(b->any_warm ? OP_LINKQ_WARM : OP_LINKQ, BK_LINKQ);
+    launch_bulk_batch(b->storage, b->bw, b->d_cases, b->d_blk, b->nblocks, b->phase & 1, b->main);
+    HIPCHK(hipStreamWaitEvent(b->main, b->ev_flags[0], 0));
     for (int i = 0; i < b->n; ++i) {
         lbm_ctx *c = b->cs[i];
         const int old = c->ic;
@@ -1389,7 +1497,7 @@ lbm_status enqueue_batch_step(lbm_batch *b) {
         std::swap(c->A, c->B);
         c->steps++;
     }
-    b->parity ^= 1;
+    b->phase = (b->phase + 1) % GRAPH_PERIOD;
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }
@@ -1451,7 +1559,7 @@ void free_batch(lbm_batch *b) {
 
 struct BatchLayout {
     std::vector<size_t> off, bytes;
-    size_t off_cases, off_blk, off_blk1, blk_cap, blk1_cap, total;
+    size_t off_cases, off_blk, off_blk1, blk_cap, blk1_cap, off_args, off_map, map_cap, total;
 };
 
 lbm_status batch_layout(int32_t n, const lbm_config *cfgs, const int32_t *n_p, const lbm_particle *parts,
@@ -1459,16 +1567,23 @@ lbm_status batch_layout(int32_t n, const lbm_config *cfgs, const int32_t *n_p, c
     if (n < 1) return fail(LBM_E_INVALID, "n_cases must be >= 1");
     if (!cfgs || !n_p) return fail(LBM_E_INVALID, "cfgs and n_p must not be NULL");
     size_t o = 0;
-    long long pofs = 0, cap = 0, cap1 = 0;
+    long long pofs = 0, cap = 0, cap1 = 0, mcap = 0;
     for (int i = 0; i < n; ++i) {
         if (n_p[i] < 0) return fail(LBM_E_INVALID, "case %d: n_p < 0", i);
         if (cfgs[i].storage != cfgs[0].storage) return fail(LBM_E_INVALID, "all cases must use one storage type");
-        size_t by = 0;
-        lbm_status s = lbm_arena_bytes(&cfgs[i], n_p[i], parts ? parts + pofs : nullptr, &by);
+        std::vector<DevParticle> hp;
+        Plan pl;
+        lbm_status s = prepare(&cfgs[i], n_p[i], parts ? parts + pofs : nullptr, &hp, &pl);
         if (s) {
             const std::string m = g_err;
             return fail(s, "case %d: %s", i, m.c_str());
         }
+        const size_t by = pl.total;
+        Params pc{};
+        pc.np = pl.np;
+        pc.link_cap = pl.link_cap;
+        pc.region_blocks = pl.region_blocks;
+        mcap += case_blocks_cap(pc);
         L.off.push_back(o);
         L.bytes.push_back(by);
         o = align256(o + by);
@@ -1478,12 +1593,15 @@ lbm_status batch_layout(int32_t n, const lbm_config *cfgs, const int32_t *n_p, c
         cap += mx;
         cap1 = std::max(cap1, mx);
     }
-    if (cap > 0x7fffffffll) return fail(LBM_E_INVALID, "ensemble too large for one launch");
+    if (cap > 0x7fffffffll || mcap > 0x7fffffffll) return fail(LBM_E_INVALID, "ensemble too large for one launch");
     L.blk_cap = (size_t)cap;
     L.blk1_cap = (size_t)cap1;
     L.off_cases = o; o = align256(o + sizeof(BulkCase) * (n + 1));
     L.off_blk = o; o = align256(o + 4 * L.blk_cap);
     L.off_blk1 = o; o = align256(o + 4 * L.blk1_cap);
+    L.off_args = o; o = align256(o + sizeof(CaseArgs) * GRAPH_PERIOD * (size_t)n);
+    L.map_cap = (size_t)mcap;
+    L.off_map = o; o = align256(o + 4 * L.map_cap);
     L.total = o;
     return LBM_OK;
 }
@@ -1537,6 +1655,9 @@ lbm_status lbm_batch_init(int32_t n_cases, const lbm_config *cfgs, const int32_t
     b->d_blk1 = (int *)(base + L.off_blk1);
     b->blk_cap = L.blk_cap;
     b->blk1_cap = L.blk1_cap;
+    b->d_args = (CaseArgs *)(base + L.off_args);
+    b->d_map = (int *)(base + L.off_map);
+    b->map_cap = L.map_cap;
     long long pofs = 0;
     for (int i = 0; i < n_cases; ++i) {
         lbm_ctx *c = nullptr;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace mdl {
@@ -125,5 +126,38 @@ struct RegionMap {
     const int *first;
     const int *dims;  // [np][3] region extent per axis
 };
+
+// Kernel kinds of the batched boundary launches (the three region kernels
+// share one block range).
+enum : int { BK_LINKS = 0, BK_REDUCE = 1, BK_RIGID = 2, BK_REGION = 3, BK_LINKQ = 4, BK_N = 5 };
+
+// One system of an ensemble as seen by the batched boundary kernels: its
+// constants and the buffers of one step, and its block range in each kind of
+// launch (a block of a batched launch finds its system in a block -> system
+// map and works as block  blockIdx.x - first[kind]  of a grid of nblk[kind]).
+struct CaseArgs {
+    Params p;
+    RegionMap rm;
+    void *A, *B;
+    const int32_t *own_old;
+    int32_t *own_new, *own_dead;
+    uint8_t *skip_next;
+    DevParticle *P;
+    const int *part_first_blk;
+    int *blk_cnt, *l_off, *body_stats;
+    uint32_t *lmask, *l_node, *l_do, *special;
+    double *l_q, *part;
+    Counters *cnt;
+    ContactBufs cb;
+    NrStats nrs;
+    const _Float16 *warm;   // warm-start MLP parameters, or NULL: plain Newton
+    const float *mlp_body;  // [np][80] constant MLP inputs of each body
+    int update;             // the force reduction also moves the bodies (no contact)
+    int first[BK_N], nblk[BK_N];
+};
+// the host writes these tables for the device: one layout on both sides
+static_assert(sizeof(Params) == 192 && sizeof(CaseArgs) == 504 && offsetof(CaseArgs, nrs) == 416 &&
+                  offsetof(CaseArgs, first) == 460,
+              "CaseArgs layout");
 
 }  // namespace mdl

@@ -338,21 +338,22 @@ __device__ __forceinline__ float collide_lane(float d, int i, float dr, float jx
 // exchange  dP = (e_ib - u_w) f+_ib(x_f) - (e_i - u_w) f_i(x_f, t+1) with
 // both populations relative to w rho0, dT = (x_w - X) x dP.  Each chunk of 256 links sums its links per body
 // segment (fixed segmented tree) into part[chunk + body] (deterministic).
+// Block bid of nblk (a whole grid, or one system's range of a batched grid).
 template <int S>
-__global__ __launch_bounds__(256) void k_links(Params p, const typename Store<S>::T *__restrict__ A,
-                                               typename Store<S>::T *__restrict__ B,
-                                               const int32_t *__restrict__ own,
-                                               const DevParticle *__restrict__ P,
-                                               const uint32_t *__restrict__ l_node,
-                                               const uint32_t *__restrict__ l_do,
-                                               const double *__restrict__ l_q, double *__restrict__ part,
-                                               Counters *__restrict__ cnt) {
+__device__ __forceinline__ void links_body(const Params &p, const typename Store<S>::T *__restrict__ A,
+                                           typename Store<S>::T *__restrict__ B,
+                                           const int32_t *__restrict__ own,
+                                           const DevParticle *__restrict__ P,
+                                           const uint32_t *__restrict__ l_node,
+                                           const uint32_t *__restrict__ l_do,
+                                           const double *__restrict__ l_q, double *__restrict__ part,
+                                           Counters *__restrict__ cnt, const int bid, const int nblk) {
     __shared__ double sv[6][256];
     __shared__ int spid[256];
     const int t = threadIdx.x;
     const int nl = cnt->n_links;
     const int nchunk = (nl + 255) >> 8;
-    for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    for (int ch = bid; ch < nchunk; ch += nblk) {
         const int l = (ch << 8) + t;
         double dP[3] = {0, 0, 0}, dT[3] = {0, 0, 0};
         int pi = -1;
@@ -438,6 +439,18 @@ __global__ __launch_bounds__(256) void k_links(Params p, const typename Store<S>
         }
         __syncthreads();
     }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_links(Params p, const typename Store<S>::T *__restrict__ A,
+                                               typename Store<S>::T *__restrict__ B,
+                                               const int32_t *__restrict__ own,
+                                               const DevParticle *__restrict__ P,
+                                               const uint32_t *__restrict__ l_node,
+                                               const uint32_t *__restrict__ l_do,
+                                               const double *__restrict__ l_q, double *__restrict__ part,
+                                               Counters *__restrict__ cnt) {
+    links_body<S>(p, A, B, own, P, l_node, l_do, l_q, part, cnt, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------- rigid body (FP64)
@@ -527,17 +540,22 @@ __device__ void reset_step_counters(Counters *cnt) {
 
 // One block per particle: reduce_body.  Block 0 also clears the per-step
 // counters.
-__global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restrict__ P,
-                                                const int *__restrict__ l_off,
-                                                const double *__restrict__ part,
-                                                Counters *__restrict__ cnt, int update, int *body_stats) {
+__device__ __forceinline__ void reduce_case(const Params &p, DevParticle *__restrict__ P,
+                                            const int *__restrict__ l_off, const double *__restrict__ part,
+                                            Counters *__restrict__ cnt, int update, int *body_stats, const int pi) {
     __shared__ double red[6][256];
     __shared__ DevParticle sp;
-    const int pi = blockIdx.x;
     if (pi == 0 && threadIdx.x == 0) reset_step_counters(cnt);
     if (pi >= p.np) return;
     if (threadIdx.x < 4) body_stats[4 * pi + threadIdx.x] = 0;  // counts of the coming classification
     reduce_body(p, P, pi, l_off, part, cnt, update, red, sp);
+}
+
+__global__ __launch_bounds__(256) void k_reduce(Params p, DevParticle *__restrict__ P,
+                                                const int *__restrict__ l_off,
+                                                const double *__restrict__ part,
+                                                Counters *__restrict__ cnt, int update, int *body_stats) {
+    reduce_case(p, P, l_off, part, cnt, update, body_stats, blockIdx.x);
 }
 
 
@@ -790,8 +808,8 @@ __device__ void body_substep(const Params &p, DevParticle &P, const double F[3],
 // (partners by index, then faces).  Finally end-of-step checks, periodic
 // wrap of the centroid and the region origin.
 constexpr int RIGID_LDS = 32;
-__global__ __launch_bounds__(256) void k_rigid(Params p, DevParticle *__restrict__ Pg, ContactBufs cb,
-                                               Counters *__restrict__ cnt) {
+__device__ __forceinline__ void rigid_case(const Params &p, DevParticle *__restrict__ Pg, const ContactBufs &cb,
+                                           Counters *__restrict__ cnt) {
     __shared__ DevParticle sP[RIGID_LDS];
     const int t = threadIdx.x, np = p.np;
     const bool lds = np <= RIGID_LDS;
@@ -895,6 +913,11 @@ __global__ __launch_bounds__(256) void k_rigid(Params p, DevParticle *__restrict
         for (int k = t; k < W * np; k += 256) ((int *)Pg)[k] = ((const int *)sP)[k];
 }
 
+__global__ __launch_bounds__(256) void k_rigid(Params p, DevParticle *__restrict__ Pg, ContactBufs cb,
+                                               Counters *__restrict__ cnt) {
+    rigid_case(p, Pg, cb, cnt);
+}
+
 // End of a lattice step for one body: error checks (non-finite state, more
 // than one lattice unit moved), periodic wrap of the centroid, pose refresh.
 __device__ void end_of_step(const Params &p, DevParticle &B, Counters *cnt) {
@@ -933,12 +956,12 @@ __device__ __forceinline__ void tile_local(int f, int dx, int dy, int t, int &lx
 }
 
 __device__ __forceinline__ bool region_node(const Params &p, const RegionMap &rm,
-                                            const DevParticle *P, int &pi, int &x, int &y, int &z,
+                                            const DevParticle *P, int bid, int &pi, int &x, int &y, int &z,
                                             long long &n) {
-    pi = rm.part[blockIdx.x];
+    pi = rm.part[bid];
     const int dx = rm.dims[3 * pi], dy = rm.dims[3 * pi + 1], dz = rm.dims[3 * pi + 2];
     int lx, ly, lz;
-    tile_local(rm.first[blockIdx.x], dx, dy, threadIdx.x, lx, ly, lz);
+    tile_local(rm.first[bid], dx, dy, threadIdx.x, lx, ly, lz);
     if (lx >= dx || ly >= dy || lz >= dz) return false;
     const DevParticle &B = P[pi];
     if (!(B.full[0] | B.full[1] | B.full[2])) {
@@ -965,16 +988,21 @@ __device__ __forceinline__ bool region_node(const Params &p, const RegionMap &rm
 
 // Flags (sec. 2.1): C >= 1 is solid; the owner is the lowest body index
 // (atomicMin).  own_new must hold FLUID on the region beforehand.
-__global__ __launch_bounds__(BLK) void k_region_mark(Params p, RegionMap rm, const DevParticle *P,
-                                                     int32_t *own_new) {
+__device__ __forceinline__ void mark_body(const Params &p, const RegionMap &rm, const DevParticle *P,
+                                          int32_t *own_new, const int bid) {
     __shared__ CPs cps;
-    stage_cps(cps, P[rm.part[blockIdx.x]]);
+    stage_cps(cps, P[rm.part[bid]]);
     __syncthreads();
     int pi, x, y, z;
     long long n;
-    if (!region_node(p, rm, P, pi, x, y, z, n)) return;
+    if (!region_node(p, rm, P, bid, pi, x, y, z, n)) return;
     const double xp[3] = {(double)x, (double)y, (double)z};
     if (metaball(p, cps, xp) >= 1.0) atomicMin(&own_new[n], pi);
+}
+
+__global__ __launch_bounds__(BLK) void k_region_mark(Params p, RegionMap rm, const DevParticle *P,
+                                                     int32_t *own_new) {
+    mark_body(p, rm, P, own_new, blockIdx.x);
 }
 
 __device__ __forceinline__ int block_sum(int v, int *sh) {
@@ -1084,14 +1112,14 @@ __device__ void special_update(const Params &p, const typename Store<S>::T *__re
 //   - with blk_cnt set, the block also counts the cut links of the new flags
 //     for its body (first pass of the link build).
 template <int S>
-__global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm, const DevParticle *P,
-                                                         const int32_t *__restrict__ own_old,
-                                                         const int32_t *__restrict__ own_new,
-                                                         uint8_t *__restrict__ skip_next,
-                                                         uint32_t *special, Counters *cnt, int *blk_cnt,
-                                                         uint32_t *lmask, int *body_stats,
-                                                         const typename Store<S>::T *A,
-                                                         typename Store<S>::T *B, int do_special) {
+__device__ __forceinline__ void classify_body(const Params &p, const RegionMap &rm, const DevParticle *P,
+                                              const int32_t *__restrict__ own_old,
+                                              const int32_t *__restrict__ own_new,
+                                              uint8_t *__restrict__ skip_next,
+                                              uint32_t *special, Counters *cnt, int *blk_cnt,
+                                              uint32_t *lmask, int *body_stats,
+                                              const typename Store<S>::T *A,
+                                              typename Store<S>::T *B, int do_special, const int bid) {
     __shared__ int sh[BLK];
     __shared__ int sh3[3][BLK];
     // owners before / after over the tile and a one-node halo (beyond a wall: OUTSIDE)
@@ -1099,10 +1127,10 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     constexpr int32_t OUTSIDE = -2;
     __shared__ int32_t h_old[HN], h_new[HN];
     {
-        const int bp = rm.part[blockIdx.x];
+        const int bp = rm.part[bid];
         const int dx = rm.dims[3 * bp], dy = rm.dims[3 * bp + 1];
         int bx, by, bz;
-        tile_local(rm.first[blockIdx.x], dx, dy, 0, bx, by, bz);
+        tile_local(rm.first[bid], dx, dy, 0, bx, by, bz);
         const DevParticle &Bp = P[bp];
         const int L[3] = {p.nx, p.ny, p.nz};
         for (int h = threadIdx.x; h < HN; h += BLK) {
@@ -1121,7 +1149,7 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     __syncthreads();
     int pi, x, y, z;
     long long n;
-    const bool in = region_node(p, rm, P, pi, x, y, z, n);
+    const bool in = region_node(p, rm, P, bid, pi, x, y, z, n);
     uint32_t m = 0u, wall = 0u, solid = 0u;
     // owners before / after, lowest owner among the neighbours before / after
     int32_t oo = FLUID, on = FLUID, mo = FLUID, mn = FLUID;
@@ -1172,19 +1200,32 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
     // per-body node counts (one atomic per block and count, integers: order-free)
     block_sum3(c_solid, c_refill, c_spec, sh3);
     if (threadIdx.x == 0) {
-        int *bs = body_stats + 4 * rm.part[blockIdx.x];
+        int *bs = body_stats + 4 * rm.part[bid];
         if (c_solid) atomicAdd(bs + 1, c_solid);
         if (c_refill) atomicAdd(bs + 2, c_refill);
         if (c_spec) atomicAdd(bs + 3, c_spec);
     }
     if (!blk_cnt) return;
     // first pass of the link build: this body's cut links of the new flags
-    lmask[blockIdx.x * BLK + threadIdx.x] = m;
+    lmask[bid * BLK + threadIdx.x] = m;
     const int s = block_sum(__popc(m), sh);
     if (threadIdx.x == 0) {
-        blk_cnt[blockIdx.x] = s;
-        if (s) atomicAdd(body_stats + 4 * rm.part[blockIdx.x], s);
+        blk_cnt[bid] = s;
+        if (s) atomicAdd(body_stats + 4 * rm.part[bid], s);
     }
+}
+
+template <int S>
+__global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm, const DevParticle *P,
+                                                         const int32_t *__restrict__ own_old,
+                                                         const int32_t *__restrict__ own_new,
+                                                         uint8_t *__restrict__ skip_next,
+                                                         uint32_t *special, Counters *cnt, int *blk_cnt,
+                                                         uint32_t *lmask, int *body_stats,
+                                                         const typename Store<S>::T *A,
+                                                         typename Store<S>::T *B, int do_special) {
+    classify_body<S>(p, rm, P, own_old, own_new, skip_next, special, cnt, blk_cnt, lmask, body_stats, A, B,
+                     do_special, blockIdx.x);
 }
 
 // Plain fluid node (skip mask clear: fluid with no solid neighbour at the
@@ -1391,25 +1432,25 @@ __global__ void k_fill_u8(uint8_t *a, long long n, uint8_t v) {
 // body's offset, the last block the total) and lists
 // its links (masks from the classification; thread order, then direction
 // order).  The link fractions follow in k_link_q.
-__global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const DevParticle *P,
-                                                   const uint32_t *__restrict__ lmask,
-                                                   const int *__restrict__ blk_cnt,
-                                                   const int *__restrict__ body_stats,
-                                                   const int *__restrict__ part_first_blk, int *__restrict__ l_off,
-                                                   uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
-                                                   Counters *cnt, int32_t *clear) {
+__device__ __forceinline__ void emit_body(const Params &p, const RegionMap &rm, const DevParticle *P,
+                                          const uint32_t *__restrict__ lmask,
+                                          const int *__restrict__ blk_cnt,
+                                          const int *__restrict__ body_stats,
+                                          const int *__restrict__ part_first_blk, int *__restrict__ l_off,
+                                          uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
+                                          Counters *cnt, int32_t *clear, const int bid, const int nblk) {
     __shared__ int sh[BLK];
     const int t = threadIdx.x;
-    const int pid = rm.part[blockIdx.x];
+    const int pid = rm.part[bid];
     int before = 0;
     for (int q = t; q < pid; q += BLK) before += body_stats[4 * q];
-    for (int b = part_first_blk[pid] + t; b < (int)blockIdx.x; b += BLK) before += blk_cnt[b];
+    for (int b = part_first_blk[pid] + t; b < bid; b += BLK) before += blk_cnt[b];
     const int base = block_sum(before, sh);
     __syncthreads();  // every thread has read the sum before sh is reused
     if (t == 0) {
-        if (part_first_blk[pid] == (int)blockIdx.x) l_off[pid] = min(base, p.link_cap);
-        if (blockIdx.x == gridDim.x - 1) {
-            const int total = base + blk_cnt[blockIdx.x];
+        if (part_first_blk[pid] == bid) l_off[pid] = min(base, p.link_cap);
+        if (bid == nblk - 1) {
+            const int total = base + blk_cnt[bid];
             if (total > p.link_cap) atomicOr(&cnt->err, ERR_LINK_OVERFLOW);
             cnt->n_links = min(total, p.link_cap);
             l_off[p.np] = min(total, p.link_cap);
@@ -1417,8 +1458,8 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
     }
     int pi, x, y, z;
     long long n;
-    const bool in = region_node(p, rm, P, pi, x, y, z, n);
-    const uint32_t m = in ? lmask[blockIdx.x * BLK + t] : 0u;
+    const bool in = region_node(p, rm, P, bid, pi, x, y, z, n);
+    const uint32_t m = in ? lmask[bid * BLK + t] : 0u;
     if (in && clear) clear[n] = FLUID;
     const int c = __popc(m);
     sh[t] = c;
@@ -1440,6 +1481,17 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
         }
 }
 
+__global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const DevParticle *P,
+                                                   const uint32_t *__restrict__ lmask,
+                                                   const int *__restrict__ blk_cnt,
+                                                   const int *__restrict__ body_stats,
+                                                   const int *__restrict__ part_first_blk, int *__restrict__ l_off,
+                                                   uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
+                                                   Counters *cnt, int32_t *clear) {
+    emit_body(p, rm, P, lmask, blk_cnt, body_stats, part_first_blk, l_off, l_node, l_do, cnt, clear, blockIdx.x,
+              gridDim.x);
+}
+
 // Link build, third pass: the link fractions of the whole list, eight lanes
 // per link (32 links per block, blocks stride over the list), each group
 // with its body's control points staged in its own LDS slot.  With WARM the
@@ -1450,12 +1502,15 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
 // is replaced by the plain one.  Per block: iteration histogram and largest
 // final |C - 1|, added to the statistics.
 constexpr int NR_WARM_MAX = 30, NR_MAX = 100;
+// WARM sizes the LDS for the network; a system without weights (wts NULL)
+// takes the plain iteration in either form.
 template <bool WARM>
-__global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__restrict__ P,
-                                                const uint32_t *__restrict__ l_node,
-                                                const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
-                                                Counters *cnt, NrStats nrs,
-                                                const _Float16 *__restrict__ wts, const float *__restrict__ body) {
+__device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *__restrict__ P,
+                                            const uint32_t *__restrict__ l_node,
+                                            const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
+                                            Counters *cnt, const NrStats &nrs,
+                                            const _Float16 *__restrict__ wts, const float *__restrict__ body,
+                                            const int bid, const int nblk) {
     __shared__ CPs cps[32];
     __shared__ int sh[256];
     __shared__ unsigned hist[NR_HIST];
@@ -1463,13 +1518,14 @@ __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__r
     __shared__ _Float16 wsh[WARM ? MLP_P : 1];
     __shared__ _Float16 act[WARM ? 32 : 1][WARM ? MLP_IN + 2 * MLP_H : 1];  // inputs, h1, h2
     const int t = threadIdx.x, g = t >> 3, j = t & 7;
+    const bool warm = WARM && wts != nullptr;  // block-uniform
     for (int b = t; b < NR_HIST; b += 256) hist[b] = 0u;
     if (t == 0) rmax = 0u;
-    if (WARM)
+    if (warm)
         for (int k = t; k < MLP_P; k += 256) wsh[k] = wts[k];
     const int nl = min(cnt->n_links, p.link_cap);
     int it_sum = 0, links = 0;
-    for (int l0 = blockIdx.x * 32; l0 < nl; l0 += gridDim.x * 32) {  // block-uniform trip count
+    for (int l0 = bid * 32; l0 < nl; l0 += nblk * 32) {  // block-uniform trip count
         const int l = l0 + g;
         const bool ok0 = l < nl;
         int pid = 0, i = 1;
@@ -1495,7 +1551,7 @@ __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__r
             }
             if (j == 0) cps[g].n = n4;
             node_xyz(p, n, x, y, z);
-            if (WARM) {
+            if (warm) {
                 if (j == 0) {
                     const int e[3] = {c_ex[i], c_ey[i], c_ez[i]};
                     double head[7];
@@ -1507,7 +1563,7 @@ __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__r
         }
         __syncthreads();
         double guess = -1.0;
-        if (WARM) {
+        if (warm) {
             // hidden layer 1: units 8j .. 8j+7 of this group's link
             if (ok) {
                 float zz[8];
@@ -1541,9 +1597,9 @@ __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__r
         if (ok) {
             double q, resid;
             bool conv;
-            int its = link_fraction8(p, cps[g], x, y, z, i, guess, WARM ? NR_WARM_MAX : NR_MAX, q, resid,
+            int its = link_fraction8(p, cps[g], x, y, z, i, guess, warm ? NR_WARM_MAX : NR_MAX, q, resid,
                                      conv);
-            if (WARM && !conv) {
+            if (warm && !conv) {
                 its += link_fraction8(p, cps[g], x, y, z, i, -1.0, NR_MAX, q, resid, conv);
             }
             if (j == 0) {
@@ -1559,33 +1615,96 @@ __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__r
     const int its = block_sum(it_sum, sh);
     __syncthreads();
     const int nls = block_sum(links, sh);
-    if (blockIdx.x >= NR_BLOCKS) return;  // never: the launcher caps the grid
+    if (bid >= NR_BLOCKS) return;  // never: the launchers cap the grid
     if (t == 0 && nls > 0) {  // this block's own slot: plain read-modify-write
-        nrs.work[2 * blockIdx.x] += (unsigned long long)its;
-        nrs.work[2 * blockIdx.x + 1] += (unsigned long long)nls;
-        nrs.resid[blockIdx.x] = max(nrs.resid[blockIdx.x], rmax);
+        nrs.work[2 * bid] += (unsigned long long)its;
+        nrs.work[2 * bid + 1] += (unsigned long long)nls;
+        nrs.resid[bid] = max(nrs.resid[bid], rmax);
     }
     for (int b = t; b < NR_HIST; b += 256)
-        if (hist[b]) nrs.hist[blockIdx.x * NR_HIST + b] += hist[b];
+        if (hist[b]) nrs.hist[bid * NR_HIST + b] += hist[b];
+}
+
+template <bool WARM>
+__global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__restrict__ P,
+                                                const uint32_t *__restrict__ l_node,
+                                                const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
+                                                Counters *cnt, NrStats nrs,
+                                                const _Float16 *__restrict__ wts, const float *__restrict__ body) {
+    link_q_body<WARM>(p, P, l_node, l_do, l_q, cnt, nrs, wts, body, blockIdx.x, gridDim.x);
+}
+
+// ------------------------------------------------- batched boundary kernels
+// One launch of a kind for every system of an ensemble: block b works for
+// system map[b] as its block b - first[kind] (the same code as the
+// one-system launches above).
+template <int S>
+__global__ __launch_bounds__(256) void k_links_batch(const CaseArgs *__restrict__ cs, const int *__restrict__ map) {
+    using T = typename Store<S>::T;
+    const CaseArgs &a = cs[map[blockIdx.x]];
+    links_body<S>(a.p, (const T *)a.A, (T *)a.B, a.own_old, a.P, a.l_node, a.l_do, a.l_q, a.part, a.cnt,
+                  (int)blockIdx.x - a.first[BK_LINKS], a.nblk[BK_LINKS]);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_batch(const CaseArgs *__restrict__ cs, const int *__restrict__ map) {
+    const CaseArgs &a = cs[map[blockIdx.x]];
+    reduce_case(a.p, a.P, a.l_off, a.part, a.cnt, a.update, a.body_stats, (int)blockIdx.x - a.first[BK_REDUCE]);
+}
+
+__global__ __launch_bounds__(256) void k_rigid_batch(const CaseArgs *__restrict__ cs, const int *__restrict__ map) {
+    const CaseArgs &a = cs[map[blockIdx.x]];
+    rigid_case(a.p, a.P, a.cb, a.cnt);
+}
+
+__global__ __launch_bounds__(BLK) void k_region_mark_batch(const CaseArgs *__restrict__ cs,
+                                                           const int *__restrict__ map) {
+    const CaseArgs &a = cs[map[blockIdx.x]];
+    mark_body(a.p, a.rm, a.P, a.own_new, (int)blockIdx.x - a.first[BK_REGION]);
+}
+
+// with the boundary/uncovered update and the link count of the new flags
+template <int S>
+__global__ __launch_bounds__(BLK) void k_region_classify_batch(const CaseArgs *__restrict__ cs,
+                                                               const int *__restrict__ map) {
+    using T = typename Store<S>::T;
+    const CaseArgs &a = cs[map[blockIdx.x]];
+    classify_body<S>(a.p, a.rm, a.P, a.own_old, a.own_new, a.skip_next, a.special, a.cnt, a.blk_cnt, a.lmask,
+                     a.body_stats, (const T *)a.A, (T *)a.B, 1, (int)blockIdx.x - a.first[BK_REGION]);
+}
+
+__global__ __launch_bounds__(BLK) void k_link_emit_batch(const CaseArgs *__restrict__ cs,
+                                                         const int *__restrict__ map) {
+    const CaseArgs &a = cs[map[blockIdx.x]];
+    emit_body(a.p, a.rm, a.P, a.lmask, a.blk_cnt, a.body_stats, a.part_first_blk, a.l_off, a.l_node, a.l_do, a.cnt,
+              a.own_dead, (int)blockIdx.x - a.first[BK_REGION], a.nblk[BK_REGION]);
+}
+
+template <bool WARM>
+__global__ __launch_bounds__(256) void k_link_q_batch(const CaseArgs *__restrict__ cs, const int *__restrict__ map) {
+    const CaseArgs &a = cs[map[blockIdx.x]];
+    link_q_body<WARM>(a.p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm, a.mlp_body,
+                      (int)blockIdx.x - a.first[BK_LINKQ], a.nblk[BK_LINKQ]);
 }
 
 // ------------------------------------------------------------ host launchers
 static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// list kernels stride over their lists; size their grids for the expected lengths
+static int expected_links(const Params &p) { return p.est_links > 0 ? min(p.est_links, p.link_cap) : p.link_cap; }
+int link_grid(const Params &p) { return max(1, min(cdiv(expected_links(p), 256), 2048)); }
+int link_q_grid(const Params &p) { return max(1, min(cdiv(expected_links(p), 32), NR_BLOCKS)); }
 
 template <int S>
 static void launch_step_kernels_t(const StepArgs &a) {
     using T = typename Store<S>::T;
     const Params &p = a.p;
     T *A = (T *)a.A, *B = (T *)a.B;
-    // list kernels stride over their lists; size their grids for the expected lengths
-    const int nlink = p.est_links > 0 ? min(p.est_links, p.link_cap) : p.link_cap;
     const int nspec = p.est_special > 0 ? min(p.est_special, p.special_cap) : p.special_cap;
-    const int link_grid = max(1, min(cdiv(nlink, 256), 2048));
     const int spec_grid = max(1, min(cdiv(nspec, 4), 2048));
     if (a.phase == PHASE_LINKS) {
         const int update = a.move && !p.contact;
         if (p.np > 0)
-            k_links<S><<<link_grid, 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.l_node, a.l_do, a.l_q,
+            k_links<S><<<link_grid(p), 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.l_node, a.l_do, a.l_q,
                                                          a.part, a.cnt);
         k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, update, a.body_stats);
         if (a.move && p.contact && p.np > 0) k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
@@ -1618,7 +1737,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
             k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt, a.body_stats,
                                                                 a.part_first_blk, a.l_off,
                                                                 a.l_node, a.l_do, a.cnt, a.own_dead);
-            const int qg = max(1, min(cdiv(nlink, 32), NR_BLOCKS));
+            const int qg = link_q_grid(p);
             if (a.warm)
                 k_link_q<true><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm,
                                                           a.mlp_body);
@@ -1660,6 +1779,27 @@ void launch_bulk_batch(int storage, int bw, const BulkCase *cases, const int *bl
     if (storage == 1) launch_bulk_batch_t<1>(bw, cases, blk_case, nblocks, parity, s);
     else if (storage == 2) launch_bulk_batch_t<2>(bw, cases, blk_case, nblocks, parity, s);
     else launch_bulk_batch_t<0>(bw, cases, blk_case, nblocks, parity, s);
+}
+
+template <int S>
+static void launch_case_batch_t(BatchOp op, const CaseArgs *cs, const int *map, int nblocks, hipStream_t s) {
+    switch (op) {
+        case OP_LINKS: k_links_batch<S><<<nblocks, 256, 0, s>>>(cs, map); break;
+        case OP_REDUCE: k_reduce_batch<<<nblocks, 256, 0, s>>>(cs, map); break;
+        case OP_RIGID: k_rigid_batch<<<nblocks, 256, 0, s>>>(cs, map); break;
+        case OP_MARK: k_region_mark_batch<<<nblocks, BLK, 0, s>>>(cs, map); break;
+        case OP_CLASSIFY: k_region_classify_batch<S><<<nblocks, BLK, 0, s>>>(cs, map); break;
+        case OP_EMIT: k_link_emit_batch<<<nblocks, BLK, 0, s>>>(cs, map); break;
+        case OP_LINKQ: k_link_q_batch<false><<<nblocks, 256, 0, s>>>(cs, map); break;
+        case OP_LINKQ_WARM: k_link_q_batch<true><<<nblocks, 256, 0, s>>>(cs, map); break;
+    }
+}
+
+void launch_case_batch(int storage, BatchOp op, const CaseArgs *cs, const int *map, int nblocks, hipStream_t s) {
+    if (nblocks <= 0) return;
+    if (storage == 1) launch_case_batch_t<1>(op, cs, map, nblocks, s);
+    else if (storage == 2) launch_case_batch_t<2>(op, cs, map, nblocks, s);
+    else launch_case_batch_t<0>(op, cs, map, nblocks, s);
 }
 
 void launch_reset_counters(Counters *cnt, hipStream_t s) { k_reset_counters<<<1, 1, 0, s>>>(cnt); }

@@ -55,4 +55,13 @@ void launch_bulk_batch(int storage, int bw, const BulkCase *cases, const int *bl
                        hipStream_t s);
 void launch_refresh_pose(const Params &p, DevParticle *P, hipStream_t s);
 
+// Batched boundary kernels of an ensemble: one launch of a kind for every
+// system (cs: the systems' argument blocks, map: block -> system).
+enum BatchOp { OP_LINKS, OP_REDUCE, OP_RIGID, OP_MARK, OP_CLASSIFY, OP_EMIT, OP_LINKQ, OP_LINKQ_WARM };
+void launch_case_batch(int storage, BatchOp op, const CaseArgs *cs, const int *map, int nblocks, hipStream_t s);
+// Launch sizes of the one-system boundary kernels (also the block ranges of
+// a system in the batched launches).
+int link_grid(const Params &p);
+int link_q_grid(const Params &p);
+
 }  // namespace mdl

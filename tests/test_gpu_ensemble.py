@@ -117,3 +117,40 @@ def test_ensemble_with_a_system_without_bodies(mdl):
     for i, (sim, ref) in enumerate(zip(ens.cases, refs)):
         assert_same(sim, ref, f"case {i} ({cfgs[i].name})")
     ens.close()
+
+
+def test_ensemble_with_contact_and_several_bodies(mdl):
+    """Systems whose bodies collide (the rigid-body pass with contacts) and
+    one with six bodies (per-body link offsets inside a system) batched with
+    a plain settling system."""
+    cfgs = [workloads.settle_on_floor(), workloads.mini_ensemble(1)[0], workloads.suspension_small()]
+    steps = 14
+    refs = [alone(mdl, c, steps) for c in cfgs]
+    ens = mdl.Ensemble(cfgs)
+    ens.step(steps)
+    for i, (sim, ref) in enumerate(zip(ens.cases, refs)):
+        assert_same(sim, ref, f"case {i} ({cfgs[i].name})")
+    ens.close()
+
+
+def test_ensemble_with_one_warm_started_system(mdl):
+    """One system warm-starts its link fractions with a network, the others
+    do not (one launch serves both): each matches itself stepped alone."""
+    cfgs = workloads.mini_ensemble(3)
+    net = mdl.Mlp(workloads.mlp_init(7))
+    steps = 13
+    refs = []
+    for i, c in enumerate(cfgs):
+        sim = mdl.Simulation(c)
+        if i == 1:
+            sim.set_warmstart(net)
+        sim.step(steps)
+        refs.append((sim.populations(), sim.owner(), sim.particles(), sim.links()[3]))
+        sim.close()
+    ens = mdl.Ensemble(cfgs)
+    ens.cases[1].set_warmstart(net)
+    ens.step(steps)
+    for i, (sim, ref) in enumerate(zip(ens.cases, refs)):
+        assert_same(sim, ref[:3], f"case {i}")
+        assert np.array_equal(sim.links()[3], ref[3]), f"case {i}: link fractions differ"
+    ens.close()
