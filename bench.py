@@ -86,6 +86,7 @@ def run_ensemble(n_cases, steps, warmup):
     torch.cuda.synchronize()
     dt_seq = time.perf_counter() - t0
     hist = {f"{64 >> (6 - t)}x{64 >> t}": tiles.count(t) for t in (6, 5, 4)}
+    hist["64 in lattice order"] = tiles.count(7)
     ens.close()
     return {"workload": f"{n_cases}-case settling ensemble, walls, FP32, 64..128 x 64..128 x 64..256, "
                         "tau U[0.55,1], density ratio U[1.1,2.5], 4..16 cp",

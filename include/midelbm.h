@@ -270,8 +270,8 @@ lbm_status lbm_nr_histogram(lbm_ctx *ctx, int64_t *hist, double *resid_max);
  * n_cases systems (each as lbm_init would set it up: configs cfgs[i],
  * particles parts[n_p[0] + ... + n_p[i-1] ...] concatenated) stepped
  * together: the stream-collide of all systems runs as one launch over a table
- * of equal tiles (a wave covers a tile of 64x1, 32x2 or 16x4 nodes, chosen
- * per system by lbm_autotune), each kind of boundary kernel runs as one
+ * of equal tiles (a wave covers a tile of 64x1, 32x2 or 16x4 nodes, or 64
+ * consecutive nodes in lattice order, chosen per system by lbm_autotune), each kind of boundary kernel runs as one
  * launch for all systems (a block finds its system in a block table) on a
  * second stream owned by the batch, and six consecutive coupled steps (the
  * period of the library's buffer rotation) are captured once into a HIP
@@ -307,7 +307,7 @@ lbm_status lbm_batch_case(lbm_batch *b, int32_t i, lbm_ctx **ctx);
  * of the next step are unchanged by the tiles (only the launch shape is). */
 lbm_status lbm_autotune(lbm_batch *b, double budget_ms, const char *cache_path /* nullable */);
 /* Current choices: tw_log2[i] = log2 of the tile width of system i (6, 5 or
- * 4), and the waves per block. */
+ * 4; 7: 64 consecutive nodes in lattice order), and the waves per block. */
 lbm_status lbm_batch_tiles(lbm_batch *b, int32_t *tw_log2 /* [n_cases] */, int32_t *waves_per_block);
 void lbm_batch_destroy(lbm_batch *b);
 

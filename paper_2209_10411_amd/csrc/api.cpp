@@ -1257,7 +1257,7 @@ void lbm_destroy(lbm_ctx *c) {
 namespace {
 constexpr int GRAPH_PERIOD = 6;
 constexpr int BATCH_AUX = 1;  // stream of the batched boundary kernels
-constexpr int TW_CANDIDATES[3] = {6, 5, 4};  // wave tiles 64x1, 32x2, 16x4
+constexpr int TW_CANDIDATES[4] = {6, 5, 4, TW_FLAT};  // wave tiles 64x1, 32x2, 16x4, 64 in lattice order
 }  // namespace
 
 struct lbm_batch {
@@ -1293,6 +1293,7 @@ struct lbm_batch {
 namespace {
 
 long long tile_blocks(const lbm_config &c, int twl, int bw) {
+    if (twl == TW_FLAT) return ((long long)c.nx * c.ny * c.nz + 64ll * bw - 1) / (64ll * bw);
     const long long nsx = (c.nx + (1 << twl) - 1) >> twl, th = 64 >> twl;
     const long long nsy = (c.ny + th - 1) / th;
     return (nsx * nsy * c.nz + bw - 1) / bw;
@@ -1305,8 +1306,10 @@ BulkCase bulk_case(const lbm_ctx *c, int twl, int bw, int first_block) {
     b.rho0f = p.rho0f; b.omega = p.omega; b.fcoef = p.fcoef;
     b.gx = p.gx; b.gy = p.gy; b.gz = p.gz; b.scale = p.scale; b.inv_scale = p.inv_scale;
     b.tw_log2 = twl;
-    b.nsx = (p.nx + (1 << twl) - 1) >> twl;
-    b.nsy = (p.ny + (64 >> twl) - 1) / (64 >> twl);
+    if (twl != TW_FLAT) {
+        b.nsx = (p.nx + (1 << twl) - 1) >> twl;
+        b.nsy = (p.ny + (64 >> twl) - 1) / (64 >> twl);
+    }
     b.first_block = first_block;
     b.n_blocks = (int)tile_blocks(c->cfg, twl, bw);
     b.A[0] = c->A; b.B[0] = c->B; b.A[1] = c->B; b.B[1] = c->A;
@@ -1765,7 +1768,7 @@ lbm_status lbm_autotune(lbm_batch *b, double budget_ms, const char *cache_path) 
         if (!cache_int(txt, "bw", bw) || (bw != 4 && bw != 8)) complete = false;
         std::vector<int> tw(b->n, 6);
         for (int i = 0; i < b->n && complete; ++i)
-            if (!cache_int(txt, case_key(b->cs[i]), tw[i]) || tw[i] < 4 || tw[i] > 6) complete = false;
+            if (!cache_int(txt, case_key(b->cs[i]), tw[i]) || tw[i] < 4 || tw[i] > TW_FLAT) complete = false;
         if (complete) {
             b->bw = bw;
             b->tw = tw;

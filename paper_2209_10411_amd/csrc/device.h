@@ -102,6 +102,8 @@ struct ContactBufs {
     double *xiW;     // [np*6][3] tangential springs, walls
 };
 
+constexpr int TW_FLAT = 7;
+
 // One system of an ensemble as seen by the batched stream-collide: sizes,
 // collision constants, tile shape and block range, and the buffers of a step
 // of either parity (parity 0: the assignment when the table was written).
@@ -110,7 +112,8 @@ struct BulkCase {
     unsigned periodic;
     long long N;
     float rho0f, omega, fcoef, gx, gy, gz, scale, inv_scale;
-    int tw_log2;      // wave tile: 2^tw_log2 consecutive x by 64 >> tw_log2 rows of y
+    int tw_log2;      // wave tile: 2^tw_log2 consecutive x by 64 >> tw_log2 rows of y (4..6), or
+                      // TW_FLAT: 64 consecutive nodes in lattice order (rows wrap within a wave)
     int nsx, nsy;     // tiles along x and along y per z plane
     int first_block;  // first block of this system in the launch
     int n_blocks;     // blocks of this system

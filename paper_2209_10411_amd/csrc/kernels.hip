@@ -1283,8 +1283,9 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typena
 
 // An ensemble of systems in one launch: the block table names each block's
 // system; within a system a wave covers a tile of 2^tw_log2 consecutive x by
-// 64 / 2^tw_log2 rows of y (the tile shape is chosen per system by the
-// autotuner), BW waves per block, tiles in lattice order.
+// 64 / 2^tw_log2 rows of y, or (TW_FLAT) 64 consecutive nodes in lattice
+// order, which leaves no lane idle whatever nx (the tile shape is chosen per
+// system by the autotuner), BW waves per block, tiles in lattice order.
 template <int S, int BW>
 __global__ __launch_bounds__(64 * BW) void k_bulk_batch(const BulkCase *__restrict__ cases,
                                                         const int *__restrict__ blk_case, int parity) {
@@ -1292,15 +1293,25 @@ __global__ __launch_bounds__(64 * BW) void k_bulk_batch(const BulkCase *__restri
     const BulkCase &c = cases[blk_case[blockIdx.x]];
     const int wave = ((int)blockIdx.x - c.first_block) * BW + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int per_plane = c.nsx * c.nsy;
-    const int z = wave / per_plane;
-    if (z >= c.nz) return;
-    const int r = wave - z * per_plane;
-    const int ty = r / c.nsx, tx = r - ty * c.nsx;
-    const int x = (tx << c.tw_log2) + (lane & ((1 << c.tw_log2) - 1));
-    const int y = ty * (64 >> c.tw_log2) + (lane >> c.tw_log2);
-    if (x >= c.nx || y >= c.ny) return;
-    const int n = (z * c.ny + y) * c.nx + x;
+    int x, y, z, n;
+    if (c.tw_log2 == TW_FLAT) {
+        n = wave * 64 + lane;
+        if (n >= c.N) return;
+        const unsigned row = (unsigned)n / (unsigned)c.nx;
+        x = n - (int)row * c.nx;
+        z = (int)(row / (unsigned)c.ny);
+        y = (int)row - z * c.ny;
+    } else {
+        const int per_plane = c.nsx * c.nsy;
+        z = wave / per_plane;
+        if (z >= c.nz) return;
+        const int r = wave - z * per_plane;
+        const int ty = r / c.nsx, tx = r - ty * c.nsx;
+        x = (tx << c.tw_log2) + (lane & ((1 << c.tw_log2) - 1));
+        y = ty * (64 >> c.tw_log2) + (lane >> c.tw_log2);
+        if (x >= c.nx || y >= c.ny) return;
+        n = (z * c.ny + y) * c.nx + x;
+    }
     if (c.skip[parity][n]) return;
     Params p;
     p.nx = c.nx; p.ny = c.ny; p.nz = c.nz; p.periodic = c.periodic; p.N = c.N;
