@@ -18,6 +18,7 @@
 #include "../../include/midelbm.h"
 #include "device.h"
 #include "launch.h"
+#include "min_image.h"
 #include "mlp_dev.h"
 
 using namespace mdl;
@@ -448,7 +449,7 @@ lbm_status body_counts(lbm_ctx *c, long long &solid, long long &refilled, long l
 }
 
 lbm_status reflag(lbm_ctx *c) {
-    launch_refresh_pose(c->p, c->P, c->stream);
+    launch_refresh_pose(c->p, c->P, 0, c->stream);
     launch_fill_i32(c->own[c->in], c->pl.N, FLUID, c->stream);
     launch_fill_i32(c->own[c->id], c->pl.N, FLUID, c->stream);
     launch_fill_u8(c->skip[0], c->pl.N, 0, c->stream);
@@ -459,8 +460,12 @@ lbm_status reflag(lbm_ctx *c) {
     a.phase = PHASE_FLAGS;
     a.move = 1;
     launch_phase(a);
+    launch_uncovered(c->p, a.own_old, a.own_new, c->special, c->cnt, c->body_stats, c->stream);
     a.phase = PHASE_LINKBUILD;
     launch_phase(a);
+    // the next steps find the new flags only (the others are cleared, the
+    // pre-flag ones go with the refill)
+    launch_refresh_pose(c->p, c->P, 1, c->stream);
     const int old = c->ic;
     c->ic = c->in; c->in = c->id; c->id = old;
     c->is = 1 - c->is;
@@ -549,6 +554,9 @@ static lbm_status prepare(const lbm_config *cfg, int32_t n_p, const lbm_particle
         d.rb = bounding_radius(q.n_cp, q.cp_xyz, q.cp_k, bp.c);
         rb[p] = d.rb;
         re[p] = bp.re;
+        d.re = std::min(bp.re, d.rb);
+        d.reach = 1e30;
+        d.hist = 0;
         for (int a = 0; a < 3; ++a)
             if (!((cfg->periodic >> a) & 1u) && (d.X[a] - d.rb < 0.0 || d.X[a] + d.rb > L[a] - 1.0))
                 return fail(LBM_E_INVALID, "particle %d: bounding sphere crosses a wall on axis %d", p, a);
@@ -659,6 +667,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     p.link_cap = pl.link_cap;
     p.special_cap = pl.special_cap;
     p.region_blocks = pl.region_blocks;
+    for (int a = 0; a < 3; ++a) min_image_thresholds(a == 0 ? p.nx : a == 1 ? p.ny : p.nz, p.mi_up[a], p.mi_dn[a]);
 
     auto bail = [&](lbm_status st) {
         if (c->ev_main) (void)hipEventDestroy(c->ev_main);
@@ -1012,7 +1021,7 @@ lbm_status lbm_set_particles(lbm_ctx *c, const lbm_particle_state *in) {
         for (int a = 0; a < 4; ++a) d.q[a] = o.quat[a] / qn;
     }
     if (c->p.np) HIPCHK(hipMemcpy(c->P, hp.data(), sizeof(DevParticle) * c->p.np, hipMemcpyHostToDevice));
-    launch_refresh_pose(c->p, c->P, c->stream);
+    launch_refresh_pose(c->p, c->P, 0, c->stream);
     return check_device(c);
 }
 

@@ -42,6 +42,15 @@ struct DevParticle {
     int lo[3];                      // region origin (unwrapped), set from X each pose change
     int full[3];                    // 1: the region spans a whole periodic axis
     double X0[3];                   // centroid at the start of the current step
+    // Region work is limited to balls about X: flags within re (extent of
+    // the C >= 1 set), classification and link build within
+    // re + sqrt 2 + reach, reach = distance to the centroids of the two
+    // previous flaggings (Xf; hist = how many of them are known, reach
+    // 1e30 until both are).
+    double re;
+    double reach;
+    double Xf[2][3];
+    int hist;
 };
 
 // Small device-side counters, reset and read by the host at sync points.
@@ -88,6 +97,11 @@ struct Params {
     int est_links, est_special; // expected list lengths (launch sizes of the list kernels; 0: capacities)
     int contact;                // contact enabled
     double c_rs, c_kn, c_en, c_mu;
+    // minimum image on a periodic axis of length L: for |d| < 1.25 L the
+    // image shift k = floor(d / L + 0.5) (FP64) is +1 exactly when d >= mi_up
+    // and -1 exactly when d < mi_dn (k is monotone in d; the host finds both
+    // thresholds with the same FP64 operations)
+    double mi_up[3], mi_dn[3];
 };
 
 // Per-sub-step contact results and tangential springs (arena), for bodies
@@ -159,8 +173,8 @@ struct CaseArgs {
     int first[BK_N], nblk[BK_N];
 };
 // the host writes these tables for the device: one layout on both sides
-static_assert(sizeof(Params) == 192 && sizeof(CaseArgs) == 504 && offsetof(CaseArgs, nrs) == 416 &&
-                  offsetof(CaseArgs, first) == 460,
+static_assert(sizeof(Params) == 240 && sizeof(CaseArgs) == 552 && offsetof(CaseArgs, nrs) == 464 &&
+                  offsetof(CaseArgs, first) == 508,
               "CaseArgs layout");
 
 }  // namespace mdl

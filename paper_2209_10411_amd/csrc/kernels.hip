@@ -28,6 +28,7 @@
 
 #include "device.h"
 #include "launch.h"
+#include "min_image.h"
 #include "mlp_dev.h"
 
 namespace mdl {
@@ -109,11 +110,13 @@ __device__ __forceinline__ bool nbr(const Params &p, int x, int y, int z, int dx
     return true;
 }
 
+// d - L floor(d / L + 0.5) per periodic axis (min_image_axis: the same
+// result without a division within 1.25 L of zero).
 __device__ __forceinline__ void min_image(const Params &p, double d[3]) {
     const double L[3] = {(double)p.nx, (double)p.ny, (double)p.nz};
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-        if (p.periodic & (1u << a)) d[a] -= L[a] * floor(d[a] / L[a] + 0.5);
+        if (p.periodic & (1u << a)) d[a] = min_image_axis(d[a], L[a], p.mi_up[a], p.mi_dn[a]);
 }
 
 // Control points of one body staged in LDS by the whole block, padded to a
@@ -929,18 +932,41 @@ __device__ void end_of_step(const Params &p, DevParticle &B, Counters *cnt) {
     }
     if (!finite) atomicOr(&cnt->err, ERR_NONFINITE);
     else if (d2 > 1.0) atomicOr(&cnt->err, ERR_FAST_PARTICLE);
+    // distance to the poses of the two previous flaggings (minimum image),
+    // then this pose (flagged next) joins the history
+    double reach = 1e30;
+    if (B.hist >= 2 && finite) {
+        reach = 0.0;
+        for (int h = 0; h < 2; ++h) {
+            double d[3] = {B.X[0] - B.Xf[h][0], B.X[1] - B.Xf[h][1], B.X[2] - B.Xf[h][2]};
+            min_image(p, d);
+            reach = fmax(reach, sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+        }
+    }
+    B.reach = reach;
     const int L[3] = {p.nx, p.ny, p.nz};
     for (int c = 0; c < 3; ++c)  // keep the centroid inside a periodic box
         if ((p.periodic >> c) & 1u) {
             if (B.X[c] < 0.0) B.X[c] += L[c];
             else if (B.X[c] >= L[c]) B.X[c] -= L[c];
         }
+    for (int a = 0; a < 3; ++a) { B.Xf[1][a] = B.Xf[0][a]; B.Xf[0][a] = B.X[a]; }
+    B.hist = min(B.hist + 1, 2);
     refresh_pose(p, B);
 }
 
-__global__ void k_refresh_pose(Params p, DevParticle *P) {
+// Pose refresh after a change from the host.  fresh = 0: the flag buffers
+// may hold flags of unknown poses (no history: full regions); fresh = 1:
+// the only flags are of the current pose (after a re-flag that cleared the
+// other buffers).
+__global__ void k_refresh_pose(Params p, DevParticle *P, int fresh) {
     const int pi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pi < p.np) refresh_pose(p, P[pi]);
+    if (pi >= p.np) return;
+    DevParticle &B = P[pi];
+    refresh_pose(p, B);
+    for (int a = 0; a < 3; ++a) B.Xf[0][a] = B.Xf[1][a] = B.X[a];
+    B.hist = fresh ? 2 : 0;
+    B.reach = fresh ? 0.0 : 1e30;
 }
 
 // Region node of a region kernel thread; false if outside the region or the
@@ -955,9 +981,33 @@ __device__ __forceinline__ void tile_local(int f, int dx, int dy, int t, int &lx
     lz = tz * TILE_Z + t / (TILE_X * TILE_Y);
 }
 
+// Ball radii of the region kernels about the body's centroid: flagging
+// (the C >= 1 set lies within re; half a node to spare), and classification
+// and link build (a neighbour, sqrt 2, of the flags of this pose or of the
+// two before, within reach).
+__device__ __forceinline__ double flag_radius(const DevParticle &B) { return B.re + 0.5; }
+__device__ __forceinline__ double class_radius(const DevParticle &B) { return B.re + 1.5 + B.reach; }
+
+// True if no node of tile f of body B's region lies within rad of its
+// centroid (block-uniform; never for a region spanning a periodic axis).
+__device__ __forceinline__ bool tile_outside(const RegionMap &rm, const DevParticle &B, int pi, int f, double rad) {
+    if (B.full[0] | B.full[1] | B.full[2]) return false;
+    const int dx = rm.dims[3 * pi], dy = rm.dims[3 * pi + 1];
+    int bx, by, bz;
+    tile_local(f, dx, dy, 0, bx, by, bz);
+    const int b0[3] = {B.lo[0] + bx, B.lo[1] + by, B.lo[2] + bz};
+    const int w[3] = {TILE_X - 1, TILE_Y - 1, TILE_Z - 1};
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double g = fmax(0.0, fmax((double)b0[a] - B.X[a], B.X[a] - (double)(b0[a] + w[a])));
+        d2 += g * g;
+    }
+    return d2 > rad * rad;
+}
+
 __device__ __forceinline__ bool region_node(const Params &p, const RegionMap &rm,
-                                            const DevParticle *P, int bid, int &pi, int &x, int &y, int &z,
-                                            long long &n) {
+                                            const DevParticle *P, int bid, double rad, int &pi, int &x, int &y,
+                                            int &z, long long &n) {
     pi = rm.part[bid];
     const int dx = rm.dims[3 * pi], dy = rm.dims[3 * pi + 1], dz = rm.dims[3 * pi + 2];
     int lx, ly, lz;
@@ -972,6 +1022,10 @@ __device__ __forceinline__ bool region_node(const Params &p, const RegionMap &rm
         // from the centre (sqrt 3): r_e + 5.15 < ceil(r_e) + 6 = half + 2
         const int ax = lx - B.half, ay = ly - B.half, az = lz - B.half, rr = B.half + 2;
         if (ax * ax + ay * ay + az * az > rr * rr) return false;
+        // and within rad of the centroid itself
+        const double ex = (double)(B.lo[0] + lx) - B.X[0], ey = (double)(B.lo[1] + ly) - B.X[1],
+                     ez = (double)(B.lo[2] + lz) - B.X[2];
+        if (ex * ex + ey * ey + ez * ez > rad * rad) return false;
     }
     int c[3] = {B.lo[0] + lx, B.lo[1] + ly, B.lo[2] + lz};
     const int L[3] = {p.nx, p.ny, p.nz};
@@ -991,11 +1045,14 @@ __device__ __forceinline__ bool region_node(const Params &p, const RegionMap &rm
 __device__ __forceinline__ void mark_body(const Params &p, const RegionMap &rm, const DevParticle *P,
                                           int32_t *own_new, const int bid) {
     __shared__ CPs cps;
-    stage_cps(cps, P[rm.part[bid]]);
+    const int bp = rm.part[bid];
+    const double rad = flag_radius(P[bp]);
+    if (tile_outside(rm, P[bp], bp, rm.first[bid], rad)) return;  // the whole block
+    stage_cps(cps, P[bp]);
     __syncthreads();
     int pi, x, y, z;
     long long n;
-    if (!region_node(p, rm, P, bid, pi, x, y, z, n)) return;
+    if (!region_node(p, rm, P, bid, rad, pi, x, y, z, n)) return;
     const double xp[3] = {(double)x, (double)y, (double)z};
     if (metaball(p, cps, xp) >= 1.0) atomicMin(&own_new[n], pi);
 }
@@ -1101,11 +1158,15 @@ __device__ void special_update(const Params &p, const typename Store<S>::T *__re
 // solid nodes by the lowest body index among those neighbours (old and new
 // flags), whose region always contains it; a plain fluid node (no solid
 // node around) only gets skip = 0, which any region may write.
-//   - nodes fluid after the step that were solid before (uncovered: refill)
-//     or had an in-domain solid neighbour before (cut links: bounce-back)
-//     are updated right here with do_special (special_update), else listed
-//     for the in-place refill;
-//   - per-body counts of solid, uncovered and special nodes and of cut links;
+//   - with do_special (a step), nodes fluid after the step that were solid
+//     before (uncovered: refill) or had an in-domain solid neighbour before
+//     (cut links: bounce-back) are updated right here (special_update);
+//     without (a re-flag), k_uncovered lists the uncovered nodes for the
+//     in-place refill over the whole domain;
+//   - per-body counts of solid, uncovered and special nodes and of cut links
+//     (a re-flag: solid and boundary nodes; k_uncovered adds the rest);
+//   - only nodes within the body's classification ball (class_radius) are
+//     visited;
 //   - skip mask of the NEXT step's stream-collide: solid after, or with an
 //     in-domain solid neighbour after (those nodes are left to the links and
 //     special passes);
@@ -1126,6 +1187,11 @@ __device__ __forceinline__ void classify_body(const Params &p, const RegionMap &
     constexpr int HX = TILE_X + 2, HY = TILE_Y + 2, HN = HX * HY * (TILE_Z + 2);
     constexpr int32_t OUTSIDE = -2;
     __shared__ int32_t h_old[HN], h_new[HN];
+    const double rad = class_radius(P[rm.part[bid]]);
+    if (tile_outside(rm, P[rm.part[bid]], rm.part[bid], rm.first[bid], rad)) {  // the whole block
+        if (blk_cnt && threadIdx.x == 0) blk_cnt[bid] = 0;
+        return;
+    }
     {
         const int bp = rm.part[bid];
         const int dx = rm.dims[3 * bp], dy = rm.dims[3 * bp + 1];
@@ -1149,7 +1215,7 @@ __device__ __forceinline__ void classify_body(const Params &p, const RegionMap &
     __syncthreads();
     int pi, x, y, z;
     long long n;
-    const bool in = region_node(p, rm, P, bid, pi, x, y, z, n);
+    const bool in = region_node(p, rm, P, bid, rad, pi, x, y, z, n);
     uint32_t m = 0u, wall = 0u, solid = 0u;
     // owners before / after, lowest owner among the neighbours before / after
     int32_t oo = FLUID, on = FLUID, mo = FLUID, mn = FLUID;
@@ -1183,15 +1249,11 @@ __device__ __forceinline__ void classify_body(const Params &p, const RegionMap &
         const bool lo = !so && nb_old;
         const bool spec = !sn && (so || lo);
         c_solid = sn;
-        c_refill = !sn && so;
-        c_spec = spec;
-        if (!do_special) {  // the list is for the in-place refill that follows a re-flag
-            const int k = wave_append(&cnt->n_special, spec);
-            if (k >= 0) {
-                if (k < p.special_cap) special[k] = (uint32_t)n;
-                else atomicOr(&cnt->err, ERR_SPECIAL_OVERFLOW);
-            }
-        }
+        // a re-flag (no boundary update) lists and counts its uncovered nodes
+        // over the whole domain instead (k_uncovered): a body moved from
+        // outside may leave them outside its new region
+        c_refill = !sn && so && do_special;
+        c_spec = do_special ? spec : lo && !sn;
         if (spec && do_special) {
             if (so && (oo < 0 || oo >= p.np)) atomicOr(&cnt->err, ERR_BAD_INDEX);  // never expected
             else special_update<S>(p, A, B, P, x, y, z, n, wall, solid, oo);
@@ -1226,6 +1288,31 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
                                                          typename Store<S>::T *B, int do_special) {
     classify_body<S>(p, rm, P, own_old, own_new, skip_next, special, cnt, blk_cnt, lmask, body_stats, A, B,
                      do_special, blockIdx.x);
+}
+
+// Nodes uncovered by a re-flag (solid before, fluid after) anywhere in the
+// domain: listed for the in-place refill and counted per body (uncovered and
+// special).  The trip count is block-uniform, so a wave's lanes append
+// together.
+__global__ __launch_bounds__(256) void k_uncovered(Params p, const int32_t *__restrict__ own_old,
+                                                   const int32_t *__restrict__ own_new, uint32_t *special,
+                                                   Counters *cnt, int *body_stats) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long n0 = (long long)blockIdx.x * blockDim.x; n0 < p.N; n0 += stride) {
+        const long long n = n0 + threadIdx.x;
+        const int32_t oo = n < p.N ? own_old[n] : FLUID;
+        const bool unc = n < p.N && oo != FLUID && own_new[n] == FLUID;
+        const int k = wave_append(&cnt->n_special, unc);
+        if (k < 0) continue;
+        if (oo < 0 || oo >= p.np) {  // never expected: report, list nothing
+            atomicOr(&cnt->err, ERR_BAD_INDEX);
+            continue;
+        }
+        if (k < p.special_cap) special[k] = (uint32_t)n;
+        else atomicOr(&cnt->err, ERR_SPECIAL_OVERFLOW);
+        atomicAdd(body_stats + 4 * oo + 2, 1);
+        atomicAdd(body_stats + 4 * oo + 3, 1);
+    }
 }
 
 // Plain fluid node (skip mask clear: fluid with no solid neighbour at the
@@ -1453,6 +1540,11 @@ __device__ __forceinline__ void emit_body(const Params &p, const RegionMap &rm, 
     __shared__ int sh[BLK];
     const int t = threadIdx.x;
     const int pid = rm.part[bid];
+    const double rad = class_radius(P[pid]);
+    // a block with no node in the ball lists nothing (its classification
+    // counted none); the first block of a body and the last block still
+    // record the offsets
+    if (tile_outside(rm, P[pid], pid, rm.first[bid], rad) && part_first_blk[pid] != bid && bid != nblk - 1) return;
     int before = 0;
     for (int q = t; q < pid; q += BLK) before += body_stats[4 * q];
     for (int b = part_first_blk[pid] + t; b < bid; b += BLK) before += blk_cnt[b];
@@ -1469,7 +1561,7 @@ __device__ __forceinline__ void emit_body(const Params &p, const RegionMap &rm, 
     }
     int pi, x, y, z;
     long long n;
-    const bool in = region_node(p, rm, P, bid, pi, x, y, z, n);
+    const bool in = region_node(p, rm, P, bid, rad, pi, x, y, z, n);
     const uint32_t m = in ? lmask[bid * BLK + t] : 0u;
     if (in && clear) clear[n] = FLUID;
     const int c = __popc(m);
@@ -1814,8 +1906,12 @@ void launch_case_batch(int storage, BatchOp op, const CaseArgs *cs, const int *m
 }
 
 void launch_reset_counters(Counters *cnt, hipStream_t s) { k_reset_counters<<<1, 1, 0, s>>>(cnt); }
-void launch_refresh_pose(const Params &p, DevParticle *P, hipStream_t s) {
-    if (p.np > 0) k_refresh_pose<<<cdiv(p.np, 64), 64, 0, s>>>(p, P);
+void launch_uncovered(const Params &p, const int32_t *own_old, const int32_t *own_new, uint32_t *special,
+                      Counters *cnt, int *body_stats, hipStream_t s) {
+    if (p.np > 0) k_uncovered<<<2048, 256, 0, s>>>(p, own_old, own_new, special, cnt, body_stats);
+}
+void launch_refresh_pose(const Params &p, DevParticle *P, int fresh, hipStream_t s) {
+    if (p.np > 0) k_refresh_pose<<<cdiv(p.np, 64), 64, 0, s>>>(p, P, fresh);
 }
 
 }  // namespace mdl

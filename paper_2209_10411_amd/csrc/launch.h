@@ -50,10 +50,15 @@ void launch_phase(const StepArgs &a);
 void launch_fill_i32(int32_t *a, long long n, int32_t v, hipStream_t s);
 void launch_fill_u8(uint8_t *a, long long n, uint8_t v, hipStream_t s);
 void launch_reset_counters(Counters *cnt, hipStream_t s);
+// Re-flag: every node solid in own_old and fluid in own_new, listed for the
+// in-place refill and counted per body.
+void launch_uncovered(const Params &p, const int32_t *own_old, const int32_t *own_new, uint32_t *special,
+                      Counters *cnt, int *body_stats, hipStream_t s);
 // Batched stream-collide of an ensemble (bw: waves per block, 4 or 8).
 void launch_bulk_batch(int storage, int bw, const BulkCase *cases, const int *blk_case, int nblocks, int parity,
                        hipStream_t s);
-void launch_refresh_pose(const Params &p, DevParticle *P, hipStream_t s);
+// fresh: the flag buffers hold flags of the current pose only (after a re-flag)
+void launch_refresh_pose(const Params &p, DevParticle *P, int fresh, hipStream_t s);
 
 // Batched boundary kernels of an ensemble: one launch of a kind for every
 // system (cs: the systems' argument blocks, map: block -> system).

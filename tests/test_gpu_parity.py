@@ -115,6 +115,10 @@ def test_settling_body_with_refill(mdl, bc):
             ref.step(1)
             refilled += ref.n_refilled
         compare_fields(sim, ref, label=f"settle bc={bc} step {10 * (k + 1)}")
+        # same links; q follows the pose, which differs from the oracle's by
+        # ~1e-7 (FP32 fluid), more on grazing links
+        dq = compare_links(sim, ref)
+        assert np.median(dq) < 1e-7 and dq.max() < 1e-4
         pg, po = sim.particles()[0], ref.particle(0)
         assert np.abs(pg["x"] - po["x"]).max() < 1e-6
         assert np.abs(pg["v"] - po["v"]).max() < 1e-6 * max(1.0, np.abs(po["v"]).max())
@@ -209,6 +213,42 @@ def test_fluid_only_then_flag_and_refill(mdl):
     assert n_ref == int(((own0 >= 0) & (own1 < 0)).sum()) and n_ref > 0
 
 
+@pytest.mark.parametrize("move", [(0.6, -0.4, -0.9), (2.6, -1.7, 3.2), (-4.0, 3.0, -12.25)])
+def test_moved_body_keeps_matching_flags_links_and_fields(mdl, move):
+    """A settling body moved from outside (set_particles, metaball_flag,
+    refill) by about a node, by several nodes and by more than its size, then
+    stepped on from the oracle's state (the oracle's re-flag refills nothing,
+    so both continue from its populations): the flags of every later step,
+    the links and the fields match the oracle's -- the region work follows
+    the moved body and nothing of the old pose is left behind."""
+    cfg = workloads.small_settling(n=32, nz=56, R=5.0, g=5e-4)
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    sim.step(8)
+    ref.step(8)
+    assert np.array_equal(sim.owner(), ref.owner())
+    st = sim.particles()
+    p = ref.particle(0)
+    st[0]["x"] = p["x"] + np.array(move)
+    st[0]["v"], st[0]["omega"], st[0]["quat"] = p["v"], p["omega"], p["quat"]
+    sim.set_particles(st)
+    sim.metaball_flag()
+    own0 = ref.owner()
+    ref.set_particle_state(0, st[0]["x"], p["quat"], p["v"], p["omega"])
+    ref.reflag()
+    own1 = sim.owner()
+    assert np.array_equal(own1, ref.owner())
+    assert sim.refill() == int(((own0 >= 0) & (own1 < 0)).sum())
+    sim.set_populations(ref.f(), post_collision=False)
+    for k in range(4):
+        sim.step(3)
+        ref.step(3)
+        compare_fields(sim, ref, label=f"{3 * (k + 1)} steps after a move by {move}")
+    dq = compare_links(sim, ref)
+    assert np.median(dq) < 1e-7 and dq.max() < 1e-4
+    assert np.abs(sim.particles()[0]["x"] - ref.particle(0)["x"]).max() < 1e-6
+
+
 def test_run_twice_bitwise_identical(mdl):
     cfg = workloads.small_settling(n=24, nz=40, R=4.0, g=5e-4)
     out = []
@@ -297,6 +337,8 @@ def test_periodic_suspension_small(mdl):
         sim.step(20)
         ref.step(20)
         compare_fields(sim, ref, label=f"suspension step {20 * (k + 1)}")
+        dq = compare_links(sim, ref)
+        assert np.median(dq) < 1e-7 and dq.max() < 1e-4
         _compare_particles(sim, ref, cfg, 1e-6, 1e-7)
 
 
