@@ -51,6 +51,7 @@ struct DevParticle {
     double reach;
     double Xf[2][3];
     int hist;
+    int img;  // 0: no periodic image shifts any point evaluated near this body (see refresh_pose)
 };
 
 // Small device-side counters, reset and read by the host at sync points.

@@ -125,7 +125,8 @@ __device__ __forceinline__ void min_image(const Params &p, double d[3]) {
 struct CPs {
     double x[MAXCP + 3][3];
     double k[MAXCP + 3];
-    int n;  // padded count
+    int n;    // padded count
+    int img;  // the body's img: 0 = the minimum image is the identity here
 };
 
 __device__ void stage_cps(CPs &c, const DevParticle &P) {
@@ -136,7 +137,10 @@ __device__ void stage_cps(CPs &c, const DevParticle &P) {
         if (a < 3) c.x[i][a] = P.cpl[src][a];
         else c.k[i] = i < P.n_cp ? P.k[i] : 0.0;
     }
-    if (threadIdx.x == 0) c.n = n4;
+    if (threadIdx.x == 0) {
+        c.n = n4;
+        c.img = P.img;
+    }
 }
 
 // Metaball function (Eq. metaballM) at a lab point, minimum image on
@@ -152,7 +156,7 @@ __device__ double metaball(const Params &p, const CPs &P, const double x[3]) {
         for (int u = 0; u < 4; ++u) {
             const int i = i0 + u;
             double d[3] = {x[0] - P.x[i][0], x[1] - P.x[i][1], x[2] - P.x[i][2]};
-            min_image(p, d);
+            if (P.img) min_image(p, d);
             const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             hit |= r2 == 0.0;
             term[u] = P.k[i] / r2;
@@ -176,7 +180,7 @@ __device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], 
     double c = 0.0, g = 0.0;
     for (int i = threadIdx.x & 7; i < P.n; i += 8) {
         double d[3] = {xs[0] - P.x[i][0], xs[1] - P.x[i][1], xs[2] - P.x[i][2]};
-        min_image(p, d);
+        if (P.img) min_image(p, d);
         const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         if (r2 == 0.0) {
             c = __builtin_inf();
@@ -479,7 +483,12 @@ __device__ void quat_of_rotvec(const double phi[3], double o[4]) {
     o[0] = cos(0.5 * a); o[1] = s * phi[0]; o[2] = s * phi[1]; o[3] = s * phi[2];
 }
 
-// Lab-frame control points and the region origin of the current pose.
+// Lab-frame control points and the region origin of the current pose, and
+// whether the minimum image can shift anything here: the metaball is
+// evaluated at points within half + 2 + sqrt 3 (+1 along a link) of X, the
+// control points lie within rb of X; when on every periodic axis those points
+// do not wrap and |x - cp| stays 1 below L/2, floor(d / L + 0.5) is 0 for every
+// difference and the image is the identity (img = 0).
 __device__ void refresh_pose(const Params &p, DevParticle &P) {
     double R[9];
     quat_rot(P.q, R);
@@ -487,6 +496,13 @@ __device__ void refresh_pose(const Params &p, DevParticle &P) {
         for (int a = 0; a < 3; ++a)
             P.cpl[i][a] = P.X[a] + R[3 * a] * P.cpb[i][0] + R[3 * a + 1] * P.cpb[i][1] + R[3 * a + 2] * P.cpb[i][2];
     for (int a = 0; a < 3; ++a) P.lo[a] = P.full[a] ? 0 : (int)floor(P.X[a]) - P.half;
+    const double reach = P.half + 2.0 + 1.7320508075688772 + 1.0;
+    const double L[3] = {(double)p.nx, (double)p.ny, (double)p.nz};
+    int img = 0;
+    for (int a = 0; a < 3; ++a)
+        if ((p.periodic >> a) & 1u)
+            if (!(P.X[a] - reach >= 0.0 && P.X[a] + reach <= L[a] - 1.0 && reach + P.rb <= 0.5 * L[a] - 1.0)) img = 1;
+    P.img = img;
 }
 
 // One block per particle: fixed-order FP64 sum of the link momenta (chunk
@@ -1652,7 +1668,10 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
                 if (a < 3) cps[g].x[k][a] = B.cpl[src][a];
                 else cps[g].k[k] = k < B.n_cp ? B.k[k] : 0.0;
             }
-            if (j == 0) cps[g].n = n4;
+            if (j == 0) {
+                cps[g].n = n4;
+                cps[g].img = B.img;
+            }
             node_xyz(p, n, x, y, z);
             if (warm) {
                 if (j == 0) {
