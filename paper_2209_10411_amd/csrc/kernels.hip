@@ -170,6 +170,51 @@ __device__ double metaball(const Params &p, const CPs &P, const double x[3]) {
     return C;
 }
 
+// Reciprocal of x > 0: the hardware estimate and two Newton steps (a few
+// ulps; the exact quotient costs about twice the instructions).
+__device__ __forceinline__ double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(e, r, r);
+    e = fma(-x, r, 1.0);
+    return fma(e, r, r);
+}
+
+// C(x) with refined reciprocals in place of the quotients: each term within
+// a few ulps, so the sum of at most 23 terms within 1e-14 C of metaball's.
+__device__ double metaball_fast(const Params &p, const CPs &P, const double x[3]) {
+#pragma clang fp contract(off)
+    double C = 0.0;
+    for (int i0 = 0; i0 < P.n; i0 += 4) {
+        double term[4];
+        bool hit = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u;
+            double d[3] = {x[0] - P.x[i][0], x[1] - P.x[i][1], x[2] - P.x[i][2]};
+            if (P.img) min_image(p, d);
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            hit |= r2 == 0.0;
+            term[u] = P.k[i] * rcp_refined(r2);
+        }
+        if (hit) return __builtin_inf();
+        C += term[0];
+        C += term[1];
+        C += term[2];
+        C += term[3];
+    }
+    return C;
+}
+
+// Whether C(x) >= 1 exactly as metaball decides it (exact quotients summed
+// in index order): the fast sum decides unless it lies within 1e-12 of 1,
+// where metaball is evaluated.  Cf: the fast value.
+__device__ __forceinline__ bool metaball_ge1(const Params &p, const CPs &P, const double x[3], double &Cf) {
+    Cf = metaball_fast(p, P, x);
+    if (fabs(Cf - 1.0) > 1e-12) return Cf >= 1.0;
+    return metaball(p, P, x) >= 1.0;
+}
+
 // C and dC/ds at x_f - s e_i for one link held by an aligned group of eight
 // lanes: lane j sums control points j, j + 8, ... and the group adds its
 // partial sums by a butterfly, which leaves the same bits in every lane.
@@ -186,7 +231,7 @@ __device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], 
             c = __builtin_inf();
             continue;
         }
-        const double inv = 1.0 / r2;
+        const double inv = rcp_refined(r2);
         const double kr = P.k[i] * inv;
         c += kr;
         g += 2.0 * kr * inv * (d[0] * e[0] + d[1] * e[1] + d[2] * e[2]);
@@ -202,8 +247,8 @@ __device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], 
 
 // Link fraction q (sec. 2.3.2): the first root of C(x_f - s e_i) = 1 on
 // (0,1], for one link by an aligned group of eight lanes (all active).
-// Bracket: lane j evaluates C at s = (j + 1)/8 with the flagging's
-// arithmetic, and the first of the eight sub-interval ends with C >= 1 closes
+// Bracket: lane j decides C >= 1 at s = (j + 1)/8 exactly as the flagging
+// does (metaball_ge1), and the first of the eight sub-interval ends with C >= 1 closes
 // the bracket (none: q = 1).  Then a safeguarded Newton iteration
 // (rtsafe-style: a Newton step that leaves the bracket or does not halve the
 // step falls back to bisection) to |step| < 1e-13 or |C - 1| < 1e-15,
@@ -219,8 +264,9 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
     const int e[3] = {EX[i], EY[i], EZ[i]};
     const double sj = (double)(j + 1) / 8.0;
     const double xj[3] = {xf[0] - sj * e[0], xf[1] - sj * e[1], xf[2] - sj * e[2]};
-    const double Cj = metaball(p, P, xj);
-    const unsigned grp = (unsigned)((__ballot(Cj >= 1.0) >> base) & 0xffull);
+    double Cj;
+    const bool inj = metaball_ge1(p, P, xj, Cj);
+    const unsigned grp = (unsigned)((__ballot(inj) >> base) & 0xffull);
     const int k0 = grp ? __ffs(grp) - 1 : 7;
     const double Chi = __shfl(Cj, base + k0), Clo = __shfl(Cj, base + (k0 > 0 ? k0 - 1 : 0));
     resid = 0.0;
@@ -1070,7 +1116,8 @@ __device__ __forceinline__ void mark_body(const Params &p, const RegionMap &rm, 
     long long n;
     if (!region_node(p, rm, P, bid, rad, pi, x, y, z, n)) return;
     const double xp[3] = {(double)x, (double)y, (double)z};
-    if (metaball(p, cps, xp) >= 1.0) atomicMin(&own_new[n], pi);
+    double Cf;
+    if (metaball_ge1(p, cps, xp, Cf)) atomicMin(&own_new[n], pi);
 }
 
 __global__ __launch_bounds__(BLK) void k_region_mark(Params p, RegionMap rm, const DevParticle *P,
