@@ -1125,31 +1125,36 @@ __global__ __launch_bounds__(BLK) void k_region_mark(Params p, RegionMap rm, con
     mark_body(p, rm, P, own_new, blockIdx.x);
 }
 
+// Integer sum over the 64 lanes of a wave (every lane gets it).
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Block-wide integer sum (all BLK = 4 waves): wave sums, then the four
+// totals through LDS (one barrier).  sh may be reused after a barrier.
+static_assert(BLK == 256, "block reductions assume four waves");
 __device__ __forceinline__ int block_sum(int v, int *sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
+    v = wave_isum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int h = BLK / 2; h > 0; h >>= 1) {
-        if (t < h) sh[t] += sh[t + h];
-        __syncthreads();
-    }
-    return sh[0];
+    return sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // Three block-wide sums at once (all BLK threads; sh3 LDS scratch).
 __device__ __forceinline__ void block_sum3(int &a, int &b, int &c, int (*sh3)[BLK]) {
-    const int t = threadIdx.x;
-    sh3[0][t] = a; sh3[1][t] = b; sh3[2][t] = c;
-    __syncthreads();
-    for (int h = BLK / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            sh3[0][t] += sh3[0][t + h];
-            sh3[1][t] += sh3[1][t + h];
-            sh3[2][t] += sh3[2][t + h];
-        }
-        __syncthreads();
+    a = wave_isum(a);
+    b = wave_isum(b);
+    c = wave_isum(c);
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        sh3[0][w] = a; sh3[1][w] = b; sh3[2][w] = c;
     }
-    a = sh3[0][0]; b = sh3[1][0]; c = sh3[2][0];
+    __syncthreads();
+    a = sh3[0][0] + sh3[0][1] + sh3[0][2] + sh3[0][3];
+    b = sh3[1][0] + sh3[1][1] + sh3[1][2] + sh3[1][3];
+    c = sh3[2][0] + sh3[2][1] + sh3[2][2] + sh3[2][3];
 }
 
 // Boundary or uncovered node n = (x, y, z), one thread: pull the 19
@@ -1627,16 +1632,20 @@ __device__ __forceinline__ void emit_body(const Params &p, const RegionMap &rm, 
     const bool in = region_node(p, rm, P, bid, rad, pi, x, y, z, n);
     const uint32_t m = in ? lmask[bid * BLK + t] : 0u;
     if (in && clear) clear[n] = FLUID;
-    const int c = __popc(m);
-    sh[t] = c;
-    __syncthreads();
-    for (int h = 1; h < BLK; h <<= 1) {
-        const int v = t >= h ? sh[t - h] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
+    // exclusive prefix of the link counts over the block: inclusive scan
+    // within the wave, plus the totals of the earlier waves
+    const int c = __popc(m), lane = t & 63, w = t >> 6;
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
     }
-    int o = base + sh[t] - c;
+    if (lane == 63) sh[w] = incl;
+    __syncthreads();
+    int wbase = 0;
+    for (int k = 0; k < w; ++k) wbase += sh[k];
+    int o = base + wbase + incl - c;
     for (int i = 1; i < Q; ++i)
         if ((m >> i) & 1u) {
             if (o < p.link_cap) {
