@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-KERNEL_SRC = os.path.join(ROOT, "paper_2209_10411_amd", "csrc", "kernels.hip")
+# the stream-collide kernel's source: its code and the data layout it reads
+KERNEL_SRC = [os.path.join(ROOT, "paper_2209_10411_amd", "csrc", f) for f in ("stream_collide.h", "device.h")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_bulk_settling_128x128x384_pmc.txt")
 
 
@@ -190,12 +191,19 @@ def run_mlp_warmstart(steps, epochs):
             "plain": res["plain"], "mlp": res["mlp"]}
 
 
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profile():
     """FETCH/WRITE bytes per launch of the stream-collide kernel from the
     committed rocprofv3 --pmc summary, if it was taken on this kernel source."""
     if not os.path.exists(PMC_SUMMARY):
         return None
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_sha()
     vals = {}
     for line in open(PMC_SUMMARY):
         if "=" in line and not line.startswith("#"):
