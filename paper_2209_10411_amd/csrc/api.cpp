@@ -187,7 +187,7 @@ struct Plan {
         off_cnt, total;
     bool contact;
     size_t off_lmask, off_nrs, off_mlpb;
-    size_t off_pairF, off_pairTi, off_pairTj, off_wallF, off_wallT, off_xiP, off_xiW;
+    size_t off_pairF, off_pairTi, off_pairTj, off_wallF, off_wallT, off_xiP, off_xiW, off_pairOn;
 };
 
 struct HostParticle {
@@ -340,6 +340,7 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_wallT = take(24 * npw);
     pl.off_xiP = take(24 * npp);
     pl.off_xiW = take(24 * npw);
+    pl.off_pairOn = take(npp);
     pl.off_cnt = take(sizeof(Counters));
     pl.off_nrs = take(4 * (size_t)NR_BLOCKS * NR_HIST + 16 * (size_t)NR_BLOCKS + 4 * (size_t)NR_BLOCKS);
     pl.off_mlpb = take(4 * (size_t)MLP_BODY * std::max(np, 1));
@@ -634,6 +635,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->cb.pairTj = (double *)(b + pl.off_pairTj); c->cb.wallF = (double *)(b + pl.off_wallF);
     c->cb.wallT = (double *)(b + pl.off_wallT); c->cb.xiP = (double *)(b + pl.off_xiP);
     c->cb.xiW = (double *)(b + pl.off_xiW);
+    c->cb.pairOn = (uint8_t *)(b + pl.off_pairOn);
     c->aux = nullptr;
     c->ev_main = c->ev_flags = c->ev_links = c->ev_bulk = nullptr;
     c->timing = false;

@@ -115,6 +115,7 @@ struct ContactBufs {
     double *wallT;   // [np*6][3]
     double *xiP;     // [np*np][3] tangential springs, pairs
     double *xiW;     // [np*6][3] tangential springs, walls
+    uint8_t *pairOn; // [np*np] 1 where the pair is in contact this sub-step (both (i,j) and (j,i))
 };
 
 constexpr int TW_FLAT = 7;
@@ -174,8 +175,8 @@ struct CaseArgs {
     int first[BK_N], nblk[BK_N];
 };
 // the host writes these tables for the device: one layout on both sides
-static_assert(sizeof(Params) == 240 && sizeof(CaseArgs) == 552 && offsetof(CaseArgs, nrs) == 464 &&
-                  offsetof(CaseArgs, first) == 508,
+static_assert(sizeof(Params) == 240 && sizeof(CaseArgs) == 560 && offsetof(CaseArgs, nrs) == 472 &&
+                  offsetof(CaseArgs, first) == 516,
               "CaseArgs layout");
 
 }  // namespace mdl

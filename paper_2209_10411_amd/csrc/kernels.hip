@@ -581,36 +581,55 @@ __device__ bool inv3d(const double A[9], double B[9]) {
 
 // Zoomed internal metaball of the sphero-metaball: the body shrunk about its
 // centroid by s = 1 - R_s / sqrt(sum k) (points X + s (p - X), weights
-// s^2 k), translated by 'shift' (periodic image).
-__device__ int inner_metaball(const Params &p, const DevParticle &P, const double shift[3],
-                              double cp[MAXCP][3], double k[MAXCP]) {
+// s^2 k), translated by 'shift' (periodic image).  Its points are formed
+// from the body record where they are used (no per-thread copies, which
+// would live in scratch memory).
+struct InnerMB {
+    const DevParticle *P;
+    double s, s2;
+    double shift[3];
+    int n;
+};
+
+__device__ int inner_metaball(const Params &p, const DevParticle &P, const double shift[3], InnerMB &m) {
     double sk = 0.0;
     for (int i = 0; i < P.n_cp; ++i) sk += P.k[i];
     const double s = 1.0 - p.c_rs / sqrt(sk);
     if (!(s > 0.0)) return -1;
-    for (int i = 0; i < P.n_cp; ++i) {
-        for (int a = 0; a < 3; ++a) cp[i][a] = P.X[a] + shift[a] + s * (P.cpl[i][a] - P.X[a]);
-        k[i] = s * s * P.k[i];
-    }
+    m.P = &P;
+    m.s = s;
+    m.s2 = s * s;
+    for (int a = 0; a < 3; ++a) m.shift[a] = shift[a];
+    m.n = P.n_cp;
     return P.n_cp;
 }
 
-// f = sum k/r^2, gradient sum -2k d/r^4, Hessian sum 2k (4 d d^T/r^6 - I/r^4).
-__device__ void mb_eval3(int n, const double cp[MAXCP][3], const double k[MAXCP], const double x[3],
-                         double &f, double g[3], double H[9]) {
-    f = 0.0;
-    for (int a = 0; a < 3; ++a) g[a] = 0.0;
-    for (int a = 0; a < 9; ++a) H[a] = 0.0;
-    for (int i = 0; i < n; ++i) {
-        const double d[3] = {x[0] - cp[i][0], x[1] - cp[i][1], x[2] - cp[i][2]};
-        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        const double r4 = r2 * r2, r6 = r4 * r2;
-        f += k[i] / r2;
-        for (int a = 0; a < 3; ++a) {
-            g[a] += -2.0 * k[i] * d[a] / r4;
-            for (int b = 0; b < 3; ++b) H[3 * a + b] += 2.0 * k[i] * (4.0 * d[a] * d[b] / r6 - (a == b ? 1.0 : 0.0) / r4);
-        }
+__device__ __forceinline__ double inner_cp(const InnerMB &m, int i, int a) {
+    return m.P->X[a] + m.shift[a] + m.s * (m.P->cpl[i][a] - m.P->X[a]);
+}
+__device__ __forceinline__ double inner_k(const InnerMB &m, int i) { return m.s2 * m.P->k[i]; }
+
+// f = sum k/r^2, gradient sum -2k d/r^4, Hessian sum 2k (4 d d^T/r^6 - I/r^4),
+// from one reciprocal of r^2 per point (the powers and products follow; the
+// Hessian's upper triangle is mirrored).
+__device__ void mb_eval3(const InnerMB &m, const double x[3], double &f, double g[3], double H[9]) {
+    double f_ = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0, h00 = 0.0, h01 = 0.0, h02 = 0.0, h11 = 0.0, h12 = 0.0, h22 = 0.0;
+    for (int i = 0; i < m.n; ++i) {
+        const double ki = inner_k(m, i);
+        const double d0 = x[0] - inner_cp(m, i, 0), d1 = x[1] - inner_cp(m, i, 1), d2 = x[2] - inner_cp(m, i, 2);
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        const double i2 = 1.0 / r2, i4 = i2 * i2;
+        const double c1 = -2.0 * ki * i4, c2 = 8.0 * ki * i4 * i2;
+        f_ += ki * i2;
+        g0 += c1 * d0; g1 += c1 * d1; g2 += c1 * d2;
+        h00 += c2 * d0 * d0 + c1; h01 += c2 * d0 * d1; h02 += c2 * d0 * d2;
+        h11 += c2 * d1 * d1 + c1; h12 += c2 * d1 * d2; h22 += c2 * d2 * d2 + c1;
     }
+    f = f_;
+    g[0] = g0; g[1] = g1; g[2] = g2;
+    H[0] = h00; H[1] = h01; H[2] = h02;
+    H[3] = h01; H[4] = h11; H[5] = h12;
+    H[6] = h02; H[7] = h12; H[8] = h22;
 }
 
 // Contact of two bodies (Eqs. CM_coreF, eq:grad, eq:cp, eq:contactprop):
@@ -626,12 +645,12 @@ __device__ int pair_geometry(const Params &p, const DevParticle &P0, const DevPa
     min_image(p, d01);
     const double sh0[3] = {0.0, 0.0, 0.0};
     const double sh1[3] = {P0.X[0] + d01[0] - P1.X[0], P0.X[1] + d01[1] - P1.X[1], P0.X[2] + d01[2] - P1.X[2]};
-    double cp0[MAXCP][3], k0[MAXCP], cp1[MAXCP][3], k1[MAXCP];
-    const int n0 = inner_metaball(p, P0, sh0, cp0, k0), n1 = inner_metaball(p, P1, sh1, cp1, k1);
+    InnerMB m0, m1;
+    const int n0 = inner_metaball(p, P0, sh0, m0), n1 = inner_metaball(p, P1, sh1, m1);
     if (n0 < 0 || n1 < 0) return -1;
     double K0 = 0.0, K1 = 0.0;
-    for (int i = 0; i < n0; ++i) K0 += k0[i];
-    for (int i = 0; i < n1; ++i) K1 += k1[i];
+    for (int i = 0; i < n0; ++i) K0 += inner_k(m0, i);
+    for (int i = 0; i < n1; ++i) K1 += inner_k(m1, i);
     const double rho = cbrt(K0 / K1);
     double xm[3];
     for (int a = 0; a < 3; ++a) xm[a] = P0.X[a] + d01[a] * rho / (1.0 + rho);
@@ -639,8 +658,8 @@ __device__ int pair_geometry(const Params &p, const DevParticle &P0, const DevPa
     bool ok = false;
     for (int it = 0; it < 60; ++it) {
         double f0, g0[3], H0[9], f1, g1[3], H1[9], H[9], Hi[9], dx[3];
-        mb_eval3(n0, cp0, k0, xm, f0, g0, H0);
-        mb_eval3(n1, cp1, k1, xm, f1, g1, H1);
+        mb_eval3(m0, xm, f0, g0, H0);
+        mb_eval3(m1, xm, f1, g1, H1);
         for (int a = 0; a < 9; ++a) H[a] = H0[a] + H1[a];
         if (!inv3d(H, Hi)) break;
         double st = 0.0;
@@ -656,8 +675,8 @@ __device__ int pair_geometry(const Params &p, const DevParticle &P0, const DevPa
     }
     if (!ok) return -1;
     double f0, g0[3], H0[9], f1, g1[3], H1[9];
-    mb_eval3(n0, cp0, k0, xm, f0, g0, H0);
-    mb_eval3(n1, cp1, k1, xm, f1, g1, H1);
+    mb_eval3(m0, xm, f0, g0, H0);
+    mb_eval3(m1, xm, f1, g1, H1);
     const double G0 = sqrt(g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2]);
     const double G1 = sqrt(g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
     if (!(G0 > 0.0 && G1 > 0.0)) return -1;
@@ -685,17 +704,17 @@ __device__ int wall_geometry(const Params &p, const DevParticle &P, int ax, int 
     const double wpos = side ? L - 0.5 : -0.5;
     if (fabs(P.X[ax] - wpos) > P.rb + p.c_rs) return 0;
     const double sh[3] = {0.0, 0.0, 0.0};
-    double cp[MAXCP][3], k[MAXCP];
-    const int n = inner_metaball(p, P, sh, cp, k);
+    InnerMB m;
+    const int n = inner_metaball(p, P, sh, m);
     if (n < 0) return -1;
     const int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
     // start at the projection of the control point where f on the plane is largest
     double xcw[3] = {P.X[0], P.X[1], P.X[2]};
     double best = -1.0;
     for (int i = 0; i < n; ++i) {
-        double y[3] = {cp[i][0], cp[i][1], cp[i][2]}, fy, gy[3], Hy[9];
+        double y[3] = {inner_cp(m, i, 0), inner_cp(m, i, 1), inner_cp(m, i, 2)}, fy, gy[3], Hy[9];
         y[ax] = wpos;
-        mb_eval3(n, cp, k, y, fy, gy, Hy);
+        mb_eval3(m, y, fy, gy, Hy);
         if (fy > best) {
             best = fy;
             for (int a = 0; a < 3; ++a) xcw[a] = y[a];
@@ -704,7 +723,7 @@ __device__ int wall_geometry(const Params &p, const DevParticle &P, int ax, int 
     bool ok = false;
     for (int it = 0; it < 60; ++it) {
         double f, g[3], H[9];
-        mb_eval3(n, cp, k, xcw, f, g, H);
+        mb_eval3(m, xcw, f, g, H);
         const double h11 = H[3 * a1 + a1], h12 = H[3 * a1 + a2], h22 = H[3 * a2 + a2];
         const double det = h11 * h22 - h12 * h12;
         if (!(fabs(det) > 0.0)) break;
@@ -717,7 +736,7 @@ __device__ int wall_geometry(const Params &p, const DevParticle &P, int ax, int 
     }
     if (!ok) return -1;
     double f, g[3], H[9];
-    mb_eval3(n, cp, k, xcw, f, g, H);
+    mb_eval3(m, xcw, f, g, H);
     const double G = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     if (!(G > 0.0)) return -1;
     // grad f is normal to the plane at x_cw and points into the body: signed
@@ -815,6 +834,104 @@ __device__ void body_substep(const Params &p, DevParticle &P, const double F[3],
 // (partners by index, then faces).  Finally end-of-step checks, periodic
 // wrap of the centroid and the region origin.
 constexpr int RIGID_LDS = 32;
+// Contact of body pair q = i * np + j (i < j) at the sub-step's poses:
+// force on i, torques on i and j, into the pair's slots (tangential spring
+// of the pair updated).
+__device__ __forceinline__ void contact_pair(const Params &p, const DevParticle *P, const ContactBufs &cb,
+                                             Counters *__restrict__ cnt, int q, double dt) {
+    const int np = p.np;
+    const int i = q / np, j = q - i * np;
+    if (j <= i) return;
+    double F[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, Tj[3] = {0, 0, 0};
+    double *xi = cb.xiP + 3ll * q;
+    const DevParticle &Pi = P[i], &Pj = P[j];
+    if (!(Pi.mode == 1 && Pj.mode == 1)) {
+        double d[3] = {Pj.X[0] - Pi.X[0], Pj.X[1] - Pi.X[1], Pj.X[2] - Pi.X[2]};
+        min_image(p, d);
+        int r = 0;
+        double xcp[3], n[3], delta = 0.0;
+        if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) <= Pi.rb + Pj.rb)
+            r = pair_geometry(p, Pi, Pj, xcp, n, delta);
+        if (r < 0) atomicAdd(&cnt->n_contact_fail, 1ull);
+        if (r <= 0) {
+            xi[0] = xi[1] = xi[2] = 0.0;
+        } else {
+            atomicAdd(&cnt->n_contacts, 1ull);
+            double vi[3], vj[3], ri[3], rj[3], vrel[3];
+            point_velocity(p, Pi, xcp, vi, ri);
+            point_velocity(p, Pj, xcp, vj, rj);
+            for (int a = 0; a < 3; ++a) vrel[a] = vj[a] - vi[a];
+            const double meff = Pi.mode == 1 ? Pj.m : (Pj.mode == 1 ? Pi.m : Pi.m * Pj.m / (Pi.m + Pj.m));
+            spring_dashpot(p, meff, n, delta, vrel, xi, dt, F);
+            const double Fm[3] = {-F[0], -F[1], -F[2]};
+            cross3(ri, F, Ti);
+            cross3(rj, Fm, Tj);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        cb.pairF[3ll * q + a] = F[a];
+        cb.pairTi[3ll * q + a] = Ti[a];
+        cb.pairTj[3ll * q + a] = Tj[a];
+    }
+    const uint8_t on = (F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0 || Ti[0] != 0.0 || Ti[1] != 0.0 || Ti[2] != 0.0 ||
+                        Tj[0] != 0.0 || Tj[1] != 0.0 || Tj[2] != 0.0) ? 1 : 0;
+    cb.pairOn[q] = on;
+    cb.pairOn[(long long)j * np + i] = on;
+}
+
+// Contact of body i with face w = 2 * axis + side (q = 6 i + w), into its slots.
+__device__ __forceinline__ void contact_wall(const Params &p, const DevParticle *P, const ContactBufs &cb,
+                                             Counters *__restrict__ cnt, int q, double dt) {
+    const int i = q / 6, w = q - 6 * i, ax = w >> 1, side = w & 1;
+    double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+    double *xi = cb.xiW + 3ll * q;
+    const DevParticle &Pi = P[i];
+    if (Pi.mode != 1 && !((p.periodic >> ax) & 1u)) {
+        double xcp[3], n[3], delta = 0.0;
+        const int r = wall_geometry(p, Pi, ax, side, xcp, n, delta);
+        if (r < 0) atomicAdd(&cnt->n_contact_fail, 1ull);
+        if (r <= 0) {
+            xi[0] = xi[1] = xi[2] = 0.0;
+        } else {
+            atomicAdd(&cnt->n_contacts, 1ull);
+            double vi[3], ri[3], vrel[3];
+            point_velocity(p, Pi, xcp, vi, ri);
+            for (int a = 0; a < 3; ++a) vrel[a] = -vi[a];
+            spring_dashpot(p, Pi.m, n, delta, vrel, xi, dt, F);
+            for (int a = 0; a < 3; ++a) ri[a] = xcp[a] - Pi.X[a];
+            cross3(ri, F, T);
+        }
+    }
+    for (int a = 0; a < 3; ++a) { cb.wallF[3ll * q + a] = F[a]; cb.wallT[3ll * q + a] = T[a]; }
+}
+
+// Sub-step of body q: hydrodynamic load (held) plus its contacts summed in a
+// fixed order (partners by index, then faces); partners whose pair slots hold
+// only zeros are passed over (adding them changes no bit of the sums).
+__device__ __forceinline__ void contact_body(const Params &p, DevParticle &B, int q, const ContactBufs &cb,
+                                             double dt) {
+    const int np = p.np;
+    double F[3] = {B.F[0], B.F[1], B.F[2]}, T[3] = {B.T[0], B.T[1], B.T[2]};
+    if (p.contact) {
+        double Fc[3] = {0, 0, 0}, Tc[3] = {0, 0, 0};
+        const uint8_t *on = cb.pairOn + (long long)q * np;
+        for (int j = 0; j < np; ++j) {
+            if (j == q || !on[j]) continue;
+            if (j < q) {
+                const long long k = (long long)j * np + q;
+                for (int a = 0; a < 3; ++a) { Fc[a] -= cb.pairF[3 * k + a]; Tc[a] += cb.pairTj[3 * k + a]; }
+            } else {
+                const long long k = (long long)q * np + j;
+                for (int a = 0; a < 3; ++a) { Fc[a] += cb.pairF[3 * k + a]; Tc[a] += cb.pairTi[3 * k + a]; }
+            }
+        }
+        for (int w = 0; w < 6; ++w)
+            for (int a = 0; a < 3; ++a) { Fc[a] += cb.wallF[3ll * (6 * q + w) + a]; Tc[a] += cb.wallT[3ll * (6 * q + w) + a]; }
+        for (int a = 0; a < 3; ++a) { F[a] += Fc[a]; T[a] += Tc[a]; }
+    }
+    body_substep(p, B, F, T, dt);
+}
+
 __device__ __forceinline__ void rigid_case(const Params &p, DevParticle *__restrict__ Pg, const ContactBufs &cb,
                                            Counters *__restrict__ cnt) {
     __shared__ DevParticle sP[RIGID_LDS];
@@ -831,93 +948,40 @@ __device__ __forceinline__ void rigid_case(const Params &p, DevParticle *__restr
     const double dt = 1.0 / p.n_sub;
     for (int s = 0; s < p.n_sub; ++s) {
         if (p.contact) {
-            for (int q = t; q < np * np; q += 256) {
-                const int i = q / np, j = q - i * np;
-                if (j <= i) continue;
-                double F[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, Tj[3] = {0, 0, 0};
-                double *xi = cb.xiP + 3ll * q;
-                const DevParticle &Pi = P[i], &Pj = P[j];
-                if (!(Pi.mode == 1 && Pj.mode == 1)) {
-                    double d[3] = {Pj.X[0] - Pi.X[0], Pj.X[1] - Pi.X[1], Pj.X[2] - Pi.X[2]};
-                    min_image(p, d);
-                    int r = 0;
-                    double xcp[3], n[3], delta = 0.0;
-                    if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) <= Pi.rb + Pj.rb)
-                        r = pair_geometry(p, Pi, Pj, xcp, n, delta);
-                    if (r < 0) atomicAdd(&cnt->n_contact_fail, 1ull);
-                    if (r <= 0) {
-                        xi[0] = xi[1] = xi[2] = 0.0;
-                    } else {
-                        atomicAdd(&cnt->n_contacts, 1ull);
-                        double vi[3], vj[3], ri[3], rj[3], vrel[3];
-                        point_velocity(p, Pi, xcp, vi, ri);
-                        point_velocity(p, Pj, xcp, vj, rj);
-                        for (int a = 0; a < 3; ++a) vrel[a] = vj[a] - vi[a];
-                        const double meff = Pi.mode == 1 ? Pj.m : (Pj.mode == 1 ? Pi.m : Pi.m * Pj.m / (Pi.m + Pj.m));
-                        spring_dashpot(p, meff, n, delta, vrel, xi, dt, F);
-                        const double Fm[3] = {-F[0], -F[1], -F[2]};
-                        cross3(ri, F, Ti);
-                        cross3(rj, Fm, Tj);
-                    }
-                }
-                for (int a = 0; a < 3; ++a) {
-                    cb.pairF[3ll * q + a] = F[a];
-                    cb.pairTi[3ll * q + a] = Ti[a];
-                    cb.pairTj[3ll * q + a] = Tj[a];
-                }
-            }
-            for (int q = t; q < np * 6; q += 256) {
-                const int i = q / 6, w = q - 6 * i, ax = w >> 1, side = w & 1;
-                double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-                double *xi = cb.xiW + 3ll * q;
-                const DevParticle &Pi = P[i];
-                if (Pi.mode != 1 && !((p.periodic >> ax) & 1u)) {
-                    double xcp[3], n[3], delta = 0.0;
-                    const int r = wall_geometry(p, Pi, ax, side, xcp, n, delta);
-                    if (r < 0) atomicAdd(&cnt->n_contact_fail, 1ull);
-                    if (r <= 0) {
-                        xi[0] = xi[1] = xi[2] = 0.0;
-                    } else {
-                        atomicAdd(&cnt->n_contacts, 1ull);
-                        double vi[3], ri[3], vrel[3];
-                        point_velocity(p, Pi, xcp, vi, ri);
-                        for (int a = 0; a < 3; ++a) vrel[a] = -vi[a];
-                        spring_dashpot(p, Pi.m, n, delta, vrel, xi, dt, F);
-                        for (int a = 0; a < 3; ++a) ri[a] = xcp[a] - Pi.X[a];
-                        cross3(ri, F, T);
-                    }
-                }
-                for (int a = 0; a < 3; ++a) { cb.wallF[3ll * q + a] = F[a]; cb.wallT[3ll * q + a] = T[a]; }
-            }
+            for (int q = t; q < np * np; q += 256) contact_pair(p, P, cb, cnt, q, dt);
+            for (int q = t; q < np * 6; q += 256) contact_wall(p, P, cb, cnt, q, dt);
             __syncthreads();
         }
-        for (int q = t; q < np; q += 256) {
-            DevParticle &B = P[q];
-            double F[3] = {B.F[0], B.F[1], B.F[2]}, T[3] = {B.T[0], B.T[1], B.T[2]};
-            if (p.contact) {
-                double Fc[3] = {0, 0, 0}, Tc[3] = {0, 0, 0};
-                for (int j = 0; j < np; ++j) {
-                    if (j == q) continue;
-                    if (j < q) {
-                        const long long k = (long long)j * np + q;
-                        for (int a = 0; a < 3; ++a) { Fc[a] -= cb.pairF[3 * k + a]; Tc[a] += cb.pairTj[3 * k + a]; }
-                    } else {
-                        const long long k = (long long)q * np + j;
-                        for (int a = 0; a < 3; ++a) { Fc[a] += cb.pairF[3 * k + a]; Tc[a] += cb.pairTi[3 * k + a]; }
-                    }
-                }
-                for (int w = 0; w < 6; ++w)
-                    for (int a = 0; a < 3; ++a) { Fc[a] += cb.wallF[3ll * (6 * q + w) + a]; Tc[a] += cb.wallT[3ll * (6 * q + w) + a]; }
-                for (int a = 0; a < 3; ++a) { F[a] += Fc[a]; T[a] += Tc[a]; }
-            }
-            body_substep(p, B, F, T, dt);
-        }
+        for (int q = t; q < np; q += 256) contact_body(p, P[q], q, cb, dt);
         __syncthreads();
     }
     for (int q = t; q < np; q += 256) end_of_step(p, P[q], cnt);
     __syncthreads();
     if (lds)
         for (int k = t; k < W * np; k += 256) ((int *)Pg)[k] = ((const int *)sP)[k];
+}
+
+// The same sub-step over many blocks (many bodies): every pair and face in
+// parallel, then every body (one thread each); the caller launches the pair
+// kernel and then the body kernel once per sub-step.
+__global__ __launch_bounds__(256) void k_contact_pairs(Params p, const DevParticle *__restrict__ P, ContactBufs cb,
+                                                       Counters *__restrict__ cnt) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int np2 = p.np * p.np;
+    const double dt = 1.0 / p.n_sub;
+    if (q < np2) contact_pair(p, P, cb, cnt, q, dt);
+    else if (q < np2 + 6 * p.np) contact_wall(p, P, cb, cnt, q - np2, dt);
+}
+
+__global__ __launch_bounds__(256) void k_contact_bodies(Params p, DevParticle *__restrict__ P, ContactBufs cb,
+                                                        Counters *__restrict__ cnt, int first, int last) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p.np) return;
+    DevParticle &B = P[q];
+    if (first)
+        for (int a = 0; a < 3; ++a) B.X0[a] = B.X[a];
+    contact_body(p, B, q, cb, 1.0 / p.n_sub);
+    if (last) end_of_step(p, B, cnt);
 }
 
 __global__ __launch_bounds__(256) void k_rigid(Params p, DevParticle *__restrict__ Pg, ContactBufs cb,
@@ -1734,7 +1798,18 @@ static void launch_step_kernels_t(const StepArgs &a) {
             k_links<S><<<link_grid(p), 256, 0, a.stream>>>(p, A, B, a.own_old, a.P, a.l_node, a.l_do, a.l_q,
                                                          a.part, a.cnt);
         k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, update, a.body_stats);
-        if (a.move && p.contact && p.np > 0) k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
+        if (a.move && p.contact && p.np > 0) {
+            if (p.np <= RIGID_LDS) {  // few bodies: one block, records in LDS
+                k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
+            } else {
+                const int nq = p.np * p.np + 6 * p.np;
+                for (int s2 = 0; s2 < p.n_sub; ++s2) {
+                    k_contact_pairs<<<cdiv(nq, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
+                    k_contact_bodies<<<cdiv(p.np, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt, s2 == 0,
+                                                                            s2 == p.n_sub - 1);
+                }
+            }
+        }
     } else if (a.phase == PHASE_FLAGS) {
         if (p.np > 0) {
             if (a.move) k_region_mark<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.own_new);

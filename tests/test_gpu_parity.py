@@ -342,6 +342,27 @@ def test_periodic_suspension_small(mdl):
         _compare_particles(sim, ref, cfg, 1e-6, 1e-7)
 
 
+def test_periodic_suspension_many_bodies(mdl):
+    """Forty bodies with contact (more than the one-block rigid-body kernel
+    holds in LDS: contacts of all pairs and faces over many blocks, then one
+    thread per body) against the oracle: fields, links, particles, contact
+    counts."""
+    cfg = workloads.suspension_small(n_bodies=40, box=64, seed=52)
+    assert len(cfg.particles) == 40
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    for k in range(2):
+        sim.step(15)
+        ref.step(15)
+        compare_fields(sim, ref, label=f"40-body suspension step {15 * (k + 1)}")
+        dq = compare_links(sim, ref)
+        assert np.median(dq) < 1e-7 and dq.max() < 1e-4
+        _compare_particles(sim, ref, cfg, 1e-6, 1e-7)
+    nc, nf = sim.contact_stats()
+    assert nc == ref.n_contacts and nf == 0
+    print(f"40-body suspension: {nc} contacts", flush=True)
+
+
 _TR_STEPS = (50, 100, 200, 400)
 
 
