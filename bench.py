@@ -109,7 +109,8 @@ def nr_summary(hist, resid):
 
 
 def run_suspension(steps):
-    """The 256^3 periodic suspension of 200 bodies (seed 5), plain Newton."""
+    """The 256^3 periodic suspension of 200 bodies (seed 5, contact on),
+    plain Newton."""
     import torch
 
     import paper_2209_10411_amd as mdl
@@ -127,16 +128,20 @@ def run_suspension(steps):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     h, r = sim.nr_histogram()
+    nc, nf = sim.contact_stats()
     sim.close()
-    return dict(nr_summary(h, r), workload="256^3 periodic suspension, 200 bodies, FP32, IBB", steps=steps,
+    return dict(nr_summary(h, r), workload="256^3 periodic suspension, 200 bodies, contact, FP32, IBB", steps=steps,
+                contacts=nc, contact_failures=nf,
                 mlups=round(cfg.n_nodes * steps / dt / 1e6, 1), ms_per_step=round(dt * 1e3 / steps, 4))
 
 
 def run_mlp_warmstart(steps, epochs):
-    """Link-fraction warm start on the 256^3 periodic suspension of 200
-    bodies (FP32): the MLP is trained on the link fractions the method
-    solved at the initial geometries of seeds 5, 6 and 7, then seed 5 runs
-    with plain and with warm-started Newton iterations."""
+    """Warm start on the 256^3 periodic suspension of 200 bodies (FP32,
+    contact): the MLP is trained on the link fractions the method solved at
+    the initial geometries of seeds 5, 6 and 7 and on the stationary points
+    of the candidate body pairs over their first 10 steps (closest-point
+    task), then seed 5 runs with plain and with warm-started Newton
+    iterations (link fractions and pair solves)."""
     import torch
 
     import paper_2209_10411_amd as mdl
@@ -145,6 +150,7 @@ def run_mlp_warmstart(steps, epochs):
     feats, targets = [], []
     sim5 = None
     t0 = time.perf_counter()
+    n_contact = 0
     for seed in (5, 6, 7):
         sim = mdl.Simulation(workloads.config5(seed=seed), device="cuda:0")
         f, t = mdl.mlp_collect(sim)
@@ -153,6 +159,14 @@ def run_mlp_warmstart(steps, epochs):
         if seed == 5:
             sim5 = sim
         else:
+            for _ in range(10):
+                sim.step(1)
+                f, t = mdl.mlp_collect_contact(sim)
+                # a few thousand pair samples against millions of link samples:
+                # repeated to weigh the two tasks alike
+                feats.append(f.repeat(100, 1))
+                targets.append(t.repeat(100, 1))
+                n_contact += int(f.shape[0])
             sim.close()
     t_setup = time.perf_counter() - t0
     feat, target = torch.cat(feats), torch.cat(targets)
@@ -173,6 +187,7 @@ def run_mlp_warmstart(steps, epochs):
         sim5.step(5)
         sim5.sync()
         sim5.nr_histogram()
+        sim5.contact_nr_stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim5.step(steps)
@@ -180,12 +195,16 @@ def run_mlp_warmstart(steps, epochs):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         h, r = sim5.nr_histogram()
+        ns, ni = sim5.contact_nr_stats()
         res[mode] = dict(nr_summary(h, r), mlups=round(cfg.n_nodes * steps / dt / 1e6, 1),
-                         ms_per_step=round(dt * 1e3 / steps, 4))
+                         ms_per_step=round(dt * 1e3 / steps, 4), pair_solves=ns,
+                         pair_evaluations_per_solve=round(ni / max(ns, 1), 3),
+                         contacts=sim5.contact_stats()[0])
     sim5.close()
     return {"workload": "256^3 periodic suspension, 200 bodies (6..20 cp, R 6..12), density ratio 1.5, "
-                        "counter-force, FP32, IBB",
-            "training_samples": int(feat.shape[0]), "epochs": epochs, "batch": 1024,
+                        "counter-force, contact, FP32, IBB",
+            "training_samples": int(feat.shape[0]), "closest_point_samples": n_contact, "epochs": epochs,
+            "batch": 1024,
             "train_s": round(t_train, 2), "setup_s": round(t_setup, 1),
             "loss_before": round(loss0, 5), "loss_after": round(loss1, 5), "steps": steps,
             "plain": res["plain"], "mlp": res["mlp"]}

@@ -201,6 +201,10 @@ lbm_status lbm_nr_stats(lbm_ctx *ctx, int64_t *links, int64_t *iterations);
  * and contact iterations that did not converge, since lbm_init
  * (synchronises). */
 lbm_status lbm_contact_stats(lbm_ctx *ctx, int64_t *contacts, int64_t *failures);
+/* Stationary-point solves of candidate body pairs (bounding spheres
+ * overlapping, per rigid-body sub-step) and their Newton evaluations since
+ * the last call (resets the counts; synchronises). */
+lbm_status lbm_contact_nr_stats(lbm_ctx *ctx, int64_t *solves, int64_t *iterations);
 /* Waits for the context's stream and reports device-side errors. */
 lbm_status lbm_sync(lbm_ctx *ctx);
 
@@ -239,6 +243,18 @@ lbm_status mlp_get_params(const void *dev_weights, float *params, void *hip_stre
  * dev_feat [n][87] FP16 and targets dev_target [n][4] FP32 (q, 0, 0, 0),
  * n = min(n_max, links); synchronises. */
 lbm_status mlp_collect(lbm_ctx *ctx, int64_t n_max, void *dev_feat, void *dev_target, int64_t *n_out);
+/* Closest-point samples (task bit 1) from the last contact sub-step: one per
+ * candidate pair i < j whose stationary-point iteration converged, in pair
+ * order, seen from body i -- the query point is body j's centroid, the
+ * direction 0 -- with targets (0, p) where p = the stationary point relative
+ * to body i's centroid in its frame, scaled by 1/sqrt(sum k) (outputs 1..3);
+ * n = min(n_max, such pairs); none without contact.  With a warm start set
+ * (lbm_set_warmstart), the same network's outputs 1..3 start each pair's
+ * iteration, kept only if it converges within 20 evaluations to a point
+ * between the two centroids, outside both inner bodies, with positive
+ * curvature along the centroid segment (else the plain start follows).
+ * Synchronises. */
+lbm_status mlp_collect_contact(lbm_ctx *ctx, int64_t n_max, void *dev_feat, void *dev_target, int64_t *n_out);
 /* Outputs [n][4] FP32 of the network for features [n][87]: precision 0 =
  * FP16 features/weights/activations (the production form), 1 = FP32
  * throughout (a test instantiation; features are then FP32).  Enqueued on

@@ -58,12 +58,14 @@ class lbm_particle_state(C.Structure):
 EXPORTS = ["lbm_arena_bytes", "lbm_init", "metaball_flag", "lbm_step", "particle_forces", "refill",
            "lbm_get_macros", "lbm_get_populations", "lbm_set_populations", "lbm_get_flags",
            "lbm_get_links", "lbm_get_particles", "lbm_set_particles", "lbm_get_gfluid",
-           "lbm_timing_enable", "lbm_timing_read", "lbm_nr_stats", "lbm_contact_stats", "lbm_sync",
+           "lbm_timing_enable", "lbm_timing_read", "lbm_nr_stats", "lbm_contact_stats", "lbm_contact_nr_stats",
+           "lbm_sync",
            "lbm_destroy",
            "lbm_last_error",
            "lbm_batch_arena_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_case", "lbm_autotune",
            "lbm_batch_tiles", "lbm_batch_destroy",
-           "mlp_weights_bytes", "mlp_param_count", "mlp_init", "mlp_get_params", "mlp_collect", "mlp_forward",
+           "mlp_weights_bytes", "mlp_param_count", "mlp_init", "mlp_get_params", "mlp_collect",
+           "mlp_collect_contact", "mlp_forward",
            "mlp_grad", "mlp_train", "lbm_set_warmstart", "lbm_nr_histogram"]
 
 _lib = None
@@ -99,6 +101,7 @@ def lib():
         L.lbm_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_nr_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_contact_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.lbm_contact_nr_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_sync.argtypes = [vp]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
@@ -122,6 +125,7 @@ def lib():
         L.mlp_init.argtypes = [vp, fp, vp]
         L.mlp_get_params.argtypes = [vp, fp, vp]
         L.mlp_collect.argtypes = [vp, C.c_int64, vp, vp, C.POINTER(C.c_int64)]
+        L.mlp_collect_contact.argtypes = [vp, C.c_int64, vp, vp, C.POINTER(C.c_int64)]
         L.mlp_forward.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, vp]
         L.mlp_grad.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, fp, dp, vp]
         L.mlp_train.argtypes = [vp, vp, C.c_int64, C.c_char_p, vp, vp]
@@ -334,6 +338,12 @@ class Simulation:
         _check(lib().lbm_contact_stats(self._ctx, C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)
 
+    def contact_nr_stats(self):
+        """(pair stationary-point solves, their Newton evaluations) since the last call."""
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(lib().lbm_contact_nr_stats(self._ctx, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
+
     def nr_histogram(self):
         """(histogram of Newton evaluations per link [65], largest final |C - 1|) since the last call."""
         h = np.zeros(65, dtype=np.int64)
@@ -471,6 +481,21 @@ class Mlp:
         import json
         _check(lib().mlp_train(C.c_void_p(feat.data_ptr()), C.c_void_p(target.data_ptr()), feat.shape[0],
                                json.dumps(hp).encode(), C.c_void_p(self.blob.data_ptr()), self._s()))
+
+
+def mlp_collect_contact(sim, n_max: int | None = None):
+    """Closest-point training samples (features float16 [n][87], targets
+    float32 [n][4]) from the last contact sub-step of a Simulation."""
+    import torch
+    L = lib()
+    if n_max is None:
+        n_max = max(1, sim.np * (sim.np - 1) // 2)
+    feat = torch.empty((n_max, Mlp.N_IN), dtype=torch.float16, device="cuda:0")
+    target = torch.empty((n_max, Mlp.N_OUT), dtype=torch.float32, device="cuda:0")
+    n = C.c_int64(0)
+    _check(L.mlp_collect_contact(sim._ctx, int(n_max), C.c_void_p(feat.data_ptr()),
+                                 C.c_void_p(target.data_ptr()), C.byref(n)))
+    return feat[:n.value], target[:n.value]
 
 
 def mlp_collect(sim, n_max: int | None = None):

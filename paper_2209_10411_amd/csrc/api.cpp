@@ -187,7 +187,8 @@ struct Plan {
         off_cnt, total;
     bool contact;
     size_t off_lmask, off_nrs, off_mlpb;
-    size_t off_pairF, off_pairTi, off_pairTj, off_wallF, off_wallT, off_xiP, off_xiW, off_pairOn;
+    size_t off_pairF, off_pairTi, off_pairTj, off_wallF, off_wallT, off_xiP, off_xiW, off_pairOn, off_pairXm,
+        off_pairOk, off_pairGuess;
 };
 
 struct HostParticle {
@@ -341,6 +342,9 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_xiP = take(24 * npp);
     pl.off_xiW = take(24 * npw);
     pl.off_pairOn = take(npp);
+    pl.off_pairXm = take(24 * npp);
+    pl.off_pairOk = take(npp);
+    pl.off_pairGuess = take(32 * npp);
     pl.off_cnt = take(sizeof(Counters));
     pl.off_nrs = take(4 * (size_t)NR_BLOCKS * NR_HIST + 16 * (size_t)NR_BLOCKS + 4 * (size_t)NR_BLOCKS);
     pl.off_mlpb = take(4 * (size_t)MLP_BODY * std::max(np, 1));
@@ -636,6 +640,9 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->cb.wallT = (double *)(b + pl.off_wallT); c->cb.xiP = (double *)(b + pl.off_xiP);
     c->cb.xiW = (double *)(b + pl.off_xiW);
     c->cb.pairOn = (uint8_t *)(b + pl.off_pairOn);
+    c->cb.pairXm = (double *)(b + pl.off_pairXm);
+    c->cb.pairOk = (uint8_t *)(b + pl.off_pairOk);
+    c->cb.pairGuess = (double *)(b + pl.off_pairGuess);
     c->aux = nullptr;
     c->ev_main = c->ev_flags = c->ev_links = c->ev_bulk = nullptr;
     c->timing = false;
@@ -701,6 +708,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     if (n_p > 0)
         HIPCHK_C(hipMemcpyAsync(c->mlp_body, mb.data(), 4 * mb.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK_C(hipStreamSynchronize(c->stream));  // host buffers above are released on return
+    if (pl.contact) launch_fill_u8(c->cb.pairOk, (long long)n_p * n_p, 0, c->stream);  // no solve yet
     if (pl.contact) {  // tangential springs start relaxed
         std::vector<double> z((size_t)n_p * n_p * 3, 0.0);
         HIPCHK_C(hipMemcpyAsync(c->cb.xiP, z.data(), 24 * (size_t)n_p * n_p, hipMemcpyHostToDevice, c->stream));
@@ -1226,6 +1234,36 @@ lbm_status mlp_train(void *dev_feat, void *dev_target, int64_t n, const char *hp
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(b.t, &t, 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
+    return LBM_OK;
+}
+
+lbm_status lbm_contact_nr_stats(lbm_ctx *c, int64_t *solves, int64_t *iterations) {
+    if (!c) return fail(LBM_E_INVALID, "ctx is NULL");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    Counters h;
+    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+    if (solves) *solves = (int64_t)h.n_contact_nr;
+    if (iterations) *iterations = (int64_t)h.n_contact_it;
+    const unsigned long long z[2] = {0ull, 0ull};
+    HIPCHK(hipMemcpy((char *)c->cnt + offsetof(Counters, n_contact_nr), z, sizeof z, hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status mlp_collect_contact(lbm_ctx *c, int64_t n_max, void *dev_feat, void *dev_target, int64_t *n_out) {
+    if (!c || !dev_feat || !dev_target || !n_out) return fail(LBM_E_INVALID, "NULL argument");
+    if (n_max < 0) return fail(LBM_E_INVALID, "n_max < 0");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    *n_out = 0;
+    if (!c->pl.contact || n_max == 0) return LBM_OK;
+    launch_mlp_collect_contact(c->p, c->P, c->mlp_body, c->cb, (int)std::min<int64_t>(n_max, 0x7fffffff),
+                               (_Float16 *)dev_feat, (float *)dev_target, c->cnt, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    Counters h;
+    HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
+    *n_out = h.n_collect;
     return LBM_OK;
 }
 

@@ -58,12 +58,15 @@ struct DevParticle {
 struct Counters {
     int n_links;    // links of the current geometry
     int n_special;  // boundary and uncovered nodes listed this step
-    int pad1, pad2;
+    int n_collect;  // samples written by the last contact-sample collection
+    int pad2;
     int err;        // ERR_* bits
     uint32_t pad0;
     int pad[2];
     unsigned long long n_contacts;      // contacts resolved (pairs + walls, per sub-step)
     unsigned long long n_contact_fail;  // contact iterations that did not converge
+    unsigned long long n_contact_nr;    // pair stationary-point solves (candidate pairs, per sub-step)
+    unsigned long long n_contact_it;    // their Newton iterations
 };
 
 // Link-fraction solver statistics since the last read, one slot per block
@@ -116,6 +119,9 @@ struct ContactBufs {
     double *xiP;     // [np*np][3] tangential springs, pairs
     double *xiW;     // [np*6][3] tangential springs, walls
     uint8_t *pairOn; // [np*np] 1 where the pair is in contact this sub-step (both (i,j) and (j,i))
+    double *pairXm;     // [np*np][3] stationary point of the pair's last solve (i < j; frame of body i)
+    uint8_t *pairOk;    // [np*np] 1 where that solve ran and converged
+    double *pairGuess;  // [np*np][4] warm-start stationary point (x, y, z; NaN: none)
 };
 
 constexpr int TW_FLAT = 7;
@@ -175,8 +181,8 @@ struct CaseArgs {
     int first[BK_N], nblk[BK_N];
 };
 // the host writes these tables for the device: one layout on both sides
-static_assert(sizeof(Params) == 240 && sizeof(CaseArgs) == 560 && offsetof(CaseArgs, nrs) == 472 &&
-                  offsetof(CaseArgs, first) == 516,
+static_assert(sizeof(Params) == 240 && sizeof(CaseArgs) == 584 && offsetof(CaseArgs, nrs) == 496 &&
+                  offsetof(CaseArgs, first) == 540,
               "CaseArgs layout");
 
 }  // namespace mdl

@@ -632,15 +632,47 @@ __device__ void mb_eval3(const InnerMB &m, const double x[3], double &f, double 
     H[6] = h02; H[7] = h12; H[8] = h22;
 }
 
+// Newton-Raphson for a stationary point of f0 + f1 from xm (in place), the
+// step capped at L/4, for at most it_max iterations; true when the step
+// fell below 1e-12 (1 + L).  iters: evaluations made.
+__device__ bool pair_newton(const InnerMB &m0, const InnerMB &m1, double xm[3], double L, int it_max, int &iters) {
+    for (int it = 0; it < it_max; ++it) {
+        double f0, g0[3], H0[9], f1, g1[3], H1[9], H[9], Hi[9], dx[3];
+        mb_eval3(m0, xm, f0, g0, H0);
+        mb_eval3(m1, xm, f1, g1, H1);
+        ++iters;
+        for (int a = 0; a < 9; ++a) H[a] = H0[a] + H1[a];
+        if (!inv3d(H, Hi)) return false;
+        double st = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            dx[a] = -(Hi[3 * a] * (g0[0] + g1[0]) + Hi[3 * a + 1] * (g0[1] + g1[1]) + Hi[3 * a + 2] * (g0[2] + g1[2]));
+            st += dx[a] * dx[a];
+        }
+        st = sqrt(st);
+        if (st > 0.25 * L)
+            for (int a = 0; a < 3; ++a) dx[a] *= 0.25 * L / st;
+        for (int a = 0; a < 3; ++a) xm[a] += dx[a];
+        if (st < 1e-12 * (1.0 + L)) return true;
+    }
+    return false;
+}
+
 // Contact of two bodies (Eqs. CM_coreF, eq:grad, eq:cp, eq:contactprop):
 // Newton-Raphson for the stationary point x_m of f0 + f1 between the inner
 // metaballs from the point of the centroid segment dividing it in the ratio
 // (K0/K1)^(1/3); Taylor projections x_c = x_m + q grad f, q = (1 - f)/|grad f|^2;
 // n from body 1 to body 0; delta = 2 R_s - |x_c0 - x_c1| (signed form); contact
 // point in the middle of the overlap.  1 = contact, 0 = none, -1 = iteration
-// failed.
+// failed.  With a guess (warm start, finite), the iteration starts there for
+// at most PAIR_WARM_MAX evaluations and its point is kept only if it
+// converged to the kind of point the plain start finds between separate
+// bodies: projection on the centroid segment inside it, outside both inner
+// bodies (f0, f1 < 1), positive curvature of f0 + f1 along the segment;
+// otherwise (also in deep contact) the plain start follows.  xm_out: the
+// stationary point (body 0's frame), iters: evaluations.
+constexpr int PAIR_WARM_MAX = 20, PAIR_NR_MAX = 60;
 __device__ int pair_geometry(const Params &p, const DevParticle &P0, const DevParticle &P1, double xcp[3],
-                             double nrm[3], double &delta) {
+                             double nrm[3], double &delta, const double *guess, double xm_out[3], int &iters) {
     double d01[3] = {P1.X[0] - P0.X[0], P1.X[1] - P0.X[1], P1.X[2] - P0.X[2]};
     min_image(p, d01);
     const double sh0[3] = {0.0, 0.0, 0.0};
@@ -653,30 +685,34 @@ __device__ int pair_geometry(const Params &p, const DevParticle &P0, const DevPa
     for (int i = 0; i < n1; ++i) K1 += inner_k(m1, i);
     const double rho = cbrt(K0 / K1);
     double xm[3];
-    for (int a = 0; a < 3; ++a) xm[a] = P0.X[a] + d01[a] * rho / (1.0 + rho);
     const double L = sqrt(d01[0] * d01[0] + d01[1] * d01[1] + d01[2] * d01[2]);
     bool ok = false;
-    for (int it = 0; it < 60; ++it) {
-        double f0, g0[3], H0[9], f1, g1[3], H1[9], H[9], Hi[9], dx[3];
+    double f0, g0[3], H0[9], f1, g1[3], H1[9];  // at the final point
+    if (guess && isfinite(guess[0]) && isfinite(guess[1]) && isfinite(guess[2])) {
+        for (int a = 0; a < 3; ++a) xm[a] = guess[a];
+        ok = pair_newton(m0, m1, xm, L, PAIR_WARM_MAX, iters);
+        if (ok) {  // the saddle between two separate bodies, as the plain start finds it
+            const double t =
+                ((xm[0] - P0.X[0]) * d01[0] + (xm[1] - P0.X[1]) * d01[1] + (xm[2] - P0.X[2]) * d01[2]) / (L * L);
+            mb_eval3(m0, xm, f0, g0, H0);
+            mb_eval3(m1, xm, f1, g1, H1);
+            double curv = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) curv += d01[a] * (H0[3 * a + b] + H1[3 * a + b]) * d01[b];
+            ok = t > 0.0 && t < 1.0 && f0 < 1.0 && f1 < 1.0 && curv > 0.0;
+        }
+    }
+    const bool warm_kept = ok;
+    if (!ok) {
+        for (int a = 0; a < 3; ++a) xm[a] = P0.X[a] + d01[a] * rho / (1.0 + rho);
+        ok = pair_newton(m0, m1, xm, L, PAIR_NR_MAX, iters);
+    }
+    for (int a = 0; a < 3; ++a) xm_out[a] = xm[a];
+    if (!ok) return -1;
+    if (!warm_kept) {
         mb_eval3(m0, xm, f0, g0, H0);
         mb_eval3(m1, xm, f1, g1, H1);
-        for (int a = 0; a < 9; ++a) H[a] = H0[a] + H1[a];
-        if (!inv3d(H, Hi)) break;
-        double st = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            dx[a] = -(Hi[3 * a] * (g0[0] + g1[0]) + Hi[3 * a + 1] * (g0[1] + g1[1]) + Hi[3 * a + 2] * (g0[2] + g1[2]));
-            st += dx[a] * dx[a];
-        }
-        st = sqrt(st);
-        if (st > 0.25 * L)
-            for (int a = 0; a < 3; ++a) dx[a] *= 0.25 * L / st;
-        for (int a = 0; a < 3; ++a) xm[a] += dx[a];
-        if (st < 1e-12 * (1.0 + L)) { ok = true; break; }
     }
-    if (!ok) return -1;
-    double f0, g0[3], H0[9], f1, g1[3], H1[9];
-    mb_eval3(m0, xm, f0, g0, H0);
-    mb_eval3(m1, xm, f1, g1, H1);
     const double G0 = sqrt(g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2]);
     const double G1 = sqrt(g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
     if (!(G0 > 0.0 && G1 > 0.0)) return -1;
@@ -837,21 +873,36 @@ constexpr int RIGID_LDS = 32;
 // Contact of body pair q = i * np + j (i < j) at the sub-step's poses:
 // force on i, torques on i and j, into the pair's slots (tangential spring
 // of the pair updated).
+// Whether bodies i and j are a candidate pair (bounding spheres overlap, not
+// both kinematic).
+__device__ __forceinline__ bool contact_candidate(const Params &p, const DevParticle &Pi, const DevParticle &Pj) {
+    if (Pi.mode == 1 && Pj.mode == 1) return false;
+    double d[3] = {Pj.X[0] - Pi.X[0], Pj.X[1] - Pi.X[1], Pj.X[2] - Pi.X[2]};
+    min_image(p, d);
+    return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) <= Pi.rb + Pj.rb;
+}
+
 __device__ __forceinline__ void contact_pair(const Params &p, const DevParticle *P, const ContactBufs &cb,
-                                             Counters *__restrict__ cnt, int q, double dt) {
+                                             Counters *__restrict__ cnt, int q, double dt, bool use_guess) {
     const int np = p.np;
     const int i = q / np, j = q - i * np;
     if (j <= i) return;
     double F[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, Tj[3] = {0, 0, 0};
     double *xi = cb.xiP + 3ll * q;
     const DevParticle &Pi = P[i], &Pj = P[j];
+    uint8_t solved = 0;
     if (!(Pi.mode == 1 && Pj.mode == 1)) {
-        double d[3] = {Pj.X[0] - Pi.X[0], Pj.X[1] - Pi.X[1], Pj.X[2] - Pi.X[2]};
-        min_image(p, d);
         int r = 0;
         double xcp[3], n[3], delta = 0.0;
-        if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) <= Pi.rb + Pj.rb)
-            r = pair_geometry(p, Pi, Pj, xcp, n, delta);
+        if (contact_candidate(p, Pi, Pj)) {
+            double xm[3];
+            int its = 0;
+            r = pair_geometry(p, Pi, Pj, xcp, n, delta, use_guess ? cb.pairGuess + 4ll * q : nullptr, xm, its);
+            atomicAdd(&cnt->n_contact_nr, 1ull);
+            atomicAdd(&cnt->n_contact_it, (unsigned long long)its);
+            for (int a = 0; a < 3; ++a) cb.pairXm[3ll * q + a] = xm[a];
+            solved = r >= 0 ? 1 : 0;
+        }
         if (r < 0) atomicAdd(&cnt->n_contact_fail, 1ull);
         if (r <= 0) {
             xi[0] = xi[1] = xi[2] = 0.0;
@@ -873,6 +924,7 @@ __device__ __forceinline__ void contact_pair(const Params &p, const DevParticle 
         cb.pairTi[3ll * q + a] = Ti[a];
         cb.pairTj[3ll * q + a] = Tj[a];
     }
+    cb.pairOk[q] = solved;
     const uint8_t on = (F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0 || Ti[0] != 0.0 || Ti[1] != 0.0 || Ti[2] != 0.0 ||
                         Tj[0] != 0.0 || Tj[1] != 0.0 || Tj[2] != 0.0) ? 1 : 0;
     cb.pairOn[q] = on;
@@ -948,7 +1000,7 @@ __device__ __forceinline__ void rigid_case(const Params &p, DevParticle *__restr
     const double dt = 1.0 / p.n_sub;
     for (int s = 0; s < p.n_sub; ++s) {
         if (p.contact) {
-            for (int q = t; q < np * np; q += 256) contact_pair(p, P, cb, cnt, q, dt);
+            for (int q = t; q < np * np; q += 256) contact_pair(p, P, cb, cnt, q, dt, false);
             for (int q = t; q < np * 6; q += 256) contact_wall(p, P, cb, cnt, q, dt);
             __syncthreads();
         }
@@ -965,12 +1017,71 @@ __device__ __forceinline__ void rigid_case(const Params &p, DevParticle *__restr
 // parallel, then every body (one thread each); the caller launches the pair
 // kernel and then the body kernel once per sub-step.
 __global__ __launch_bounds__(256) void k_contact_pairs(Params p, const DevParticle *__restrict__ P, ContactBufs cb,
-                                                       Counters *__restrict__ cnt) {
+                                                       Counters *__restrict__ cnt, int use_guess) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int np2 = p.np * p.np;
     const double dt = 1.0 / p.n_sub;
-    if (q < np2) contact_pair(p, P, cb, cnt, q, dt);
+    if (q < np2) contact_pair(p, P, cb, cnt, q, dt, use_guess != 0);
     else if (q < np2 + 6 * p.np) contact_wall(p, P, cb, cnt, q - np2, dt);
+}
+
+// Warm start of the pair solves: the closest-point task of the MLP for every
+// candidate pair (i < j), seen from body i, one wave per pair (four per
+// block): inputs staged in LDS (FP16), hidden unit u on lane u (FP32 sums of
+// FP16 products, FP16 activations), outputs 1..3 taken back to the lab frame
+// as the starting stationary point; NaN where the pair is no candidate.
+__global__ __launch_bounds__(256) void k_contact_guess(Params p, const DevParticle *__restrict__ P, ContactBufs cb,
+                                                       const _Float16 *__restrict__ w, const float *__restrict__ body) {
+    __shared__ _Float16 act[4][MLP_IN + 2 * MLP_H];  // inputs, h1, h2
+    __shared__ float outs[4][MLP_OUT];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + wv;
+    const int np = p.np;
+    const int i = q / np, j = q - i * np;
+    const bool cand = q < np * np && j > i && contact_candidate(p, P[i], P[j]);
+    if (cand) {
+        if (lane == 0) {
+            double head[7];
+            mlp_contact_head(p, P[i], P[j], head);
+            for (int a = 0; a < 7; ++a) act[wv][a] = (_Float16)head[a];
+        }
+        for (int c = lane; c < MLP_BODY; c += 64) act[wv][7 + c] = (_Float16)body[i * MLP_BODY + c];
+    }
+    __syncthreads();
+    if (cand) {
+        float z = (float)w[MLP_OFF_B1 + lane];
+        for (int k = 0; k < MLP_IN; ++k) z += (float)act[wv][k] * (float)w[MLP_OFF_W1 + k * MLP_H + lane];
+        act[wv][MLP_IN + lane] = (_Float16)tanhf(z);
+    }
+    __syncthreads();
+    if (cand) {
+        float z = (float)w[MLP_OFF_B2 + lane];
+        for (int k = 0; k < MLP_H; ++k) z += (float)act[wv][MLP_IN + k] * (float)w[MLP_OFF_W2 + k * MLP_H + lane];
+        act[wv][MLP_IN + MLP_H + lane] = (_Float16)tanhf(z);
+    }
+    __syncthreads();
+    if (cand && lane < MLP_OUT) {
+        float o = (float)w[MLP_OFF_B3 + lane];
+        for (int k = 0; k < MLP_H; ++k) o += (float)act[wv][MLP_IN + MLP_H + k] * (float)w[MLP_OFF_W3 + k * MLP_OUT + lane];
+        outs[wv][lane] = o;
+    }
+    __syncthreads();
+    if (q >= np * np || j <= i || lane != 0) return;
+    double *g = cb.pairGuess + 4ll * q;
+    if (!cand) {
+        g[0] = __builtin_nan("");
+        return;
+    }
+    // offset in body i's frame times sqrt(sum k), rotated to the lab frame
+    const DevParticle &B = P[i];
+    double K = 0.0;
+    for (int c = 0; c < B.n_cp; ++c) K += B.k[c];
+    const double s = sqrt(K);
+    double R[9];
+    quat_rot(B.q, R);
+    const double ob[3] = {outs[wv][1] * s, outs[wv][2] * s, outs[wv][3] * s};
+    for (int a = 0; a < 3; ++a) g[a] = B.X[a] + R[3 * a] * ob[0] + R[3 * a + 1] * ob[1] + R[3 * a + 2] * ob[2];
+    g[3] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_contact_bodies(Params p, DevParticle *__restrict__ P, ContactBufs cb,
@@ -1799,12 +1910,15 @@ static void launch_step_kernels_t(const StepArgs &a) {
                                                          a.part, a.cnt);
         k_reduce<<<max(p.np, 1), 256, 0, a.stream>>>(p, a.P, a.l_off, a.part, a.cnt, update, a.body_stats);
         if (a.move && p.contact && p.np > 0) {
-            if (p.np <= RIGID_LDS) {  // few bodies: one block, records in LDS
+            if (p.np <= RIGID_LDS && !a.warm) {  // few bodies: one block, records in LDS
                 k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
             } else {
                 const int nq = p.np * p.np + 6 * p.np;
                 for (int s2 = 0; s2 < p.n_sub; ++s2) {
-                    k_contact_pairs<<<cdiv(nq, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
+                    if (a.warm)
+                        k_contact_guess<<<cdiv((long long)p.np * p.np, 4), 256, 0, a.stream>>>(p, a.P, a.cb, a.warm,
+                                                                                            a.mlp_body);
+                    k_contact_pairs<<<cdiv(nq, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt, a.warm ? 1 : 0);
                     k_contact_bodies<<<cdiv(p.np, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt, s2 == 0,
                                                                             s2 == p.n_sub - 1);
                 }

@@ -200,6 +200,61 @@ __global__ void k_mlp_collect(Params p, const DevParticle *__restrict__ P, const
     t[1] = t[2] = t[3] = 0.f;
 }
 
+// Closest-point samples, one block scanning the pair slots in order: a
+// converged pair (i < j) gets the next sample (block prefix of the flags),
+// inputs from body i with the partner's centroid as the query point, target
+// outputs 1..3 = the stationary point in body i's frame scaled by
+// 1/sqrt(sum k) (output 0 untargeted).
+__global__ __launch_bounds__(1024) void k_mlp_collect_contact(Params p, const DevParticle *__restrict__ P,
+                                                              const float *__restrict__ body, ContactBufs cb,
+                                                              int n_max, _Float16 *__restrict__ feat,
+                                                              float *__restrict__ target, Counters *cnt) {
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int np = p.np;
+    const long long np2 = (long long)np * np;
+    int base = 0;
+    for (long long q0 = 0; q0 < np2; q0 += 1024) {
+        const long long q = q0 + t;
+        int i = 0, j = 0;
+        bool ok = false;
+        if (q < np2) {
+            i = (int)(q / np);
+            j = (int)(q - (long long)i * np);
+            ok = j > i && cb.pairOk[q];
+        }
+        int incl = ok ? 1 : 0;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        int wb = 0, tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wv) wb += wsum[k];
+            tot += wsum[k];
+        }
+        const int idx = base + wb + incl - (ok ? 1 : 0);
+        if (ok && idx < n_max) {
+            _Float16 *f = feat + (long long)idx * MLP_IN;
+            float *tg = target + (long long)idx * MLP_OUT;
+            double head[7];
+            mlp_contact_head(p, P[i], P[j], head);
+            for (int a = 0; a < 7; ++a) f[a] = (_Float16)head[a];
+            for (int c = 0; c < MLP_BODY; ++c) f[7 + c] = (_Float16)body[i * MLP_BODY + c];
+            const int zero[3] = {0, 0, 0};
+            double off[7];
+            mlp_point_head(p, P[i], cb.pairXm + 3 * q, zero, 1.0, off);
+            tg[0] = 0.f;
+            for (int a = 0; a < 3; ++a) tg[1 + a] = (float)off[a];
+        }
+        base += tot;
+        __syncthreads();  // wsum is written again
+    }
+    if (t == 0) cnt->n_collect = min(base, n_max);
+}
+
 static int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 void launch_mlp_init(const MlpBlob &b, hipStream_t s) {
@@ -254,6 +309,11 @@ void launch_mlp_loss_grad(const MlpBlob &b, const void *X, const float *T, int n
 void launch_mlp_adam(const MlpBlob &b, float lr, float beta1, float beta2, float eps, float bc1, float bc2,
                      hipStream_t s) {
     k_mlp_adam<<<cdiv(MLP_P, 256), 256, 0, s>>>(b.theta, b.g, b.m, b.v, b.w16, lr, beta1, beta2, eps, bc1, bc2);
+}
+
+void launch_mlp_collect_contact(const Params &p, const DevParticle *P, const float *body, const ContactBufs &cb,
+                                int n_max, _Float16 *feat, float *target, Counters *cnt, hipStream_t s) {
+    k_mlp_collect_contact<<<1, 1024, 0, s>>>(p, P, body, cb, n_max, feat, target, cnt);
 }
 
 void launch_mlp_collect(const Params &p, const DevParticle *P, const float *body, const uint32_t *l_node,

@@ -24,9 +24,11 @@ constexpr int MLP_BODY = 4 * MAXCP;  // constant per-body inputs
 // constant block (control points sorted by weight, scaled), computed once
 // at set-up.  This computes the first 7 entries (e: the link direction
 // e_i); the caller appends the body block.
-__device__ __forceinline__ void mlp_link_head(const Params &p, const DevParticle &B, int x, int y, int z,
-                                              const int e_i[3], double head[7]) {
-    double d[3] = {x - B.X[0], y - B.X[1], z - B.X[2]};
+// The first 7 inputs of a query point pt (lab frame) with direction e_i and
+// task bit 'task' for body B.
+__device__ __forceinline__ void mlp_point_head(const Params &p, const DevParticle &B, const double pt[3],
+                                               const int e_i[3], double task, double head[7]) {
+    double d[3] = {pt[0] - B.X[0], pt[1] - B.X[1], pt[2] - B.X[2]};
     const int L[3] = {p.nx, p.ny, p.nz};
     for (int a = 0; a < 3; ++a)
         if ((p.periodic >> a) & 1u) d[a] -= L[a] * floor(d[a] / L[a] + 0.5);
@@ -43,7 +45,23 @@ __device__ __forceinline__ void mlp_link_head(const Params &p, const DevParticle
         head[a] = (R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2]) * inv_s;
         head[3 + a] = R[a] * e[0] + R[3 + a] * e[1] + R[6 + a] * e[2];
     }
-    head[6] = 0.0;
+    head[6] = task;
+}
+
+__device__ __forceinline__ void mlp_link_head(const Params &p, const DevParticle &B, int x, int y, int z,
+                                              const int e_i[3], double head[7]) {
+    const double pt[3] = {(double)x, (double)y, (double)z};
+    mlp_point_head(p, B, pt, e_i, 0.0, head);
+}
+
+// Closest-point task (task bit 1) of a body pair seen from body Bi: the
+// partner's centroid as the query point, no direction.  Outputs 1..3 are
+// the pair's stationary point relative to Bi's centroid, in Bi's frame,
+// scaled by 1/sqrt(sum k of Bi).
+__device__ __forceinline__ void mlp_contact_head(const Params &p, const DevParticle &Bi, const DevParticle &Bj,
+                                                 double head[7]) {
+    const int zero[3] = {0, 0, 0};
+    mlp_point_head(p, Bi, Bj.X, zero, 1.0, head);
 }
 
 // Training and inference entry points (mlp.hip).  'precision' 0: FP16
@@ -71,5 +89,9 @@ void launch_mlp_adam(const MlpBlob &b, float lr, float beta1, float beta2, float
 void launch_mlp_collect(const Params &p, const DevParticle *P, const float *body, const uint32_t *l_node,
                         const uint32_t *l_do, const double *l_q, int n, _Float16 *feat, float *target,
                         hipStream_t s);
+// Closest-point samples of the pairs whose last solve converged (pair order
+// i < j, seen from body i), at most n_max; the count goes to cnt->n_collect.
+void launch_mlp_collect_contact(const Params &p, const DevParticle *P, const float *body, const ContactBufs &cb,
+                                int n_max, _Float16 *feat, float *target, Counters *cnt, hipStream_t s);
 
 }  // namespace mdl

@@ -164,3 +164,104 @@ def test_warm_start_finds_the_plain_roots(mdl, trained):
     assert r1 <= 1e-10 and r0 <= 1e-10
     plain.close()
     warm.close()
+
+
+def _at_rest(cfg):
+    """No gravity and no initial motion: the fluid stays at rest, so the
+    bodies feel no load and keep their poses through a step."""
+    cfg.g_particle = np.zeros(3)
+    for p in cfg.particles:
+        p.v = np.zeros(3)
+        p.omega = np.zeros(3)
+    return cfg
+
+
+def test_contact_samples_match_oracle(mdl):
+    """Closest-point samples (task bit 1) of the candidate pairs of a packed
+    periodic suspension at rest: inputs equal to the oracle's features of the
+    partner's centroid (within an FP16 ulp), targets equal to the oracle's
+    stationary point of the pair in the lower body's frame."""
+    cfg = _at_rest(workloads.suspension_small(n_bodies=40, box=64, seed=52))
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    sim.step(1)
+    body = []
+    for p in cfg.particles:
+        _, c, _, _ = oracle.body_properties(p.cp_xyz, p.cp_k, cfg.quad_h)
+        body.append((np.asarray(p.cp_xyz) - c, np.asarray(p.cp_k)))
+    parts = [ref.particle(i) for i in range(len(cfg.particles))]
+    gparts = sim.particles()
+    dims = (cfg.nx, cfg.ny, cfg.nz)
+    for a, b in zip(gparts, parts):  # at rest: the poses of the contact sub-step (modulo the box)
+        dx = a["x"] - b["x"]
+        dx -= np.array(dims) * np.round(dx / np.array(dims))
+        assert np.abs(dx).max() < 1e-12
+    expect = []
+    for i in range(len(parts)):
+        for j in range(i + 1, len(parts)):
+            d = parts[j]["x"] - parts[i]["x"]
+            d -= np.array(dims) * np.floor(d / np.array(dims) + 0.5)
+            if np.linalg.norm(d) > parts[i]["rb"] + parts[j]["rb"]:
+                continue
+            r, xm = ref.pair_geometry(i, j)[:2]
+            if r < 0:
+                continue
+            cpb, k = body[i]
+            x_in = omlp.features(cpb, k, parts[i]["x"], parts[i]["quat"], parts[j]["x"], np.zeros(3), dims=dims,
+                                 periodic=cfg.periodic, task=1)
+            off = omlp.features(cpb, k, parts[i]["x"], parts[i]["quat"], xm, np.zeros(3), dims=dims,
+                                periodic=cfg.periodic, task=1)[:3]
+            expect.append((x_in, off))
+    feat, target = mdl.mlp_collect_contact(sim)
+    f = feat.float().cpu().numpy()
+    t = target.cpu().numpy()
+    print(f"{len(expect)} candidate pairs solved by the oracle, {len(f)} samples", flush=True)
+    assert len(f) == len(expect) and len(f) >= 3
+    for s, (x_in, off) in enumerate(expect):
+        ref16 = x_in.astype(np.float16).astype(np.float64)
+        ulp = np.spacing(np.abs(ref16).astype(np.float16)).astype(np.float64)
+        assert np.all(np.abs(f[s] - ref16) <= ulp), (s, np.abs(f[s] - ref16).max())
+        assert t[s, 0] == 0.0
+        assert np.abs(t[s, 1:] - off).max() < 1e-6, (s, t[s, 1:], off)
+    sim.close()
+
+
+@pytest.mark.parametrize("trained", [True, False])
+def test_warm_started_contacts_match_plain(mdl, trained):
+    """Forty bodies with contact, the pair stationary points warm-started by
+    the network's closest-point outputs (trained on the method's own pair
+    solutions, or untrained): the same contacts and trajectories as the plain
+    start (the iteration's tolerance, the fallback and the between-centroids
+    check judge the guess); solves and Newton evaluations reported."""
+    import torch
+    cfg = workloads.suspension_small(n_bodies=40, box=64, seed=52)
+    net = mdl.Mlp(workloads.mlp_init(17).astype(np.float32))
+    if trained:
+        s0 = mdl.Simulation(cfg)
+        fs, ts = [], []
+        for _ in range(12):
+            s0.step(1)
+            f, t = mdl.mlp_collect_contact(s0)
+            fs.append(f.clone())
+            ts.append(t.clone())
+        s0.close()
+        feat, target = torch.cat(fs), torch.cat(ts)
+        perm = torch.randperm(feat.shape[0], generator=torch.Generator().manual_seed(0)).to(feat.device)
+        net.train(feat[perm].contiguous(), target[perm].contiguous(), lr=3e-3, epochs=300, batch=64)
+    plain, warm = mdl.Simulation(cfg), mdl.Simulation(cfg)
+    warm.set_warmstart(net)
+    plain.contact_nr_stats()
+    warm.contact_nr_stats()
+    plain.step(15)
+    warm.step(15)
+    s0_, i0_ = plain.contact_nr_stats()
+    s1_, i1_ = warm.contact_nr_stats()
+    print(f"trained={trained}: pair solves {s0_} / {s1_}, Newton evaluations per solve plain {i0_ / s0_:.2f} "
+          f"warm {i1_ / s1_:.2f}", flush=True)
+    assert s0_ == s1_ and s0_ > 0
+    assert plain.contact_stats() == warm.contact_stats()
+    for a, b in zip(plain.particles(), warm.particles()):
+        assert np.abs(a["x"] - b["x"]).max() < 1e-9
+        assert np.abs(a["v"] - b["v"]).max() < 1e-9
+    plain.close()
+    warm.close()

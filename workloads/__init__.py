@@ -125,7 +125,8 @@ def config2(scale: float = 1.0, seed: int = 1, bc: int = BC_IBB) -> Config:
 def config3(scale: float = 1.0, storage: int = STORE_F16, bc: int = BC_IBB) -> Config:
     """160x160x640 walled box, tau 0.6, two bodies (6 control points seed 2
     leading at z = 544, 12 control points seed 3 at z = 584) on the axis
-    x = y = 80, density ratio 1.2, gravity 2e-5, 5000 steps."""
+    x = y = 80, density ratio 1.2, gravity 2e-5, contact on (the kissing
+    stage), 5000 steps."""
     R = 10.0 * scale
     bodies = []
     for seed, n_cp, z in ((2, 6, 544.0), (3, 12, 584.0)):
@@ -135,7 +136,8 @@ def config3(scale: float = 1.0, storage: int = STORE_F16, bc: int = BC_IBB) -> C
     nx, ny, nz = int(round(160 * scale)), int(round(160 * scale)), int(round(640 * scale))
     return Config(nx=nx, ny=ny, nz=nz, periodic=0, tau=0.6, rho0=1.0,
                   g_particle=np.array([0.0, 0.0, -2e-5]), bc=bc, storage=storage,
-                  particles=bodies, name=f"cfg3-{nx}x{ny}x{nz}", steps=5000)
+                  particles=bodies, contact_rs=1.0, contact_kn=20.0, contact_en=0.5, contact_mu=0.5,
+                  name=f"cfg3-{nx}x{ny}x{nz}", steps=5000)
 
 
 def config4_case(b: int, ragged: bool = False) -> Config:
@@ -212,8 +214,8 @@ def config5(n_bodies: int = 200, box: int = 256, seed: int = 5,
     between the spheres that enclose each body's C >= 1 region about its
     control-point origin (the looser bounding spheres max|p| + sqrt(sum k)
     would fill 38 % of the box, at the jamming limit of the placement),
-    density ratio 1.5, gravity 2e-5, fluid counter-force; body-property
-    quadrature cell 1/4."""
+    density ratio 1.5, gravity 2e-5, fluid counter-force, contact on;
+    body-property quadrature cell 1/4."""
     rng = _rng(seed)
     bodies: List[Particle] = []
     centers = np.zeros((0, 3))
@@ -240,7 +242,8 @@ def config5(n_bodies: int = 200, box: int = 256, seed: int = 5,
         bodies.append(p)
     return Config(nx=box, ny=box, nz=box, periodic=7, tau=0.6, rho0=1.0,
                   g_particle=np.array([0.0, 0.0, -2e-5]), bc=BC_IBB, counter_force=1, quad_h=0.25,
-                  particles=bodies, name=f"cfg5-{box}^3-{n_bodies}-seed{seed}", steps=200)
+                  particles=bodies, contact_rs=1.0, contact_kn=20.0, contact_en=0.5, contact_mu=0.5,
+                  name=f"cfg5-{box}^3-{n_bodies}-seed{seed}", steps=200)
 
 
 # ------------------------------------------------------- validation cases
