@@ -174,6 +174,7 @@ bool finite_all(const double *v, int n) {
 // configuration; lbm_arena_bytes and lbm_init share this plan.
 struct Plan {
     long long N;
+    long long Ns;  // population array stride (N rounded up to 128)
     int np;
     int storage_bytes;
     int region_blocks;
@@ -256,6 +257,7 @@ double bounding_radius(int n_cp, const double *cp, const double *k, const double
 lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb, const std::vector<double> &re,
                      Plan &pl) {
     pl.N = (long long)c->nx * c->ny * c->nz;
+    pl.Ns = (pl.N + 127) / 128 * 128;
     pl.np = np;
     pl.storage_bytes = c->storage == 0 ? 4 : 2;
     pl.dims.assign(3 * np, 0);
@@ -311,7 +313,7 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.special_cap = (int)scap;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    const size_t pop = (size_t)Q * pl.N * pl.storage_bytes;
+    const size_t pop = (size_t)Q * pl.Ns * pl.storage_bytes;
     pl.off_A = take(pop);
     pl.off_B = take(pop);
     for (int k = 0; k < 3; ++k) pl.off_own[k] = take(4 * pl.N);
@@ -656,6 +658,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     p.nx = cfg->nx; p.ny = cfg->ny; p.nz = cfg->nz;
     p.periodic = cfg->periodic;
     p.N = pl.N;
+    p.Ns = pl.Ns;
     p.np = n_p;
     p.bc = cfg->bc;
     p.n_sub = cfg->n_sub;
@@ -875,13 +878,13 @@ lbm_status particle_forces(lbm_ctx *c, double *F, double *T) {
 static lbm_status read_state(lbm_ctx *c, double *host) {
     lbm_status s = check_device(c);
     if (s) return s;
-    const long long N = c->pl.N;
+    const long long N = c->pl.N, Ns = c->pl.Ns;
     const size_t sb = c->pl.storage_bytes;
-    std::vector<char> raw((size_t)Q * N * sb);
+    std::vector<char> raw((size_t)Q * Ns * sb);
     HIPCHK(hipMemcpy(raw.data(), c->A, raw.size(), hipMemcpyDeviceToHost));
     for (int i = 0; i < Q; ++i)
         for (long long n = 0; n < N; ++n) {
-            const size_t k = (size_t)i * N + n;
+            const size_t k = (size_t)i * Ns + n;  // device layout: stride Ns
             double d;
             if (sb == 4) {
                 d = ((const float *)raw.data())[k];
@@ -893,7 +896,7 @@ static lbm_status read_state(lbm_ctx *c, double *host) {
                 memcpy(&f, &u, 4);
                 d = f;
             }
-            host[k] = d + WD[i] * c->p.rho0;
+            host[(size_t)i * N + n] = d + WD[i] * c->p.rho0;
         }
     return LBM_OK;
 }
@@ -907,14 +910,14 @@ lbm_status lbm_set_populations(lbm_ctx *c, const double *f, int32_t post_collisi
     if (!c || !f) return fail(LBM_E_INVALID, "NULL argument");
     lbm_status s = check_device(c);
     if (s) return s;
-    const long long N = c->pl.N;
+    const long long N = c->pl.N, Ns = c->pl.Ns;
     for (long long k = 0; k < (long long)Q * N; ++k)
         if (!std::isfinite(f[k])) return fail(LBM_E_INVALID, "non-finite population at %lld", k);
-    std::vector<char> raw((size_t)Q * N * c->pl.storage_bytes);
+    std::vector<char> raw((size_t)Q * Ns * c->pl.storage_bytes, 0);
     for (int i = 0; i < Q; ++i)
         for (long long n = 0; n < N; ++n) {
-            const size_t k = (size_t)i * N + n;
-            const double d = f[k] - WD[i] * c->p.rho0;
+            const size_t k = (size_t)i * Ns + n;  // device layout: stride Ns
+            const double d = f[(size_t)i * N + n] - WD[i] * c->p.rho0;
             if (c->pl.storage_bytes == 4) {
                 ((float *)raw.data())[k] = (float)d;
             } else if (c->p.storage == 1) {
@@ -1351,7 +1354,7 @@ long long tile_blocks(const lbm_config &c, int twl, int bw) {
 BulkCase bulk_case(const lbm_ctx *c, int twl, int bw, int first_block) {
     BulkCase b{};
     const Params &p = c->p;
-    b.nx = p.nx; b.ny = p.ny; b.nz = p.nz; b.periodic = p.periodic; b.N = p.N;
+    b.nx = p.nx; b.ny = p.ny; b.nz = p.nz; b.periodic = p.periodic; b.N = p.N; b.Ns = p.Ns;
     b.rho0f = p.rho0f; b.omega = p.omega; b.fcoef = p.fcoef;
     b.gx = p.gx; b.gy = p.gy; b.gz = p.gz; b.scale = p.scale; b.inv_scale = p.inv_scale;
     b.tw_log2 = twl;

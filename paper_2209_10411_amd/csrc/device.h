@@ -86,6 +86,7 @@ struct Params {
     int nx, ny, nz;
     unsigned periodic;
     long long N;
+    long long Ns;  // stride of the population arrays: N rounded up to 128 (each array 256-byte aligned)
     int np;
     int bc;
     int n_sub;
@@ -132,7 +133,7 @@ constexpr int TW_FLAT = 7;
 struct BulkCase {
     int nx, ny, nz;
     unsigned periodic;
-    long long N;
+    long long N, Ns;
     float rho0f, omega, fcoef, gx, gy, gz, scale, inv_scale;
     int tw_log2;      // wave tile: 2^tw_log2 consecutive x by 64 >> tw_log2 rows of y (4..6), or
                       // TW_FLAT: 64 consecutive nodes in lattice order (rows wrap within a wave)
@@ -181,8 +182,8 @@ struct CaseArgs {
     int first[BK_N], nblk[BK_N];
 };
 // the host writes these tables for the device: one layout on both sides
-static_assert(sizeof(Params) == 240 && sizeof(CaseArgs) == 584 && offsetof(CaseArgs, nrs) == 496 &&
-                  offsetof(CaseArgs, first) == 540,
+static_assert(sizeof(Params) == 248 && sizeof(CaseArgs) == 592 && offsetof(CaseArgs, nrs) == 504 &&
+                  offsetof(CaseArgs, first) == 548,
               "CaseArgs layout");
 
 }  // namespace mdl

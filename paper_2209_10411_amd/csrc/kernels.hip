@@ -379,7 +379,7 @@ __device__ __forceinline__ void links_body(const Params &p, const typename Store
             cross3(Bd.w, r, uw);
             for (int a = 0; a < 3; ++a) uw[a] += Bd.v[a];
             const double w = c_wd[i];
-            const double fb = w * p.rho0 + (double)Store<S>::ld(A, (long long)ib * p.N + n, p.inv_scale);
+            const double fb = w * p.rho0 + (double)Store<S>::ld(A, (long long)ib * p.Ns + n, p.inv_scale);
             const double mw = 6.0 * w * p.rho0 * (c_ex[i] * uw[0] + c_ey[i] * uw[1] + c_ez[i] * uw[2]);
             double val;
             if (!ibb) {
@@ -388,8 +388,8 @@ __device__ __forceinline__ void links_body(const Params &p, const typename Store
                 double m0 = 0, m1 = 0, m2 = 0, m3 = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0;
 #pragma unroll
                 for (int j = 0; j < Q; ++j) {
-                    const double d0 = (double)Store<S>::ld(A, (long long)j * p.N + n, p.inv_scale);
-                    const double d1 = (double)Store<S>::ld(A, (long long)j * p.N + ff, p.inv_scale);
+                    const double d0 = (double)Store<S>::ld(A, (long long)j * p.Ns + n, p.inv_scale);
+                    const double d1 = (double)Store<S>::ld(A, (long long)j * p.Ns + ff, p.inv_scale);
                     m0 += d0; m1 += EX[j] * d0; m2 += EY[j] * d0; m3 += EZ[j] * d0;
                     k0 += d1; k1 += EX[j] * d1; k2 += EY[j] * d1; k3 += EZ[j] * d1;
                 }
@@ -405,7 +405,7 @@ __device__ __forceinline__ void links_body(const Params &p, const typename Store
                 }
                 val = feq64d(ib, rf, ud) + fb - feq64d(ib, rf, uf) + mw;
             }
-            Store<S>::st(B, (long long)i * p.N + n, (float)(val - w * p.rho0), p.scale);
+            Store<S>::st(B, (long long)i * p.Ns + n, (float)(val - w * p.rho0), p.scale);
             // exchanged populations relative to w rho0: the uniform reference
             // pressure exerts no force (its per-link terms cancel over a closed
             // surface; a surface touching a wall has no links there)
@@ -1299,14 +1299,14 @@ __device__ void special_update(const Params &p, const typename Store<S>::T *__re
         d[i] = 0.f;
         if ((wall >> i) & 1u) {
             if (unc) missing |= 1u << i;
-            else d[i] = Store<S>::ld(A, (long long)OPP[i] * p.N + n, p.inv_scale);
+            else d[i] = Store<S>::ld(A, (long long)OPP[i] * p.Ns + n, p.inv_scale);
         } else if ((solid >> i) & 1u) {
             if (unc) missing |= 1u << i;
-            else d[i] = Store<S>::ld(B, (long long)i * p.N + n, p.inv_scale);
+            else d[i] = Store<S>::ld(B, (long long)i * p.Ns + n, p.inv_scale);
         } else {
             long long src;
             nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], src);
-            d[i] = Store<S>::ld(A, (long long)i * p.N + src, p.inv_scale);
+            d[i] = Store<S>::ld(A, (long long)i * p.Ns + src, p.inv_scale);
         }
     }
     if (missing) {
@@ -1334,7 +1334,7 @@ __device__ void special_update(const Params &p, const typename Store<S>::T *__re
     }
     collide(d, p);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Store<S>::st(B, (long long)i * p.N + n, d[i], p.scale);
+    for (int i = 0; i < Q; ++i) Store<S>::st(B, (long long)i * p.Ns + n, d[i], p.scale);
 }
 
 // Node classification over the body regions.  Where regions overlap, one
@@ -1539,12 +1539,12 @@ __global__ __launch_bounds__(256) void k_special(Params p, const typename Store<
             long long s;
             if (!nbr(p, x, y, z, -c_ex[i], -c_ey[i], -c_ez[i], s)) {
                 if (unc) missing = true;
-                else d = Store<S>::ld(A, (long long)c_opp[i] * p.N + n, p.inv_scale);
+                else d = Store<S>::ld(A, (long long)c_opp[i] * p.Ns + n, p.inv_scale);
             } else if (own_old[s] != FLUID) {
                 if (unc) missing = true;
-                else d = Store<S>::ld(B, (long long)i * p.N + n, p.inv_scale);
+                else d = Store<S>::ld(B, (long long)i * p.Ns + n, p.inv_scale);
             } else {
-                d = Store<S>::ld(A, (long long)i * p.N + s, p.inv_scale);
+                d = Store<S>::ld(A, (long long)i * p.Ns + s, p.inv_scale);
             }
         }
         if (unc) {
@@ -1571,7 +1571,7 @@ __global__ __launch_bounds__(256) void k_special(Params p, const typename Store<
         const float jx = wave_sum(lane < Q ? c_ex[i] * dv : 0.f);
         const float jy = wave_sum(lane < Q ? c_ey[i] * dv : 0.f);
         const float jz = wave_sum(lane < Q ? c_ez[i] * dv : 0.f);
-        if (lane < Q) Store<S>::st(B, (long long)i * p.N + n, collide_lane(d, i, dr, jx, jy, jz, p), p.scale);
+        if (lane < Q) Store<S>::st(B, (long long)i * p.Ns + n, collide_lane(d, i, dr, jx, jy, jz, p), p.scale);
     }
 }
 
@@ -1585,7 +1585,7 @@ __global__ void k_init_state(Params p, typename Store<S>::T *A, const int32_t *o
         for (int i = 0; i < Q; ++i) d[i] = 0.f;
         if (own[n] == FLUID) collide(d, p);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Store<S>::st(A, (long long)i * p.N + n, d[i], p.scale);
+        for (int i = 0; i < Q; ++i) Store<S>::st(A, (long long)i * p.Ns + n, d[i], p.scale);
     }
 }
 
@@ -1598,10 +1598,10 @@ __global__ void k_collide_stored(Params p, typename Store<S>::T *A, const int32_
         if (own[n] != FLUID) continue;
         float d[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = Store<S>::ld(A, (long long)i * p.N + n, p.inv_scale);
+        for (int i = 0; i < Q; ++i) d[i] = Store<S>::ld(A, (long long)i * p.Ns + n, p.inv_scale);
         collide(d, p);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Store<S>::st(A, (long long)i * p.N + n, d[i], p.scale);
+        for (int i = 0; i < Q; ++i) Store<S>::st(A, (long long)i * p.Ns + n, d[i], p.scale);
     }
 }
 

@@ -96,13 +96,13 @@ __device__ __forceinline__ void bulk_update(const Params &p, const typename Stor
     for (int i = 0; i < Q; ++i) {
         const int xs = sx[EX[i] + 1], ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
         const bool wall = (xs | ys | zs) < 0;
-        const T *Ai = wall ? A + (long long)OPP[i] * p.N : A + (long long)i * p.N;
+        const T *Ai = wall ? A + (long long)OPP[i] * p.Ns : A + (long long)i * p.Ns;
         const int src = wall ? n : (zs * p.ny + ys) * p.nx + xs;
         d[i] = Store<S>::ld(Ai, src, p.inv_scale);
     }
     collide(d, p);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Store<S>::st_nt(B + (long long)i * p.N, n, d[i], p.scale);
+    for (int i = 0; i < Q; ++i) Store<S>::st_nt(B + (long long)i * p.Ns, n, d[i], p.scale);
 }
 
 // One system: one wave covers 64 consecutive x of one (y, z) row; a block of
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(64 * BW) void k_bulk_batch(const BulkCase *__restri
     }
     if (c.skip[parity][n]) return;
     Params p;
-    p.nx = c.nx; p.ny = c.ny; p.nz = c.nz; p.periodic = c.periodic; p.N = c.N;
+    p.nx = c.nx; p.ny = c.ny; p.nz = c.nz; p.periodic = c.periodic; p.N = c.N; p.Ns = c.Ns;
     p.rho0f = c.rho0f; p.omega = c.omega; p.fcoef = c.fcoef;
     p.gx = c.gx; p.gy = c.gy; p.gz = c.gz;
     p.scale = c.scale; p.inv_scale = c.inv_scale;
