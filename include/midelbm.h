@@ -257,8 +257,10 @@ lbm_status mlp_collect(lbm_ctx *ctx, int64_t n_max, void *dev_feat, void *dev_ta
 lbm_status mlp_collect_contact(lbm_ctx *ctx, int64_t n_max, void *dev_feat, void *dev_target, int64_t *n_out);
 /* Outputs [n][4] FP32 of the network for features [n][87]: precision 0 =
  * FP16 features/weights/activations (the production form), 1 = FP32
- * throughout (a test instantiation; features are then FP32).  Enqueued on
- * the stream; uses the blob's workspace. */
+ * throughout (a test instantiation; features are then FP32), 2 = FP16 with
+ * the hidden layers as matrix-core (MFMA) tiles of 32 samples, the form the
+ * warm-started solvers use.  Enqueued on the stream; uses the blob's
+ * workspace. */
 lbm_status mlp_forward(void *dev_weights, const void *dev_feat, int64_t n, int32_t precision, float *dev_out,
                        void *hip_stream);
 /* Gradient (host [P], FP32) and loss of one batch of n <= 4096 samples:

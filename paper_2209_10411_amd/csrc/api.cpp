@@ -1168,7 +1168,7 @@ lbm_status mlp_collect(lbm_ctx *c, int64_t n_max, void *dev_feat, void *dev_targ
 lbm_status mlp_forward(void *dev_weights, const void *dev_feat, int64_t n, int32_t precision, float *dev_out,
                        void *hip_stream) {
     if (!dev_weights || !dev_feat || !dev_out) return fail(LBM_E_INVALID, "NULL argument");
-    if (n < 0 || (precision != 0 && precision != 1)) return fail(LBM_E_INVALID, "bad n or precision");
+    if (n < 0 || precision < 0 || precision > 2) return fail(LBM_E_INVALID, "bad n or precision");
     hipStream_t st = (hipStream_t)hip_stream;
     const MlpBlob b = mlp_blob(dev_weights);
     const size_t xb = precision == 1 ? 4 : 2;

@@ -1701,6 +1701,15 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
 // is replaced by the plain one.  Per block: iteration histogram and largest
 // final |C - 1|, added to the statistics.
 constexpr int NR_WARM_MAX = 30, NR_MAX = 100;
+// LDS of the warm start: the network (weights transposed for the matrix
+// cores) and one activation row per link of the round.
+template <bool WARM> struct WarmLds {
+    MlpLds L;
+    _Float16 act[32][MLP_ROW];
+};
+template <> struct WarmLds<false> {
+    int unused;
+};
 // WARM sizes the LDS for the network; a system without weights (wts NULL)
 // takes the plain iteration in either form.
 template <bool WARM>
@@ -1714,14 +1723,13 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
     __shared__ int sh[256];
     __shared__ unsigned hist[NR_HIST];
     __shared__ unsigned rmax;
-    __shared__ _Float16 wsh[WARM ? MLP_P : 1];
-    __shared__ _Float16 act[WARM ? 32 : 1][WARM ? MLP_IN + 2 * MLP_H : 1];  // inputs, h1, h2
+    __shared__ __align__(16) WarmLds<WARM> wl;
     const int t = threadIdx.x, g = t >> 3, j = t & 7;
     const bool warm = WARM && wts != nullptr;  // block-uniform
     for (int b = t; b < NR_HIST; b += 256) hist[b] = 0u;
     if (t == 0) rmax = 0u;
-    if (warm)
-        for (int k = t; k < MLP_P; k += 256) wsh[k] = wts[k];
+    if constexpr (WARM)
+        if (warm) mlp_stage_lds(wl.L, wts);  // read after the round's first barrier
     const int nl = min(cnt->n_links, p.link_cap);
     int it_sum = 0, links = 0;
     for (int l0 = bid * 32; l0 < nl; l0 += nblk * 32) {  // block-uniform trip count
@@ -1753,48 +1761,27 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
                 cps[g].img = B.img;
             }
             node_xyz(p, n, x, y, z);
-            if (warm) {
-                if (j == 0) {
-                    const int e[3] = {c_ex[i], c_ey[i], c_ez[i]};
-                    double head[7];
-                    mlp_link_head(p, B, x, y, z, e, head);
-                    for (int a = 0; a < 7; ++a) act[g][a] = (_Float16)head[a];
+            if constexpr (WARM) {
+                if (warm) {
+                    if (j == 0) {
+                        const int e[3] = {c_ex[i], c_ey[i], c_ez[i]};
+                        double head[7];
+                        mlp_link_head(p, B, x, y, z, e, head);
+                        for (int a = 0; a < 7; ++a) wl.act[g][a] = (_Float16)head[a];
+                    }
+                    for (int c = j; c < MLP_BODY; c += 8) wl.act[g][7 + c] = (_Float16)body[pid * MLP_BODY + c];
                 }
-                for (int c = j; c < MLP_BODY; c += 8) act[g][7 + c] = (_Float16)body[pid * MLP_BODY + c];
             }
         }
         __syncthreads();
         double guess = -1.0;
-        if (warm) {
-            // hidden layer 1: units 8j .. 8j+7 of this group's link
-            if (ok) {
-                float zz[8];
-                for (int u = 0; u < 8; ++u) zz[u] = (float)wsh[MLP_OFF_B1 + 8 * j + u];
-                for (int k = 0; k < MLP_IN; ++k) {
-                    const float xk = (float)act[g][k];
-                    for (int u = 0; u < 8; ++u) zz[u] += xk * (float)wsh[MLP_OFF_W1 + k * MLP_H + 8 * j + u];
-                }
-                for (int u = 0; u < 8; ++u) act[g][MLP_IN + 8 * j + u] = (_Float16)tanhf(zz[u]);
+        if constexpr (WARM) {
+            if (warm) {
+                // the round's 32 links through the hidden layers on the matrix
+                // cores (rows of groups without a link are computed and unused)
+                mlp_block_hidden(wl.L, wl.act);
+                guess = (double)mlp_group_output(wl.L, wl.act, g, 0, j);  // q: output 0
             }
-            __syncthreads();
-            if (ok) {  // hidden layer 2 (h1 occupies act[MLP_IN .. MLP_IN + 64))
-                float zz[8];
-                for (int u = 0; u < 8; ++u) zz[u] = (float)wsh[MLP_OFF_B2 + 8 * j + u];
-                for (int k = 0; k < MLP_H; ++k) {
-                    const float hk = (float)act[g][MLP_IN + k];
-                    for (int u = 0; u < 8; ++u) zz[u] += hk * (float)wsh[MLP_OFF_W2 + k * MLP_H + 8 * j + u];
-                }
-                for (int u = 0; u < 8; ++u) act[g][MLP_IN + MLP_H + 8 * j + u] = (_Float16)tanhf(zz[u]);
-            }
-            __syncthreads();
-            float o = 0.f;
-            if (ok && j < MLP_OUT) {  // output j (only q = output 0 is used)
-                o = (float)wsh[MLP_OFF_B3 + j];
-                for (int k = 0; k < MLP_H; ++k)
-                    o += (float)act[g][MLP_IN + MLP_H + k] * (float)wsh[MLP_OFF_W3 + k * MLP_OUT + j];
-            }
-            const float q0 = __shfl(o, (t & 63) & 56);
-            guess = (double)q0;
         }
         if (ok) {
             double q, resid;
@@ -1895,6 +1882,7 @@ static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b)
 static int expected_links(const Params &p) { return p.est_links > 0 ? min(p.est_links, p.link_cap) : p.link_cap; }
 int link_grid(const Params &p) { return max(1, min(cdiv(expected_links(p), 256), 2048)); }
 int link_q_grid(const Params &p) { return max(1, min(cdiv(expected_links(p), 32), NR_BLOCKS)); }
+constexpr int LINKQ_WARM_BLOCKS = 1024;
 
 template <int S>
 static void launch_step_kernels_t(const StepArgs &a) {
@@ -1954,8 +1942,8 @@ static void launch_step_kernels_t(const StepArgs &a) {
                                                                 a.part_first_blk, a.l_off,
                                                                 a.l_node, a.l_do, a.cnt, a.own_dead);
             const int qg = link_q_grid(p);
-            if (a.warm)
-                k_link_q<true><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm,
+            if (a.warm)  // fewer, longer-lived blocks: each stages the network once
+                k_link_q<true><<<min(qg, LINKQ_WARM_BLOCKS), 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm,
                                                           a.mlp_body);
             else
                 k_link_q<false><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, nullptr,

@@ -272,9 +272,31 @@ static void forward_t(const MlpBlob &b, const TA *X, const TW *W, int n, hipStre
                                                                           MLP_OUT, n, nullptr, b.out);
 }
 
+// Forward pass of 32 samples per block with the matrix-core hidden layers
+// (the link solver's form): outputs [n][4] into out.
+__global__ __launch_bounds__(256) void k_mlp_forward_mfma(const _Float16 *__restrict__ X,
+                                                          const _Float16 *__restrict__ w, int n,
+                                                          float *__restrict__ out) {
+    __shared__ __align__(16) MlpLds L;
+    __shared__ __align__(16) _Float16 act[32][MLP_ROW];
+    mlp_stage_lds(L, w);
+    const int s0 = blockIdx.x * 32;
+    for (int e = threadIdx.x; e < 32 * MLP_IN; e += blockDim.x) {
+        const int r = e / MLP_IN, k = e - r * MLP_IN;
+        act[r][k] = s0 + r < n ? X[(long long)(s0 + r) * MLP_IN + k] : (_Float16)0.f;
+    }
+    mlp_block_hidden(L, act);
+    if (threadIdx.x < 32 * MLP_OUT) {
+        const int r = threadIdx.x / MLP_OUT, o = threadIdx.x - r * MLP_OUT;
+        if (s0 + r < n) out[(long long)(s0 + r) * MLP_OUT + o] = mlp_block_output(L, act, r, o);
+    }
+}
+
 void launch_mlp_forward(const MlpBlob &b, const void *X, int n, int precision, hipStream_t s) {
     if (precision == 1) forward_t<float, float>(b, (const float *)X, b.theta, n, s);
-    else forward_t<_Float16, _Float16>(b, (const _Float16 *)X, b.w16, n, s);
+    else if (precision == 2) {
+        if (n > 0) k_mlp_forward_mfma<<<cdiv(n, 32), 256, 0, s>>>((const _Float16 *)X, b.w16, n, b.out);
+    } else forward_t<_Float16, _Float16>(b, (const _Float16 *)X, b.w16, n, s);
 }
 
 template <typename TA>

@@ -64,8 +64,106 @@ __device__ __forceinline__ void mlp_contact_head(const Params &p, const DevParti
     mlp_point_head(p, Bi, Bj.X, zero, 1.0, head);
 }
 
+// Block inference on the matrix cores: the hidden layers of 32 samples at
+// once, (32 x 88) x (88 x 64) and (32 x 64) x (64 x 64), as 32 x 32 x 8 FP16
+// MFMA tiles with FP32 accumulation (waves 0 and 1 of a 256-thread block
+// take the two 32-column halves), tanh on the accumulators, FP16
+// activations.  Weights staged in LDS transposed (row = hidden unit, the
+// reduction index contiguous), inputs padded to 88 with zeros.
+constexpr int MLP_K1 = 88;                    // inputs padded to a multiple of 8
+constexpr int MLP_ROW = MLP_K1 + 2 * MLP_H;  // one sample's LDS row: inputs, h1, h2
+struct MlpLds {
+    _Float16 w1t[MLP_H * MLP_K1];  // [unit][input]
+    _Float16 w2t[MLP_H * MLP_H];   // [unit][h1]
+    _Float16 b1[MLP_H], b2[MLP_H], w3[MLP_H * MLP_OUT], b3[MLP_OUT];
+};
+
+// All threads of the block; the caller synchronises before reading L.
+// Global reads in parameter order (coalesced), transposed on the LDS side.
+__device__ __forceinline__ void mlp_stage_lds(MlpLds &L, const _Float16 *__restrict__ w) {
+    for (int e = threadIdx.x; e < MLP_IN * MLP_H; e += blockDim.x) {
+        const int k = e / MLP_H, j = e - k * MLP_H;
+        L.w1t[j * MLP_K1 + k] = w[MLP_OFF_W1 + e];
+    }
+    for (int j = threadIdx.x; j < MLP_H; j += blockDim.x) L.w1t[j * MLP_K1 + MLP_IN] = (_Float16)0.f;
+    for (int e = threadIdx.x; e < MLP_H * MLP_H; e += blockDim.x) {
+        const int k = e / MLP_H, j = e - k * MLP_H;
+        L.w2t[j * MLP_H + k] = w[MLP_OFF_W2 + e];
+    }
+    for (int e = threadIdx.x; e < MLP_H; e += blockDim.x) {
+        L.b1[e] = w[MLP_OFF_B1 + e];
+        L.b2[e] = w[MLP_OFF_B2 + e];
+    }
+    for (int e = threadIdx.x; e < MLP_H * MLP_OUT; e += blockDim.x) L.w3[e] = w[MLP_OFF_W3 + e];
+    for (int e = threadIdx.x; e < MLP_OUT; e += blockDim.x) L.b3[e] = w[MLP_OFF_B3 + e];
+}
+
+typedef _Float16 mlp_h4 __attribute__((ext_vector_type(4)));
+typedef float mlp_f16 __attribute__((ext_vector_type(16)));
+
+// One hidden layer for 32 rows: act[r][out0 + j] = tanh(sum_k act[r][in0 + k]
+// wt[j][k] + b[j]), K a multiple of 8.  Waves 0 and 1 (columns 32w..32w+31).
+// Operand layout of v_mfma_f32_32x32x8f16: lane l holds A[l % 32][k0 + 4 (l / 32) + e]
+// and B[k0 + 4 (l / 32) + e][l % 32], e = 0..3; result register v of lane l is
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+__device__ __forceinline__ void mlp_layer_mfma(_Float16 (*act)[MLP_ROW], int in0, int K, const _Float16 *wt,
+                                               const _Float16 *b, int out0) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w >= 2) return;
+    const int r = lane & 31, kq = (lane >> 5) * 4, j = 32 * w + (lane & 31);
+    mlp_f16 acc = {};
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        const mlp_h4 a = *(const mlp_h4 *)(&act[r][in0 + k0 + kq]);
+        const mlp_h4 bb = *(const mlp_h4 *)(&wt[j * K + k0 + kq]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a, bb, acc, 0, 0, 0);
+    }
+    const float bj = (float)b[j];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        act[row][out0 + j] = (_Float16)tanhf(acc[v] + bj);
+    }
+}
+
+// Both hidden layers of the 32 rows of act (inputs in columns 0..86 written
+// and synchronised by the caller); all threads of the 256-thread block.
+// On return h1 = act[r][MLP_K1 ..], h2 = act[r][MLP_K1 + MLP_H ..] are
+// visible to every thread.
+__device__ __forceinline__ void mlp_block_hidden(const MlpLds &L, _Float16 (*act)[MLP_ROW]) {
+    if (threadIdx.x < 32) act[threadIdx.x][MLP_IN] = (_Float16)0.f;  // the padding input
+    __syncthreads();
+    mlp_layer_mfma(act, 0, MLP_K1, L.w1t, L.b1, MLP_K1);
+    __syncthreads();
+    mlp_layer_mfma(act, MLP_K1, MLP_H, L.w2t, L.b2, MLP_K1 + MLP_H);
+    __syncthreads();
+}
+
+// Output o of row r from h2 (FP32 sum of FP16 products).
+__device__ __forceinline__ float mlp_block_output(const MlpLds &L, const _Float16 (*act)[MLP_ROW], int r, int o) {
+    float z = (float)L.b3[o];
+    for (int k = 0; k < MLP_H; ++k) z += (float)act[r][MLP_K1 + MLP_H + k] * (float)L.w3[k * MLP_OUT + o];
+    return z;
+}
+
+// The same output split over an aligned group of 8 lanes (lane j of the group
+// sums h2 entries 8j .. 8j+7, then a butterfly over the group); every lane of
+// the wave calls it, and every lane of the group gets the sum.
+__device__ __forceinline__ float mlp_group_output(const MlpLds &L, const _Float16 (*act)[MLP_ROW], int r, int o,
+                                                  int j) {
+    float z = 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        z += (float)act[r][MLP_K1 + MLP_H + 8 * j + u] * (float)L.w3[(8 * j + u) * MLP_OUT + o];
+    z += __shfl_xor(z, 1);
+    z += __shfl_xor(z, 2);
+    z += __shfl_xor(z, 4);
+    return z + (float)L.b3[o];
+}
+
 // Training and inference entry points (mlp.hip).  'precision' 0: FP16
-// inputs, weights and activations; 1: FP32 throughout (test instantiation).
+// inputs, weights and activations; 1: FP32 throughout (test instantiation);
+// 2 (forward only): FP16 with the hidden layers on the matrix cores, the
+// form the link solver's warm start uses.
 // Workspace for minibatches of at most MLP_MAX_BATCH samples.
 constexpr int MLP_MAX_BATCH = 4096;
 struct MlpBlob {

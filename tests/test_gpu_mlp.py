@@ -98,6 +98,26 @@ def test_forward_and_gradient_match_oracle(mdl, precision):
     assert loss == pytest.approx(omlp.loss(th, Xr, Tr), rel=tol)
 
 
+@pytest.mark.parametrize("n", [250, 33, 1])
+def test_matrix_core_forward_matches_oracle_and_fma_form(mdl, n):
+    """Precision 2 (hidden layers on the matrix cores, 32 samples a block,
+    ragged last block) against the oracle on the same FP16-rounded inputs
+    and weights, and against the FMA form (precision 0), which differs only
+    in the order of the FP32 sums."""
+    import torch
+    theta = params(21).astype(np.float32)
+    net = mdl.Mlp(theta)
+    X, _ = rand_batch(np.random.default_rng(22), n)
+    Xd = torch.tensor(X, dtype=torch.float16, device="cuda:0")
+    out = net.forward(Xd, 2).cpu().numpy()
+    ref, _ = omlp.forward(theta.astype(np.float16).astype(np.float64), X.astype(np.float16).astype(np.float64))
+    scale = np.abs(ref).max()
+    assert out.shape == (n, 4) and np.all(np.isfinite(out))
+    assert np.abs(out - ref).max() <= 2e-2 * scale, np.abs(out - ref).max() / scale
+    fma = net.forward(Xd, 0).cpu().numpy()
+    assert np.abs(out - fma).max() <= 4e-3 * scale, np.abs(out - fma).max() / scale
+
+
 def test_adam_steps_match_oracle(mdl):
     """FP32 instantiation, two minibatches; eps large enough that tiny
     gradients do not make the step sign-sensitive to rounding."""
