@@ -542,10 +542,13 @@ static lbm_status prepare(const lbm_config *cfg, int32_t n_p, const lbm_particle
         for (int a = 0; a < 4; ++a) d.q[a] = q.quat[a] / qn;
         double R[9];
         rot_of_quat(d.q, R);
+        double ksum = 0.0;
         for (int i = 0; i < q.n_cp; ++i) {
             d.k[i] = q.cp_k[i];
+            ksum += d.k[i];
             for (int a = 0; a < 3; ++a) d.cpb[i][a] = q.cp_xyz[3 * i + a] - bp.c[a];
         }
+        d.rsk = 1.0 / std::sqrt(ksum);
         for (int a = 0; a < 3; ++a) {
             d.X[a] = q.x[a] + R[3 * a] * bp.c[0] + R[3 * a + 1] * bp.c[1] + R[3 * a + 2] * bp.c[2];
             d.v[a] = q.v[a];

@@ -51,7 +51,8 @@ struct DevParticle {
     double reach;
     double Xf[2][3];
     int hist;
-    int img;  // 0: no periodic image shifts any point evaluated near this body (see refresh_pose)
+    int img;     // 0: no periodic image shifts any point evaluated near this body (see refresh_pose)
+    double rsk;  // 1 / sqrt(sum k), the warm start's length scale (sum in point order)
 };
 
 // Small device-side counters, reset and read by the host at sync points.

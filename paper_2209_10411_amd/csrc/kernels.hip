@@ -1701,17 +1701,76 @@ __global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const
 // is replaced by the plain one.  Per block: iteration histogram and largest
 // final |C - 1|, added to the statistics.
 constexpr int NR_WARM_MAX = 30, NR_MAX = 100;
-// LDS of the warm start: the network (weights transposed for the matrix
-// cores) and one activation row per link of the round.
-template <bool WARM> struct WarmLds {
-    MlpLds L;
-    _Float16 act[32][MLP_ROW];
-};
-template <> struct WarmLds<false> {
-    int unused;
-};
-// WARM sizes the LDS for the network; a system without weights (wts NULL)
-// takes the plain iteration in either form.
+// Warm start, first pass: the network's q for every link of the list, written
+// to l_q as the solver's start (one wave per 32 links, the wave inference of
+// mlp_dev.h; links with an invalid record get nothing, the solver reports
+// them).  No block barrier: a wave without links returns at once.
+__device__ __forceinline__ void link_guess_body(const Params &p, const DevParticle *__restrict__ P,
+                                                const uint32_t *__restrict__ l_node,
+                                                const uint32_t *__restrict__ l_do, const Counters *cnt,
+                                                const _Float16 *__restrict__ wts, const float *__restrict__ body,
+                                                double *__restrict__ l_q, const int bid, const int nblk) {
+    const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
+    const int wv = bid * 4 + (threadIdx.x >> 6), nw = nblk * 4;  // 256-thread blocks
+    const int nl = min(cnt->n_links, p.link_cap);
+    if (wts == nullptr || p.np <= 0 || wv * 32 >= nl) return;
+    MlpWave W;
+    mlp_wave_load(W, wts);
+    _Float16 w3[1][32];
+    mlp_wave_load_out(w3[0], wts, 0);
+    const float b3 = (float)wts[MLP_OFF_B3];
+    for (int l0 = wv * 32; l0 < nl; l0 += nw * 32) {
+        const int l = l0 + s;
+        bool ok = l < nl;
+        int pid = 0, i = 1;
+        long long n = 0;
+        if (ok) {
+            n = l_node[l];
+            i = (int)(l_do[l] & 31u);
+            pid = (int)(l_do[l] >> 8);
+            ok = n < p.N && pid < p.np && i >= 1 && i < Q;
+        }
+        if (!ok) pid = 0;  // loads stay inside body 0's block; the row is zeroed
+        double head[7] = {};
+        if (ok && h == 0) {  // chunk 0: inputs 0..6
+            int x, y, z;
+            node_xyz(p, n, x, y, z);
+            const int e[3] = {c_ex[i], c_ey[i], c_ez[i]};
+            mlp_link_head(p, P[pid], x, y, z, e, head);
+        }
+        // chunks 2m + h of the body block (chunk c = body entries 8 (c - 1) ..)
+        const float4 *bb = (const float4 *)(body + (long long)pid * MLP_BODY);  // 320-byte rows
+        mlp_h8 xin[MLP_S1];
+#pragma unroll
+        for (int m = 0; m < MLP_S1; ++m) {
+            const int c = m == 0 ? 1 : (m == MLP_S1 - 1 ? 10 : 2 * m + h);  // a body chunk, 1..10
+            const float4 u0 = bb[2 * (c - 1)], u1 = bb[2 * (c - 1) + 1];
+            const float bv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+            const int cm = 2 * m + h;  // the chunk this slot takes
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                _Float16 v;
+                if (m == 0) v = h == 0 ? (e < 7 ? (_Float16)head[e < 7 ? e : 0] : (_Float16)1.f) : (_Float16)bv[e];
+                else v = cm <= 10 ? (_Float16)bv[e] : (_Float16)0.f;
+                xin[m][e] = ok ? v : (_Float16)(cm == 0 && e == 7 ? 1.f : 0.f);
+            }
+        }
+        float q[1];
+        mlp_wave_forward<1>(W, xin, w3, &b3, q);
+        if (ok && h == 0) l_q[l] = (double)q[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_link_guess(Params p, const DevParticle *__restrict__ P,
+                                                    const uint32_t *__restrict__ l_node,
+                                                    const uint32_t *__restrict__ l_do, const Counters *cnt,
+                                                    const _Float16 *__restrict__ wts,
+                                                    const float *__restrict__ body, double *__restrict__ l_q) {
+    link_guess_body(p, P, l_node, l_do, cnt, wts, body, l_q, blockIdx.x, gridDim.x);
+}
+
+// Second pass (or the plain solve): WARM takes the start from l_q; a system
+// without weights (wts NULL) takes the plain iteration in either form.
 template <bool WARM>
 __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *__restrict__ P,
                                             const uint32_t *__restrict__ l_node,
@@ -1723,13 +1782,10 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
     __shared__ int sh[256];
     __shared__ unsigned hist[NR_HIST];
     __shared__ unsigned rmax;
-    __shared__ __align__(16) WarmLds<WARM> wl;
     const int t = threadIdx.x, g = t >> 3, j = t & 7;
     const bool warm = WARM && wts != nullptr;  // block-uniform
     for (int b = t; b < NR_HIST; b += 256) hist[b] = 0u;
     if (t == 0) rmax = 0u;
-    if constexpr (WARM)
-        if (warm) mlp_stage_lds(wl.L, wts);  // read after the round's first barrier
     const int nl = min(cnt->n_links, p.link_cap);
     int it_sum = 0, links = 0;
     for (int l0 = bid * 32; l0 < nl; l0 += nblk * 32) {  // block-uniform trip count
@@ -1761,28 +1817,10 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
                 cps[g].img = B.img;
             }
             node_xyz(p, n, x, y, z);
-            if constexpr (WARM) {
-                if (warm) {
-                    if (j == 0) {
-                        const int e[3] = {c_ex[i], c_ey[i], c_ez[i]};
-                        double head[7];
-                        mlp_link_head(p, B, x, y, z, e, head);
-                        for (int a = 0; a < 7; ++a) wl.act[g][a] = (_Float16)head[a];
-                    }
-                    for (int c = j; c < MLP_BODY; c += 8) wl.act[g][7 + c] = (_Float16)body[pid * MLP_BODY + c];
-                }
-            }
         }
-        __syncthreads();
         double guess = -1.0;
-        if constexpr (WARM) {
-            if (warm) {
-                // the round's 32 links through the hidden layers on the matrix
-                // cores (rows of groups without a link are computed and unused)
-                mlp_block_hidden(wl.L, wl.act);
-                guess = (double)mlp_group_output(wl.L, wl.act, g, 0, j);  // q: output 0
-            }
-        }
+        if (warm && ok) guess = l_q[l];  // the first pass's network output
+        __syncthreads();
         if (ok) {
             double q, resid;
             bool conv;
@@ -1868,6 +1906,13 @@ __global__ __launch_bounds__(BLK) void k_link_emit_batch(const CaseArgs *__restr
               a.own_dead, (int)blockIdx.x - a.first[BK_REGION], a.nblk[BK_REGION]);
 }
 
+__global__ __launch_bounds__(256) void k_link_guess_batch(const CaseArgs *__restrict__ cs,
+                                                          const int *__restrict__ map) {
+    const CaseArgs &a = cs[map[blockIdx.x]];
+    link_guess_body(a.p, a.P, a.l_node, a.l_do, a.cnt, a.warm, a.mlp_body, a.l_q,
+                    (int)blockIdx.x - a.first[BK_LINKQ], a.nblk[BK_LINKQ]);
+}
+
 template <bool WARM>
 __global__ __launch_bounds__(256) void k_link_q_batch(const CaseArgs *__restrict__ cs, const int *__restrict__ map) {
     const CaseArgs &a = cs[map[blockIdx.x]];
@@ -1882,7 +1927,7 @@ static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b)
 static int expected_links(const Params &p) { return p.est_links > 0 ? min(p.est_links, p.link_cap) : p.link_cap; }
 int link_grid(const Params &p) { return max(1, min(cdiv(expected_links(p), 256), 2048)); }
 int link_q_grid(const Params &p) { return max(1, min(cdiv(expected_links(p), 32), NR_BLOCKS)); }
-constexpr int LINKQ_WARM_BLOCKS = 1024;
+constexpr int LINK_GUESS_BLOCKS = 1024;  // 4096 waves, each loads the network once
 
 template <int S>
 static void launch_step_kernels_t(const StepArgs &a) {
@@ -1942,10 +1987,12 @@ static void launch_step_kernels_t(const StepArgs &a) {
                                                                 a.part_first_blk, a.l_off,
                                                                 a.l_node, a.l_do, a.cnt, a.own_dead);
             const int qg = link_q_grid(p);
-            if (a.warm)  // fewer, longer-lived blocks: each stages the network once
-                k_link_q<true><<<min(qg, LINKQ_WARM_BLOCKS), 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm,
+            if (a.warm) {  // the network's guesses over the list, then the solve
+                k_link_guess<<<min(cdiv(expected_links(p), 128), LINK_GUESS_BLOCKS), 256, 0, a.stream>>>(
+                    p, a.P, a.l_node, a.l_do, a.cnt, a.warm, a.mlp_body, a.l_q);
+                k_link_q<true><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm,
                                                           a.mlp_body);
-            else
+            } else
                 k_link_q<false><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, nullptr,
                                                            nullptr);
         }
@@ -1995,7 +2042,10 @@ static void launch_case_batch_t(BatchOp op, const CaseArgs *cs, const int *map, 
         case OP_CLASSIFY: k_region_classify_batch<S><<<nblocks, BLK, 0, s>>>(cs, map); break;
         case OP_EMIT: k_link_emit_batch<<<nblocks, BLK, 0, s>>>(cs, map); break;
         case OP_LINKQ: k_link_q_batch<false><<<nblocks, 256, 0, s>>>(cs, map); break;
-        case OP_LINKQ_WARM: k_link_q_batch<true><<<nblocks, 256, 0, s>>>(cs, map); break;
+        case OP_LINKQ_WARM:  // guesses of the systems with a network, then every solve
+            k_link_guess_batch<<<nblocks, 256, 0, s>>>(cs, map);
+            k_link_q_batch<true><<<nblocks, 256, 0, s>>>(cs, map);
+            break;
     }
 }
 

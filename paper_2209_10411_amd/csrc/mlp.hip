@@ -274,28 +274,48 @@ static void forward_t(const MlpBlob &b, const TA *X, const TW *W, int n, hipStre
 
 // Forward pass of 32 samples per block with the matrix-core hidden layers
 // (the link solver's form): outputs [n][4] into out.
+// Wave inference: each wave loads the network once and takes tiles of 32
+// samples (grid stride).
 __global__ __launch_bounds__(256) void k_mlp_forward_mfma(const _Float16 *__restrict__ X,
                                                           const _Float16 *__restrict__ w, int n,
                                                           float *__restrict__ out) {
-    __shared__ __align__(16) MlpLds L;
-    __shared__ __align__(16) _Float16 act[32][MLP_ROW];
-    mlp_stage_lds(L, w);
-    const int s0 = blockIdx.x * 32;
-    for (int e = threadIdx.x; e < 32 * MLP_IN; e += blockDim.x) {
-        const int r = e / MLP_IN, k = e - r * MLP_IN;
-        act[r][k] = s0 + r < n ? X[(long long)(s0 + r) * MLP_IN + k] : (_Float16)0.f;
+    const int lane = threadIdx.x & 63, s = lane & 31, h = lane >> 5;
+    const int wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nw = gridDim.x * (blockDim.x >> 6);
+    if (wv * 32 >= n) return;  // wave-uniform; no block barrier in this kernel
+    MlpWave W;
+    mlp_wave_load(W, w);
+    _Float16 w3[MLP_OUT][32];
+    float b3[MLP_OUT];
+#pragma unroll
+    for (int o = 0; o < MLP_OUT; ++o) {
+        mlp_wave_load_out(w3[o], w, o);
+        b3[o] = (float)w[MLP_OFF_B3 + o];
     }
-    mlp_block_hidden(L, act);
-    if (threadIdx.x < 32 * MLP_OUT) {
-        const int r = threadIdx.x / MLP_OUT, o = threadIdx.x - r * MLP_OUT;
-        if (s0 + r < n) out[(long long)(s0 + r) * MLP_OUT + o] = mlp_block_output(L, act, r, o);
+    for (int r0 = wv * 32; r0 < n; r0 += nw * 32) {
+        const int r = r0 + s;
+        const bool ok = r < n;
+        const _Float16 *xr = X + (long long)(ok ? r : 0) * MLP_IN;
+        mlp_h8 x[MLP_S1];
+#pragma unroll
+        for (int m = 0; m < MLP_S1; ++m)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = mlp_l1_input(2 * m + h, e);
+                const _Float16 v = xr[k >= 0 ? k : 0];
+                x[m][e] = k >= 0 ? (ok ? v : (_Float16)0.f) : (k == -1 ? (_Float16)1.f : (_Float16)0.f);
+            }
+        float z[MLP_OUT];
+        mlp_wave_forward<MLP_OUT>(W, x, w3, b3, z);
+#pragma unroll
+        for (int o = 0; o < MLP_OUT; ++o)
+            if (ok && h == (o & 1)) out[(long long)r * MLP_OUT + o] = z[o];
     }
 }
 
 void launch_mlp_forward(const MlpBlob &b, const void *X, int n, int precision, hipStream_t s) {
     if (precision == 1) forward_t<float, float>(b, (const float *)X, b.theta, n, s);
     else if (precision == 2) {
-        if (n > 0) k_mlp_forward_mfma<<<cdiv(n, 32), 256, 0, s>>>((const _Float16 *)X, b.w16, n, b.out);
+        if (n > 0) k_mlp_forward_mfma<<<min(cdiv(n, 128), 1024), 256, 0, s>>>((const _Float16 *)X, b.w16, n, b.out);
     } else forward_t<_Float16, _Float16>(b, (const _Float16 *)X, b.w16, n, s);
 }
 

@@ -32,9 +32,7 @@ __device__ __forceinline__ void mlp_point_head(const Params &p, const DevParticl
     const int L[3] = {p.nx, p.ny, p.nz};
     for (int a = 0; a < 3; ++a)
         if ((p.periodic >> a) & 1u) d[a] -= L[a] * floor(d[a] / L[a] + 0.5);
-    double K = 0.0;
-    for (int c = 0; c < B.n_cp; ++c) K += B.k[c];
-    const double inv_s = 1.0 / sqrt(K);
+    const double inv_s = B.rsk;
     const double w = B.q[0], qx = B.q[1], qy = B.q[2], qz = B.q[3];
     // body -> lab rotation R; the body frame takes R^T
     const double R[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - w * qz), 2.0 * (qx * qz + w * qy),
@@ -64,106 +62,128 @@ __device__ __forceinline__ void mlp_contact_head(const Params &p, const DevParti
     mlp_point_head(p, Bi, Bj.X, zero, 1.0, head);
 }
 
-// Block inference on the matrix cores: the hidden layers of 32 samples at
-// once, (32 x 88) x (88 x 64) and (32 x 64) x (64 x 64), as 32 x 32 x 8 FP16
-// MFMA tiles with FP32 accumulation (waves 0 and 1 of a 256-thread block
-// take the two 32-column halves), tanh on the accumulators, FP16
-// activations.  Weights staged in LDS transposed (row = hidden unit, the
-// reduction index contiguous), inputs padded to 88 with zeros.
-constexpr int MLP_K1 = 88;                    // inputs padded to a multiple of 8
-constexpr int MLP_ROW = MLP_K1 + 2 * MLP_H;  // one sample's LDS row: inputs, h1, h2
-struct MlpLds {
-    _Float16 w1t[MLP_H * MLP_K1];  // [unit][input]
-    _Float16 w2t[MLP_H * MLP_H];   // [unit][h1]
-    _Float16 b1[MLP_H], b2[MLP_H], w3[MLP_H * MLP_OUT], b3[MLP_OUT];
-};
-
-// All threads of the block; the caller synchronises before reading L.
-// Global reads in parameter order (coalesced), transposed on the LDS side.
-__device__ __forceinline__ void mlp_stage_lds(MlpLds &L, const _Float16 *__restrict__ w) {
-    for (int e = threadIdx.x; e < MLP_IN * MLP_H; e += blockDim.x) {
-        const int k = e / MLP_H, j = e - k * MLP_H;
-        L.w1t[j * MLP_K1 + k] = w[MLP_OFF_W1 + e];
-    }
-    for (int j = threadIdx.x; j < MLP_H; j += blockDim.x) L.w1t[j * MLP_K1 + MLP_IN] = (_Float16)0.f;
-    for (int e = threadIdx.x; e < MLP_H * MLP_H; e += blockDim.x) {
-        const int k = e / MLP_H, j = e - k * MLP_H;
-        L.w2t[j * MLP_H + k] = w[MLP_OFF_W2 + e];
-    }
-    for (int e = threadIdx.x; e < MLP_H; e += blockDim.x) {
-        L.b1[e] = w[MLP_OFF_B1 + e];
-        L.b2[e] = w[MLP_OFF_B2 + e];
-    }
-    for (int e = threadIdx.x; e < MLP_H * MLP_OUT; e += blockDim.x) L.w3[e] = w[MLP_OFF_W3 + e];
-    for (int e = threadIdx.x; e < MLP_OUT; e += blockDim.x) L.b3[e] = w[MLP_OFF_B3 + e];
-}
-
-typedef _Float16 mlp_h4 __attribute__((ext_vector_type(4)));
+// Wave inference on the matrix cores: 32 samples per wave, every operand in
+// registers.  With the transposed product Z^T = W^T X^T the weights are the A
+// operands of v_mfma_f32_32x32x16_f16 (loaded once per wave and kept) and
+// the samples the B operands; a 32 x 32 tile of units x samples per MFMA
+// chain, FP32 accumulation, tanh on the accumulators, FP16 activations.
+// Operand layout (32 x 32 x 16): lane l holds A[l % 32][8 (l / 32) + e] and
+// B[8 (l / 32) + e][l % 32], e = 0..7; result register v of lane l is
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].  So lane l holds, for sample
+// l % 32, sixteen units of each 32-unit tile, and those are the B operands
+// of the next layer once its contraction index follows the same order
+// (mlp_l2_unit); no activation leaves the registers.
+// The order of a contraction is free, so layer 1 takes its inputs in chunks
+// of 8 that a lane loads whole: chunk c = 2 m + h fills the slots of step m,
+// lane half h: chunk 0 = inputs 0..6 and a constant 1 (carries b1), chunks
+// 1..10 = the body block (inputs 7 + 8 (c - 1) + e), chunk 11 = zeros.
+// Layer 2 takes b2 on a constant 1 in a fifth step.
+constexpr int MLP_S1 = 6;  // K steps of layer 1 (12 chunks of 8)
+constexpr int MLP_S2 = 5;  // K steps of layer 2: 64 units, then 1 and zeros
+typedef _Float16 mlp_h8 __attribute__((ext_vector_type(8)));
 typedef float mlp_f16 __attribute__((ext_vector_type(16)));
 
-// One hidden layer for 32 rows: act[r][out0 + j] = tanh(sum_k act[r][in0 + k]
-// wt[j][k] + b[j]), K a multiple of 8.  Waves 0 and 1 (columns 32w..32w+31).
-// Operand layout of v_mfma_f32_32x32x8f16: lane l holds A[l % 32][k0 + 4 (l / 32) + e]
-// and B[k0 + 4 (l / 32) + e][l % 32], e = 0..3; result register v of lane l is
-// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
-__device__ __forceinline__ void mlp_layer_mfma(_Float16 (*act)[MLP_ROW], int in0, int K, const _Float16 *wt,
-                                               const _Float16 *b, int out0) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (w >= 2) return;
-    const int r = lane & 31, kq = (lane >> 5) * 4, j = 32 * w + (lane & 31);
-    mlp_f16 acc = {};
-    for (int k0 = 0; k0 < K; k0 += 8) {
-        const mlp_h4 a = *(const mlp_h4 *)(&act[r][in0 + k0 + kq]);
-        const mlp_h4 bb = *(const mlp_h4 *)(&wt[j * K + k0 + kq]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a, bb, acc, 0, 0, 0);
+struct MlpWave {
+    mlp_h8 w1[2][MLP_S1];  // A operands: tile t (units 32t..32t+31), step m
+    mlp_h8 w2[2][MLP_S2];
+};
+
+// Input in slot e of chunk c (-1: the constant 1, -2: zero).
+__device__ __forceinline__ int mlp_l1_input(int c, int e) {
+    return c == 0 ? (e < 7 ? e : -1) : (c <= 10 ? 7 + 8 * (c - 1) + e : -2);
+}
+// Unit of layer 1 in slot e of layer-2 step m for lane half h: registers
+// 8 (m % 2) + e of layer 1's tile m / 2.
+__device__ __forceinline__ int mlp_l2_unit(int m, int h, int e) {
+    return 32 * (m >> 1) + 16 * (m & 1) + 8 * (e >> 2) + 4 * h + (e & 3);
+}
+// Unit in register v of tile t of a layer's result, lane half h.
+__device__ __forceinline__ int mlp_out_unit(int t, int v, int h) { return 32 * t + 8 * (v >> 2) + 4 * h + (v & 3); }
+
+// tanh as 1 - 2 / (1 + e^(2x)) on the hardware exp2 and reciprocal (a few
+// ulp of FP32 away from tanhf, below the FP16 rounding that follows).
+__device__ __forceinline__ float mlp_tanh(float x) {
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 / ln 2
+    return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
+}
+
+// The calling wave's A operands from the parameters w (FP16, parameter order).
+__device__ __forceinline__ void mlp_wave_load(MlpWave &W, const _Float16 *__restrict__ w) {
+    const int lane = threadIdx.x & 63, jl = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int j = 32 * t + jl;
+#pragma unroll
+        for (int m = 0; m < MLP_S1; ++m)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = mlp_l1_input(2 * m + h, e);
+                W.w1[t][m][e] = k >= 0 ? w[MLP_OFF_W1 + k * MLP_H + j]
+                                       : (k == -1 ? w[MLP_OFF_B1 + j] : (_Float16)0.f);
+            }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) W.w2[t][m][e] = w[MLP_OFF_W2 + mlp_l2_unit(m, h, e) * MLP_H + j];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) W.w2[t][4][e] = (h == 0 && e == 0) ? w[MLP_OFF_B2 + j] : (_Float16)0.f;
     }
-    const float bj = (float)b[j];
+}
+
+// Output o's weights of the lane's 32 units (tile t, register v at 16 t + v).
+__device__ __forceinline__ void mlp_wave_load_out(_Float16 w3[32], const _Float16 *__restrict__ w, int o) {
+    const int h = (threadIdx.x & 63) >> 5;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) w3[16 * t + v] = w[MLP_OFF_W3 + mlp_out_unit(t, v, h) * MLP_OUT + o];
+}
+
+// Both hidden layers of the wave's 32 samples and NO outputs.  x: the B
+// operands of layer 1 (lane l: chunk 2 m + l / 32 of sample l % 32 in step
+// m); w3[o]: mlp_wave_load_out's weights of output o, b3[o] its bias.  Every
+// lane of the wave calls it; both lanes of a sample get its outputs.
+// Activations are rounded to FP16 as stored ones are.
+template <int NO>
+__device__ __forceinline__ void mlp_wave_forward(const MlpWave &W, const mlp_h8 x[MLP_S1], const _Float16 (*w3)[32],
+                                                 const float *b3, float out[NO]) {
+    const int h = (threadIdx.x & 63) >> 5;
+    mlp_f16 a0 = {}, a1 = {};
+#pragma unroll
+    for (int m = 0; m < MLP_S1; ++m) {
+        a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(W.w1[0][m], x[m], a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(W.w1[1][m], x[m], a1, 0, 0, 0);
+    }
+    mlp_h8 y[MLP_S2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) y[m][e] = (_Float16)mlp_tanh((m < 2 ? a0 : a1)[8 * (m & 1) + e]);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) y[4][e] = (h == 0 && e == 0) ? (_Float16)1.f : (_Float16)0.f;
+    a0 = mlp_f16{};
+    a1 = mlp_f16{};
+#pragma unroll
+    for (int m = 0; m < MLP_S2; ++m) {
+        a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(W.w2[0][m], y[m], a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(W.w2[1][m], y[m], a1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o) out[o] = 0.f;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        act[row][out0 + j] = (_Float16)tanhf(acc[v] + bj);
-    }
-}
-
-// Both hidden layers of the 32 rows of act (inputs in columns 0..86 written
-// and synchronised by the caller); all threads of the 256-thread block.
-// On return h1 = act[r][MLP_K1 ..], h2 = act[r][MLP_K1 + MLP_H ..] are
-// visible to every thread.
-__device__ __forceinline__ void mlp_block_hidden(const MlpLds &L, _Float16 (*act)[MLP_ROW]) {
-    if (threadIdx.x < 32) act[threadIdx.x][MLP_IN] = (_Float16)0.f;  // the padding input
-    __syncthreads();
-    mlp_layer_mfma(act, 0, MLP_K1, L.w1t, L.b1, MLP_K1);
-    __syncthreads();
-    mlp_layer_mfma(act, MLP_K1, MLP_H, L.w2t, L.b2, MLP_K1 + MLP_H);
-    __syncthreads();
-}
-
-// Output o of row r from h2 (FP32 sum of FP16 products).
-__device__ __forceinline__ float mlp_block_output(const MlpLds &L, const _Float16 (*act)[MLP_ROW], int r, int o) {
-    float z = (float)L.b3[o];
-    for (int k = 0; k < MLP_H; ++k) z += (float)act[r][MLP_K1 + MLP_H + k] * (float)L.w3[k * MLP_OUT + o];
-    return z;
-}
-
-// The same output split over an aligned group of 8 lanes (lane j of the group
-// sums h2 entries 8j .. 8j+7, then a butterfly over the group); every lane of
-// the wave calls it, and every lane of the group gets the sum.
-__device__ __forceinline__ float mlp_group_output(const MlpLds &L, const _Float16 (*act)[MLP_ROW], int r, int o,
-                                                  int j) {
-    float z = 0.f;
+        const float y0 = (float)(_Float16)mlp_tanh(a0[v]), y1 = (float)(_Float16)mlp_tanh(a1[v]);
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-        z += (float)act[r][MLP_K1 + MLP_H + 8 * j + u] * (float)L.w3[(8 * j + u) * MLP_OUT + o];
-    z += __shfl_xor(z, 1);
-    z += __shfl_xor(z, 2);
-    z += __shfl_xor(z, 4);
-    return z + (float)L.b3[o];
+        for (int o = 0; o < NO; ++o) out[o] += y0 * (float)w3[o][v] + y1 * (float)w3[o][16 + v];
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o) out[o] += __shfl_xor(out[o], 32) + b3[o];
 }
 
 // Training and inference entry points (mlp.hip).  'precision' 0: FP16
 // inputs, weights and activations; 1: FP32 throughout (test instantiation);
-// 2 (forward only): FP16 with the hidden layers on the matrix cores, the
-// form the link solver's warm start uses.
+// 2 (forward only): FP16 with the hidden layers on the matrix cores (the
+// wave inference above, the form of the link solver's warm start).
 // Workspace for minibatches of at most MLP_MAX_BATCH samples.
 constexpr int MLP_MAX_BATCH = 4096;
 struct MlpBlob {
