@@ -35,6 +35,13 @@
 namespace mdl {
 
 __device__ __forceinline__ void node_xyz(const Params &p, long long n, int &x, int &y, int &z) {
+    if (p.N <= 0xffffffffLL) {  // 32-bit quotients (far shorter than 64-bit division)
+        const unsigned u = (unsigned)n, r = u / (unsigned)p.nx;
+        x = (int)(u - r * (unsigned)p.nx);
+        y = (int)(r % (unsigned)p.ny);
+        z = (int)(r / (unsigned)p.ny);
+        return;
+    }
     x = (int)(n % p.nx);
     long long r = n / p.nx;
     y = (int)(r % p.ny);
@@ -1775,8 +1782,7 @@ template <bool WARM>
 __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *__restrict__ P,
                                             const uint32_t *__restrict__ l_node,
                                             const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
-                                            Counters *cnt, const NrStats &nrs,
-                                            const _Float16 *__restrict__ wts, const float *__restrict__ body,
+                                            Counters *cnt, const NrStats &nrs, const _Float16 *__restrict__ wts,
                                             const int bid, const int nblk) {
     __shared__ CPs cps[32];
     __shared__ int sh[256];
@@ -1788,15 +1794,26 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
     if (t == 0) rmax = 0u;
     const int nl = min(cnt->n_links, p.link_cap);
     int it_sum = 0, links = 0;
+    // the next round's link record is loaded while this round solves
+    uint32_t nx_node = 0, nx_do = 0;
+    if (bid * 32 + g < nl) {
+        nx_node = l_node[bid * 32 + g];
+        nx_do = l_do[bid * 32 + g];
+    }
     for (int l0 = bid * 32; l0 < nl; l0 += nblk * 32) {  // block-uniform trip count
         const int l = l0 + g;
         const bool ok0 = l < nl;
+        const uint32_t cur_node = nx_node, cur_do = nx_do;
+        if (l + nblk * 32 < nl) {
+            nx_node = l_node[l + nblk * 32];
+            nx_do = l_do[l + nblk * 32];
+        }
         int pid = 0, i = 1;
         long long n = 0;
         if (ok0) {
-            n = l_node[l];
-            i = (int)(l_do[l] & 31u);
-            pid = (int)(l_do[l] >> 8);
+            n = cur_node;
+            i = (int)(cur_do & 31u);
+            pid = (int)(cur_do >> 8);
             if (n >= p.N || pid >= p.np || i < 1 || i >= Q) {  // never expected: report, solve nothing
                 if (j == 0) atomicOr(&cnt->err, ERR_BAD_INDEX);
             }
@@ -1856,9 +1873,8 @@ template <bool WARM>
 __global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__restrict__ P,
                                                 const uint32_t *__restrict__ l_node,
                                                 const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
-                                                Counters *cnt, NrStats nrs,
-                                                const _Float16 *__restrict__ wts, const float *__restrict__ body) {
-    link_q_body<WARM>(p, P, l_node, l_do, l_q, cnt, nrs, wts, body, blockIdx.x, gridDim.x);
+                                                Counters *cnt, NrStats nrs, const _Float16 *__restrict__ wts) {
+    link_q_body<WARM>(p, P, l_node, l_do, l_q, cnt, nrs, wts, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------- batched boundary kernels
@@ -1916,8 +1932,8 @@ __global__ __launch_bounds__(256) void k_link_guess_batch(const CaseArgs *__rest
 template <bool WARM>
 __global__ __launch_bounds__(256) void k_link_q_batch(const CaseArgs *__restrict__ cs, const int *__restrict__ map) {
     const CaseArgs &a = cs[map[blockIdx.x]];
-    link_q_body<WARM>(a.p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm, a.mlp_body,
-                      (int)blockIdx.x - a.first[BK_LINKQ], a.nblk[BK_LINKQ]);
+    link_q_body<WARM>(a.p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm, (int)blockIdx.x - a.first[BK_LINKQ],
+                      a.nblk[BK_LINKQ]);
 }
 
 // ------------------------------------------------------------ host launchers
@@ -1990,11 +2006,9 @@ static void launch_step_kernels_t(const StepArgs &a) {
             if (a.warm) {  // the network's guesses over the list, then the solve
                 k_link_guess<<<min(cdiv(expected_links(p), 128), LINK_GUESS_BLOCKS), 256, 0, a.stream>>>(
                     p, a.P, a.l_node, a.l_do, a.cnt, a.warm, a.mlp_body, a.l_q);
-                k_link_q<true><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm,
-                                                          a.mlp_body);
+                k_link_q<true><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, a.warm);
             } else
-                k_link_q<false><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, nullptr,
-                                                           nullptr);
+                k_link_q<false><<<qg, 256, 0, a.stream>>>(p, a.P, a.l_node, a.l_do, a.l_q, a.cnt, a.nrs, nullptr);
         }
     } else if (a.phase == PHASE_INIT_STATE) {
         k_init_state<S><<<2048, 256, 0, a.stream>>>(p, A, a.own_old);
