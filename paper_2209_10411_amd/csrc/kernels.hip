@@ -1091,14 +1091,40 @@ __global__ __launch_bounds__(256) void k_contact_guess(Params p, const DevPartic
     g[3] = 0.0;
 }
 
+// One wave per body: lane l sums the pairs j = l, l + 64, ... in contact and
+// wall l (< 6), the wave adds the partial sums by a butterfly (a fixed
+// order), and lane 0 steps the body.
 __global__ __launch_bounds__(256) void k_contact_bodies(Params p, DevParticle *__restrict__ P, ContactBufs cb,
                                                         Counters *__restrict__ cnt, int first, int last) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= p.np) return;
+    const int lane = threadIdx.x & 63, q = blockIdx.x * 4 + (threadIdx.x >> 6), np = p.np;
+    if (q >= np) return;  // wave-uniform
+    double s[6] = {0, 0, 0, 0, 0, 0};  // contact force, torque
+    if (p.contact) {
+        const uint8_t *on = cb.pairOn + (long long)q * np;
+        for (int j = lane; j < np; j += 64) {
+            if (j == q || !on[j]) continue;
+            if (j < q) {
+                const long long k = (long long)j * np + q;
+                for (int a = 0; a < 3; ++a) { s[a] -= cb.pairF[3 * k + a]; s[3 + a] += cb.pairTj[3 * k + a]; }
+            } else {
+                const long long k = (long long)q * np + j;
+                for (int a = 0; a < 3; ++a) { s[a] += cb.pairF[3 * k + a]; s[3 + a] += cb.pairTi[3 * k + a]; }
+            }
+        }
+        if (lane < 6)
+            for (int a = 0; a < 3; ++a) {
+                s[a] += cb.wallF[3ll * (6 * q + lane) + a];
+                s[3 + a] += cb.wallT[3ll * (6 * q + lane) + a];
+            }
+    }
+    for (int c = 0; c < 6; ++c) s[c] = wave_sum64(s[c]);
+    if (lane != 0) return;
     DevParticle &B = P[q];
     if (first)
         for (int a = 0; a < 3; ++a) B.X0[a] = B.X[a];
-    contact_body(p, B, q, cb, 1.0 / p.n_sub);
+    const double F[3] = {B.F[0] + s[0], B.F[1] + s[1], B.F[2] + s[2]};
+    const double T[3] = {B.T[0] + s[3], B.T[1] + s[4], B.T[2] + s[5]};
+    body_substep(p, B, F, T, 1.0 / p.n_sub);
     if (last) end_of_step(p, B, cnt);
 }
 
@@ -1968,8 +1994,8 @@ static void launch_step_kernels_t(const StepArgs &a) {
                         k_contact_guess<<<cdiv((long long)p.np * p.np, 4), 256, 0, a.stream>>>(p, a.P, a.cb, a.warm,
                                                                                             a.mlp_body);
                     k_contact_pairs<<<cdiv(nq, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt, a.warm ? 1 : 0);
-                    k_contact_bodies<<<cdiv(p.np, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt, s2 == 0,
-                                                                            s2 == p.n_sub - 1);
+                    k_contact_bodies<<<cdiv(p.np, 4), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt, s2 == 0,
+                                                                          s2 == p.n_sub - 1);
                 }
             }
         }
