@@ -2011,9 +2011,19 @@ static void launch_step_kernels_t(const StepArgs &a) {
             (void)hipEventRecord(a.ev_stop, a.stream);
         }
     } else if (a.phase == PHASE_BULK) {
+        // events ride on the dispatch itself (no separate marker packets)
+        if constexpr (S != 0) {
+            if (p.nx % 2 == 0) {  // 16-bit storage: node pairs, 32-bit accesses
+                const int nseg = cdiv(p.nx, 128);
+                const long long waves = (long long)nseg * p.ny * p.nz;
+                hipExtLaunchKernelGGL(k_bulk_pair<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0,
+                                      a.stream, a.ev_start, a.ev_stop, 0, p, (const T *)A, B,
+                                      (const uint8_t *)a.skip, nseg);
+                return;
+            }
+        }
         const int nseg = cdiv(p.nx, 64);
         const long long waves = (long long)nseg * p.ny * p.nz;
-        // events ride on the dispatch itself (no separate marker packets)
         hipExtLaunchKernelGGL(k_bulk<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0, a.stream,
                               a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip, nseg);
     } else if (a.phase == PHASE_SPECIAL) {

@@ -124,6 +124,129 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typena
     bulk_update<S>(p, A, B, x, y, z, n);
 }
 
+// 16-bit storage, nx even: a lane takes the node pair (x, x + 1), x even, and
+// moves one aligned 32-bit word per population (twice the bytes of a 16-bit
+// access per instruction); a wave covers 128 consecutive x of a row.  The
+// pulls along x shift a pair by one node: the missing value comes from the
+// neighbouring lane's word (wave shift by one lane) or, at the wave's ends,
+// from one extra 16-bit load (periodic wrap, or the node's own opposite
+// population at a wall).  Per node the arithmetic is bulk_update's.
+// c ? a : b without a branch.
+__device__ __forceinline__ long long bsel(bool c, long long a, long long b) { return b ^ ((a ^ b) & -(long long)c); }
+
+template <int S> struct Pair16;
+template <> struct Pair16<1> {
+    __device__ static float lo(uint32_t w, float inv) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)) * inv;
+    }
+    __device__ static float hi(uint32_t w, float inv) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)) * inv;
+    }
+    __device__ static uint32_t one(float v, float s) {
+        return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(v * s));
+    }
+};
+template <> struct Pair16<2> {
+    __device__ static float lo(uint32_t w, float) { return __uint_as_float(w << 16); }
+    __device__ static float hi(uint32_t w, float) { return __uint_as_float(w & 0xffff0000u); }
+    __device__ static uint32_t one(float v, float) { return (uint32_t)Store<2>::rne(v); }
+};
+
+template <int S>
+__global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const typename Store<S>::T *__restrict__ A,
+                                                               typename Store<S>::T *__restrict__ B,
+                                                               const uint8_t *__restrict__ skip, int nseg) {
+    using T = typename Store<S>::T;
+    using W = Pair16<S>;
+    // the wave's row and segment are uniform: scalar registers, scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * BULK_WAVES + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int seg = wave % nseg, row = wave / nseg;
+    if (row >= p.ny * p.nz) return;
+    const int x0 = seg * 128 + 2 * lane;
+    const bool act = x0 < p.nx;  // the pair exists (nx even: then so does x0 + 1)
+    const int xc = act ? x0 : p.nx - 2;  // lanes past the row end read the row's last pair, unused
+    const int y = row % p.ny, z = row / p.ny;
+    const int n0 = row * p.nx + xc;
+    const unsigned sk = act ? (unsigned)*(const uint16_t *)(skip + n0) : 0x0101u;  // 2-byte aligned
+    const bool live0 = !(sk & 0xffu), live1 = !(sk >> 8);
+    if (!__any(live0 || live1)) return;  // wave-uniform: every lane below takes part in the shifts
+    int sy[3], sz[3];
+    sy[1] = y; sz[1] = z;
+    sy[2] = y - 1; sy[0] = y + 1;
+    sz[2] = z - 1; sz[0] = z + 1;
+    if (sy[2] < 0) sy[2] = (p.periodic & 2u) ? p.ny - 1 : -1;
+    if (sy[0] >= p.ny) sy[0] = (p.periodic & 2u) ? 0 : -1;
+    if (sz[2] < 0) sz[2] = (p.periodic & 4u) ? p.nz - 1 : -1;
+    if (sz[0] >= p.nz) sz[0] = (p.periodic & 4u) ? 0 : -1;
+    const bool perx = p.periodic & 1u;
+    const float inv = p.inv_scale;
+    const long long Ns = p.Ns;
+    const int r0 = row * p.nx;  // this row's first node
+    // The only lanes that pull along x from outside their wave's words: lane
+    // 0 for e_x = +1 (the node before the segment), and for e_x = -1 lane 63
+    // when the row continues past the segment, else the lane of the row's
+    // last pair; either way one node per population, at a wave-uniform
+    // address (periodic wrap, or the node's own opposite population at a wall).
+    const bool more = (seg + 1) * 128 < p.nx;
+    const bool edge_lo = lane == 0;
+    const bool edge_hi = more ? lane == 63 : xc + 2 >= p.nx;
+    // pass 1: every load at once, unconditionally (indices chosen by bitwise
+    // selects, which stay selects: a branch here would hold each load back)
+    uint32_t w[Q], eb[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
+        const bool rwall = (ys | zs) < 0;  // the source row lies beyond a wall: both nodes bounce
+        const long long rb = (long long)(rwall ? 0 : (zs * p.ny + ys) * p.nx);  // source row
+        const long long io = OPP[i] * Ns, ii = i * Ns + rb;
+        w[i] = *(const uint32_t *)(A + bsel(rwall, io + n0, ii + xc));
+        if (EX[i] > 0) {
+            const long long e = bsel(seg > 0, ii + seg * 128 - 1, bsel(perx, ii + p.nx - 1, io + r0));
+            eb[i] = *(const uint16_t *)(A + bsel(rwall, io + r0, e));
+        } else if (EX[i] < 0) {
+            const long long e = bsel(more, ii + (seg + 1) * 128, bsel(perx, ii, io + r0 + p.nx - 1));
+            eb[i] = *(const uint16_t *)(A + bsel(rwall, io + r0, e));
+        }
+    }
+    // pass 2: the pulls along x from the neighbouring lanes' words
+    float d0[Q], d1[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
+        const bool rwall = (ys | zs) < 0;
+        uint32_t b0 = w[i] & 0xffffu, b1 = w[i] >> 16;
+        if (EX[i] > 0) {
+            const uint32_t wl = (uint32_t)__shfl_up((int)w[i], 1);
+            const uint32_t s0 = edge_lo ? eb[i] : wl >> 16;
+            b1 = rwall ? b1 : b0;
+            b0 = rwall ? b0 : s0;
+        } else if (EX[i] < 0) {
+            const uint32_t wr = (uint32_t)__shfl_down((int)w[i], 1);
+            const uint32_t s1 = edge_hi ? eb[i] : wr & 0xffffu;
+            b0 = rwall ? b0 : b1;
+            b1 = rwall ? b1 : s1;
+        }
+        d0[i] = W::lo(b0, inv);
+        d1[i] = W::lo(b1, inv);
+    }
+    if (!(live0 || live1)) return;
+    collide(d0, p);
+    collide(d1, p);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T *Bi = B + (long long)i * p.Ns;
+        const uint32_t v0 = W::one(d0[i], p.scale), v1 = W::one(d1[i], p.scale);
+        if (live0 && live1) {
+            __builtin_nontemporal_store(v0 | (v1 << 16), (uint32_t *)(Bi + n0));
+        } else if (live0) {
+            __builtin_nontemporal_store((uint16_t)v0, (uint16_t *)(Bi + n0));
+        } else {
+            __builtin_nontemporal_store((uint16_t)v1, (uint16_t *)(Bi + n0 + 1));
+        }
+    }
+}
+
 // An ensemble of systems in one launch: the block table names each block's
 // system; within a system a wave covers a tile of 2^tw_log2 consecutive x by
 // 64 / 2^tw_log2 rows of y, or (TW_FLAT) 64 consecutive nodes in lattice

@@ -157,6 +157,58 @@ def test_one_step_from_random_state(mdl):
         assert err < 2e-9
 
 
+def _half_step_bound(storage, dmax):
+    """A priori bound on one step from deviations of size <= dmax with 16-bit
+    storage (derivation in test_gpu_fullsize.py): the input and the result
+    each rounded once to storage, the collision's sensitivity to its inputs
+    at most 12, plus the FP32 arithmetic."""
+    u = 2.0 ** -11 if storage == workloads.STORE_F16 else 2.0 ** -8
+    return 13.0 * u * dmax + 250.0 * 2.0 ** -24 * dmax
+
+
+def _box(nx, ny, nz, periodic, storage, g=(0.0, 0.0, 0.0)):
+    return workloads.Config(nx=nx, ny=ny, nz=nz, periodic=periodic, tau=0.6, storage=storage,
+                            g_fluid=np.array(g))
+
+
+@pytest.mark.parametrize("storage", [workloads.STORE_F16, workloads.STORE_BF16])
+@pytest.mark.parametrize("case", ["periodic-32", "periodic-200", "walls-136", "walls-odd-37", "body-24"])
+def test_one_step_half_storage_node_pairs(mdl, storage, case):
+    """16-bit storage streams node pairs with 32-bit accesses when nx is even
+    (shifts across lanes, extra loads at a wave's ends, periodic wrap and
+    walls along x, a ragged second 128-node segment, idle lanes); odd nx
+    takes the one-node form.  One step from a random state, every population
+    of every fluid node against the oracle within the rounding bound."""
+    if case == "periodic-32":
+        cfg = _box(32, 10, 12, 7, storage, g=(1e-5, -2e-5, 3e-5))
+    elif case == "periodic-200":
+        cfg = _box(200, 6, 8, 7, storage, g=(2e-5, 0.0, -1e-5))
+    elif case == "walls-136":
+        cfg = _box(136, 7, 9, 0, storage)
+    elif case == "walls-odd-37":
+        cfg = _box(37, 9, 8, 2, storage)
+    else:
+        cfg = workloads.small_settling(n=24, nz=32, R=4.0)
+        cfg.storage = storage
+    print(f"half storage one step: {case} storage {storage}", flush=True)
+    N = cfg.nx * cfg.ny * cfg.nz
+    d0 = workloads.random_populations(5, N, amp=2e-3)
+    f0 = oracle.feq(1.0, [0, 0, 0])[:, None] + d0
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    sim.set_populations(f0)
+    ref.set_f(f0)
+    sim.step(1)
+    ref.step(1)
+    fl = ref.owner() < 0
+    assert np.array_equal(sim.owner(), ref.owner())
+    err = np.abs(sim.populations()[:, fl] - ref.fpost()[:, fl]).max()
+    tol = _half_step_bound(storage, np.abs(d0).max())
+    print(f"  max|df| = {err:.2e} (bound {tol:.1e})", flush=True)
+    assert err <= tol
+    sim.close()
+
+
 def test_comoving_equilibrium_on_gpu(mdl):
     U = np.array([0.02, 0.011, -0.007])
     cfg = workloads.comoving(U=U, n=24)
