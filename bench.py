@@ -210,6 +210,23 @@ def run_mlp_warmstart(steps, epochs):
             "plain": res["plain"], "mlp": res["mlp"]}
 
 
+def run_fp16(steps, warmup):
+    """The same settling workload with FP16 deviation storage (the
+    stream-collide in its node-pair form)."""
+    import workloads
+    cfg16 = workloads.config2()
+    cfg16.storage = workloads.STORE_F16
+    N = cfg16.n_nodes
+    dt16, k16_ms, k16_n, k16_nodes, _, _ = run_gpu(cfg16, steps, warmup)
+    k16_s = k16_ms / 1e3 / max(k16_n, 1)
+    ach16 = (k16_nodes * bytes_per_node(1) + N) / k16_s / 1e9
+    return {"value": round(N * steps / dt16 / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(dt16 * 1e3 / steps, 5), "kernel": "k_bulk_pair<f16>",
+            "kernel_avg_ms": round(k16_ms / max(k16_n, 1), 5),
+            "kernel_achieved_GBs": round(ach16, 1),
+            "kernel_frac": round(ach16 / HBM_PEAK_GBS, 4)}
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     for f in KERNEL_SRC:
@@ -281,7 +298,7 @@ def main():
     ap.add_argument("--mlp-steps", type=int, default=100)
     ap.add_argument("--mlp-epochs", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB copy (PMC calibration)")
-    ap.add_argument("--only", choices=["ensemble", "warm-start", "suspension"],
+    ap.add_argument("--only", choices=["ensemble", "warm-start", "suspension", "fp16"],
                     help="run only this part and print its JSON object (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -300,6 +317,9 @@ def main():
         return
     if args.only == "warm-start":
         print(json.dumps(run_mlp_warmstart(args.mlp_steps, args.mlp_epochs)), flush=True)
+        return
+    if args.only == "fp16":
+        print(json.dumps(run_fp16(args.steps, args.warmup)), flush=True)
         return
     import workloads
 
@@ -332,16 +352,7 @@ def main():
         "link_fraction_newton": {"links": nr[0], "mean_iterations": round(nr[1] / max(nr[0], 1), 3)},
     }
     if not args.no_fp16:
-        cfg16 = workloads.config2()
-        cfg16.storage = workloads.STORE_F16
-        dt16, k16_ms, k16_n, k16_nodes, _, _ = run_gpu(cfg16, args.steps, args.warmup)
-        k16_s = k16_ms / 1e3 / max(k16_n, 1)
-        ach16 = (k16_nodes * bytes_per_node(1) + N) / k16_s / 1e9
-        out["fp16_store"] = {"value": round(N * args.steps / dt16 / 1e6, 1), "unit": "MLUPS",
-                             "ms_per_step": round(dt16 * 1e3 / args.steps, 5),
-                             "kernel_avg_ms": round(k16_ms / max(k16_n, 1), 5),
-                             "kernel_achieved_GBs": round(ach16, 1),
-                             "kernel_frac": round(ach16 / HBM_PEAK_GBS, 4)}
+        out["fp16_store"] = run_fp16(args.steps, args.warmup)
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(64, args.ensemble_steps, 12)
     if not args.no_mlp:
