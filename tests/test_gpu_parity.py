@@ -172,7 +172,8 @@ def _box(nx, ny, nz, periodic, storage, g=(0.0, 0.0, 0.0)):
 
 
 @pytest.mark.parametrize("storage", [workloads.STORE_F16, workloads.STORE_BF16])
-@pytest.mark.parametrize("case", ["periodic-32", "periodic-200", "walls-136", "walls-odd-37", "body-24"])
+@pytest.mark.parametrize("case", ["periodic-32", "periodic-200", "walls-136", "walls-odd-37", "body-24",
+                                  "periodic-4", "walls-4"])
 def test_one_step_half_storage_node_pairs(mdl, storage, case):
     """16-bit storage streams node pairs with 32-bit accesses when nx is even
     (shifts across lanes, extra loads at a wave's ends, periodic wrap and
@@ -187,6 +188,10 @@ def test_one_step_half_storage_node_pairs(mdl, storage, case):
         cfg = _box(136, 7, 9, 0, storage)
     elif case == "walls-odd-37":
         cfg = _box(37, 9, 8, 2, storage)
+    elif case == "periodic-4":  # the narrowest even row (sizes start at 3): two pairs
+        cfg = _box(4, 6, 5, 7, storage, g=(1e-5, 1e-5, 0.0))
+    elif case == "walls-4":
+        cfg = _box(4, 5, 6, 6, storage)
     else:
         cfg = workloads.small_settling(n=24, nz=32, R=4.0)
         cfg.storage = storage
