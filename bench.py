@@ -303,7 +303,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by z-slabs across GPUs, which this build does not implement)",
+              "(the path would shard by z-slabs across GPUs; that is not implemented)",
               file=sys.stderr)
         sys.exit(2)
     if args.calib_copy:

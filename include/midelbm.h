@@ -211,8 +211,8 @@ lbm_status lbm_sync(lbm_ctx *ctx);
 void lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(void);
 
-/* ---- warm start of the link fractions (spec form: an MLP trained on
- * the method's own Newton solutions) ----
+/* ---- warm start of the link fractions (an extension beyond the paper: an
+ * MLP trained on the method's own Newton solutions) ----
  * The link fraction q of a cut link is the first root of C(x_f - s e_i) = 1
  * on (0,1] (sec. 2.3.2), bracketed by eight samples and found by a
  * safeguarded Newton iteration.  A small MLP (87 inputs -> 64 -> 64 -> 4,
