@@ -135,6 +135,26 @@ def run_suspension(steps):
                 mlups=round(cfg.n_nodes * steps / dt / 1e6, 1), ms_per_step=round(dt * 1e3 / steps, 4))
 
 
+def run_pair(steps, warmup):
+    """The two-body drafting workload (160x160x640 walls, 6- and 12-point
+    bodies, contact) in its storage forms: FP32, FP16 and BF16 deviations."""
+    import workloads
+
+    out = {"workload": "two bodies 160x160x640 walls, tau 0.6, density ratio 1.2, g 2e-5, contact, IBB",
+           "steps": steps}
+    for name, st in (("f32", workloads.STORE_F32), ("f16", workloads.STORE_F16), ("bf16", workloads.STORE_BF16)):
+        cfg = workloads.config3(storage=st)
+        N = cfg.n_nodes
+        dt, k_ms, k_n, k_nodes, _, _ = run_gpu(cfg, steps, warmup)
+        k_s = k_ms / 1e3 / max(k_n, 1)
+        ach = (k_nodes * bytes_per_node(st) + N) / k_s / 1e9
+        out[name] = {"mlups": round(N * steps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / steps, 5),
+                     "kernel": "k_bulk<f32>" if st == workloads.STORE_F32 else f"k_bulk_pair<{name}>",
+                     "kernel_avg_ms": round(k_ms / max(k_n, 1), 5), "kernel_achieved_GBs": round(ach, 1),
+                     "kernel_frac": round(ach / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def run_mlp_warmstart(steps, epochs):
     """Warm start on the 256^3 periodic suspension of 200 bodies (FP32,
     contact): the MLP is trained on the link fractions the method solved at
@@ -298,7 +318,9 @@ def main():
     ap.add_argument("--mlp-steps", type=int, default=100)
     ap.add_argument("--mlp-epochs", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true", help="only run a 1 GiB copy (PMC calibration)")
-    ap.add_argument("--only", choices=["ensemble", "warm-start", "suspension", "fp16"],
+    ap.add_argument("--no-pair", action="store_true", help="skip the two-body 160x160x640 storage runs")
+    ap.add_argument("--pair-steps", type=int, default=300)
+    ap.add_argument("--only", choices=["ensemble", "warm-start", "suspension", "fp16", "pair"],
                     help="run only this part and print its JSON object (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -320,6 +342,9 @@ def main():
         return
     if args.only == "fp16":
         print(json.dumps(run_fp16(args.steps, args.warmup)), flush=True)
+        return
+    if args.only == "pair":
+        print(json.dumps(run_pair(args.pair_steps, args.warmup)), flush=True)
         return
     import workloads
 
@@ -353,6 +378,8 @@ def main():
     }
     if not args.no_fp16:
         out["fp16_store"] = run_fp16(args.steps, args.warmup)
+    if not args.no_pair:
+        out["pair_160x160x640"] = run_pair(args.pair_steps, args.warmup)
     if not args.no_ensemble:
         out["ensemble"] = run_ensemble(64, args.ensemble_steps, 12)
     if not args.no_mlp:
