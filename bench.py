@@ -149,7 +149,8 @@ def run_pair(steps, warmup):
         k_s = k_ms / 1e3 / max(k_n, 1)
         ach = (k_nodes * bytes_per_node(st) + N) / k_s / 1e9
         out[name] = {"mlups": round(N * steps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / steps, 5),
-                     "kernel": "k_bulk<f32>" if st == workloads.STORE_F32 else f"k_bulk_pair<{name}>",
+                     "kernel": "k_bulk<f32>" if st == workloads.STORE_F32 else
+                     (f"k_bulk_pair<{name}>" if cfg.nx % 128 == 0 else f"k_bulk_pair_flat<{name}>"),
                      "kernel_avg_ms": round(k_ms / max(k_n, 1), 5), "kernel_achieved_GBs": round(ach, 1),
                      "kernel_frac": round(ach / HBM_PEAK_GBS, 4)}
     return out

@@ -2013,7 +2013,13 @@ static void launch_step_kernels_t(const StepArgs &a) {
     } else if (a.phase == PHASE_BULK) {
         // events ride on the dispatch itself (no separate marker packets)
         if constexpr (S != 0) {
-            if (p.nx % 2 == 0) {  // 16-bit storage: node pairs, 32-bit accesses
+            if (p.nx % 2 == 0 && p.nx % 128 != 0) {  // node pairs in lattice order (no idle lanes)
+                hipExtLaunchKernelGGL(k_bulk_pair_flat<S>, dim3(cdiv(cdiv(p.N, 128), BULK_WAVES)),
+                                      dim3(64 * BULK_WAVES), 0, a.stream, a.ev_start, a.ev_stop, 0, p, (const T *)A,
+                                      B, (const uint8_t *)a.skip);
+                return;
+            }
+            if (p.nx % 128 == 0) {  // 16-bit storage: node pairs, 32-bit accesses, a wave per 128 x of a row
                 const int nseg = cdiv(p.nx, 128);
                 const long long waves = (long long)nseg * p.ny * p.nz;
                 hipExtLaunchKernelGGL(k_bulk_pair<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0,

@@ -247,6 +247,101 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const t
     }
 }
 
+// The same pair update with the pairs in lattice order: a wave takes 64
+// consecutive pairs (128 nodes), rows wrap inside the wave, so no lane idles
+// whatever the (even) nx.  A lane pulls from the neighbouring lane's word
+// when that pair lies in its own row; at a row's ends and at the wave's ends
+// it loads the one missing node itself (a per-lane index, loaded by every
+// lane so that all loads stay unconditional).
+template <int S>
+__global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair_flat(Params p,
+                                                                    const typename Store<S>::T *__restrict__ A,
+                                                                    typename Store<S>::T *__restrict__ B,
+                                                                    const uint8_t *__restrict__ skip) {
+    using T = typename Store<S>::T;
+    using W = Pair16<S>;
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * BULK_WAVES + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int N = (int)p.N;  // even (nx even)
+    if (wave * 128 >= N) return;  // wave-uniform
+    const int nraw = wave * 128 + 2 * lane;
+    const bool act = nraw < N;
+    const int n0 = act ? nraw : N - 2;  // lanes past the end read the last pair, unused
+    const unsigned sk = act ? (unsigned)*(const uint16_t *)(skip + n0) : 0x0101u;  // 2-byte aligned
+    const bool live0 = !(sk & 0xffu), live1 = !(sk >> 8);
+    if (!__any(live0 || live1)) return;  // wave-uniform: every lane below takes part in the shifts
+    const unsigned row = (unsigned)n0 / (unsigned)p.nx;
+    const int x0 = n0 - (int)row * p.nx;  // even
+    const int z = (int)(row / (unsigned)p.ny), y = (int)row - z * p.ny;
+    int sy[3], sz[3];
+    sy[1] = y; sz[1] = z;
+    sy[2] = y - 1; sy[0] = y + 1;
+    sz[2] = z - 1; sz[0] = z + 1;
+    if (sy[2] < 0) sy[2] = (p.periodic & 2u) ? p.ny - 1 : -1;
+    if (sy[0] >= p.ny) sy[0] = (p.periodic & 2u) ? 0 : -1;
+    if (sz[2] < 0) sz[2] = (p.periodic & 4u) ? p.nz - 1 : -1;
+    if (sz[0] >= p.nz) sz[0] = (p.periodic & 4u) ? 0 : -1;
+    const bool perx = p.periodic & 1u;
+    const float inv = p.inv_scale;
+    const long long Ns = p.Ns;
+    // x0 - 1 is outside the lane-below's word at a row start or in lane 0;
+    // x0 + 2 outside the lane-above's word at a row end or in lane 63
+    const bool edge_lo = lane == 0 || x0 == 0;
+    const bool edge_hi = lane == 63 || x0 + 2 >= p.nx;
+    uint32_t w[Q], eb[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
+        const bool rwall = (ys | zs) < 0;  // the source row lies beyond a wall: both nodes bounce
+        const long long rb = (long long)(rwall ? 0 : (zs * p.ny + ys) * p.nx);
+        const long long io = OPP[i] * Ns, ii = i * Ns + rb;
+        const long long wi = bsel(rwall, io + n0, ii + x0);
+        w[i] = *(const uint32_t *)(A + wi);
+        if (EX[i] > 0) {
+            const long long e = bsel(x0 > 0, ii + x0 - 1, bsel(perx, ii + p.nx - 1, io + n0));
+            eb[i] = *(const uint16_t *)(A + bsel(edge_lo && !rwall, e, wi));
+        } else if (EX[i] < 0) {
+            const long long e = bsel(x0 + 2 < p.nx, ii + x0 + 2, bsel(perx, ii, io + n0 + 1));
+            eb[i] = *(const uint16_t *)(A + bsel(edge_hi && !rwall, e, wi));
+        }
+    }
+    float d0[Q], d1[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
+        const bool rwall = (ys | zs) < 0;
+        uint32_t b0 = w[i] & 0xffffu, b1 = w[i] >> 16;
+        if (EX[i] > 0) {
+            const uint32_t wl = (uint32_t)__shfl_up((int)w[i], 1);
+            const uint32_t s0 = edge_lo ? eb[i] : wl >> 16;
+            b1 = rwall ? b1 : b0;
+            b0 = rwall ? b0 : s0;
+        } else if (EX[i] < 0) {
+            const uint32_t wr = (uint32_t)__shfl_down((int)w[i], 1);
+            const uint32_t s1 = edge_hi ? eb[i] : wr & 0xffffu;
+            b0 = rwall ? b0 : b1;
+            b1 = rwall ? b1 : s1;
+        }
+        d0[i] = W::lo(b0, inv);
+        d1[i] = W::lo(b1, inv);
+    }
+    if (!(live0 || live1)) return;
+    collide(d0, p);
+    collide(d1, p);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T *Bi = B + (long long)i * p.Ns;
+        const uint32_t v0 = W::one(d0[i], p.scale), v1 = W::one(d1[i], p.scale);
+        if (live0 && live1) {
+            __builtin_nontemporal_store(v0 | (v1 << 16), (uint32_t *)(Bi + n0));
+        } else if (live0) {
+            __builtin_nontemporal_store((uint16_t)v0, (uint16_t *)(Bi + n0));
+        } else {
+            __builtin_nontemporal_store((uint16_t)v1, (uint16_t *)(Bi + n0 + 1));
+        }
+    }
+}
+
 // An ensemble of systems in one launch: the block table names each block's
 // system; within a system a wave covers a tile of 2^tw_log2 consecutive x by
 // 64 / 2^tw_log2 rows of y, or (TW_FLAT) 64 consecutive nodes in lattice

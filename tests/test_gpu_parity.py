@@ -173,12 +173,13 @@ def _box(nx, ny, nz, periodic, storage, g=(0.0, 0.0, 0.0)):
 
 @pytest.mark.parametrize("storage", [workloads.STORE_F16, workloads.STORE_BF16])
 @pytest.mark.parametrize("case", ["periodic-32", "periodic-200", "walls-136", "walls-odd-37", "body-24",
-                                  "periodic-4", "walls-4"])
+                                  "periodic-4", "walls-4", "periodic-256"])
 def test_one_step_half_storage_node_pairs(mdl, storage, case):
-    """16-bit storage streams node pairs with 32-bit accesses when nx is even
-    (shifts across lanes, extra loads at a wave's ends, periodic wrap and
-    walls along x, a ragged second 128-node segment, idle lanes); odd nx
-    takes the one-node form.  One step from a random state, every population
+    """16-bit storage streams node pairs with 32-bit accesses when nx is even:
+    a wave per 128 x of a row when nx is a multiple of 128, else 64 pairs in
+    lattice order with rows wrapping inside the wave (shifts across lanes,
+    extra loads at row and wave ends, periodic wrap and walls along x, idle
+    lanes past the end); odd nx takes the one-node form.  One step from a random state, every population
     of every fluid node against the oracle within the rounding bound."""
     if case == "periodic-32":
         cfg = _box(32, 10, 12, 7, storage, g=(1e-5, -2e-5, 3e-5))
@@ -192,6 +193,8 @@ def test_one_step_half_storage_node_pairs(mdl, storage, case):
         cfg = _box(4, 6, 5, 7, storage, g=(1e-5, 1e-5, 0.0))
     elif case == "walls-4":
         cfg = _box(4, 5, 6, 6, storage)
+    elif case == "periodic-256":  # nx a multiple of 128: a wave per 128 x of a row
+        cfg = _box(256, 4, 5, 7, storage, g=(-1e-5, 2e-5, 1e-5))
     else:
         cfg = workloads.small_settling(n=24, nz=32, R=4.0)
         cfg.storage = storage
