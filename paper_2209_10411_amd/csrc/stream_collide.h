@@ -124,23 +124,25 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typena
     bulk_update<S>(p, A, B, x, y, z, n);
 }
 
-// 16-bit storage, nx even: a lane takes the node pair (x, x + 1), x even, and
-// moves one aligned 32-bit word per population (twice the bytes of a 16-bit
-// access per instruction); a wave covers 128 consecutive x of a row.  The
-// pulls along x shift a pair by one node: the missing value comes from the
-// neighbouring lane's word (wave shift by one lane) or, at the wave's ends,
-// from one extra 16-bit load (periodic wrap, or the node's own opposite
-// population at a wall).  Per node the arithmetic is bulk_update's.
 // c ? a : b without a branch.
 __device__ __forceinline__ long long bsel(bool c, long long a, long long b) { return b ^ ((a ^ b) & -(long long)c); }
 
+// 16-bit storage, nx even: a lane takes the node pair (x, x + 1), x even, and
+// moves one aligned 32-bit word per population (twice the bytes of a 16-bit
+// access per instruction).  The pulls along x shift a pair by one node: the
+// missing value comes from the neighbouring lane's word (wave shift by one
+// lane) or, where that lane holds no pair of the same row, from one extra
+// 16-bit load (the next node, its periodic image, or the node's own opposite
+// population at a wall).  Per node the arithmetic is bulk_update's.
+// k_bulk_pair (nx a multiple of 128): a wave covers 128 consecutive x of a
+// row.  k_bulk_pair_flat (other even nx): a wave covers 64 consecutive pairs
+// in lattice order.
 template <int S> struct Pair16;
+// lo: the value in the low 16 bits of a word (callers shift the high half
+// down first); one: a value's 16-bit storage code.
 template <> struct Pair16<1> {
     __device__ static float lo(uint32_t w, float inv) {
         return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)) * inv;
-    }
-    __device__ static float hi(uint32_t w, float inv) {
-        return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)) * inv;
     }
     __device__ static uint32_t one(float v, float s) {
         return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(v * s));
@@ -148,7 +150,6 @@ template <> struct Pair16<1> {
 };
 template <> struct Pair16<2> {
     __device__ static float lo(uint32_t w, float) { return __uint_as_float(w << 16); }
-    __device__ static float hi(uint32_t w, float) { return __uint_as_float(w & 0xffff0000u); }
     __device__ static uint32_t one(float v, float) { return (uint32_t)Store<2>::rne(v); }
 };
 
