@@ -292,6 +292,32 @@ def cpu_baseline(cfg, budget_s):
                       f"(FP64, {oracle.threads()} OpenMP threads, {t_init:.1f} s setup excluded)"}
 
 
+def copy_achievable(gib: float = 1.0, reps: int = 10):
+    """Bandwidth of a plain device-to-device copy (GB/s, bytes read plus
+    written), timed with events on torch's stream: the practical ceiling of a
+    streaming kernel on this machine, reported beside the published peak.  None
+    where it cannot be taken (no GPU)."""
+    try:
+        import torch
+        n = int(gib * (1 << 30))
+        a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        del a, b
+        torch.cuda.empty_cache()
+        return round(2 * n / (ms * 1e-3) / 1e9, 1)
+    except Exception:
+        return None
+
+
 def calib_copy(gib: float = 1.0):
     """A plain copy of known size, for scaling the PMC byte counters."""
     import torch
@@ -357,6 +383,7 @@ def main():
     alg_bytes = k_nodes * bytes_per_node(0) + N  # populations of updated nodes + class byte of all
     achieved = alg_bytes / k_avg_s / 1e9
     traffic = traffic_from_profile()
+    copy_gbs = copy_achievable()
     out = {
         "metric": "MLUPS with moving metaball boundaries (FP32 vs FP16-store) + % HBM peak",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -371,6 +398,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_bulk<f32>",
+                     "copy_achievable_GBs": copy_gbs,
+                     "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
                      "kernel_avg_ms": round(k_ms / max(k_n, 1), 5),
                      "algorithmic_bytes_per_launch": alg_bytes},
         "kernel_mlups": round(k_nodes / k_avg_s / 1e6, 1),

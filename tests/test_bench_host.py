@@ -17,6 +17,13 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr and not r.stdout.strip()
 
 
+def test_copy_ceiling_is_null_without_a_gpu():
+    import torch
+    if torch.cuda.is_available():
+        return
+    assert bench.copy_achievable() is None
+
+
 def test_algorithmic_bytes_per_node():
     # 19 populations read and 19 written: 4 bytes each (FP32), 2 bytes (FP16 / BF16)
     assert bench.bytes_per_node(0) == 152
