@@ -461,7 +461,8 @@ class Mlp:
         return a
 
     def forward(self, feat, precision: int = 0):
-        """feat: device tensor [n][87] (float16 for precision 0, float32 for 1)."""
+        """feat: device tensor [n][87] (float16 for precision 0 and 2, float32
+        for 1); precision 2 runs the hidden layers on the matrix cores."""
         import torch
         n = feat.shape[0]
         out = torch.empty((n, self.N_OUT), dtype=torch.float32, device=self.device)
