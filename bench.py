@@ -274,6 +274,17 @@ def traffic_from_profile():
         return None
 
 
+def cpu_model():
+    """The host CPU's model name, or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(cfg, budget_s):
     import oracle
 
@@ -287,7 +298,7 @@ def cpu_baseline(cfg, budget_s):
         steps += 1
     dt = time.perf_counter() - t0
     return {"value": round(cfg.n_nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{steps} coupled steps of the same 128x128x384 settling case "
                       f"(FP64, {oracle.threads()} OpenMP threads, {t_init:.1f} s setup excluded)"}
 

@@ -24,6 +24,11 @@ def test_copy_ceiling_is_null_without_a_gpu():
     assert bench.copy_achievable() is None
 
 
+def test_cpu_model_is_a_name_or_none():
+    m = bench.cpu_model()
+    assert m is None or (isinstance(m, str) and m)
+
+
 def test_algorithmic_bytes_per_node():
     # 19 populations read and 19 written: 4 bytes each (FP32), 2 bytes (FP16 / BF16)
     assert bench.bytes_per_node(0) == 152
