@@ -1,9 +1,13 @@
 """Seeded synthetic inputs for the metaball-coupled lattice Boltzmann step.
 
 This module only draws numbers and lays them out; it holds none of the
-method's arithmetic (no lattice tables, no metaball evaluation, no body
-properties).  Both the CPU oracle and the HIP library read exactly what it
-returns, so the two sides start from identical inputs.
+method's arithmetic (no lattice tables, no body properties, no fit).  Two
+helpers evaluate a metaball, only to place inputs: extent_radius (the size of
+a drawn body, for placing bodies without overlap) and mi_hull (points on the
+surface of a known metaball, the synthetic stand-in for the XRCT point hull
+that the Metaball-Imaging fit takes as input).  Both the CPU oracle and the
+HIP library read exactly what it returns, so the two sides start from
+identical inputs.
 
 A metaball body (paper section 2.1, Eq. metaballM) is a set of control points
 p_i with positive weights k_i; its surface is sum_i k_i/|x - p_i|^2 = 1.  The
@@ -365,3 +369,83 @@ def mlp_init(seed: int = 7):
         parts.append(rng.uniform(-a, a, size=(fan_in, fan_out)).reshape(-1))
         parts.append(np.zeros(fan_out))
     return np.concatenate(parts)
+
+
+# ------------------------------------------------ Metaball-Imaging inputs
+def mi_body(seed: int = 61, n_cp: int = 8, R: float = 10.0):
+    """A known metaball (control points about the origin, weights summing to
+    R^2) from which a synthetic point hull is sampled."""
+    off, k = random_body(_rng(seed), n_cp, R)
+    return off - off.mean(0), k
+
+
+def mi_hull(cp, k, m: int = 2048, dr: float = 0.02):
+    """m points on the outer surface of the metaball (cp, k): along m
+    Fibonacci directions from the origin, the outermost radius where
+    sum k / |x - p|^2 >= 1 (found on a radial grid of step dr, then by 60
+    bisections), then translated to their mean (the paper's TOC).  Returns
+    the hull [m][3] and the half-spaces of its convex hull [n_pl][4]
+    (n . x + d <= 0 inside, scipy.spatial.ConvexHull)."""
+    from scipy.spatial import ConvexHull
+
+    cp = np.asarray(cp, dtype=np.float64).reshape(-1, 3)
+    k = np.asarray(k, dtype=np.float64)
+    i = np.arange(m) + 0.5
+    phi = np.arccos(1 - 2 * i / m)
+    th = np.pi * (1 + 5 ** 0.5) * i
+    dirs = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
+
+    def C(pts):
+        d2 = ((pts[..., None, :] - cp) ** 2).sum(-1)
+        return (k / d2).sum(-1)
+
+    rmax = float(np.max(np.linalg.norm(cp, axis=1)) + np.sqrt(k.sum())) + 1.0
+    r = np.arange(rmax, 0.0, -dr)
+    hull = np.zeros((m, 3))
+    for j in range(m):
+        v = C(dirs[j][None, :] * r[:, None])
+        first = int(np.argmax(v >= 1.0))  # outermost sample inside
+        lo, hi = r[first], r[first] + dr   # C(lo) >= 1 > C(hi)
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            if C(dirs[j] * mid) >= 1.0:
+                lo = mid
+            else:
+                hi = mid
+        hull[j] = dirs[j] * lo
+    shift = hull.mean(0)
+    hull = hull - shift
+    planes = ConvexHull(hull).equations.copy()
+    return hull, planes, shift
+
+
+def mi_population(hull, planes, N_I: int, n: int, seed: int = 62, k_scale: float | None = None):
+    """Initial GA population [N_I][n][4] (k, x, y, z): control points uniform
+    in the hull's bounding box, redrawn until inside its convex hull; weights
+    uniform in (0, 2 k_scale], k_scale = (mean hull radius)^2 / n."""
+    rng = _rng(seed)
+    lo, hi = hull.min(0), hull.max(0)
+    if k_scale is None:
+        k_scale = float(np.mean(np.linalg.norm(hull, axis=1)) ** 2 / n)
+    pop = np.zeros((N_I, n, 4))
+    for a in range(N_I):
+        for j in range(n):
+            while True:
+                p = rng.uniform(lo, hi)
+                if np.all(planes[:, :3] @ p + planes[:, 3] <= 0.0):
+                    break
+            pop[a, j, 1:4] = p
+        pop[a, :, 0] = rng.uniform(0.0, 2.0 * k_scale, size=n)
+        pop[a, :, 0] = np.maximum(pop[a, :, 0], 1e-3 * k_scale)
+    return pop
+
+
+def mi_draws(E: int, N_I: int, n: int, seed: int = 63):
+    """Random numbers of E GA generations: U (uniform [0,1)) and Z (standard
+    normal), both [E][N_I][n][4], and the pairings PERM [E][N_I]
+    (permutations)."""
+    rng = _rng(seed)
+    U = rng.random((E, N_I, n, 4))
+    Z = rng.standard_normal((E, N_I, n, 4))
+    PERM = np.stack([rng.permutation(N_I) for _ in range(E)]).astype(np.int32)
+    return U, Z, PERM
