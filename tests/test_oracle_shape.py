@@ -1,0 +1,77 @@
+"""Pins of the shape-descriptor oracle (paper sec. 4: sphericity, nominal
+and surface-equivalent diameters, Corey shape factor) against mathematics.
+
+- A single control point is the ball of radius sqrt(k) (sec. 2.1): volume
+  4/3 pi R^3, surface 4 pi R^2, projected area pi R^2, hence Phi = 1,
+  d_n = d_s = 2R and CSF = 1; the surface error falls as h^2 (marching
+  tetrahedra on a smooth surface).
+- Two equal control points at +-a: the axial extent is the real root of
+  k/(x - a)^2 + k/(x + a)^2 = 1, x^2 = a^2 + k + sqrt(k^2 + 4 k a^2); the body
+  is axisymmetric (d_S = d_I) and elongated (CSF < 1, Phi < 1).
+- Scaling the body by s (p -> s p, k -> s^2 k) on a grid scaled by s leaves
+  every evaluated C unchanged: V, S, A_p and the dimensions scale exactly by
+  s^3, s^2, s^2, s; Phi and CSF are unchanged.
+- The descriptors do not depend on the body's orientation beyond the grid
+  resolution.
+"""
+import numpy as np
+import pytest
+
+from oracle import shape
+
+
+def test_sphere():
+    R = 10.0
+    d = shape.descriptors(np.zeros((1, 3)), np.array([R * R]), 0.25)
+    assert d["V"] == pytest.approx(4 / 3 * np.pi * R ** 3, rel=2e-3)
+    assert d["S"] == pytest.approx(4 * np.pi * R ** 2, rel=1e-3)
+    assert d["A_p"] == pytest.approx(np.pi * R ** 2, rel=2e-3)
+    assert d["Phi"] == pytest.approx(1.0, abs=2e-3)
+    assert d["d_n"] == pytest.approx(2 * R, rel=1e-3) and d["d_s"] == pytest.approx(2 * R, rel=1e-3)
+    assert d["CSF"] == pytest.approx(1.0, abs=1e-12)
+    assert np.allclose(d["dims"], 2 * R, atol=0.25)
+
+
+def test_surface_error_is_second_order():
+    R = 6.0
+    e = [abs(shape.surface_area(np.zeros((1, 3)), np.array([R * R]), h) / (4 * np.pi * R * R) - 1)
+         for h in (0.5, 0.25)]
+    assert 2.5 < e[0] / e[1] < 6.0
+
+
+def test_two_point_body():
+    a, k = 4.0, 30.0
+    d = shape.descriptors(np.array([[-a, 0, 0], [a, 0, 0]]), np.array([k, k]), 0.25)
+    L = 2 * np.sqrt(a * a + k + np.sqrt(k * k + 4 * k * a * a))
+    assert abs(d["dims"][2] - L) <= 0.25
+    assert abs(d["dims"][0] - d["dims"][1]) <= 0.25
+    assert abs(abs(d["axes"][0, 2]) - 1) < 1e-6  # the longest axis is x
+    assert d["CSF"] < 0.9 and d["Phi"] < 1.0
+
+
+def test_scaling_is_exact():
+    rng = np.random.default_rng(3)
+    cp = rng.normal(0, 2.0, (4, 3))
+    k = rng.uniform(5, 12, 4)
+    s = 2.0
+    d1 = shape.descriptors(cp, k, 0.5)
+    d2 = shape.descriptors(s * cp, s * s * k, 0.5 * s)
+    assert d2["V"] == pytest.approx(s ** 3 * d1["V"], rel=1e-12)
+    assert d2["S"] == pytest.approx(s ** 2 * d1["S"], rel=1e-12)
+    assert d2["A_p"] == pytest.approx(s ** 2 * d1["A_p"], rel=1e-12)
+    assert np.allclose(d2["dims"], s * d1["dims"], rtol=1e-12)
+    assert d2["Phi"] == pytest.approx(d1["Phi"], rel=1e-12) and d2["CSF"] == pytest.approx(d1["CSF"], rel=1e-12)
+
+
+def test_orientation():
+    rng = np.random.default_rng(4)
+    cp = rng.normal(0, 2.0, (5, 3))
+    k = rng.uniform(5, 12, 5)
+    th = 0.7
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    d1 = shape.descriptors(cp, k, 0.25)
+    d2 = shape.descriptors(cp @ Rz.T, k, 0.25)
+    assert d2["V"] == pytest.approx(d1["V"], rel=5e-3)
+    assert d2["S"] == pytest.approx(d1["S"], rel=5e-3)
+    assert d2["Phi"] == pytest.approx(d1["Phi"], abs=5e-3)
+    assert d2["CSF"] == pytest.approx(d1["CSF"], abs=0.03)
