@@ -79,6 +79,7 @@ def lib():
         L.orc_collide_node.argtypes = [_dp, _dp, C.c_double, _dp]
         L.orc_lattice.argtypes = [_i32p, _dp, _i32p]
         L.orc_set_contact.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_set_link_c0.argtypes = [C.c_void_p, C.c_int]
         L.orc_pair_geometry.restype = C.c_int
         L.orc_pair_geometry.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_wall_geometry.restype = C.c_int
@@ -159,6 +160,8 @@ class Oracle:
         L.orc_set_contact(self._h, float(cfg.contact_rs), float(cfg.contact_kn),
                           float(cfg.contact_en), float(cfg.contact_mu))
         L.orc_init(self._h)
+        if getattr(cfg, "link_c0", 0):
+            L.orc_set_link_c0(self._h, 1)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -80,6 +80,9 @@ typedef struct orc_ctx {
     /* contact (sec. 2.3.1): sphere radius R_s of the sphero-metaball, normal
      * stiffness k_n (0 disables contact), restitution e, friction mu_s */
     double c_rs, c_kn, c_en, c_mu;
+    /* link fractions on the sphero-metaball level set (sec. 2.3.2: q solves
+     * f = c_0 with c_0 depending on R_s): 0 = the C = 1 surface */
+    int link_c0;
     double *xi_pair; /* [np][np][3] tangential springs of body pairs (i < j) */
     double *xi_wall; /* [np][6][3] tangential springs against the six faces */
     long n_contacts, n_contact_fail;
@@ -424,20 +427,43 @@ static void flag_all(const orc_ctx *c, int32_t *own) {
  * towards its solid neighbour x_f - e_i, q in (0, 1] is the first root of
  * g(s) = C_owner(x_f - s e_i) - 1 (g(0) < 0 <= g(1)).  The root is located in
  * the first of 8 equal sub-intervals where g changes sign and then refined
- * by bisection to full FP64 resolution. */
+ * by bisection to full FP64 resolution.
+ * With link_c0 (and a sphere radius R_s > 0), the surface the fluid sees is
+ * the paper's level set f = c_0 of the sphero-metaball's zoomed inner body:
+ * f_in(x) = sum s^2 k_j / |x - X - s (p_j - X)|^2 with s = 1 - R_s/sqrt(sum k),
+ * and c_0 = s^2, the level at which f_in gives back a sphere's own radius
+ * (the inner sphere of radius s sqrt(k) dilated by R_s).  Since
+ * f_in(x) = C(X + (x - X)/s), g(s) = C(X + (x_f - s e_i - X)/s) - s^2.  When
+ * this surface and C = 1 differ, g may keep one sign on (0, 1]: q = 1 when no
+ * sample reaches the level, and q -> 0 when x_f itself lies inside. */
+static double link_g(const orc_ctx *c, const orc_particle *P, const double xs[3], double *level) {
+    if (!c->link_c0 || !(c->c_rs > 0.0)) {
+        *level = 1.0;
+        return metaball(c, P, xs);
+    }
+    double sk = 0.0;
+    for (int j = 0; j < P->n_cp; ++j) sk += P->k[j];
+    const double sc = 1.0 - c->c_rs / sqrt(sk);
+    double r[3] = {xs[0] - P->X[0], xs[1] - P->X[1], xs[2] - P->X[2]};
+    min_image(c, r);
+    const double y[3] = {P->X[0] + r[0] / sc, P->X[1] + r[1] / sc, P->X[2] + r[2] / sc};
+    *level = sc * sc;
+    return metaball(c, P, y);
+}
+
 static double link_q(const orc_ctx *c, const orc_particle *P, int x, int y, int z, int i) {
     const int M = 8;
-    double lo = 0.0, hi = 1.0;
+    double lo = 0.0, hi = 1.0, L;
     for (int k = 1; k <= M; ++k) {
         double s = (double)k / M;
         double xs[3] = {x - s * EV[i][0], y - s * EV[i][1], z - s * EV[i][2]};
-        if (metaball(c, P, xs) >= 1.0) { lo = (double)(k - 1) / M; hi = s; break; }
+        if (link_g(c, P, xs, &L) >= L) { lo = (double)(k - 1) / M; hi = s; break; }
     }
     for (int it = 0; it < 200; ++it) {
         double mid = 0.5 * (lo + hi);
         if (mid <= lo || mid >= hi) break;
         double xs[3] = {x - mid * EV[i][0], y - mid * EV[i][1], z - mid * EV[i][2]};
-        if (metaball(c, P, xs) >= 1.0) hi = mid; else lo = mid;
+        if (link_g(c, P, xs, &L) >= L) hi = mid; else lo = mid;
     }
     return 0.5 * (lo + hi);
 }
@@ -995,6 +1021,8 @@ int orc_dem_only(orc_ctx *c, int nsteps) {
     for (int t = 0; t < nsteps; ++t) rigid_update_all(c);
     return 0;
 }
+
+void orc_set_link_c0(orc_ctx *c, int on) { c->link_c0 = on; build_links(c); }
 
 void orc_set_contact(orc_ctx *c, double rs, double kn, double en, double mu) {
     c->c_rs = rs; c->c_kn = kn; c->c_en = en; c->c_mu = mu;

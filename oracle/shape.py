@@ -33,9 +33,11 @@ box [min p - sqrt(sum k), max p + sqrt(sum k)] (C >= 1 needs some
         by linear interpolation of C - 1 along the edges)
   axes  eigenvectors of the inertia tensor of the inside cell centres
   d_*   max - min of the inside cell centres projected on each axis, plus h
-  A_p   on a square grid of step h in the plane of the two longer axes:
-        columns along the shortest axis, sampled every h, with at least one
-        sample with C >= 1; their count times h^2
+  A_p   on a square grid of step h in the plane of the two longer axes
+        (-half + h i, half = dimension / 2 + 2 h, i < ceil(2 half / h) + 1
+        on each axis, about the centroid): columns along the shortest axis,
+        sampled the same way, with at least one sample with C >= 1; their
+        count times h^2
 """
 from __future__ import annotations
 
@@ -139,11 +141,16 @@ def surface_area(cp, k, h):
 
 def principal_frame(P):
     """Centroid and principal axes (columns, by increasing extent) of the
-    inside cell centres P, with the extents along them."""
+    inside cell centres P, with the extents along them.  Each axis is signed
+    so that its component of largest magnitude is positive (a convention
+    that makes the projection grid below unique)."""
     c = P.mean(0)
     r = P - c
     I = np.eye(3) * (r * r).sum() - r.T @ r  # per unit mass and cell volume
     _, vec = np.linalg.eigh(I)
+    for j in range(3):
+        if vec[np.argmax(np.abs(vec[:, j])), j] < 0:
+            vec[:, j] = -vec[:, j]
     proj = r @ vec
     ext = proj.max(0) - proj.min(0)
     order = np.argsort(ext, kind="stable")
@@ -155,9 +162,10 @@ def projected_area(cp, k, h, c, axes, ext):
     along the shortest axis with at least one sample inside."""
     aS, aI, aL = axes[:, 0], axes[:, 1], axes[:, 2]
     half = 0.5 * ext + 2 * h
-    u = np.arange(-half[2], half[2] + h, h)
-    v = np.arange(-half[1], half[1] + h, h)
-    w = np.arange(-half[0], half[0] + h, h)
+    cnt = np.ceil(2 * half / h).astype(int) + 1
+    u = -half[2] + h * np.arange(cnt[2])
+    v = -half[1] + h * np.arange(cnt[1])
+    w = -half[0] + h * np.arange(cnt[0])
     U, Vv = np.meshgrid(u, v, indexing="ij")
     hit = np.zeros(U.shape, dtype=bool)
     for ww in w:

@@ -184,3 +184,67 @@ def test_body_properties_two_spheres_far():
     # parallel-axis theorem: I_yy ~ 2 (2/5 v k + v 20^2)
     v = V / 2
     assert I[1, 1] == pytest.approx(2 * (0.4 * v * k + v * 400.0), rel=2e-2)
+
+
+@pytest.mark.parametrize("rs", [0.5, 1.5, 3.0])
+def test_sphero_metaball_level_keeps_a_sphere(rs):
+    """Sec. 2.3.2 (q solves f = c_0, c_0 depending on R_s), read with the
+    sphero-metaball's inner body (the body scaled by s = 1 - R_s/sqrt(k)
+    about its centre, weights s^2 k) at c_0 = s^2: for one control point the
+    inner ball of radius s sqrt(k) dilated by R_s is the ball itself, so the
+    link fractions equal the C = 1 closed form for every R_s."""
+    cfg = workloads.config1()
+    cfg.contact_rs, cfg.link_c0 = rs, 1
+    o = oracle.Oracle(cfg)
+    node, d, ow, q = o.links()
+    e, _, _ = oracle.lattice()
+    p = np.array(cfg.particles[0].x)
+    k = cfg.particles[0].cp_k[0]
+    xf = np.stack([node % 64, (node // 64) % 64, node // 4096], 1).astype(float)
+    ev = e[d].astype(float)
+    dd = xf - p
+    de = (dd * ev).sum(1)
+    ee = (ev * ev).sum(1)
+    disc = de * de - ee * ((dd * dd).sum(1) - k)
+    qa = (de - np.sqrt(disc)) / ee
+    good = disc > 1e-3
+    assert len(q) == 4530
+    assert np.abs(q - qa)[good].max() < 1e-12
+    assert np.abs(q - qa).max() < 2e-7
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_sphero_metaball_level_general_body(seed):
+    """An 8-point body with R_s = 1: each q in (0, 1) is a root of the inner
+    body's level equation sum s^2 k / |x_w - X - s (p - X)|^2 = s^2 (to 1e-12),
+    with no sample between x_f and x_w at or above the level; q = 1 only where
+    the solid node is below the level, and q -> 0 only where x_f is at or above
+    it (the two surfaces differ for a non-spherical body)."""
+    off, k = workloads.random_body(np.random.Generator(np.random.PCG64(seed)), 8, 6.0)
+    cfg = workloads.Config(nx=40, ny=40, nz=40, periodic=7, tau=0.8, bc=workloads.BC_IBB, contact_rs=1.0,
+                           link_c0=1,
+                           particles=[workloads.Particle(cp_xyz=off, cp_k=k, x=np.array([20.3, 19.6, 20.1]),
+                                                         density=1.0, mode=workloads.MODE_KINEMATIC)])
+    o = oracle.Oracle(cfg)
+    lab, kk = o.cps(0)
+    X = o.particle(0)["x"]
+    s = 1.0 - 1.0 / np.sqrt(kk.sum())
+    inner, kin = X + s * (lab - X), s * s * kk
+    node, d, ow, q = o.links()
+    e, _, _ = oracle.lattice()
+    xf = np.stack([node % 40, (node // 40) % 40, node // 1600], 1).astype(float)
+    ev = e[d].astype(float)
+
+    def f(x):
+        return oracle.metaball_eval(inner, kin, x)
+
+    mid = (q > 1e-9) & (q < 1.0)
+    assert mid.sum() > 0.5 * len(q)
+    for j in np.flatnonzero(mid)[::7]:
+        assert abs(f(xf[j] - q[j] * ev[j]) - s * s) < 1e-12
+        for t in np.linspace(0, 1, 33)[:-1]:
+            assert f(xf[j] - t * q[j] * ev[j]) < s * s * (1 + 1e-12)
+    for j in np.flatnonzero(q >= 1.0):
+        assert all(f(xf[j] - t * ev[j]) < s * s for t in np.arange(1, 9) / 8)
+    for j in np.flatnonzero(q <= 1e-9):
+        assert f(xf[j] - (1 / 8) * ev[j]) >= s * s

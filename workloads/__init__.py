@@ -77,6 +77,8 @@ class Config:
     contact_kn: float = 0.0
     contact_en: float = 0.5
     contact_mu: float = 0.5
+    # 1: link fractions on the sphero-metaball level set f_in = c_0 (needs contact_rs > 0)
+    link_c0: int = 0
     particles: List[Particle] = dataclasses.field(default_factory=list)
     name: str = ""
     steps: int = 0
@@ -420,23 +422,25 @@ def mi_hull(cp, k, m: int = 2048, dr: float = 0.02):
 
 
 def mi_population(hull, planes, N_I: int, n: int, seed: int = 62, k_scale: float | None = None):
-    """Initial GA population [N_I][n][4] (k, x, y, z): control points uniform
-    in the hull's bounding box, redrawn until inside its convex hull; weights
-    uniform in (0, 2 k_scale], k_scale = (mean hull radius)^2 / n."""
+    """Initial GA population [N_I][n][4] (k, x, y, z): control points drawn
+    uniformly in the hull's bounding box in batches of 4096, those inside its
+    convex hull taken in draw order; weights uniform in (0, 2 k_scale],
+    k_scale = (mean hull radius)^2 / n."""
     rng = _rng(seed)
     lo, hi = hull.min(0), hull.max(0)
     if k_scale is None:
         k_scale = float(np.mean(np.linalg.norm(hull, axis=1)) ** 2 / n)
+    need = N_I * n
+    pts = []
+    got = 0
+    while got < need:
+        c = rng.uniform(lo, hi, size=(4096, 3))
+        ok = np.all(c @ planes[:, :3].T + planes[:, 3] <= 0.0, axis=1)
+        pts.append(c[ok])
+        got += int(ok.sum())
     pop = np.zeros((N_I, n, 4))
-    for a in range(N_I):
-        for j in range(n):
-            while True:
-                p = rng.uniform(lo, hi)
-                if np.all(planes[:, :3] @ p + planes[:, 3] <= 0.0):
-                    break
-            pop[a, j, 1:4] = p
-        pop[a, :, 0] = rng.uniform(0.0, 2.0 * k_scale, size=n)
-        pop[a, :, 0] = np.maximum(pop[a, :, 0], 1e-3 * k_scale)
+    pop[:, :, 1:4] = np.concatenate(pts)[:need].reshape(N_I, n, 3)
+    pop[:, :, 0] = np.maximum(rng.uniform(0.0, 2.0 * k_scale, size=(N_I, n)), 1e-3 * k_scale)
     return pop
 
 
@@ -449,3 +453,36 @@ def mi_draws(E: int, N_I: int, n: int, seed: int = 63):
     Z = rng.standard_normal((E, N_I, n, 4))
     PERM = np.stack([rng.permutation(N_I) for _ in range(E)]).astype(np.int32)
     return U, Z, PERM
+
+
+# ------------------------------------------------ drafting-kissing-tumbling
+def dkt_shapes(n_shapes: int = 6, R: float = 5.0, a_max: float = 4.0):
+    """Bodies of stepped elongation: two equal control points at +-a along
+    the body x axis, a = 0 (the sphere of radius R) to a_max, weights summing
+    to R^2 (the far field of a sphere of radius R).  Sizes are made equal in
+    volume by the caller from the measured volumes (exact shape scaling
+    p -> s p, k -> s^2 k)."""
+    out = []
+    for j in range(n_shapes):
+        a = a_max * j / max(n_shapes - 1, 1)
+        cp = np.array([[-a, 0.0, 0.0], [a, 0.0, 0.0]])
+        out.append((cp, np.array([0.5 * R * R, 0.5 * R * R])))
+    return out
+
+
+def dkt_pair(cp, k, D_e: float = 10.0, g: float = 5e-5, tau: float = 0.6) -> Config:
+    """Two bodies of one shape settling in a walled box, scaled from the
+    paper's set-up (sec. 4): box 0.20 x 0.20 x 0.30 m for a volume-equivalent
+    diameter D_e = 0.0125 m, i.e. 16 D_e x 16 D_e x 24 D_e; the bodies start
+    0.270 and 0.255 m above the bottom (trailing and leading) with 0.004 m
+    between them horizontally; density ratio 2800/976; contact on."""
+    s = D_e / 0.0125
+    nx, ny, nz = int(round(0.20 * s)), int(round(0.20 * s)), int(round(0.30 * s))
+    c = np.array([nx / 2, ny / 2])
+    bodies = []
+    for z, dx in ((0.255, -0.002), (0.270, 0.002)):  # leading first
+        bodies.append(Particle(cp_xyz=np.asarray(cp, float), cp_k=np.asarray(k, float),
+                               x=np.array([c[0] + dx * s, c[1], z * s]), density=2800.0 / 976.0))
+    return Config(nx=nx, ny=ny, nz=nz, periodic=0, tau=tau, rho0=1.0, g_particle=np.array([0.0, 0.0, -g]),
+                  bc=BC_IBB, particles=bodies, contact_rs=1.0, contact_kn=20.0, contact_en=0.5, contact_mu=0.5,
+                  quad_h=0.25, name=f"dkt-{nx}x{ny}x{nz}")
