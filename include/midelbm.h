@@ -48,8 +48,11 @@
  *   - Every call returns an lbm_status; lbm_last_error() gives a message for
  *     the last failure on the calling thread.  Device-side conditions (link
  *     list overflow, a particle moving more than one lattice unit per step,
- *     a non-finite particle state) are recorded on the device and reported
- *     as LBM_E_DIVERGED or LBM_E_NOMEM by the next synchronising call.
+ *     a non-finite particle state, and the fluid sentinel: a plain fluid node
+ *     whose moments are not finite or whose velocity exceeds 0.3 lattice
+ *     units, checked by the stream-collide at every node of every step) are
+ *     recorded on the device, stay set, and are reported as LBM_E_DIVERGED or
+ *     LBM_E_NOMEM by every later synchronising call.
  */
 #ifndef MIDELBM_H
 #define MIDELBM_H
@@ -69,7 +72,8 @@ typedef enum {
     LBM_E_INVALID = -1,  /* argument out of range, NaN input, bad geometry        */
     LBM_E_NOMEM = -2,    /* arena too small, or a device list ran out of capacity */
     LBM_E_HIP = -3,      /* a HIP runtime call failed                             */
-    LBM_E_DIVERGED = -4, /* non-finite or too fast particle state                 */
+    LBM_E_DIVERGED = -4, /* non-finite or too fast particle state, or a fluid node
+                            with non-finite moments or |u| > 0.3 (sentinel)      */
     LBM_E_STATE = -5     /* call not valid in the current state                   */
 } lbm_status;
 
@@ -95,7 +99,15 @@ typedef struct {
     double quad_h;        /* cell size of the body-property quadrature, > 0       */
     float fp16_scale;     /* FP16 storage multiplies deviations by this power of
                              two (0 selects 1024); ignored for FP32 and BF16       */
-    int32_t reserved;
+    int32_t link_c0;      /* 0: link fractions on the C = 1 surface that defines the
+                             flags; 1: on the sphero-metaball's surface (sec. 2.3.2:
+                             q solves f = c_0, c_0 depending on R_s): the level
+                             c_0 = s^2 of the inner body (the body scaled by
+                             s = 1 - contact_rs/sqrt(sum k) about its centroid,
+                             weights s^2 k), which gives back a sphere's own radius;
+                             needs contact_rs > 0.  Where that surface and C = 1
+                             differ, q is 1 when the solid node lies outside it and
+                             tends to 0 when the fluid node lies inside it        */
     /* contact (sec. 2.3.1): sphero-metaball of sphere radius contact_rs around
      * the body shrunk by 1 - contact_rs/sqrt(sum k); linear spring-dashpot with
      * stiffness contact_kn (0 disables contact), damping from the restitution
@@ -152,8 +164,10 @@ lbm_status metaball_flag(lbm_ctx *ctx, int64_t *n_solid, int64_t *n_links);
 lbm_status lbm_step(lbm_ctx *ctx, int32_t n_steps, int32_t mode);
 
 /* Hydrodynamic force and torque (about the centroid) on each particle from the
- * momentum exchange of the last step; F and T are [n_p][3] host arrays.
- * Synchronises. */
+ * momentum exchange of the last step (sec. 2.3.2, MEM paragraph: per cut link
+ * dP = (e_ib - u_w) f+_ib(x_f) - (e_i - u_w) f_i(x_f), both populations taken
+ * relative to w_i rho0, and dT = (x_w - X) x dP with x_w = x_f - q e_i, summed
+ * in a fixed order in FP64); F and T are [n_p][3] host arrays.  Synchronises. */
 lbm_status particle_forces(lbm_ctx *ctx, double *F, double *T);
 
 /* Local refilling (sec. 2.3.2) of the nodes uncovered by the last
@@ -207,6 +221,36 @@ lbm_status lbm_contact_stats(lbm_ctx *ctx, int64_t *contacts, int64_t *failures)
 lbm_status lbm_contact_nr_stats(lbm_ctx *ctx, int64_t *solves, int64_t *iterations);
 /* Waits for the context's stream and reports device-side errors. */
 lbm_status lbm_sync(lbm_ctx *ctx);
+
+/* ---- checkpoint / resume (not part of the paper's method: I/O around it) ----
+ * lbm_save writes the context's whole state to the file at path: the
+ * populations in their storage type (both buffers), flags and owners, skip
+ * masks, cut links with their fractions, the FP64 particle records
+ * (pose, velocities, loads, control points, region history), contact
+ * springs, the step counter and the kernel constants.  A pending refill is
+ * applied first.  Synchronises.  lbm_load replaces the state of ctx, which
+ * must have been set up by lbm_init with the same configuration and the same
+ * number of particles of the same sizes (the arena layout must match), with
+ * the file's; the steps after it are bitwise those that would have followed
+ * the save.  The warm-start network (lbm_set_warmstart) and the timing state
+ * are not part of the file.  Errors: LBM_E_INVALID (NULL argument, file
+ * cannot be opened, read or written, not a checkpoint), LBM_E_STATE (written
+ * by a context of another configuration; ctx is unchanged), LBM_E_HIP. */
+lbm_status lbm_save(lbm_ctx *ctx, const char *path);
+lbm_status lbm_load(lbm_ctx *ctx, const char *path);
+
+/* ---- measurement aid: streaming-copy ceiling ----
+ * Times a plain copy with the stream-collide's access shape: 19 arrays of n
+ * elements (elem_bytes 4 or 2) at a stride of `stride` elements in dev_src are
+ * read and written to dev_dst with non-temporal stores, one element per lane
+ * per array.  One warm-up launch, then reps launches bracketed by HIP events
+ * on hip_stream; *ms receives the mean duration of one launch, which moves
+ * 2 * 19 * n * elem_bytes bytes.  Both buffers are caller-owned device memory
+ * of at least 19 * stride elements (dev_dst is overwritten).  Synchronises.
+ * Errors: LBM_E_INVALID (NULL pointer, n <= 0, stride < n, reps < 1, other
+ * element size), LBM_E_HIP.  lbm_last_error() is not set by this call. */
+lbm_status lbm_copy_probe(const void *dev_src, void *dev_dst, int64_t n, int64_t stride, int32_t elem_bytes,
+                          int32_t reps, void *hip_stream, double *ms);
 
 void lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(void);

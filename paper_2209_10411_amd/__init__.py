@@ -38,7 +38,7 @@ class lbm_config(C.Structure):
                 ("tau", C.c_double), ("rho0", C.c_double), ("g_fluid", C.c_double * 3),
                 ("g_particle", C.c_double * 3), ("storage", C.c_int32), ("bc", C.c_int32),
                 ("n_sub", C.c_int32), ("counter_force", C.c_int32), ("quad_h", C.c_double),
-                ("fp16_scale", C.c_float), ("reserved", C.c_int32),
+                ("fp16_scale", C.c_float), ("link_c0", C.c_int32),
                 ("contact_rs", C.c_double), ("contact_kn", C.c_double), ("contact_en", C.c_double),
                 ("contact_mu", C.c_double)]
 
@@ -55,18 +55,26 @@ class lbm_particle_state(C.Structure):
                 ("mass", C.c_double), ("volume", C.c_double), ("inertia", C.c_double * 9)]
 
 
+class mb_shape(C.Structure):
+    _fields_ = [("V", C.c_double), ("S", C.c_double), ("A_p", C.c_double), ("dims", C.c_double * 3),
+                ("axes", C.c_double * 9), ("centroid", C.c_double * 3), ("d_n", C.c_double), ("d_s", C.c_double),
+                ("Phi", C.c_double), ("CSF", C.c_double), ("cells_inside", C.c_int64), ("columns_hit", C.c_int64)]
+
+
 EXPORTS = ["lbm_arena_bytes", "lbm_init", "metaball_flag", "lbm_step", "particle_forces", "refill",
            "lbm_get_macros", "lbm_get_populations", "lbm_set_populations", "lbm_get_flags",
            "lbm_get_links", "lbm_get_particles", "lbm_set_particles", "lbm_get_gfluid",
            "lbm_timing_enable", "lbm_timing_read", "lbm_nr_stats", "lbm_contact_stats", "lbm_contact_nr_stats",
-           "lbm_sync",
+           "lbm_sync", "lbm_save", "lbm_load", "lbm_copy_probe",
            "lbm_destroy",
            "lbm_last_error",
            "lbm_batch_arena_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_case", "lbm_autotune",
            "lbm_batch_tiles", "lbm_batch_destroy",
            "mlp_weights_bytes", "mlp_param_count", "mlp_init", "mlp_get_params", "mlp_collect",
            "mlp_collect_contact", "mlp_forward",
-           "mlp_grad", "mlp_train", "lbm_set_warmstart", "lbm_nr_histogram"]
+           "mlp_grad", "mlp_train", "lbm_set_warmstart", "lbm_nr_histogram",
+           "mi_fitness_work_bytes", "mi_fitness", "mi_ga_work_bytes", "mi_ga", "mi_gs",
+           "mb_shape_work_bytes", "mb_shape_descriptors"]
 
 _lib = None
 
@@ -103,6 +111,9 @@ def lib():
         L.lbm_contact_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_contact_nr_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_sync.argtypes = [vp]
+        L.lbm_copy_probe.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, vp, dp]
+        L.lbm_save.argtypes = [vp, C.c_char_p]
+        L.lbm_load.argtypes = [vp, C.c_char_p]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         L.lbm_last_error.restype = C.c_char_p
@@ -131,9 +142,21 @@ def lib():
         L.mlp_train.argtypes = [vp, vp, C.c_int64, C.c_char_p, vp, vp]
         L.lbm_set_warmstart.argtypes = [vp, vp]
         L.lbm_nr_histogram.argtypes = [vp, C.POINTER(C.c_int64), dp]
+        L.mi_fitness_work_bytes.argtypes = [C.c_int64, C.c_int32]
+        L.mi_fitness_work_bytes.restype = C.c_size_t
+        L.mi_fitness.argtypes = [vp, C.c_int64, vp, C.c_int32, C.c_int32, vp, vp, C.c_size_t, vp]
+        L.mi_ga_work_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32]
+        L.mi_ga_work_bytes.restype = C.c_size_t
+        L.mi_ga.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                            C.c_double, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.mi_gs.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, vp, vp, vp]
+        L.mb_shape_work_bytes.argtypes = [dp, dp, C.c_int32, C.c_double]
+        L.mb_shape_work_bytes.restype = C.c_size_t
+        L.mb_shape_descriptors.argtypes = [dp, dp, C.c_int32, C.c_double, vp, C.c_size_t, vp, C.POINTER(mb_shape)]
         for name in EXPORTS:
             if name not in ("lbm_destroy", "lbm_last_error", "lbm_batch_destroy", "mlp_weights_bytes",
-                            "mlp_param_count"):
+                            "mlp_param_count", "mi_fitness_work_bytes", "mi_ga_work_bytes",
+                            "mb_shape_work_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -162,6 +185,7 @@ def make_config(cfg) -> lbm_config:
     c.contact_kn = float(getattr(cfg, "contact_kn", 0.0))
     c.contact_en = float(getattr(cfg, "contact_en", 0.5))
     c.contact_mu = float(getattr(cfg, "contact_mu", 0.5))
+    c.link_c0 = int(getattr(cfg, "link_c0", 0))
     return c
 
 
@@ -264,6 +288,14 @@ class Simulation:
     # ---- state access
     def sync(self):
         _check(lib().lbm_sync(self._ctx))
+
+    def save(self, path: str):
+        """Checkpoint of the whole state (lbm_save)."""
+        _check(lib().lbm_save(self._ctx, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Replaces the state with a checkpoint of the same configuration (lbm_load)."""
+        _check(lib().lbm_load(self._ctx, os.fsencode(path)))
 
     def macros(self):
         rho, u = np.zeros(self.N), np.zeros(3 * self.N)
@@ -512,3 +544,111 @@ def mlp_collect(sim, n_max: int | None = None):
     _check(L.mlp_collect(sim._ctx, int(n_max), C.c_void_p(feat.data_ptr()), C.c_void_p(target.data_ptr()),
                          C.byref(n)))
     return feat[:n.value], target[:n.value]
+
+
+def copy_probe(n: int, elem_bytes: int = 4, reps: int = 20, device: str = "cuda:0") -> float:
+    """Mean milliseconds of one streaming copy of 19 arrays of n elements
+    (read + non-temporal write, lbm_copy_probe) on the current stream of
+    ``device``; buffers are allocated here and freed on return."""
+    import torch
+
+    stride = (n + 127) // 128 * 128
+    dev = torch.device(device)
+    src = torch.zeros(19 * stride * elem_bytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    ms = C.c_double(0.0)
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev)
+        rc = lib().lbm_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), int(n), int(stride),
+                                  int(elem_bytes), int(reps), C.c_void_p(stream.cuda_stream), C.byref(ms))
+    if rc != 0:
+        raise LbmError(rc, "lbm_copy_probe failed")
+    del src, dst
+    return float(ms.value)
+
+
+# ---- Metaball-Imaging fit (include/mifit.h): numpy in, numpy out; device
+# buffers are torch tensors allocated here for the call
+def _dev(a, dtype, device):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(torch.device(device)).cuda_stream)
+
+
+def mi_fitness(hull, pop, device: str = "cuda:0", work=None):
+    """F [P] of the individuals pop [P][n][4] over the hull [m][3] (mi_fitness)."""
+    import torch
+    hull = np.asarray(hull, dtype=np.float64).reshape(-1, 3)
+    pop = np.asarray(pop, dtype=np.float64)
+    P, n = pop.shape[0], pop.shape[1]
+    h, p = _dev(hull, torch.float64, device), _dev(pop, torch.float64, device)
+    F = torch.empty(P, dtype=torch.float64, device=device)
+    wb = lib().mi_fitness_work_bytes(hull.shape[0], P)
+    w = torch.empty(max(int(wb), 1), dtype=torch.uint8, device=device)
+    _check(lib().mi_fitness(_ptr(h), hull.shape[0], _ptr(p), P, n, _ptr(F), _ptr(w), int(wb), _stream(device)))
+    torch.cuda.synchronize(device)
+    return F.cpu().numpy()
+
+
+def mi_ga(hull, pop0, E, C_m, C_c, sigma_x, sigma_k, U, Z, PERM, device: str = "cuda:0"):
+    """Final population (fittest first) and fitness of Alg. GA (mi_ga)."""
+    import torch
+    hull = np.asarray(hull, dtype=np.float64).reshape(-1, 3)
+    pop0 = np.asarray(pop0, dtype=np.float64)
+    N, n = pop0.shape[0], pop0.shape[1]
+    h, p = _dev(hull, torch.float64, device), _dev(pop0, torch.float64, device)
+    u, z = _dev(U[:E], torch.float64, device), _dev(Z[:E], torch.float64, device)
+    pm = _dev(PERM[:E], torch.int32, device)
+    F = torch.empty(N, dtype=torch.float64, device=device)
+    wb = int(lib().mi_ga_work_bytes(hull.shape[0], N, n))
+    w = torch.empty(max(wb, 1), dtype=torch.uint8, device=device)
+    _check(lib().mi_ga(_ptr(h), hull.shape[0], N, n, int(E), float(C_m), float(C_c), float(sigma_x),
+                       float(sigma_k), _ptr(u), _ptr(z), _ptr(pm), _ptr(p), _ptr(F), _ptr(w), wb,
+                       _stream(device)))
+    return p.cpu().numpy(), F.cpu().numpy()
+
+
+def mi_gs(hulls, planes, M0, E, eta, device: str = "cuda:0"):
+    """Alg. GS for a batch: hulls and planes are lists (one per model), M0
+    [B][n][4]; returns (M [B][n][4], loss [B][3])."""
+    import torch
+    M0 = np.asarray(M0, dtype=np.float64)
+    B, n = M0.shape[0], M0.shape[1]
+    ho = np.concatenate([[0], np.cumsum([len(h) for h in hulls])]).astype(np.int64)
+    po = np.concatenate([[0], np.cumsum([len(q) for q in planes])]).astype(np.int64)
+    H = _dev(np.concatenate([np.asarray(h, dtype=np.float64).reshape(-1, 3) for h in hulls]), torch.float64, device)
+    Pl = _dev(np.concatenate([np.asarray(q, dtype=np.float64).reshape(-1, 4) for q in planes]), torch.float64, device)
+    dho, dpo = _dev(ho, torch.int64, device), _dev(po, torch.int64, device)
+    M = _dev(M0, torch.float64, device)
+    loss = torch.empty(B * 3, dtype=torch.float64, device=device)
+    _check(lib().mi_gs(_ptr(H), _ptr(dho), _ptr(Pl), _ptr(dpo), B, n, int(E), float(eta), _ptr(M), _ptr(loss),
+                       _stream(device)))
+    torch.cuda.synchronize(device)
+    return M.cpu().numpy(), loss.cpu().numpy().reshape(B, 3)
+
+
+def shape_descriptors(cp, k, h: float = 0.25, device: str = "cuda:0") -> dict:
+    """Sphericity, d_n, d_s, CSF and the quantities behind them for the
+    metaball (cp [n][3], k [n]) on a grid of step h (mb_shape_descriptors)."""
+    import torch
+    cp = np.ascontiguousarray(cp, dtype=np.float64).reshape(-1)
+    k = np.ascontiguousarray(k, dtype=np.float64).reshape(-1)
+    wb = int(lib().mb_shape_work_bytes(_dptr(cp), _dptr(k), k.size, float(h)))
+    if wb == 0:
+        raise LbmError(-1, "mb_shape_work_bytes: invalid body or grid")
+    w = torch.empty(wb, dtype=torch.uint8, device=device)
+    out = mb_shape()
+    _check(lib().mb_shape_descriptors(_dptr(cp), _dptr(k), k.size, float(h), _ptr(w), wb, _stream(device),
+                                      C.byref(out)))
+    return {"V": out.V, "S": out.S, "A_p": out.A_p, "dims": np.array(out.dims[:]),
+            "axes": np.array(out.axes[:]).reshape(3, 3).T, "centroid": np.array(out.centroid[:]),
+            "d_n": out.d_n, "d_s": out.d_s, "Phi": out.Phi, "CSF": out.CSF,
+            "cells_inside": int(out.cells_inside), "columns_hit": int(out.columns_hit)}

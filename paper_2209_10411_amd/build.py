@@ -5,7 +5,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "mlp.hip"),
-       os.path.join(HERE, "csrc", "api.cpp")]
+       os.path.join(HERE, "csrc", "api.cpp"), os.path.join(HERE, "csrc", "copy_probe.hip"),
+       os.path.join(HERE, "csrc", "mifit.hip"), os.path.join(HERE, "csrc", "shape.hip")]
 LIB = os.path.join(HERE, "libmidelbm.so")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

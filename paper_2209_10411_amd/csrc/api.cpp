@@ -215,6 +215,9 @@ lbm_status validate_config(const lbm_config *c) {
         if (!(c->contact_en > 0.0 && c->contact_en <= 1.0)) return fail(LBM_E_INVALID, "contact_en must be in (0, 1]");
         if (!(c->contact_mu >= 0.0) || !std::isfinite(c->contact_mu)) return fail(LBM_E_INVALID, "contact_mu must be >= 0");
     }
+    if (c->link_c0 != 0 && c->link_c0 != 1) return fail(LBM_E_INVALID, "link_c0 must be 0 or 1");
+    if (c->link_c0 && (!(c->contact_rs > 0.0) || !std::isfinite(c->contact_rs)))
+        return fail(LBM_E_INVALID, "link_c0 needs contact_rs > 0");
     if (c->storage == 1 && c->fp16_scale != 0.f) {
         int e;
         const float m = std::frexp(c->fp16_scale, &e);
@@ -414,6 +417,8 @@ lbm_status check_device(lbm_ctx *c) {
     HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
     if (h.err & ERR_NONFINITE) return fail(LBM_E_DIVERGED, "a particle state became non-finite");
     if (h.err & ERR_FAST_PARTICLE) return fail(LBM_E_DIVERGED, "a particle moved more than one lattice unit in a step");
+    if (h.err & ERR_FLUID)
+        return fail(LBM_E_DIVERGED, "the fluid diverged: a fluid node had non-finite moments or |u| > 0.3");
     if (h.err & ERR_LINK_OVERFLOW) return fail(LBM_E_NOMEM, "cut-link list exceeded its capacity (%d)", c->p.link_cap);
     if (h.err & ERR_SPECIAL_OVERFLOW) return fail(LBM_E_NOMEM, "boundary-node list exceeded its capacity (%d)", c->p.special_cap);
     if (h.err & ERR_BAD_INDEX) return fail(LBM_E_STATE, "an index list held an out-of-range entry (skipped)");
@@ -678,6 +683,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
         p.inv_scale = 1.f / p.scale;
     }
     p.contact = pl.contact ? 1 : 0;
+    p.link_c0 = cfg->link_c0;
     p.c_rs = cfg->contact_rs; p.c_kn = cfg->contact_kn; p.c_en = cfg->contact_en; p.c_mu = cfg->contact_mu;
     p.link_cap = pl.link_cap;
     p.special_cap = pl.special_cap;
@@ -1284,6 +1290,120 @@ lbm_status lbm_contact_stats(lbm_ctx *c, int64_t *contacts, int64_t *failures) {
     return LBM_OK;
 }
 
+// ---------------------------------------------------------------- checkpoint
+// File: a header (magic, version, the configuration, the particle count, the
+// arena plan's offsets, the host-side step state and the kernel constants),
+// then the arena's bytes [0, plan total) verbatim: populations in their
+// storage type in both buffers, the three flag buffers, skip masks, particle
+// records (FP64 state, control points, region history), cut links with q,
+// contact springs, counters.  The arena holds no pointers, so a checkpoint
+// loads into any arena of a context set up with the same configuration.
+namespace {
+constexpr char CKPT_MAGIC[8] = {'M', 'I', 'D', 'E', 'L', 'B', 'M', 0};
+constexpr uint32_t CKPT_VERSION = 1;
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, n_sig;
+    lbm_config cfg;
+    int32_t n_p, ic, in, id, is, a_first, pending_refill, pad;
+    int64_t steps;
+    Params p;
+};
+std::vector<uint64_t> plan_signature(const Plan &pl) {
+    std::vector<uint64_t> v = {(uint64_t)pl.N, (uint64_t)pl.Ns, (uint64_t)pl.np, (uint64_t)pl.storage_bytes,
+                               (uint64_t)pl.region_blocks, (uint64_t)pl.link_cap, (uint64_t)pl.special_cap,
+                               pl.off_A, pl.off_B, pl.off_own[0], pl.off_own[1], pl.off_own[2], pl.off_skip[0],
+                               pl.off_skip[1], pl.off_P, pl.off_part, pl.off_first, pl.off_dims, pl.off_pfb,
+                               pl.off_bcnt, pl.off_blinks, pl.off_loff, pl.off_lnode, pl.off_ldo, pl.off_lq,
+                               pl.off_lpart, pl.off_special, pl.off_cnt, pl.off_lmask, pl.off_nrs, pl.off_mlpb,
+                               pl.off_pairF, pl.off_pairTi, pl.off_pairTj, pl.off_wallF, pl.off_wallT, pl.off_xiP,
+                               pl.off_xiW, pl.off_pairOn, pl.off_pairXm, pl.off_pairOk, pl.off_pairGuess, pl.total};
+    return v;
+}
+constexpr size_t CKPT_CHUNK = size_t(64) << 20;
+}  // namespace
+
+lbm_status lbm_save(lbm_ctx *c, const char *path) {
+    if (!c || !path) return fail(LBM_E_INVALID, "NULL argument");
+    if (c->pending_refill) do_refill(c);
+    lbm_status s = check_device(c);
+    if (s) return s;
+    CkptHeader h;
+    memset(&h, 0, sizeof h);
+    memcpy(h.magic, CKPT_MAGIC, 8);
+    h.version = CKPT_VERSION;
+    const std::vector<uint64_t> sig = plan_signature(c->pl);
+    h.n_sig = (uint32_t)sig.size();
+    h.cfg = c->cfg;
+    h.n_p = c->p.np;
+    h.ic = c->ic; h.in = c->in; h.id = c->id; h.is = c->is;
+    h.a_first = c->A == (void *)(c->arena + c->pl.off_A);
+    h.pending_refill = 0;
+    h.steps = c->steps;
+    h.p = c->p;
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(LBM_E_INVALID, "cannot open %s for writing", path);
+    bool ok = fwrite(&h, sizeof h, 1, f) == 1 && fwrite(sig.data(), 8, sig.size(), f) == sig.size();
+    std::vector<char> buf(std::min(CKPT_CHUNK, c->pl.total));
+    for (size_t o = 0; ok && o < c->pl.total; o += buf.size()) {
+        const size_t n = std::min(buf.size(), c->pl.total - o);
+        if (hipMemcpy(buf.data(), c->arena + o, n, hipMemcpyDeviceToHost) != hipSuccess) {
+            fclose(f);
+            return fail(LBM_E_HIP, "reading the arena for %s failed", path);
+        }
+        ok = fwrite(buf.data(), 1, n, f) == n;
+    }
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(LBM_E_INVALID, "writing %s failed", path);
+    return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx *c, const char *path) {
+    if (!c || !path) return fail(LBM_E_INVALID, "NULL argument");
+    lbm_status s = check_device(c);
+    if (s) return s;
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(LBM_E_INVALID, "cannot open %s", path);
+    CkptHeader h;
+    if (fread(&h, sizeof h, 1, f) != 1 || memcmp(h.magic, CKPT_MAGIC, 8) != 0) {
+        fclose(f);
+        return fail(LBM_E_INVALID, "%s is not a checkpoint of this library", path);
+    }
+    if (h.version != CKPT_VERSION) {
+        fclose(f);
+        return fail(LBM_E_INVALID, "%s: checkpoint version %u, expected %u", path, h.version, CKPT_VERSION);
+    }
+    const std::vector<uint64_t> sig = plan_signature(c->pl);
+    std::vector<uint64_t> fsig(h.n_sig);
+    if (h.n_sig != sig.size() || fread(fsig.data(), 8, fsig.size(), f) != fsig.size() || fsig != sig ||
+        memcmp(&h.cfg, &c->cfg, sizeof h.cfg) != 0 || h.n_p != c->p.np) {
+        fclose(f);
+        return fail(LBM_E_STATE, "%s was written by a context of another configuration", path);
+    }
+    std::vector<char> buf(std::min(CKPT_CHUNK, c->pl.total));
+    for (size_t o = 0; o < c->pl.total; o += buf.size()) {
+        const size_t n = std::min(buf.size(), c->pl.total - o);
+        if (fread(buf.data(), 1, n, f) != n) {
+            fclose(f);
+            return fail(LBM_E_INVALID, "%s is truncated (the context's state is now undefined)", path);
+        }
+        if (hipMemcpy(c->arena + o, buf.data(), n, hipMemcpyHostToDevice) != hipSuccess) {
+            fclose(f);
+            return fail(LBM_E_HIP, "writing the arena from %s failed", path);
+        }
+    }
+    fclose(f);
+    char *b = c->arena;
+    c->A = b + (h.a_first ? c->pl.off_A : c->pl.off_B);
+    c->B = b + (h.a_first ? c->pl.off_B : c->pl.off_A);
+    c->ic = h.ic; c->in = h.in; c->id = h.id; c->is = h.is;
+    c->pending_refill = false;
+    c->steps = h.steps;
+    c->p = h.p;
+    c->ev_used = 0;
+    return check_device(c);
+}
+
 void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
@@ -1369,6 +1489,7 @@ BulkCase bulk_case(const lbm_ctx *c, int twl, int bw, int first_block) {
     b.n_blocks = (int)tile_blocks(c->cfg, twl, bw);
     b.A[0] = c->A; b.B[0] = c->B; b.A[1] = c->B; b.B[1] = c->A;
     b.skip[0] = c->skip[c->is]; b.skip[1] = c->skip[1 - c->is];
+    b.err = &c->cnt->err;
     return b;
 }
 

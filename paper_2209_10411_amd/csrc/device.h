@@ -16,7 +16,7 @@ constexpr int BLK = 256;                // threads per block of the region kerne
 constexpr int TILE_X = 8, TILE_Y = 8, TILE_Z = 4;  // a region block is a tile of BLK nodes
 
 enum : int { ERR_LINK_OVERFLOW = 1, ERR_SPECIAL_OVERFLOW = 2, ERR_FAST_PARTICLE = 4,
-             ERR_NONFINITE = 8, ERR_BAD_INDEX = 16 };
+             ERR_NONFINITE = 8, ERR_BAD_INDEX = 16, ERR_FLUID = 32 };
 
 // D3Q19 velocities in the order documented in midelbm.h.
 constexpr int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
@@ -102,6 +102,7 @@ struct Params {
     int region_blocks;          // blocks of the region kernels
     int est_links, est_special; // expected list lengths (launch sizes of the list kernels; 0: capacities)
     int contact;                // contact enabled
+    int link_c0;                // link fractions on the sphero-metaball level set (inner body, c_0 = s^2)
     double c_rs, c_kn, c_en, c_mu;
     // minimum image on a periodic axis of length L: for |d| < 1.25 L the
     // image shift k = floor(d / L + 0.5) (FP64) is +1 exactly when d >= mi_up
@@ -143,6 +144,7 @@ struct BulkCase {
     int n_blocks;     // blocks of this system
     void *A[2], *B[2];
     const uint8_t *skip[2];
+    int *err;         // the system's error word (divergence sentinel)
 };
 
 // Region block map: block b of a region kernel works on particle part[b],
@@ -183,8 +185,8 @@ struct CaseArgs {
     int first[BK_N], nblk[BK_N];
 };
 // the host writes these tables for the device: one layout on both sides
-static_assert(sizeof(Params) == 248 && sizeof(CaseArgs) == 592 && offsetof(CaseArgs, nrs) == 504 &&
-                  offsetof(CaseArgs, first) == 548,
+static_assert(sizeof(Params) == 256 && sizeof(CaseArgs) == 600 && offsetof(CaseArgs, nrs) == 512 &&
+                  offsetof(CaseArgs, first) == 556,
               "CaseArgs layout");
 
 }  // namespace mdl

@@ -76,6 +76,7 @@ struct CPs {
     double k[MAXCP + 3];
     int n;    // padded count
     int img;  // the body's img: 0 = the minimum image is the identity here
+    double level;  // the link fractions' surface: C = level (1, or c_0 of the inner body)
 };
 
 __device__ void stage_cps(CPs &c, const DevParticle &P) {
@@ -155,13 +156,16 @@ __device__ double metaball_fast(const Params &p, const CPs &P, const double x[3]
     return C;
 }
 
-// Whether C(x) >= 1 exactly as metaball decides it (exact quotients summed
-// in index order): the fast sum decides unless it lies within 1e-12 of 1,
+// Whether C(x) >= L exactly as metaball decides it (exact quotients summed
+// in index order): the fast sum decides unless it lies within 1e-12 L of L,
 // where metaball is evaluated.  Cf: the fast value.
-__device__ __forceinline__ bool metaball_ge1(const Params &p, const CPs &P, const double x[3], double &Cf) {
+__device__ __forceinline__ bool metaball_ge(const Params &p, const CPs &P, const double x[3], double L, double &Cf) {
     Cf = metaball_fast(p, P, x);
-    if (fabs(Cf - 1.0) > 1e-12) return Cf >= 1.0;
-    return metaball(p, P, x) >= 1.0;
+    if (fabs(Cf - L) > 1e-12 * L) return Cf >= L;
+    return metaball(p, P, x) >= L;
+}
+__device__ __forceinline__ bool metaball_ge1(const Params &p, const CPs &P, const double x[3], double &Cf) {
+    return metaball_ge(p, P, x, 1.0, Cf);
 }
 
 // C and dC/ds at x_f - s e_i for one link held by an aligned group of eight
@@ -194,8 +198,9 @@ __device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], 
     dC = g;
 }
 
-// Link fraction q (sec. 2.3.2): the first root of C(x_f - s e_i) = 1 on
-// (0,1], for one link by an aligned group of eight lanes (all active).
+// Link fraction q (sec. 2.3.2): the first root of C(x_f - s e_i) = L on
+// (0,1] (L = P.level: 1, or c_0 for the sphero-metaball's inner body), for
+// one link by an aligned group of eight lanes (all active).
 // Bracket: lane j decides C >= 1 at s = (j + 1)/8 exactly as the flagging
 // does (metaball_ge1), and the first of the eight sub-interval ends with C >= 1 closes
 // the bracket (none: q = 1).  Then a safeguarded Newton iteration
@@ -214,7 +219,8 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
     const double sj = (double)(j + 1) / 8.0;
     const double xj[3] = {xf[0] - sj * e[0], xf[1] - sj * e[1], xf[2] - sj * e[2]};
     double Cj;
-    const bool inj = metaball_ge1(p, P, xj, Cj);
+    const double L = P.level;
+    const bool inj = metaball_ge(p, P, xj, L, Cj);
     const unsigned grp = (unsigned)((__ballot(inj) >> base) & 0xffull);
     const int k0 = grp ? __ffs(grp) - 1 : 7;
     const double Chi = __shfl(Cj, base + k0), Clo = __shfl(Cj, base + (k0 > 0 ? k0 - 1 : 0));
@@ -225,7 +231,7 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
         return 0;
     }
     double lo = k0 / 8.0, hi = (k0 + 1) / 8.0;
-    const double ghi = Chi - 1.0, glo = Clo - 1.0;
+    const double ghi = Chi - L, glo = Clo - L;
     double s;
     if (guess > lo && guess < hi) s = guess;
     else if (k0 > 0 && ghi < __builtin_inf()) s = lo + (hi - lo) * (-glo) / (ghi - glo);
@@ -238,9 +244,9 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
         double C, dC;
         metaball_ds8(p, P, xf, e, s, C, dC);
         ++it;
-        const double g = C - 1.0;
+        const double g = C - L;
         resid = g;
-        if (fabs(g) < 1e-15) {  // C = 1 to a few ulps: nothing left to resolve (tangent links get here
+        if (fabs(g) < 1e-15 * L) {  // C = L to a few ulps: nothing left to resolve (tangent links get here
             conv = true;        // long before the step drops below 1e-13)
             break;
         }
@@ -315,21 +321,27 @@ __device__ __forceinline__ double feq64d(int i, double rho, const double u[3]) {
     return c_wd[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
 }
 
-// BGK + Guo for the one direction i a lane owns, given the node's moments.
+// BGK + Guo for the one direction i a lane owns, given the node's moments:
+// the same increments as collide (d+_i = (1 - 1/tau) d_i + S + A_i with S
+// even and A_i odd in e_i).
 __device__ __forceinline__ float collide_lane(float d, int i, float dr, float jx, float jy, float jz,
                                               const Params &p) {
     const float rho = p.rho0f + dr;
     const float Fx = rho * p.gx, Fy = rho * p.gy, Fz = rho * p.gz;
-    const float inv = 1.0f / rho;
+    const float inv = __builtin_amdgcn_rcpf(rho);
     const float ux = (jx + 0.5f * Fx) * inv, uy = (jy + 0.5f * Fy) * inv, uz = (jz + 0.5f * Fz) * inv;
     const float uu = ux * ux + uy * uy + uz * uz;
     const float uF = ux * Fx + uy * Fy + uz * Fz;
+    const float om = p.omega;
+    const float g = om * (dr - 1.5f * rho * uu) - 3.f * p.fcoef * uF;
+    const float r45 = 4.5f * om * rho, r3 = 3.f * om * rho, f9 = 9.f * p.fcoef, f3 = 3.f * p.fcoef;
     const float ex = (float)c_ex[i], ey = (float)c_ey[i], ez = (float)c_ez[i], w = c_w[i];
     const float eu = ex * ux + ey * uy + ez * uz;
     const float eF = ex * Fx + ey * Fy + ez * Fz;
-    const float deq = w * (dr + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
-    const float Fi = p.fcoef * w * (3.f * (eF - uF) + 9.f * eu * eF);
-    return d + p.omega * (deq - d) + Fi;
+    const float T = (w * r45) * eu + (w * f9) * eF;
+    const float S = eu * T + w * g;
+    const float A = (w * r3) * eu + (w * f3) * eF;
+    return (1.f - om) * d + (S + A);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -1849,15 +1861,20 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
         if (ok) {  // stage this group's control points (padded to a multiple of 4, weight 0)
             const DevParticle &B = P[pid];
             const int n4 = (B.n_cp + 3) & ~3;
+            // sphero-metaball level: the inner body (scaled by s about the
+            // centroid, weights s^2 k) at the level c_0 = s^2
+            const bool inner = p.link_c0 && p.c_rs > 0.0;
+            const double sc = inner ? 1.0 - p.c_rs * B.rsk : 1.0;
             for (int e = j; e < n4 * 4; e += 8) {
                 const int k = e >> 2, a = e & 3;
                 const int src = k < B.n_cp ? k : 0;
-                if (a < 3) cps[g].x[k][a] = B.cpl[src][a];
-                else cps[g].k[k] = k < B.n_cp ? B.k[k] : 0.0;
+                if (a < 3) cps[g].x[k][a] = inner ? B.X[a] + sc * (B.cpl[src][a] - B.X[a]) : B.cpl[src][a];
+                else cps[g].k[k] = k < B.n_cp ? (inner ? sc * sc * B.k[k] : B.k[k]) : 0.0;
             }
             if (j == 0) {
                 cps[g].n = n4;
                 cps[g].img = B.img;
+                cps[g].level = sc * sc;
             }
             node_xyz(p, n, x, y, z);
         }
@@ -2012,26 +2029,23 @@ static void launch_step_kernels_t(const StepArgs &a) {
         }
     } else if (a.phase == PHASE_BULK) {
         // events ride on the dispatch itself (no separate marker packets)
-        if constexpr (S != 0) {
-            if (p.nx % 2 == 0 && p.nx % 128 != 0) {  // node pairs in lattice order (no idle lanes)
-                hipExtLaunchKernelGGL(k_bulk_pair_flat<S>, dim3(cdiv(cdiv(p.N, 128), BULK_WAVES)),
-                                      dim3(64 * BULK_WAVES), 0, a.stream, a.ev_start, a.ev_stop, 0, p, (const T *)A,
-                                      B, (const uint8_t *)a.skip);
-                return;
-            }
-            if (p.nx % 128 == 0) {  // 16-bit storage: node pairs, 32-bit accesses, a wave per 128 x of a row
-                const int nseg = cdiv(p.nx, 128);
-                const long long waves = (long long)nseg * p.ny * p.nz;
-                hipExtLaunchKernelGGL(k_bulk_pair<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0,
-                                      a.stream, a.ev_start, a.ev_stop, 0, p, (const T *)A, B,
-                                      (const uint8_t *)a.skip, nseg);
-                return;
-            }
+        const bool fits = bulk_offsets_fit(p, (int)sizeof(T));
+        if (S != 0 && p.nx % 2 == 0 && fits) {  // 16-bit storage: node pairs in lattice order
+            hipExtLaunchKernelGGL(k_bulk_pair<S>, dim3(cdiv(cdiv(p.N, 128), BULK_WAVES)), dim3(64 * BULK_WAVES), 0,
+                                  a.stream, a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip,
+                                  &a.cnt->err);
+            return;
         }
         const int nseg = cdiv(p.nx, 64);
         const long long waves = (long long)nseg * p.ny * p.nz;
-        hipExtLaunchKernelGGL(k_bulk<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0, a.stream,
-                              a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip, nseg);
+        if (fits)
+            hipExtLaunchKernelGGL(k_bulk<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0, a.stream,
+                                  a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip, nseg,
+                                  &a.cnt->err);
+        else
+            hipExtLaunchKernelGGL(k_bulk_wide<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0, a.stream,
+                                  a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip, nseg,
+                                  &a.cnt->err);
     } else if (a.phase == PHASE_SPECIAL) {
         if (p.np > 0)
             hipExtLaunchKernelGGL(k_special<S>, dim3(spec_grid), dim3(256), 0, a.stream, a.ev_start, a.ev_stop, 0,

@@ -43,40 +43,80 @@ template <> struct Store<2> {
 };
 
 // ------------------------------------------------------------- lattice ops
-// BGK + Guo on deviations d_i = f_i - w_i rho0 (FP32).  rho = rho0 + sum d,
-// u = (sum e d + F/2)/rho with F = rho g; d+ = d + (deq - d)/tau + F_i.
-__device__ __forceinline__ void collide(float d[Q], const Params &p) {
-    float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+// Divergence sentinel: a fluid node whose velocity exceeds 0.3 lattice units
+// (Mach 0.52), or whose moments are not finite, marks the context as
+// diverged (ERR_FLUID; reported by the next synchronising call).
+constexpr float U_MAX_SQ = 0.09f;
+
+// Moments of the (possibly scaled) deviations and the BGK + Guo increments.
+// rho = rho0 + sum d, u = (sum e d + F/2)/rho with F = rho g; the update
+// d+ = d + (deq - d)/tau + F_i is evaluated per pair of opposite directions
+// (i, ib) as d+_i = (1 - 1/tau) d_i + S + A, d+_ib = (1 - 1/tau) d_ib + S - A,
+// with S the part of 1/tau deq_i + F_i even in e_i and A the odd part:
+//   S = w [1/tau (dr + 4.5 rho (e.u)^2 - 1.5 rho u.u) + (1 - 1/2tau)(9 (e.u)(e.F) - 3 u.F)]
+//   A = w [3/tau rho (e.u) + 3 (1 - 1/2tau) e.F]
+// SCALED: the stored values are s d (s = p.scale, a power of two, so every
+// scaling is exact): the moments are taken times 1/s and the increments
+// applied times s, which leaves the same bits as scaling each value.
+// Returns true when the node trips the sentinel (the comparison is false for
+// a NaN, so non-finite moments trip it too).
+template <bool SCALED = false>
+__device__ __forceinline__ bool collide(float d[Q], const Params &p) {
+    float sp[Q], dp[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        dr += d[i];
-        if (EX[i]) jx += EX[i] > 0 ? d[i] : -d[i];
-        if (EY[i]) jy += EY[i] > 0 ? d[i] : -d[i];
-        if (EZ[i]) jz += EZ[i] > 0 ? d[i] : -d[i];
+    for (int i = 1; i < Q; i += 2) {
+        sp[i] = d[i] + d[i + 1];
+        dp[i] = d[i] - d[i + 1];
+    }
+    float dr = d[0];
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) dr += sp[i];
+    float jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        if (EX[i]) jx += EX[i] > 0 ? dp[i] : -dp[i];
+        if (EY[i]) jy += EY[i] > 0 ? dp[i] : -dp[i];
+        if (EZ[i]) jz += EZ[i] > 0 ? dp[i] : -dp[i];
+    }
+    if (SCALED) {
+        dr *= p.inv_scale;
+        jx *= p.inv_scale;
+        jy *= p.inv_scale;
+        jz *= p.inv_scale;
     }
     const float rho = p.rho0f + dr;
     const float Fx = rho * p.gx, Fy = rho * p.gy, Fz = rho * p.gz;
-    const float inv = 1.0f / rho;
+    const float inv = __builtin_amdgcn_rcpf(rho);  // hardware reciprocal (1 ulp)
     const float ux = (jx + 0.5f * Fx) * inv, uy = (jy + 0.5f * Fy) * inv, uz = (jz + 0.5f * Fz) * inv;
     const float uu = ux * ux + uy * uy + uz * uz;
     const float uF = ux * Fx + uy * Fy + uz * Fz;
+    const float om = p.omega, omc = 1.f - om;
+    const float sc = SCALED ? p.scale : 1.f;
+    const float g = sc * (om * (dr - 1.5f * rho * uu) - 3.f * p.fcoef * uF);
+    const float r45 = sc * (4.5f * om * rho), r3 = sc * (3.f * om * rho);
+    const float f9 = sc * (9.f * p.fcoef), f3 = sc * (3.f * p.fcoef);
+    d[0] = omc * d[0] + (float)WD[0] * g;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; i += 2) {
         const float w = (float)WD[i];
         const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
         const float eF = EX[i] * Fx + EY[i] * Fy + EZ[i] * Fz;
-        const float deq = w * (dr + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
-        const float Fi = p.fcoef * w * (3.f * (eF - uF) + 9.f * eu * eF);
-        d[i] = d[i] + p.omega * (deq - d[i]) + Fi;
+        const float T = (w * r45) * eu + (w * f9) * eF;
+        const float S = eu * T + w * g;
+        const float A = (w * r3) * eu + (w * f3) * eF;
+        d[i] = omc * d[i] + (S + A);
+        d[i + 1] = omc * d[i + 1] + (S - A);
     }
+    return !(uu <= U_MAX_SQ);
 }
 
-// Plain fluid node (skip mask clear: fluid with no solid neighbour at the
-// start of the step): pull-stream (periodic wrap, resting halfway walls) and
-// collide.  Results are written with non-temporal stores: they are not read
-// again within the step.
+// Plain fluid node at (x, y, z), any layout of the launch (skip mask clear:
+// fluid with no solid neighbour at the start of the step): pull-stream
+// (periodic wrap, resting halfway walls) and collide; 64-bit offsets.
+// Results are written with non-temporal stores: they are not read again
+// within the step.
 template <int S>
-__device__ __forceinline__ void bulk_update(const Params &p, const typename Store<S>::T *__restrict__ A,
+__device__ __forceinline__ bool bulk_update(const Params &p, const typename Store<S>::T *__restrict__ A,
                                             typename Store<S>::T *__restrict__ B, int x, int y, int z, int n) {
     using T = typename Store<S>::T;
     // source coordinates for e = -1, 0, +1 on each axis (wrapped), -1 = wall
@@ -100,247 +140,218 @@ __device__ __forceinline__ void bulk_update(const Params &p, const typename Stor
         const int src = wall ? n : (zs * p.ny + ys) * p.nx + xs;
         d[i] = Store<S>::ld(Ai, src, p.inv_scale);
     }
-    collide(d, p);
+    const bool bad = collide(d, p);
 #pragma unroll
     for (int i = 0; i < Q; ++i) Store<S>::st_nt(B + (long long)i * p.Ns, n, d[i], p.scale);
+    return bad;
 }
 
-// One system: one wave covers 64 consecutive x of one (y, z) row; a block of
-// 8 waves takes consecutive rows in lattice order (the hardware spreads
-// consecutive blocks over the XCDs).
-constexpr int BULK_WAVES = 8;
+// Waves per block of the one-system stream-collide kernels.
+constexpr int BULK_WAVES = 4;
+
+// Whether the short forms apply: every element offset into the population
+// buffer, in bytes, fits 32 bits.
+inline bool bulk_offsets_fit(const Params &p, int storage_bytes) {
+    return (unsigned long long)Q * (unsigned long long)p.Ns * (unsigned long long)storage_bytes < (1ull << 32);
+}
+
+// One system, one node per lane (FP32; 16-bit storage with odd nx): a wave
+// covers 64 consecutive x of one (y, z) row, so the source row of each
+// population, and whether it lies beyond a wall, is wave-uniform (scalar);
+// per lane only x and its two neighbours (wrapped, or the node's own opposite
+// population at a resting wall).  Offsets are 32-bit (bulk_offsets_fit; the
+// launcher takes k_bulk_wide otherwise).  Blocks take consecutive rows in
+// lattice order (the hardware spreads consecutive blocks over the XCDs).
 template <int S>
 __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typename Store<S>::T *__restrict__ A,
                                                           typename Store<S>::T *__restrict__ B,
-                                                          const uint8_t *__restrict__ skip, int nseg) {
+                                                          const uint8_t *__restrict__ skip, int nseg,
+                                                          int *__restrict__ err) {
+    using T = typename Store<S>::T;
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * BULK_WAVES + (threadIdx.x >> 6));
+    const int seg = wave % nseg, row = wave / nseg;
+    if (row >= p.ny * p.nz) return;
+    const int x = seg * 64 + (threadIdx.x & 63);
+    if (x >= p.nx) return;
+    const int y = row % p.ny, z = row / p.ny;
+    const uint32_t n = (uint32_t)(row * p.nx + x);
+    if (skip[n]) return;
+    int sy[3], sz[3];  // source rows (uniform) by e + 1; -1 = beyond a wall
+    sy[1] = y; sz[1] = z;
+    sy[2] = y - 1; sy[0] = y + 1;
+    sz[2] = z - 1; sz[0] = z + 1;
+    if (sy[2] < 0) sy[2] = (p.periodic & 2u) ? p.ny - 1 : -1;
+    if (sy[0] >= p.ny) sy[0] = (p.periodic & 2u) ? 0 : -1;
+    if (sz[2] < 0) sz[2] = (p.periodic & 4u) ? p.nz - 1 : -1;
+    if (sz[0] >= p.nz) sz[0] = (p.periodic & 4u) ? 0 : -1;
+    int xm = x - 1, xp = x + 1;  // sources for e_x = +1 and -1; -1 = wall
+    if (xm < 0) xm = (p.periodic & 1u) ? p.nx - 1 : -1;
+    if (xp >= p.nx) xp = (p.periodic & 1u) ? 0 : -1;
+    const uint32_t Ns = (uint32_t)p.Ns;
+    const char *Ab = (const char *)A;
+    float d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
+        const bool rwall = (ys | zs) < 0;  // uniform: the node's own opposite population
+        const uint32_t base = rwall ? (uint32_t)OPP[i] * Ns + (uint32_t)(row * p.nx)
+                                    : (uint32_t)i * Ns + (uint32_t)((zs * p.ny + ys) * p.nx);
+        uint32_t off;
+        if (EX[i] == 0) {
+            off = base + (uint32_t)x;
+        } else {
+            const int xs = EX[i] > 0 ? xm : xp;
+            off = rwall ? base + (uint32_t)x : (xs < 0 ? (uint32_t)OPP[i] * Ns + n : base + (uint32_t)xs);
+        }
+        d[i] = Store<S>::ld((const T *)(Ab + off * (uint32_t)sizeof(T)), 0, p.inv_scale);
+    }
+    const bool bad = collide(d, p);
+    char *Bb = (char *)B;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        Store<S>::st_nt((T *)(Bb + ((uint32_t)i * Ns + n) * (uint32_t)sizeof(T)), 0, d[i], p.scale);
+    if (bad) atomicOr(err, ERR_FLUID);
+}
+
+// The same launch shape with 64-bit offsets (lattices whose population
+// buffer exceeds 4 GiB).
+template <int S>
+__global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_wide(Params p, const typename Store<S>::T *__restrict__ A,
+                                                               typename Store<S>::T *__restrict__ B,
+                                                               const uint8_t *__restrict__ skip, int nseg,
+                                                               int *__restrict__ err) {
     const int wave = blockIdx.x * BULK_WAVES + (threadIdx.x >> 6);
     const int seg = wave % nseg, row = wave / nseg;
     if (row >= p.ny * p.nz) return;
     const int x = seg * 64 + (threadIdx.x & 63);
     if (x >= p.nx) return;
     const int y = row % p.ny, z = row / p.ny;
-    const int n = row * p.nx + x;
+    const long long n = (long long)row * p.nx + x;
     if (skip[n]) return;
-    bulk_update<S>(p, A, B, x, y, z, n);
+    if (bulk_update<S>(p, A, B, x, y, z, (int)n)) atomicOr(err, ERR_FLUID);
 }
 
-// c ? a : b without a branch.
-__device__ __forceinline__ long long bsel(bool c, long long a, long long b) { return b ^ ((a ^ b) & -(long long)c); }
-
-// 16-bit storage, nx even: a lane takes the node pair (x, x + 1), x even, and
-// moves one aligned 32-bit word per population (twice the bytes of a 16-bit
-// access per instruction).  The pulls along x shift a pair by one node: the
-// missing value comes from the neighbouring lane's word (wave shift by one
-// lane) or, where that lane holds no pair of the same row, from one extra
-// 16-bit load (the next node, its periodic image, or the node's own opposite
-// population at a wall).  Per node the arithmetic is bulk_update's.
-// k_bulk_pair (nx a multiple of 128): a wave covers 128 consecutive x of a
-// row.  k_bulk_pair_flat (other even nx): a wave covers 64 consecutive pairs
-// in lattice order.
-template <int S> struct Pair16;
-// lo: the value in the low 16 bits of a word (callers shift the high half
-// down first); one: a value's 16-bit storage code.
-template <> struct Pair16<1> {
-    __device__ static float lo(uint32_t w, float inv) {
-        return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)) * inv;
-    }
-    __device__ static uint32_t one(float v, float s) {
-        return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(v * s));
-    }
-};
-template <> struct Pair16<2> {
-    __device__ static float lo(uint32_t w, float) { return __uint_as_float(w << 16); }
-    __device__ static uint32_t one(float v, float) { return (uint32_t)Store<2>::rne(v); }
-};
+// 16-bit storage, nx even: a lane takes the node pair (n0, n0 + 1), n0 even,
+// and moves one 32-bit word per population (twice the bytes of a 16-bit
+// access per instruction); a wave covers 64 consecutive pairs in lattice
+// order, rows wrapping inside the wave, so no lane idles whatever nx.
+// Fast path (every lane of the wave in a row whose y and z neighbours are
+// inside the box, and not across a periodic seam): the source of node n0 in
+// array i is n0 + delta_i with a uniform delta_i = i Ns - e_y nx - e_z nx ny -
+// e_x, and the word there holds both pulled values of the pair (unaligned by
+// one node when e_x != 0; the hardware reads it whole).  Only at a row's ends
+// does one value come from elsewhere (x0 - 1 or x0 + 2 outside the row: the
+// periodic image in the same row, or the node's own opposite population at a
+// resting wall), by one 16-bit load per x-shifted population, issued by every
+// lane (at the word's own address where no fix is needed) so that all loads
+// stay unconditional.  Other waves: every source by its coordinates.  The
+// collision runs on the scaled stored values (collide<SCALED>).
+template <int S> __device__ __forceinline__ float raw16(uint32_t b) {  // low 16 bits -> stored value, unscaled
+    if constexpr (S == 1) return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xffffu));
+    else return __uint_as_float(b << 16);
+}
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+template <int S> __device__ __forceinline__ uint32_t pack16(float a, float b) {  // RNE to two 16-bit codes
+    const f32x2 v = {a, b};
+    if constexpr (S == 1) return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+    else return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+typedef uint32_t u32_a2 __attribute__((aligned(2)));
 
 template <int S>
 __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const typename Store<S>::T *__restrict__ A,
                                                                typename Store<S>::T *__restrict__ B,
-                                                               const uint8_t *__restrict__ skip, int nseg) {
-    using T = typename Store<S>::T;
-    using W = Pair16<S>;
-    // the wave's row and segment are uniform: scalar registers, scalar branches
+                                                               const uint8_t *__restrict__ skip,
+                                                               int *__restrict__ err) {
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * BULK_WAVES + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int seg = wave % nseg, row = wave / nseg;
-    if (row >= p.ny * p.nz) return;
-    const int x0 = seg * 128 + 2 * lane;
-    const bool act = x0 < p.nx;  // the pair exists (nx even: then so does x0 + 1)
-    const int xc = act ? x0 : p.nx - 2;  // lanes past the row end read the row's last pair, unused
-    const int y = row % p.ny, z = row / p.ny;
-    const int n0 = row * p.nx + xc;
-    const unsigned sk = act ? (unsigned)*(const uint16_t *)(skip + n0) : 0x0101u;  // 2-byte aligned
-    const bool live0 = !(sk & 0xffu), live1 = !(sk >> 8);
-    if (!__any(live0 || live1)) return;  // wave-uniform: every lane below takes part in the shifts
-    int sy[3], sz[3];
-    sy[1] = y; sz[1] = z;
-    sy[2] = y - 1; sy[0] = y + 1;
-    sz[2] = z - 1; sz[0] = z + 1;
-    if (sy[2] < 0) sy[2] = (p.periodic & 2u) ? p.ny - 1 : -1;
-    if (sy[0] >= p.ny) sy[0] = (p.periodic & 2u) ? 0 : -1;
-    if (sz[2] < 0) sz[2] = (p.periodic & 4u) ? p.nz - 1 : -1;
-    if (sz[0] >= p.nz) sz[0] = (p.periodic & 4u) ? 0 : -1;
-    const bool perx = p.periodic & 1u;
-    const float inv = p.inv_scale;
-    const long long Ns = p.Ns;
-    const int r0 = row * p.nx;  // this row's first node
-    // The only lanes that pull along x from outside their wave's words: lane
-    // 0 for e_x = +1 (the node before the segment), and for e_x = -1 lane 63
-    // when the row continues past the segment, else the lane of the row's
-    // last pair; either way one node per population, at a wave-uniform
-    // address (periodic wrap, or the node's own opposite population at a wall).
-    const bool more = (seg + 1) * 128 < p.nx;
-    const bool edge_lo = lane == 0;
-    const bool edge_hi = more ? lane == 63 : xc + 2 >= p.nx;
-    // pass 1: every load at once, unconditionally (indices chosen by bitwise
-    // selects, which stay selects: a branch here would hold each load back)
-    uint32_t w[Q], eb[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
-        const bool rwall = (ys | zs) < 0;  // the source row lies beyond a wall: both nodes bounce
-        const long long rb = (long long)(rwall ? 0 : (zs * p.ny + ys) * p.nx);  // source row
-        const long long io = OPP[i] * Ns, ii = i * Ns + rb;
-        w[i] = *(const uint32_t *)(A + bsel(rwall, io + n0, ii + xc));
-        if (EX[i] > 0) {
-            const long long e = bsel(seg > 0, ii + seg * 128 - 1, bsel(perx, ii + p.nx - 1, io + r0));
-            eb[i] = *(const uint16_t *)(A + bsel(rwall, io + r0, e));
-        } else if (EX[i] < 0) {
-            const long long e = bsel(more, ii + (seg + 1) * 128, bsel(perx, ii, io + r0 + p.nx - 1));
-            eb[i] = *(const uint16_t *)(A + bsel(rwall, io + r0, e));
-        }
-    }
-    // pass 2: the pulls along x from the neighbouring lanes' words
-    float d0[Q], d1[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
-        const bool rwall = (ys | zs) < 0;
-        uint32_t b0 = w[i] & 0xffffu, b1 = w[i] >> 16;
-        if (EX[i] > 0) {
-            const uint32_t wl = (uint32_t)__shfl_up((int)w[i], 1);
-            const uint32_t s0 = edge_lo ? eb[i] : wl >> 16;
-            b1 = rwall ? b1 : b0;
-            b0 = rwall ? b0 : s0;
-        } else if (EX[i] < 0) {
-            const uint32_t wr = (uint32_t)__shfl_down((int)w[i], 1);
-            const uint32_t s1 = edge_hi ? eb[i] : wr & 0xffffu;
-            b0 = rwall ? b0 : b1;
-            b1 = rwall ? b1 : s1;
-        }
-        d0[i] = W::lo(b0, inv);
-        d1[i] = W::lo(b1, inv);
-    }
-    if (!(live0 || live1)) return;
-    collide(d0, p);
-    collide(d1, p);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        T *Bi = B + (long long)i * p.Ns;
-        const uint32_t v0 = W::one(d0[i], p.scale), v1 = W::one(d1[i], p.scale);
-        if (live0 && live1) {
-            __builtin_nontemporal_store(v0 | (v1 << 16), (uint32_t *)(Bi + n0));
-        } else if (live0) {
-            __builtin_nontemporal_store((uint16_t)v0, (uint16_t *)(Bi + n0));
-        } else {
-            __builtin_nontemporal_store((uint16_t)v1, (uint16_t *)(Bi + n0 + 1));
-        }
-    }
-}
-
-// The same pair update with the pairs in lattice order: a wave takes 64
-// consecutive pairs (128 nodes), rows wrap inside the wave, so no lane idles
-// whatever the (even) nx.  A lane pulls from the neighbouring lane's word
-// when that pair lies in its own row; at a row's ends and at the wave's ends
-// it loads the one missing node itself (a per-lane index, loaded by every
-// lane so that all loads stay unconditional).
-template <int S>
-__global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair_flat(Params p,
-                                                                    const typename Store<S>::T *__restrict__ A,
-                                                                    typename Store<S>::T *__restrict__ B,
-                                                                    const uint8_t *__restrict__ skip) {
-    using T = typename Store<S>::T;
-    using W = Pair16<S>;
-    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * BULK_WAVES + (threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int N = (int)p.N;  // even (nx even)
-    if (wave * 128 >= N) return;  // wave-uniform
-    const int nraw = wave * 128 + 2 * lane;
+    const uint32_t N = (uint32_t)p.N;  // even (nx even)
+    if ((uint32_t)wave * 128u >= N) return;  // wave-uniform
+    const uint32_t nraw = (uint32_t)wave * 128u + 2u * lane;
     const bool act = nraw < N;
-    const int n0 = act ? nraw : N - 2;  // lanes past the end read the last pair, unused
+    const uint32_t n0 = act ? nraw : N - 2;  // lanes past the end read the last pair, unused
     const unsigned sk = act ? (unsigned)*(const uint16_t *)(skip + n0) : 0x0101u;  // 2-byte aligned
     const bool live0 = !(sk & 0xffu), live1 = !(sk >> 8);
-    if (!__any(live0 || live1)) return;  // wave-uniform: every lane below takes part in the shifts
-    const unsigned row = (unsigned)n0 / (unsigned)p.nx;
-    const int x0 = n0 - (int)row * p.nx;  // even
-    const int z = (int)(row / (unsigned)p.ny), y = (int)row - z * p.ny;
-    int sy[3], sz[3];
-    sy[1] = y; sz[1] = z;
-    sy[2] = y - 1; sy[0] = y + 1;
-    sz[2] = z - 1; sz[0] = z + 1;
-    if (sy[2] < 0) sy[2] = (p.periodic & 2u) ? p.ny - 1 : -1;
-    if (sy[0] >= p.ny) sy[0] = (p.periodic & 2u) ? 0 : -1;
-    if (sz[2] < 0) sz[2] = (p.periodic & 4u) ? p.nz - 1 : -1;
-    if (sz[0] >= p.nz) sz[0] = (p.periodic & 4u) ? 0 : -1;
-    const bool perx = p.periodic & 1u;
-    const float inv = p.inv_scale;
-    const long long Ns = p.Ns;
-    // x0 - 1 is outside the lane-below's word at a row start or in lane 0;
-    // x0 + 2 outside the lane-above's word at a row end or in lane 63
-    const bool edge_lo = lane == 0 || x0 == 0;
-    const bool edge_hi = lane == 63 || x0 + 2 >= p.nx;
-    uint32_t w[Q], eb[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
-        const bool rwall = (ys | zs) < 0;  // the source row lies beyond a wall: both nodes bounce
-        const long long rb = (long long)(rwall ? 0 : (zs * p.ny + ys) * p.nx);
-        const long long io = OPP[i] * Ns, ii = i * Ns + rb;
-        const long long wi = bsel(rwall, io + n0, ii + x0);
-        w[i] = *(const uint32_t *)(A + wi);
-        if (EX[i] > 0) {
-            const long long e = bsel(x0 > 0, ii + x0 - 1, bsel(perx, ii + p.nx - 1, io + n0));
-            eb[i] = *(const uint16_t *)(A + bsel(edge_lo && !rwall, e, wi));
-        } else if (EX[i] < 0) {
-            const long long e = bsel(x0 + 2 < p.nx, ii + x0 + 2, bsel(perx, ii, io + n0 + 1));
-            eb[i] = *(const uint16_t *)(A + bsel(edge_hi && !rwall, e, wi));
-        }
-    }
+    if (!__any(live0 || live1)) return;
+    const uint32_t row = n0 / (uint32_t)p.nx;
+    const int x0 = (int)(n0 - row * (uint32_t)p.nx);  // even
+    const int z = (int)(row / (uint32_t)p.ny), y = (int)row - z * p.ny;
+    const uint32_t Ns = (uint32_t)p.Ns;
+    const int nx = p.nx, nxy = p.nx * p.ny;
+    const bool interior = y >= 1 && y <= p.ny - 2 && z >= 1 && z <= p.nz - 2;
+    const uint32_t n0b = n0 * 2u;  // byte offset of the pair in every array
+    const char *Ab = (const char *)A;
     float d0[Q], d1[Q];
+    if (__all(interior)) {
+        const bool perx = p.periodic & 1u;
+        const bool lo_edge = x0 == 0, hi_edge = x0 + 2 == nx;
+        uint32_t w[Q], fx[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
-        const bool rwall = (ys | zs) < 0;
-        uint32_t b0 = w[i] & 0xffffu, b1 = w[i] >> 16;
-        if (EX[i] > 0) {
-            const uint32_t wl = (uint32_t)__shfl_up((int)w[i], 1);
-            const uint32_t s0 = edge_lo ? eb[i] : wl >> 16;
-            b1 = rwall ? b1 : b0;
-            b0 = rwall ? b0 : s0;
-        } else if (EX[i] < 0) {
-            const uint32_t wr = (uint32_t)__shfl_down((int)w[i], 1);
-            const uint32_t s1 = edge_hi ? eb[i] : wr & 0xffffu;
-            b0 = rwall ? b0 : b1;
-            b1 = rwall ? b1 : s1;
+        for (int i = 0; i < Q; ++i) {
+            // uniform byte offset of node n0's source in array i
+            const long long db = 2ll * ((long long)i * Ns - EY[i] * nx - EZ[i] * (long long)nxy - EX[i]);
+            w[i] = *(const u32_a2 *)(Ab + db + n0b);
+            if (EX[i] > 0) {  // node 0 pulls x0 - 1: outside the row at its start
+                const long long fb = perx ? db + 2ll * nx : 2ll * OPP[i] * Ns;
+                fx[i] = *(const uint16_t *)(Ab + (lo_edge ? fb : db) + n0b);
+            } else if (EX[i] < 0) {  // node 1 pulls x0 + 2: outside the row at its end
+                const long long fb = perx ? db + 2 - 2ll * nx : 2ll * (OPP[i] * (long long)Ns + 1);
+                fx[i] = *(const uint16_t *)(Ab + (hi_edge ? fb : db + 2) + n0b);
+            }
         }
-        d0[i] = W::lo(b0, inv);
-        d1[i] = W::lo(b1, inv);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            uint32_t b0 = w[i], b1 = w[i] >> 16;
+            if (EX[i] > 0) b0 = lo_edge ? fx[i] : b0;
+            else if (EX[i] < 0) b1 = hi_edge ? fx[i] : b1;
+            d0[i] = raw16<S>(b0);
+            d1[i] = raw16<S>(b1);
+        }
+    } else {
+        int sx[3][2], sy[3], sz[3];
+        sy[1] = y; sz[1] = z;
+        sy[2] = y - 1; sy[0] = y + 1;
+        sz[2] = z - 1; sz[0] = z + 1;
+        if (sy[2] < 0) sy[2] = (p.periodic & 2u) ? p.ny - 1 : -1;
+        if (sy[0] >= p.ny) sy[0] = (p.periodic & 2u) ? 0 : -1;
+        if (sz[2] < 0) sz[2] = (p.periodic & 4u) ? p.nz - 1 : -1;
+        if (sz[0] >= p.nz) sz[0] = (p.periodic & 4u) ? 0 : -1;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int x = x0 + k;
+            sx[1][k] = x;
+            sx[2][k] = x - 1 < 0 ? ((p.periodic & 1u) ? nx - 1 : -1) : x - 1;
+            sx[0][k] = x + 1 >= nx ? ((p.periodic & 1u) ? 0 : -1) : x + 1;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int xs = sx[EX[i] + 1][k];
+                const bool wall = (xs | ys | zs) < 0;
+                const uint32_t off = wall ? (uint32_t)OPP[i] * Ns + n0 + k
+                                          : (uint32_t)i * Ns + (uint32_t)((zs * p.ny + ys) * nx + xs);
+                const float v = raw16<S>((uint32_t)*(const uint16_t *)(Ab + off * 2u));
+                if (k == 0) d0[i] = v;
+                else d1[i] = v;
+            }
+        }
     }
     if (!(live0 || live1)) return;
-    collide(d0, p);
-    collide(d1, p);
+    const bool bad0 = collide<S == 1>(d0, p), bad1 = collide<S == 1>(d1, p);
+    char *Bb = (char *)B;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        T *Bi = B + (long long)i * p.Ns;
-        const uint32_t v0 = W::one(d0[i], p.scale), v1 = W::one(d1[i], p.scale);
-        if (live0 && live1) {
-            __builtin_nontemporal_store(v0 | (v1 << 16), (uint32_t *)(Bi + n0));
-        } else if (live0) {
-            __builtin_nontemporal_store((uint16_t)v0, (uint16_t *)(Bi + n0));
-        } else {
-            __builtin_nontemporal_store((uint16_t)v1, (uint16_t *)(Bi + n0 + 1));
-        }
+        const uint32_t v = pack16<S>(d0[i], d1[i]);
+        char *q = Bb + 2ull * ((uint32_t)i * Ns) + n0b;
+        if (live0 && live1) __builtin_nontemporal_store(v, (uint32_t *)q);
+        else if (live0) __builtin_nontemporal_store((uint16_t)(v & 0xffffu), (uint16_t *)q);
+        else __builtin_nontemporal_store((uint16_t)(v >> 16), (uint16_t *)(q + 2));
     }
+    if ((bad0 && live0) || (bad1 && live1)) atomicOr(err, ERR_FLUID);
 }
 
 // An ensemble of systems in one launch: the block table names each block's
@@ -380,7 +391,7 @@ __global__ __launch_bounds__(64 * BW) void k_bulk_batch(const BulkCase *__restri
     p.rho0f = c.rho0f; p.omega = c.omega; p.fcoef = c.fcoef;
     p.gx = c.gx; p.gy = c.gy; p.gz = c.gz;
     p.scale = c.scale; p.inv_scale = c.inv_scale;
-    bulk_update<S>(p, (const T *)c.A[parity], (T *)c.B[parity], x, y, z, n);
+    if (bulk_update<S>(p, (const T *)c.A[parity], (T *)c.B[parity], x, y, z, n)) atomicOr(c.err, ERR_FLUID);
 }
 
 }  // namespace mdl

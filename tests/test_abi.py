@@ -1,6 +1,7 @@
 """The C ABI without a GPU: the library loads, exports every function that
-include/midelbm.h declares, and lbm_arena_bytes (host-only) validates its
-inputs with the documented status codes."""
+include/*.h declares, and the host-only calls (lbm_arena_bytes, the
+Metaball-Imaging workspace sizes and argument checks) validate their inputs
+with the documented status codes."""
 import os
 import re
 
@@ -13,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    src = open(os.path.join(ROOT, "include", "midelbm.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:lbm_status|void|size_t|int32_t|const char\s*\*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
@@ -135,3 +137,17 @@ def test_mlp_grad_rejects_oversized_batches(mdl):
     dummy = C.c_void_p(256)
     assert mdl.lib().mlp_grad(dummy, dummy, dummy, 5000, 0, None, None, None) == -1
     assert mdl.lib().mlp_grad(dummy, dummy, dummy, 10, 3, None, None, None) == -1
+
+
+def test_mifit_sizes_and_argument_checks(mdl):
+    L = mdl.lib()
+    assert L.mi_fitness_work_bytes(2048, 10) == 0          # one chunk: no workspace
+    assert L.mi_fitness_work_bytes(2049, 10) == 10 * 2 * 8  # two chunks per individual
+    assert L.mi_ga_work_bytes(100, 1, 4) == 0                # N_I >= 2
+    assert L.mi_ga_work_bytes(100, 8, 4) > 2 * 3 * 8 * 4 * 4 * 8
+    import ctypes as C
+    nul = C.c_void_p(0)
+    # NULL pointers and sizes out of range are refused before any launch
+    assert L.mi_fitness(nul, 10, nul, 4, 4, nul, nul, 0, nul) == -1
+    assert L.mi_ga(nul, 10, 4, 4, 1, 0.6, 0.5, 0.1, 0.1, nul, nul, nul, nul, nul, nul, 0, nul) == -1
+    assert L.mi_gs(nul, nul, nul, nul, 1, 4, 1, 1e-3, nul, nul, nul) == -1

@@ -43,6 +43,24 @@ def compare_fields(sim, ref, du_tol=1e-5, drho_tol=1e-7, label=""):
     return du, drho
 
 
+# Cases with fast bodies (contact tests: U ~ 0.05-0.08, ten to a hundred
+# times the settling cases) carry density deviations ~ 3 U^2 ~ 1e-2, whose
+# FP32 storage rounding (6e-8 relative per step) shows in rho at the 1e-7
+# level after tens of steps: their density bound is 1e-6 (velocity 1e-5).
+DRHO_FAST = 1e-6
+
+
+def compare_torque(Tg, po, R, label=""):
+    """Momentum-exchange torque about the centroid against the oracle's, to
+    1e-4 of the larger of |T| and a lever arm (the body radius) times 1e-2
+    |F| (a symmetric body's torque is zero up to rounding)."""
+    To, Fo = po["T"], po["F"]
+    scale = max(np.abs(To).max(), 1e-2 * R * np.abs(Fo).max())
+    err = np.abs(np.asarray(Tg) - To).max() / scale
+    print(f"{label}: |T|={np.abs(To).max():.3e} max|dT|/scale={err:.2e}", flush=True)
+    assert err <= 1e-4, f"{label}: torque {Tg} vs {To}"
+
+
 def compare_links(sim, ref):
     ng, dg, og, qg = sim.links()
     no, do, oo, qo = ref.links()
@@ -97,8 +115,10 @@ def test_config1_200_steps(mdl, bc):
         done = upto
         compare_fields(sim, ref, label=f"cfg1 bc={bc} step {upto}")
         Fg, Tg = sim.particle_forces()
-        Fo = ref.particle(0)["F"]
+        po = ref.particle(0)
+        Fo = po["F"]
         assert np.abs(Fg[0] - Fo).max() <= 1e-4 * np.abs(Fo).max()
+        compare_torque(Tg[0], po, 8.0, label=f"cfg1 bc={bc} step {upto} torque")
 
 
 @pytest.mark.parametrize("bc", [workloads.BC_SBB, workloads.BC_IBB])
@@ -123,6 +143,8 @@ def test_settling_body_with_refill(mdl, bc):
         assert np.abs(pg["x"] - po["x"]).max() < 1e-6
         assert np.abs(pg["v"] - po["v"]).max() < 1e-6 * max(1.0, np.abs(po["v"]).max())
         assert np.abs(pg["F"] - po["F"]).max() <= 1e-4 * np.abs(po["F"]).max()
+        compare_torque(pg["T"], po, 5.0, label=f"settle bc={bc} step {10 * (k + 1)} torque")
+        assert np.abs(pg["omega"] - po["omega"]).max() <= 1e-6 * max(np.abs(po["omega"]).max(), 1e-3)
     assert refilled > 0
 
 
@@ -247,7 +269,12 @@ def test_poiseuille_on_gpu(mdl):
     ux = u[:, 0].reshape(cfg.nz, cfg.ny, cfg.nx)
     err = np.abs(ux - ua[None, :, None]).max() / ua.max()
     print(f"poiseuille FP32: rel err {err:.2e}", flush=True)
-    assert err < 1e-4
+    # FP32 steady state: each step rounds the stored deviations to 2^-24
+    # relative, and the iteration contracts the slowest mode by only
+    # pi^2 nu / H^2 ~ 1/720 per step, so its fixed point sits ~720 x 6e-8
+    # ~ 4e-5 of the deviations away from the exact one; the profile's
+    # relative error is a few times that
+    assert err < 2e-4
 
 
 def test_fluid_only_then_flag_and_refill(mdl):
@@ -365,7 +392,7 @@ def test_contact_pair_collision(mdl):
     for k in range(6):
         sim.step(10)
         ref.step(10)
-        compare_fields(sim, ref, du_tol=1e-4, drho_tol=1e-6, label=f"contact pair step {10 * (k + 1)}")
+        compare_fields(sim, ref, drho_tol=DRHO_FAST, label=f"contact pair step {10 * (k + 1)}")
         _compare_particles(sim, ref, cfg, 1e-5, 1e-5)
     nc, nf = sim.contact_stats()
     assert nc == ref.n_contacts and nc > 0 and nf == 0
@@ -378,7 +405,7 @@ def test_body_lands_on_floor(mdl):
     for k in range(5):
         sim.step(40)
         ref.step(40)
-        compare_fields(sim, ref, du_tol=1e-4, drho_tol=1e-6, label=f"floor step {40 * (k + 1)}")
+        compare_fields(sim, ref, drho_tol=DRHO_FAST, label=f"floor step {40 * (k + 1)}")
         _compare_particles(sim, ref, cfg, 1e-5, 1e-5)
     nc, nf = sim.contact_stats()
     assert nc > 0 and nf == 0
@@ -396,9 +423,11 @@ def test_periodic_suspension_small(mdl):
     for k in range(3):
         sim.step(20)
         ref.step(20)
-        compare_fields(sim, ref, label=f"suspension step {20 * (k + 1)}")
+        compare_fields(sim, ref, drho_tol=DRHO_FAST, label=f"suspension step {20 * (k + 1)}")
         dq = compare_links(sim, ref)
-        assert np.median(dq) < 1e-7 and dq.max() < 1e-4
+        # q follows the poses, which differ by up to the 1e-6 position bound
+        # for these fast bodies (velocities up to 0.05)
+        assert np.median(dq) < 1e-6 and dq.max() < 1e-4
         _compare_particles(sim, ref, cfg, 1e-6, 1e-7)
 
 
@@ -418,6 +447,10 @@ def test_periodic_suspension_many_bodies(mdl):
         dq = compare_links(sim, ref)
         assert np.median(dq) < 1e-7 and dq.max() < 1e-4
         _compare_particles(sim, ref, cfg, 1e-6, 1e-7)
+        gs = sim.particles()
+        for j in range(len(cfg.particles)):
+            po = ref.particle(j)
+            compare_torque(gs[j]["T"], po, 5.0, label=f"40-body step {15 * (k + 1)} body {j} torque")
     nc, nf = sim.contact_stats()
     assert nc == ref.n_contacts and nf == 0
     print(f"40-body suspension: {nc} contacts", flush=True)
@@ -466,3 +499,45 @@ def test_storage_error_time_resolved(mdl, drafting_oracle, storage, tol_u, tol_x
         print(f"storage {storage} step {s}: U={U:.3e} max|du|/U={du:.2e} |dx|={dx:.2e}", flush=True)
         assert du < tol_u and dx < tol_x
     sim.close()
+
+
+def test_contact_pair_paper_subcycling(mdl):
+    """The paper's DEM sub-cycling, 100 rigid-body sub-steps per lattice
+    step (DEM step 2e-6 s against the LBM step 2e-4 s): the head-on pair with
+    contact against the oracle through the collision (loads held over the
+    sub-steps, contacts recomputed at each)."""
+    cfg = workloads.contact_pair()
+    cfg.n_sub = 100
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    for k in range(4):
+        sim.step(10)
+        ref.step(10)
+        compare_fields(sim, ref, drho_tol=DRHO_FAST, label=f"contact pair n_sub=100 step {10 * (k + 1)}")
+        _compare_particles(sim, ref, cfg, 1e-5, 1e-5)
+    nc, nf = sim.contact_stats()
+    assert nc == ref.n_contacts and nc > 100 and nf == 0
+    print(f"n_sub = 100: {nc} contacts over {40 * 100} sub-steps", flush=True)
+
+
+def test_sphero_metaball_link_level(mdl):
+    """Link fractions on the sphero-metaball surface (sec. 2.3.2, q from
+    f = c_0 with c_0 depending on R_s; the inner body at c_0 = s^2, R_s = 1):
+    the same link set, q against the oracle, then 30 coupled steps of a
+    settling body with covering and refilling."""
+    cfg = workloads.small_settling(n=32, nz=56, R=5.0, g=5e-4)
+    cfg.contact_rs, cfg.link_c0 = 1.0, 1
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    dq = compare_links(sim, ref)
+    print(f"c_0 links: |dq| p99 {np.quantile(dq, 0.99):.2e} max {dq.max():.2e}", flush=True)
+    assert np.quantile(dq, 0.99) < 1e-12 and dq.max() < 2e-7
+    q1 = ref.links()[3]
+    assert (q1 >= 1.0).sum() > 0 and (q1 < 1e-9).sum() > 0  # both fallbacks occur
+    for k in range(3):
+        sim.step(10)
+        ref.step(10)
+        compare_fields(sim, ref, label=f"c_0 settle step {10 * (k + 1)}")
+        dq = compare_links(sim, ref)
+        assert np.median(dq) < 1e-7 and dq.max() < 1e-4
+        assert np.abs(sim.particles()[0]["x"] - ref.particle(0)["x"]).max() < 1e-6
