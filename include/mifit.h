@@ -92,6 +92,18 @@ lbm_status mi_ga(const double *hull, int64_t m, int32_t N_I, int32_t n, int32_t 
 lbm_status mi_gs(const double *hulls, const int64_t *hull_off, const double *planes, const int64_t *plane_off,
                  int32_t B, int32_t n, int32_t E, double eta, double *M, double *loss, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mi_fitness
+ * with its per-chunk sums in a static device array of the library (1 MiB,
+ * one copy per GPU, held until the process ends) instead of a workspace;
+ * it allocates nothing.  P * ceil(m / 2048) must not exceed 131072, else
+ * LBM_E_INVALID (nothing launched).  Every call on one GPU uses the same
+ * array: calls that overlap on one GPU (several streams or host threads)
+ * race, and the array keeps the last call's sums (every slot read is written
+ * first by the same call, so nothing needs clearing).  Asynchronous. */
+lbm_status mi_fitness_noalloc(const double *hull, int64_t m, const double *pop, int32_t P, int32_t n, double *F,
+                              void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,7 +73,7 @@ EXPORTS = ["lbm_arena_bytes", "lbm_init", "metaball_flag", "lbm_step", "particle
            "mlp_weights_bytes", "mlp_param_count", "mlp_init", "mlp_get_params", "mlp_collect",
            "mlp_collect_contact", "mlp_forward",
            "mlp_grad", "mlp_train", "lbm_set_warmstart", "lbm_nr_histogram",
-           "mi_fitness_work_bytes", "mi_fitness", "mi_ga_work_bytes", "mi_ga", "mi_gs",
+           "mi_fitness_work_bytes", "mi_fitness", "mi_fitness_noalloc", "mi_ga_work_bytes", "mi_ga", "mi_gs",
            "mb_shape_work_bytes", "mb_shape_descriptors"]
 
 _lib = None
@@ -145,6 +145,7 @@ def lib():
         L.mi_fitness_work_bytes.argtypes = [C.c_int64, C.c_int32]
         L.mi_fitness_work_bytes.restype = C.c_size_t
         L.mi_fitness.argtypes = [vp, C.c_int64, vp, C.c_int32, C.c_int32, vp, vp, C.c_size_t, vp]
+        L.mi_fitness_noalloc.argtypes = [vp, C.c_int64, vp, C.c_int32, C.c_int32, vp, vp]
         L.mi_ga_work_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32]
         L.mi_ga_work_bytes.restype = C.c_size_t
         L.mi_ga.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,

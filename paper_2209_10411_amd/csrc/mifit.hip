@@ -9,6 +9,7 @@
 
 #include <cfloat>
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/mifit.h"
 
@@ -370,6 +371,39 @@ lbm_status mi_gs(const double *hulls, const int64_t *hull_off, const double *pla
     if (!ok) return LBM_E_INVALID;
     k_gs<<<B, BLK, 0, s>>>(hulls, hull_off, planes, plane_off, n, E, eta, M, loss);
     return launched();
+}
+
+// ---------------------------------------------- fitness without allocation
+// For callers that cannot allocate (graph capture, tight loops): the chunk
+// sums live in this file-scope array, one copy per GPU, held until the
+// process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t MI_SCRATCH_DOUBLES = size_t(1) << 17;  // 1 MiB: individuals x chunks <= 131072
+__device__ __align__(256) double scratch[MI_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES];
+}  // namespace
+
+lbm_status mi_fitness_noalloc(const double *hull, int64_t m, const double *pop, int32_t P, int32_t n, double *F,
+                              void *hip_stream) {
+    if (!hull || !pop || !F || m < 1 || P < 1 || n < 1 || n > MI_MAXCP) return LBM_E_INVALID;
+    if ((long long)P * chunks(m) > (long long)MI_SCRATCH_DOUBLES) return LBM_E_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return LBM_E_HIP;
+    double *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch[dev]) {
+            void *a = nullptr;
+            if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) return LBM_E_HIP;
+            g_scratch[dev] = (double *)a;
+        }
+        ptr = g_scratch[dev];
+    }
+    return fitness_launch(hull, m, pop, P, n, F, ptr, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"
