@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # the stream-collide kernel's source: its code and the data layout it reads
 KERNEL_SRC = [os.path.join(ROOT, "paper_2209_10411_amd", "csrc", f) for f in ("stream_collide.h", "device.h")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_bulk_settling_128x128x384_pmc.txt")
+PMC_PAIR_SUMMARY = os.path.join(ROOT, "profiles", "k_bulk_pair_160x160x640_pmc.txt")
 
 
 def bytes_per_node(storage: int) -> int:
@@ -162,12 +163,16 @@ def run_pair(steps, warmup, reps=3):
         dts, k_ms, k_n, k_nodes, _, _ = run_gpu(cfg, steps, warmup, reps)
         dt = median(dts)
         k_s = k_ms / 1e3 / max(k_n, 1)
-        ach = (k_nodes * bytes_per_node(st) + N) / k_s / 1e9
+        alg = k_nodes * bytes_per_node(st) + N
+        ach = alg / k_s / 1e9
+        traffic = traffic_from_profile(PMC_PAIR_SUMMARY, f"{name}_hbm_bytes_per_launch")
         out[name] = {"mlups": round(N * steps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / steps, 5),
                      "kernel": "k_bulk<f32>" if st == workloads.STORE_F32 else
                      f"k_bulk_pair<{name}>",
                      "kernel_avg_ms": round(k_ms / max(k_n, 1), 5), "kernel_achieved_GBs": round(ach, 1),
-                     "kernel_frac": round(ach / HBM_PEAK_GBS, 4)}
+                     "kernel_frac": round(ach / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes_per_launch": int(alg),
+                     "traffic": traffic, "traffic_over_algorithmic": round(traffic / alg, 4) if traffic else None}
     return out
 
 
@@ -284,21 +289,27 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """FETCH/WRITE bytes per launch of the stream-collide kernel from the
-    committed rocprofv3 --pmc summary, if it was taken on this kernel source."""
-    if not os.path.exists(PMC_SUMMARY):
+def profile_values(path):
+    """The key = value lines of a committed rocprofv3 --pmc summary, or None
+    when it is missing or was taken on another kernel source."""
+    if not os.path.exists(path):
         return None
-    sha = kernel_source_sha()
     vals = {}
-    for line in open(PMC_SUMMARY):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.strip().split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != sha:
+    if vals.get("kernel_source_sha256_16") != kernel_source_sha():
         return None
+    return vals
+
+
+def traffic_from_profile(path=None, key="hbm_bytes_per_launch"):
+    """FETCH/WRITE bytes per launch of a stream-collide kernel from the
+    committed rocprofv3 --pmc summary, if it was taken on this kernel source."""
+    vals = profile_values(path or PMC_SUMMARY)
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key]) if vals else None
     except (KeyError, ValueError):
         return None
 
@@ -380,16 +391,19 @@ def run_mifit(ga_generations=100, gs_steps=200, gs_batch=256):
                    "loss": [float(v) for v in Lg[0]]}}
 
 
-def run_dkt(steps=6000, every=50):
+def run_dkt(steps=8000, every=25):
     """Drafting-kissing-tumbling of pairs of equal bodies with stepped
     elongation (sec. 4): two-point metaballs a = 0..4 lu apart, scaled to the
     volume of the sphere of radius 5 (D_e = 10 lu) with the volumes measured
     by the shape-descriptor kernel, in a 160 x 160 x 240 walled box (the
-    paper's container scaled to D_e), density ratio 2800/976, tau 0.6,
-    gravity 5e-5, contact on.  Per shape: sphericity, d_n/d_s, CSF from the
-    GPU kernel, and from the coupled run the closest approach of the centroids
-    (kissing) and the first step at which the trailing body is lower than the
-    leading one (tumbling past), with times in units of t_r = sqrt(H/g)."""
+    paper's container scaled to D_e), density ratio 2800/976, tau 0.55,
+    gravity 1e-4 (settling Reynolds number near 20), contact on.  Per shape:
+    sphericity, d_n/d_s, CSF from the GPU kernel, and from the coupled run
+    (sampled every `every` steps) the closest approach of the centroids
+    (kissing), the first step at which the trailing body is lower than the
+    leading one (tumbling past), each body's peak settling speed and peak
+    |omega| with their times, in the paper's units: time t_r = sqrt(H/g),
+    velocity sqrt(H g), angular velocity 2 pi / t_r, distance D_e."""
     import numpy as np
 
     import paper_2209_10411_amd as mdl
@@ -405,8 +419,12 @@ def run_dkt(steps=6000, every=50):
         cp, k = cp * sc, k * sc * sc
         d = mdl.shape_descriptors(cp, k, 0.25)
         cfg = workloads.dkt_pair(cp, k)
+        g = float(-cfg.g_particle[2])
+        H = float(cfg.nz)
+        tr, ur, wr = np.sqrt(H / g), np.sqrt(H * g), 2 * np.pi / np.sqrt(H / g)
         sim = mdl.Simulation(cfg, device="cuda:0")
         dmin, t_kiss, t_pass, done = 1e30, None, None, 0
+        vmax, tv, wmax, tw = [0.0, 0.0], [0, 0], [0.0, 0.0], [0, 0]
         while done < steps:
             sim.step(every)
             done += every
@@ -416,16 +434,30 @@ def run_dkt(steps=6000, every=50):
                 dmin, t_kiss = dist, done
             if t_pass is None and p[1]["x"][2] < p[0]["x"][2]:
                 t_pass = done
+            for b in range(2):
+                v, w = -float(p[b]["v"][2]), float(np.linalg.norm(p[b]["omega"]))
+                if v > vmax[b]:
+                    vmax[b], tv[b] = v, done
+                if w > wmax[b]:
+                    wmax[b], tw[b] = w, done
+            if min(p[0]["x"][2], p[1]["x"][2]) < 1.5 * d0["d_n"]:  # near the floor
+                break
         nc, _ = sim.contact_stats()
         sim.close()
-        tr = float(np.sqrt(cfg.nz / 5e-5))
-        out.append({"a": float(cp[1, 0]), "Phi": round(d["Phi"], 4), "dn_over_ds": round(d["d_n"] / d["d_s"], 4),
-                    "CSF": round(d["CSF"], 4), "d_n": round(d["d_n"], 3), "closest_centroid_distance_over_De":
-                    round(dmin / d0["d_n"], 3), "step_closest": t_kiss, "t_closest_over_tr": round(t_kiss / tr, 4),
-                    "step_trailing_passes": t_pass, "contacts": nc})
+        out.append({"a": round(float(cp[1, 0]), 4), "Phi": round(d["Phi"], 4),
+                    "dn_over_ds": round(d["d_n"] / d["d_s"], 4), "CSF": round(d["CSF"], 4),
+                    "d_n": round(d["d_n"], 3), "steps_run": done,
+                    "closest_centroid_distance_over_De": round(dmin / d0["d_n"], 3),
+                    "t_closest_over_tr": round(t_kiss / tr, 4),
+                    "t_trailing_passes_over_tr": round(t_pass / tr, 4) if t_pass else None,
+                    "peak_settling_velocity_over_sqrtHg": [round(v / ur, 4) for v in vmax],
+                    "t_peak_velocity_over_tr": [round(t / tr, 4) for t in tv],
+                    "peak_angular_velocity_over_2pi_tr": [round(w / wr, 4) for w in wmax],
+                    "t_peak_angular_velocity_over_tr": [round(t / tr, 4) for t in tw],
+                    "contact_substeps": nc})
     return {"workload": "DKT pairs of equal-volume two-point metaballs, 160x160x240 walls, D_e = 10 lu, "
-                        "density ratio 2.87, tau 0.6, g 5e-5, contact, IBB", "steps": steps,
-            "seconds": round(time.perf_counter() - t0, 1), "shapes": out}
+                        "density ratio 2.87, tau 0.55, g 1e-4, contact, IBB; [leading, trailing] per pair",
+            "steps": steps, "seconds": round(time.perf_counter() - t0, 1), "shapes": out}
 
 
 GOLDEN = os.path.join(ROOT, "tests", "golden")

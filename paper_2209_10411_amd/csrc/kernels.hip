@@ -1988,6 +1988,33 @@ int link_grid(const Params &p) { return max(1, min(cdiv(expected_links(p), 256),
 int link_q_grid(const Params &p) { return max(1, min(cdiv(expected_links(p), 32), NR_BLOCKS)); }
 constexpr int LINK_GUESS_BLOCKS = 1024;  // 4096 waves, each loads the network once
 
+// LDS reserved (and not used) by each stream-collide block, so that at most
+// BULK_MAX_WAVES_PER_SIMD of its waves share a SIMD.  Its FP32 form needs 52
+// VGPRs, so without a cap it fills all eight wave slots of every SIMD and the
+// boundary kernels on the second stream (up to 128 VGPRs a wave) find no room
+// until the stream-collide drains: the step becomes their sum instead of their
+// maximum.  Six of eight slots leave two slots, 176 VGPRs and 22 KB of LDS per
+// SIMD (CU) to the second stream; the stream-collide itself runs as fast with
+// six waves per SIMD as with eight.  The LDS size per CU is read once per device.
+constexpr int BULK_MAX_WAVES_PER_SIMD = 6;
+
+static int bulk_lds_reserve(int waves_per_block) {
+    static int lds_cu[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (lds_cu[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+            v <= 0)
+            v = -1;
+        lds_cu[dev] = v;
+    }
+    if (lds_cu[dev] < 0) return 0;
+    const int blocks = BULK_MAX_WAVES_PER_SIMD * 4 / waves_per_block;  // 4 SIMDs per CU
+    const int r = lds_cu[dev] / (blocks + 1) + 1;                        // blocks + 1 do not fit
+    return (r + 511) & ~511;
+}
+
 template <int S>
 static void launch_step_kernels_t(const StepArgs &a) {
     using T = typename Store<S>::T;
@@ -2030,8 +2057,9 @@ static void launch_step_kernels_t(const StepArgs &a) {
     } else if (a.phase == PHASE_BULK) {
         // events ride on the dispatch itself (no separate marker packets)
         const bool fits = bulk_offsets_fit(p, (int)sizeof(T));
+        const int lds = bulk_lds_reserve(BULK_WAVES);
         if (S != 0 && p.nx % 2 == 0 && fits) {  // 16-bit storage: node pairs in lattice order
-            hipExtLaunchKernelGGL(k_bulk_pair<S>, dim3(cdiv(cdiv(p.N, 128), BULK_WAVES)), dim3(64 * BULK_WAVES), 0,
+            hipExtLaunchKernelGGL(k_bulk_pair<S>, dim3(cdiv(cdiv(p.N, 128), BULK_WAVES)), dim3(64 * BULK_WAVES), lds,
                                   a.stream, a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip,
                                   &a.cnt->err);
             return;
@@ -2039,11 +2067,11 @@ static void launch_step_kernels_t(const StepArgs &a) {
         const int nseg = cdiv(p.nx, 64);
         const long long waves = (long long)nseg * p.ny * p.nz;
         if (fits)
-            hipExtLaunchKernelGGL(k_bulk<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0, a.stream,
+            hipExtLaunchKernelGGL(k_bulk<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), lds, a.stream,
                                   a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip, nseg,
                                   &a.cnt->err);
         else
-            hipExtLaunchKernelGGL(k_bulk_wide<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), 0, a.stream,
+            hipExtLaunchKernelGGL(k_bulk_wide<S>, dim3(cdiv(waves, BULK_WAVES)), dim3(64 * BULK_WAVES), lds, a.stream,
                                   a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip, nseg,
                                   &a.cnt->err);
     } else if (a.phase == PHASE_SPECIAL) {
@@ -2091,8 +2119,8 @@ template <int S>
 static void launch_bulk_batch_t(int bw, const BulkCase *cases, const int *blk_case, int nblocks, int parity,
                                 hipStream_t s) {
     if (nblocks <= 0) return;
-    if (bw == 4) k_bulk_batch<S, 4><<<nblocks, 256, 0, s>>>(cases, blk_case, parity);
-    else k_bulk_batch<S, 8><<<nblocks, 512, 0, s>>>(cases, blk_case, parity);
+    if (bw == 4) k_bulk_batch<S, 4><<<nblocks, 256, bulk_lds_reserve(4), s>>>(cases, blk_case, parity);
+    else k_bulk_batch<S, 8><<<nblocks, 512, bulk_lds_reserve(8), s>>>(cases, blk_case, parity);
 }
 
 void launch_bulk_batch(int storage, int bw, const BulkCase *cases, const int *blk_case, int nblocks, int parity,

@@ -470,12 +470,16 @@ def dkt_shapes(n_shapes: int = 6, R: float = 5.0, a_max: float = 4.0):
     return out
 
 
-def dkt_pair(cp, k, D_e: float = 10.0, g: float = 5e-5, tau: float = 0.6) -> Config:
+def dkt_pair(cp, k, D_e: float = 10.0, g: float = 1e-4, tau: float = 0.55) -> Config:
     """Two bodies of one shape settling in a walled box, scaled from the
     paper's set-up (sec. 4): box 0.20 x 0.20 x 0.30 m for a volume-equivalent
     diameter D_e = 0.0125 m, i.e. 16 D_e x 16 D_e x 24 D_e; the bodies start
     0.270 and 0.255 m above the bottom (trailing and leading) with 0.004 m
-    between them horizontally; density ratio 2800/976; contact on."""
+    between them horizontally; density ratio 2800/976; contact on.  Viscosity
+    and gravity (tau 0.55, g 1e-4 at D_e = 10) give the Archimedes number
+    (rho_p/rho_f - 1) g D_e^3 / nu^2 = 673, a settling Reynolds number near 20
+    (the viscosity printed for this study would put it far below 1, where
+    pairs do not tumble)."""
     s = D_e / 0.0125
     nx, ny, nz = int(round(0.20 * s)), int(round(0.20 * s)), int(round(0.30 * s))
     c = np.array([nx / 2, ny / 2])
