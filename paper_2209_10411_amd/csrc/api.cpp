@@ -834,11 +834,14 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
         b.phase = PHASE_FLAGS;  // with the boundary/uncovered update
         b.do_special = 1;
         b.ev_stop = c->ev_flags;
+        // flags of step n-1 are dead: cleared by the classification on its
+        // balls, which cover them, for the next flagging
+        b.own_dead = move ? c->own[c->id] : nullptr;
         launch_phase(b);
         b.ev_stop = nullptr;
+        b.own_dead = nullptr;
         if (move) {
             b.phase = PHASE_LINKBUILD;
-            b.own_dead = c->own[c->id];  // flags of step n-1 are dead: cleared here
             launch_phase(b);
         }
         const bool t = c->timing && c->ev_used + 2 <= c->ev.size();

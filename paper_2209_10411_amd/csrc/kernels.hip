@@ -71,25 +71,50 @@ __device__ __forceinline__ void min_image(const Params &p, double d[3]) {
 // Control points of one body staged in LDS by the whole block, padded to a
 // multiple of 4 with weight-0 copies of the first point (they add exactly
 // zero) so that evaluation loops run 4 independent terms at a time.
+// Maximum over the 64 lanes of a wave (every lane gets it; all lanes take part).
+__device__ __forceinline__ float wave_fmax(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
 struct CPs {
     double x[MAXCP + 3][3];
     double k[MAXCP + 3];
+    // the same points relative to the anchor (the body's centroid) and
+    // weights in FP32, for the FP32 first decision of C >= L (metaball_ge32)
+    float4 f[MAXCP + 3];
+    double anc[3];
+    float bp;  // max over the points of |p - anchor|_1
     int n;    // padded count
     int img;  // the body's img: 0 = the minimum image is the identity here
     double level;  // the link fractions' surface: C = level (1, or c_0 of the inner body)
 };
 
+// Point i of the staged set: lab position and weight in FP64, position
+// relative to the anchor and weight in FP32.  Returns |p - anchor|_1 of the
+// FP32 form.
+__device__ __forceinline__ float stage_cp(CPs &c, int i, const double x[3], double k, const double anc[3]) {
+    c.x[i][0] = x[0]; c.x[i][1] = x[1]; c.x[i][2] = x[2];
+    c.k[i] = k;
+    const float4 f = make_float4((float)(x[0] - anc[0]), (float)(x[1] - anc[1]), (float)(x[2] - anc[2]), (float)k);
+    c.f[i] = f;
+    return fabsf(f.x) + fabsf(f.y) + fabsf(f.z);
+}
+
+// Whole block: the body's points (padded to a multiple of 4 with weight-0
+// copies of the first point) about the anchor X.
 __device__ void stage_cps(CPs &c, const DevParticle &P) {
     const int n4 = (P.n_cp + 3) & ~3;
-    for (int t = threadIdx.x; t < n4 * 4; t += blockDim.x) {
-        const int i = t >> 2, a = t & 3;
-        const int src = i < P.n_cp ? i : 0;
-        if (a < 3) c.x[i][a] = P.cpl[src][a];
-        else c.k[i] = i < P.n_cp ? P.k[i] : 0.0;
-    }
+    const float b = threadIdx.x < n4 ? stage_cp(c, threadIdx.x, P.cpl[threadIdx.x < P.n_cp ? threadIdx.x : 0],
+                                                threadIdx.x < P.n_cp ? P.k[threadIdx.x] : 0.0, P.X)
+                                     : 0.f;
+    const float bw = wave_fmax(b);  // n4 <= 24 points: all in the first wave
     if (threadIdx.x == 0) {
+        c.anc[0] = P.X[0]; c.anc[1] = P.X[1]; c.anc[2] = P.X[2];
         c.n = n4;
         c.img = P.img;
+        c.bp = bw * (1.f + 1e-6f);
     }
 }
 
@@ -168,6 +193,45 @@ __device__ __forceinline__ bool metaball_ge1(const Params &p, const CPs &P, cons
     return metaball_ge(p, P, x, 1.0, Cf);
 }
 
+// Whether C(x) >= L, decided first in FP32 where the FP32 sum is certain to
+// fall on the same side as the exact one, else by metaball_ge.  FP32 form:
+// r = x - X and the points' p - X rounded to FP32 (X the anchor), d = r - p,
+// terms k * rcp(|d|^2) on the hardware reciprocal (1 ulp), summed with fma.
+// With every |d|^2 >= 1 each component of d is off by at most
+// u (|r_a| + |p_a| + |d_a|) (u = 2^-24), so |d|^2 by at most
+// u (2.03 (|r|_1 + |p|_1) + 6.5) relative, a term by that plus 3 u, and the
+// n-term sum by n u more: rel = u (2.03 (|r|_1 + bp) + 9.5 + n), taken with
+// a factor 1.5.  The FP32 sum decides when it clears L by that bound plus
+// 1e-12 (the exact sum's own rounding); points within 1 of a control point
+// (|d|^2 < 1 in FP32), a body whose terms may take a periodic image
+// (img), and everything within the bound go to the FP64 forms.  Cf: the
+// FP32 sum when it decided, else metaball_fast's value.
+__device__ __forceinline__ bool metaball_ge32(const Params &p, const CPs &P, const double x[3], double L,
+                                              double &Cf) {
+    if (!P.img) {
+        const float rx = (float)(x[0] - P.anc[0]), ry = (float)(x[1] - P.anc[1]), rz = (float)(x[2] - P.anc[2]);
+        float C = 0.f, rmin = 1.f;
+        for (int i0 = 0; i0 < P.n; i0 += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 c = P.f[i0 + u];
+                const float dx = rx - c.x, dy = ry - c.y, dz = rz - c.z;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                rmin = fminf(rmin, r2);
+                C = fmaf(c.w, __builtin_amdgcn_rcpf(r2), C);
+            }
+        }
+        if (rmin >= 1.f) {
+            const float ax = fabsf(rx) + fabsf(ry) + fabsf(rz);
+            const double rel = 1.5 * 5.9604644775390625e-8 * (2.03 * ((double)ax + (double)P.bp) + 9.5 + P.n);
+            const double Cd = (double)C;
+            if (Cd * (1.0 - rel) > L * (1.0 + 1e-12)) { Cf = Cd; return true; }
+            if (Cd * (1.0 + rel) < L * (1.0 - 1e-12)) { Cf = Cd; return false; }
+        }
+    }
+    return metaball_ge(p, P, x, L, Cf);
+}
+
 // C and dC/ds at x_f - s e_i for one link held by an aligned group of eight
 // lanes: lane j sums control points j, j + 8, ... and the group adds its
 // partial sums by a butterfly, which leaves the same bits in every lane.
@@ -220,7 +284,7 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
     const double xj[3] = {xf[0] - sj * e[0], xf[1] - sj * e[1], xf[2] - sj * e[2]};
     double Cj;
     const double L = P.level;
-    const bool inj = metaball_ge(p, P, xj, L, Cj);
+    const bool inj = metaball_ge32(p, P, xj, L, Cj);
     const unsigned grp = (unsigned)((__ballot(inj) >> base) & 0xffull);
     const int k0 = grp ? __ffs(grp) - 1 : 7;
     const double Chi = __shfl(Cj, base + k0), Clo = __shfl(Cj, base + (k0 > 0 ? k0 - 1 : 0));
@@ -1279,7 +1343,7 @@ __device__ __forceinline__ void mark_body(const Params &p, const RegionMap &rm, 
     if (!region_node(p, rm, P, bid, rad, pi, x, y, z, n)) return;
     const double xp[3] = {(double)x, (double)y, (double)z};
     double Cf;
-    if (metaball_ge1(p, cps, xp, Cf)) atomicMin(&own_new[n], pi);
+    if (metaball_ge32(p, cps, xp, 1.0, Cf)) atomicMin(&own_new[n], pi);
 }
 
 __global__ __launch_bounds__(BLK) void k_region_mark(Params p, RegionMap rm, const DevParticle *P,
@@ -1410,7 +1474,8 @@ __device__ __forceinline__ void classify_body(const Params &p, const RegionMap &
                                               uint32_t *special, Counters *cnt, int *blk_cnt,
                                               uint32_t *lmask, int *body_stats,
                                               const typename Store<S>::T *A,
-                                              typename Store<S>::T *B, int do_special, const int bid) {
+                                              typename Store<S>::T *B, int do_special, int32_t *clear,
+                                              const int bid) {
     __shared__ int sh[BLK];
     __shared__ int sh3[3][BLK];
     // owners before / after over the tile and a one-node halo (beyond a wall: OUTSIDE)
@@ -1446,6 +1511,7 @@ __device__ __forceinline__ void classify_body(const Params &p, const RegionMap &
     int pi, x, y, z;
     long long n;
     const bool in = region_node(p, rm, P, bid, rad, pi, x, y, z, n);
+    if (in && clear) clear[n] = FLUID;  // the dead flag buffer (the flags before own_old) for the next flagging
     uint32_t m = 0u, wall = 0u, solid = 0u;
     // owners before / after, lowest owner among the neighbours before / after
     int32_t oo = FLUID, on = FLUID, mo = FLUID, mn = FLUID;
@@ -1515,9 +1581,10 @@ __global__ __launch_bounds__(BLK) void k_region_classify(Params p, RegionMap rm,
                                                          uint32_t *special, Counters *cnt, int *blk_cnt,
                                                          uint32_t *lmask, int *body_stats,
                                                          const typename Store<S>::T *A,
-                                                         typename Store<S>::T *B, int do_special) {
+                                                         typename Store<S>::T *B, int do_special,
+                                                         int32_t *clear) {
     classify_body<S>(p, rm, P, own_old, own_new, skip_next, special, cnt, blk_cnt, lmask, body_stats, A, B,
-                     do_special, blockIdx.x);
+                     do_special, clear, blockIdx.x);
 }
 
 // Nodes uncovered by a re-flag (solid before, fluid after) anywhere in the
@@ -1682,6 +1749,9 @@ __device__ __forceinline__ void emit_body(const Params &p, const RegionMap &rm, 
     // counted none); the first block of a body and the last block still
     // record the offsets
     if (tile_outside(rm, P[pid], pid, rm.first[bid], rad) && part_first_blk[pid] != bid && bid != nblk - 1) return;
+    // nor does a tile without links when the dead flags were cleared by the
+    // classification (clear == NULL)
+    if (!clear && blk_cnt[bid] == 0 && part_first_blk[pid] != bid && bid != nblk - 1) return;
     int before = 0;
     for (int q = t; q < pid; q += BLK) before += body_stats[4 * q];
     for (int b = part_first_blk[pid] + t; b < bid; b += BLK) before += blk_cnt[b];
@@ -1865,16 +1935,22 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
             // centroid, weights s^2 k) at the level c_0 = s^2
             const bool inner = p.link_c0 && p.c_rs > 0.0;
             const double sc = inner ? 1.0 - p.c_rs * B.rsk : 1.0;
-            for (int e = j; e < n4 * 4; e += 8) {
-                const int k = e >> 2, a = e & 3;
+            float bmax = 0.f;
+            for (int k = j; k < n4; k += 8) {
                 const int src = k < B.n_cp ? k : 0;
-                if (a < 3) cps[g].x[k][a] = inner ? B.X[a] + sc * (B.cpl[src][a] - B.X[a]) : B.cpl[src][a];
-                else cps[g].k[k] = k < B.n_cp ? (inner ? sc * sc * B.k[k] : B.k[k]) : 0.0;
+                double xk[3];
+                for (int a = 0; a < 3; ++a) xk[a] = inner ? B.X[a] + sc * (B.cpl[src][a] - B.X[a]) : B.cpl[src][a];
+                bmax = fmaxf(bmax, stage_cp(cps[g], k, xk, k < B.n_cp ? (inner ? sc * sc * B.k[k] : B.k[k]) : 0.0,
+                                            B.X));
             }
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) bmax = fmaxf(bmax, __shfl_xor(bmax, o));  // the group's 8 lanes
             if (j == 0) {
+                cps[g].anc[0] = B.X[0]; cps[g].anc[1] = B.X[1]; cps[g].anc[2] = B.X[2];
                 cps[g].n = n4;
                 cps[g].img = B.img;
                 cps[g].level = sc * sc;
+                cps[g].bp = bmax * (1.f + 1e-6f);
             }
             node_xyz(p, n, x, y, z);
         }
@@ -1955,7 +2031,7 @@ __global__ __launch_bounds__(BLK) void k_region_classify_batch(const CaseArgs *_
     using T = typename Store<S>::T;
     const CaseArgs &a = cs[map[blockIdx.x]];
     classify_body<S>(a.p, a.rm, a.P, a.own_old, a.own_new, a.skip_next, a.special, a.cnt, a.blk_cnt, a.lmask,
-                     a.body_stats, (const T *)a.A, (T *)a.B, 1, (int)blockIdx.x - a.first[BK_REGION]);
+                     a.body_stats, (const T *)a.A, (T *)a.B, 1, nullptr, (int)blockIdx.x - a.first[BK_REGION]);
 }
 
 __global__ __launch_bounds__(BLK) void k_link_emit_batch(const CaseArgs *__restrict__ cs,
@@ -2050,7 +2126,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
                                   a.ev_stop, 0, p, a.rm, (const DevParticle *)a.P, (const int32_t *)a.own_old,
                                   (const int32_t *)a.own_new, a.skip_next, a.special, a.cnt,
                                   a.move ? a.blk_cnt : (int *)nullptr, a.lmask, a.body_stats, (const T *)A, B,
-                                  a.do_special);
+                                  a.do_special, a.own_dead);
         } else if (a.ev_stop) {
             (void)hipEventRecord(a.ev_stop, a.stream);
         }
@@ -2085,7 +2161,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
         if (p.np > 0) {
             k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt, a.body_stats,
                                                                 a.part_first_blk, a.l_off,
-                                                                a.l_node, a.l_do, a.cnt, a.own_dead);
+                                                                a.l_node, a.l_do, a.cnt, (int32_t *)nullptr);
             const int qg = link_q_grid(p);
             if (a.warm) {  // the network's guesses over the list, then the solve
                 k_link_guess<<<min(cdiv(expected_links(p), 128), LINK_GUESS_BLOCKS), 256, 0, a.stream>>>(

@@ -26,7 +26,7 @@ struct StepArgs {
     hipStream_t stream;
     void *A, *B;
     int32_t *own_old, *own_new;
-    int32_t *own_dead;  // PHASE_LINKBUILD: flag buffer to reset to FLUID on the regions, or NULL
+    int32_t *own_dead;  // PHASE_FLAGS: flag buffer to reset to FLUID on the classification balls, or NULL
     uint8_t *skip;       // PHASE_BULK: skip mask of this step
     uint8_t *skip_next;  // PHASE_FLAGS: skip mask of the next step
     DevParticle *P;
