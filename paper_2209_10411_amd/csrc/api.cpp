@@ -385,6 +385,7 @@ struct lbm_ctx {
     hipEvent_t ev_main, ev_flags, ev_links, ev_bulk;
     bool pending_refill;
     bool timing;
+    int bulk_blocks;  // stream-collide blocks per CU (0: the default cap), from the link count
     std::vector<hipEvent_t> ev;  // start/stop pairs
     size_t ev_used;
     long long timed_launches;
@@ -407,6 +408,7 @@ StepArgs base_args(lbm_ctx *c) {
     a.l_node = c->l_node; a.l_do = c->l_do; a.l_q = c->l_q; a.part = c->lpart;
     a.special = c->special; a.cnt = c->cnt; a.cb = c->cb;
     a.nrs = c->nrs; a.warm = c->warm; a.mlp_body = c->mlp_body;
+    a.bulk_blocks = c->bulk_blocks;
     return a;
 }
 
@@ -436,6 +438,12 @@ lbm_status estimate_lists(lbm_ctx *c) {
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(&h, c->cnt, sizeof h, hipMemcpyDeviceToHost));
     c->p.est_links = std::min(c->p.link_cap, (int)std::min<long long>(0x3fffffff, 3ll * h.n_links / 2 + 1024));
+    // Where the boundary chain outweighs the stream-collide (many cut links
+    // per node: on a 256^3 box with 200 bodies, 1.45 M links for 16.8 M
+    // nodes), the stream-collide leaves it more of every CU: two blocks per
+    // CU there gave 1.52 against 1.64 ms per step with six; with few links
+    // (7.5 k for 6.3 M nodes) six blocks keep the stream-collide at full speed.
+    c->bulk_blocks = 50ll * h.n_links > (long long)c->p.N ? 2 : 0;
     // boundary nodes carry several cut links each (the special list is empty
     // right after set-up, when no previous flags exist)
     c->p.est_special = std::min(c->p.special_cap,
@@ -656,6 +664,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->aux = nullptr;
     c->ev_main = c->ev_flags = c->ev_links = c->ev_bulk = nullptr;
     c->timing = false;
+    c->bulk_blocks = 0;
     c->ev_used = 0;
     c->timed_launches = 0;
     c->timed_ms = 0;

@@ -9,14 +9,16 @@
 //                    update (sec. 2.3.1)
 //   k_rigid          one block (contact): sphero-metaball contacts and the
 //                    Newton-Euler update of all particles over the sub-steps
-//   k_region_*       per-particle cubes: metaball flags (sec. 2.1), node
-//                    classes and the list of nodes needing the slow path
+//   k_region_*       per-particle cubes in 8x8x4 tiles, a block per tile:
+//                    metaball flags (sec. 2.1), node classes and the
+//                    boundary/uncovered update
 //   k_bulk           every plain fluid node: pull-stream + BGK/Guo collide,
 //                    branch-free apart from the one class byte (HBM-bound)
 //   k_special        boundary and uncovered nodes: pull with bounce-back or
 //                    refill (sec. 2.3.2, refilling equation), then collide
-//   k_link_emit      cut-link list of the new geometry (masks and counts from
-//                    the classification)
+//   k_link_emit_*    cut-link list of the new geometry (masks and counts from
+//                    the classification; a fixed grid visits the tiles with
+//                    links)
 //   k_link_q         link fractions q, eight lanes per link, by a safeguarded
 //                    Newton iteration in FP64
 // Populations are deviations f_i - w_i rho0 in FP32, FP16 or BF16 storage;
@@ -71,6 +73,14 @@ __device__ __forceinline__ void min_image(const Params &p, double d[3]) {
 // Control points of one body staged in LDS by the whole block, padded to a
 // multiple of 4 with weight-0 copies of the first point (they add exactly
 // zero) so that evaluation loops run 4 independent terms at a time.
+// Orders the LDS accesses of the lanes of one wave (code motion and the
+// memory model at wavefront scope; a wave's LDS operations run in order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Maximum over the 64 lanes of a wave (every lane gets it; all lanes take part).
 __device__ __forceinline__ float wave_fmax(float v) {
 #pragma unroll
@@ -1795,15 +1805,57 @@ __device__ __forceinline__ void emit_body(const Params &p, const RegionMap &rm, 
         }
 }
 
-__global__ __launch_bounds__(BLK) void k_link_emit(Params p, RegionMap rm, const DevParticle *P,
-                                                   const uint32_t *__restrict__ lmask,
-                                                   const int *__restrict__ blk_cnt,
-                                                   const int *__restrict__ body_stats,
-                                                   const int *__restrict__ part_first_blk, int *__restrict__ l_off,
-                                                   uint32_t *__restrict__ l_node, uint32_t *__restrict__ l_do,
-                                                   Counters *cnt, int32_t *clear) {
-    emit_body(p, rm, P, lmask, blk_cnt, body_stats, part_first_blk, l_off, l_node, l_do, cnt, clear, blockIdx.x,
-              gridDim.x);
+// The link list runs beside the stream-collide, which holds most of the
+// compute units: a kernel there keeps few blocks resident, and one block per
+// region tile (tens of thousands, nearly all without links) took the whole
+// length of the stream-collide.  Here a block of a grid of G visits tiles b,
+// b + G, b + 2G, ... ; per round, wave 0 tests 64 of them at once (one lane
+// each) and the block then runs the per-tile body for the ones that pass,
+// one after another.  (The flagging and the classification, which run alone
+// and have work in a third of their tiles, are faster with a block per tile:
+// this form took them from 122 to 191 and from 268 to 512 us.)
+constexpr int REGION_GRID = 2048;
+inline int region_grid(const Params &p) { return p.region_blocks < REGION_GRID ? p.region_blocks : REGION_GRID; }
+
+template <class Test, class Body>
+__device__ __forceinline__ void visit_tiles(int nblk, Test test, Body body) {
+    __shared__ unsigned long long sel;
+    const int G = gridDim.x;
+    for (int base = blockIdx.x; base < nblk; base += 64 * G) {
+        if (threadIdx.x < 64) {
+            const int b = base + threadIdx.x * G;
+            const unsigned long long m = __ballot(b < nblk && test(b));
+            if (threadIdx.x == 0) sel = m;
+        }
+        __syncthreads();
+        unsigned long long m = sel;
+        __syncthreads();  // sel is rewritten in the next round
+        while (m) {
+            const int j = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            body(base + j * G);
+            __syncthreads();  // the body's LDS is restaged for the next tile
+        }
+    }
+}
+
+// The link list over the tiles with links, each body's first tile and the
+// last tile (they record the offsets); the dead flags were cleared by the
+// classification.
+__global__ __launch_bounds__(BLK) void k_link_emit_tiles(Params p, RegionMap rm, const DevParticle *P,
+                                                         const uint32_t *__restrict__ lmask,
+                                                         const int *__restrict__ blk_cnt,
+                                                         const int *__restrict__ body_stats,
+                                                         const int *__restrict__ part_first_blk,
+                                                         int *__restrict__ l_off, uint32_t *__restrict__ l_node,
+                                                         uint32_t *__restrict__ l_do, Counters *cnt) {
+    const int nblk = p.region_blocks;
+    visit_tiles(
+        nblk, [&](int b) { return blk_cnt[b] > 0 || part_first_blk[rm.part[b]] == b || b == nblk - 1; },
+        [&](int b) {
+            emit_body(p, rm, P, lmask, blk_cnt, body_stats, part_first_blk, l_off, l_node, l_do, cnt, nullptr, b,
+                      nblk);
+        });
 }
 
 // Link build, third pass: the link fractions of the whole list, eight lanes
@@ -1900,6 +1952,11 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
     const bool warm = WARM && wts != nullptr;  // block-uniform
     for (int b = t; b < NR_HIST; b += 256) hist[b] = 0u;
     if (t == 0) rmax = 0u;
+    __syncthreads();
+    // From here each wave runs its own eight groups through the rounds: a
+    // group's slot cps[g] is written and read only by the lanes of its wave,
+    // so the rounds need no block barrier (a wave does not wait for the
+    // slowest link of the other three).
     const int nl = min(cnt->n_links, p.link_cap);
     int it_sum = 0, links = 0;
     // the next round's link record is loaded while this round solves
@@ -1956,7 +2013,7 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
         }
         double guess = -1.0;
         if (warm && ok) guess = l_q[l];  // the first pass's network output
-        __syncthreads();
+        wave_sync();  // the group's slot is staged
         if (ok) {
             double q, resid;
             bool conv;
@@ -1973,8 +2030,9 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
                 atomicMax(&rmax, __float_as_uint((float)fabs(resid)));
             }
         }
-        __syncthreads();  // the group slots are restaged in the next round
+        wave_sync();  // the group's slot is restaged in the next round
     }
+    __syncthreads();
     const int its = block_sum(it_sum, sh);
     __syncthreads();
     const int nls = block_sum(links, sh);
@@ -2074,7 +2132,7 @@ constexpr int LINK_GUESS_BLOCKS = 1024;  // 4096 waves, each loads the network o
 // six waves per SIMD as with eight.  The LDS size per CU is read once per device.
 constexpr int BULK_MAX_WAVES_PER_SIMD = 6;
 
-static int bulk_lds_reserve(int waves_per_block) {
+static int bulk_lds_reserve(int waves_per_block, int max_blocks = 0) {
     static int lds_cu[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
@@ -2086,7 +2144,7 @@ static int bulk_lds_reserve(int waves_per_block) {
         lds_cu[dev] = v;
     }
     if (lds_cu[dev] < 0) return 0;
-    const int blocks = BULK_MAX_WAVES_PER_SIMD * 4 / waves_per_block;  // 4 SIMDs per CU
+    const int blocks = max_blocks > 0 ? max_blocks : BULK_MAX_WAVES_PER_SIMD * 4 / waves_per_block;  // 4 SIMDs per CU
     const int r = lds_cu[dev] / (blocks + 1) + 1;                        // blocks + 1 do not fit
     return (r + 511) & ~511;
 }
@@ -2133,7 +2191,7 @@ static void launch_step_kernels_t(const StepArgs &a) {
     } else if (a.phase == PHASE_BULK) {
         // events ride on the dispatch itself (no separate marker packets)
         const bool fits = bulk_offsets_fit(p, (int)sizeof(T));
-        const int lds = bulk_lds_reserve(BULK_WAVES);
+        const int lds = bulk_lds_reserve(BULK_WAVES, a.bulk_blocks);
         if (S != 0 && p.nx % 2 == 0 && fits) {  // 16-bit storage: node pairs in lattice order
             hipExtLaunchKernelGGL(k_bulk_pair<S>, dim3(cdiv(cdiv(p.N, 128), BULK_WAVES)), dim3(64 * BULK_WAVES), lds,
                                   a.stream, a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip,
@@ -2159,9 +2217,9 @@ static void launch_step_kernels_t(const StepArgs &a) {
             (void)hipEventRecord(a.ev_stop, a.stream);
     } else if (a.phase == PHASE_LINKBUILD) {
         if (p.np > 0) {
-            k_link_emit<<<p.region_blocks, BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt, a.body_stats,
-                                                                a.part_first_blk, a.l_off,
-                                                                a.l_node, a.l_do, a.cnt, (int32_t *)nullptr);
+            k_link_emit_tiles<<<region_grid(p), BLK, 0, a.stream>>>(p, a.rm, a.P, a.lmask, a.blk_cnt, a.body_stats,
+                                                                     a.part_first_blk, a.l_off, a.l_node, a.l_do,
+                                                                     a.cnt);
             const int qg = link_q_grid(p);
             if (a.warm) {  // the network's guesses over the list, then the solve
                 k_link_guess<<<min(cdiv(expected_links(p), 128), LINK_GUESS_BLOCKS), 256, 0, a.stream>>>(

@@ -44,6 +44,7 @@ struct StepArgs {
     const _Float16 *warm;   // warm-start MLP parameters (FP16), or NULL: plain Newton
     const float *mlp_body;  // [np][80] constant MLP inputs of each body
     hipEvent_t ev_start, ev_stop;  // PHASE_BULK / PHASE_SPECIAL: events recorded with the dispatch, or NULL
+    int bulk_blocks;  // PHASE_BULK: stream-collide blocks allowed per CU (LDS reservation), 0: the default
 };
 
 void launch_phase(const StepArgs &a);
