@@ -155,7 +155,7 @@ __device__ double metaball(const Params &p, const CPs &P, const double x[3]) {
     return C;
 }
 
-// Reciprocal of x > 0: the hardware estimate and two Newton steps (a few
+// Reciprocal of x != 0: the hardware estimate and two Newton steps (a few
 // ulps; the exact quotient costs about twice the instructions).
 __device__ __forceinline__ double rcp_refined(double x) {
     double r = __builtin_amdgcn_rcp(x);
@@ -242,18 +242,38 @@ __device__ __forceinline__ bool metaball_ge32(const Params &p, const CPs &P, con
     return metaball_ge(p, P, x, L, Cf);
 }
 
+// A double from another lane of the same row by a DPP move (both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// Sum over an aligned group of eight lanes, the same bits in every lane:
+// partners lane ^ 1, lane ^ 2 (quad permutations), then the mirror lane of
+// the other quad (7 - lane), which holds the same quad sum as lane ^ 4.
+constexpr int DPP_XOR1 = 0xb1, DPP_XOR2 = 0x4e, DPP_HALF_MIRROR = 0x141;
+__device__ __forceinline__ double group8_sum(double v) {
+    v += dpp_f64<DPP_XOR1>(v);
+    v += dpp_f64<DPP_XOR2>(v);
+    return v + dpp_f64<DPP_HALF_MIRROR>(v);
+}
+
 // C and dC/ds at x_f - s e_i for one link held by an aligned group of eight
 // lanes: lane j sums control points j, j + 8, ... and the group adds its
 // partial sums by a butterfly, which leaves the same bits in every lane.
-__device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], const int e[3], double s,
+// These values steer the Newton iteration and judge its residual to 1e-15 of
+// the level, so they are formed with fused multiply-adds and refined
+// reciprocals.
+__device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], const double e[3], double s,
                              double &C, double &dC) {
-#pragma clang fp contract(off)
     const double xs[3] = {xf[0] - s * e[0], xf[1] - s * e[1], xf[2] - s * e[2]};
     double c = 0.0, g = 0.0;
     for (int i = threadIdx.x & 7; i < P.n; i += 8) {
         double d[3] = {xs[0] - P.x[i][0], xs[1] - P.x[i][1], xs[2] - P.x[i][2]};
         if (P.img) min_image(p, d);
-        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const double r2 = fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
         if (r2 == 0.0) {
             c = __builtin_inf();
             continue;
@@ -261,15 +281,10 @@ __device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], 
         const double inv = rcp_refined(r2);
         const double kr = P.k[i] * inv;
         c += kr;
-        g += 2.0 * kr * inv * (d[0] * e[0] + d[1] * e[1] + d[2] * e[2]);
+        g = fma(2.0 * kr * inv, fma(d[0], e[0], fma(d[1], e[1], d[2] * e[2])), g);
     }
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) {
-        c += __shfl_xor(c, o);
-        g += __shfl_xor(g, o);
-    }
-    C = c;
-    dC = g;
+    C = group8_sum(c);
+    dC = group8_sum(g);
 }
 
 // Link fraction q (sec. 2.3.2): the first root of C(x_f - s e_i) = L on
@@ -289,7 +304,7 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
                               int it_max, double &q, double &resid, bool &conv) {
     const int lane = threadIdx.x & 63, j = lane & 7, base = lane & 56;
     const double xf[3] = {(double)x, (double)y, (double)z};
-    const int e[3] = {EX[i], EY[i], EZ[i]};
+    const double e[3] = {(double)EX[i], (double)EY[i], (double)EZ[i]};
     const double sj = (double)(j + 1) / 8.0;
     const double xj[3] = {xf[0] - sj * e[0], xf[1] - sj * e[1], xf[2] - sj * e[2]};
     double Cj;
@@ -325,7 +340,7 @@ __device__ int link_fraction8(const Params &p, const CPs &P, int x, int y, int z
             break;
         }
         if (g >= 0.0) hi = s; else lo = s;
-        const double sn = s - g / dC;
+        const double sn = s - g * rcp_refined(dC);  // a zero or tiny slope leaves the bracket: bisection
         if (!(dC != 0.0) || !(sn > lo && sn < hi) || fabs(2.0 * g) > fabs(dxold * dC)) {
             dxold = dx;
             dx = 0.5 * (hi - lo);
