@@ -836,6 +836,110 @@ __device__ int pair_geometry(const Params &p, const DevParticle &P0, const DevPa
     return delta > 0.0 ? 1 : 0;
 }
 
+// The same pair geometry by an aligned group of eight lanes (all active,
+// one pair): lane l sums the control points l, l + 8, ... of each inner
+// body into f, grad f and the Hessian's six entries, and the group adds the
+// partial sums (group8_sum: the same bits in every lane), so every lane
+// follows the same iteration and returns the same result.  Reciprocals are
+// refined hardware estimates.  Only the evaluations are shared out; the
+// start, the Newton step and the projections are those of pair_geometry.
+__device__ void mb_eval3_8(const InnerMB &m, const double x[3], double &f, double g[3], double H[9]) {
+    double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x & 7; i < m.n; i += 8) {
+        const double ki = inner_k(m, i);
+        const double d0 = x[0] - inner_cp(m, i, 0), d1 = x[1] - inner_cp(m, i, 1), d2 = x[2] - inner_cp(m, i, 2);
+        const double i2 = rcp_refined(fma(d0, d0, fma(d1, d1, d2 * d2))), i4 = i2 * i2;
+        const double c1 = -2.0 * ki * i4, c2 = 8.0 * ki * i4 * i2;
+        v[0] += ki * i2;
+        v[1] += c1 * d0; v[2] += c1 * d1; v[3] += c1 * d2;
+        v[4] += c2 * d0 * d0 + c1; v[5] += c2 * d0 * d1; v[6] += c2 * d0 * d2;
+        v[7] += c2 * d1 * d1 + c1; v[8] += c2 * d1 * d2; v[9] += c2 * d2 * d2 + c1;
+    }
+#pragma unroll
+    for (int a = 0; a < 10; ++a) v[a] = group8_sum(v[a]);
+    f = v[0];
+    g[0] = v[1]; g[1] = v[2]; g[2] = v[3];
+    H[0] = v[4]; H[1] = v[5]; H[2] = v[6];
+    H[3] = v[5]; H[4] = v[7]; H[5] = v[8];
+    H[6] = v[6]; H[7] = v[8]; H[8] = v[9];
+}
+
+__device__ bool pair_newton8(const InnerMB &m0, const InnerMB &m1, double xm[3], double L, int it_max, int &iters) {
+    for (int it = 0; it < it_max; ++it) {
+        double f0, g0[3], H0[9], f1, g1[3], H1[9], H[9], Hi[9], dx[3];
+        mb_eval3_8(m0, xm, f0, g0, H0);
+        mb_eval3_8(m1, xm, f1, g1, H1);
+        ++iters;
+        for (int a = 0; a < 9; ++a) H[a] = H0[a] + H1[a];
+        if (!inv3d(H, Hi)) return false;
+        double st = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            dx[a] = -(Hi[3 * a] * (g0[0] + g1[0]) + Hi[3 * a + 1] * (g0[1] + g1[1]) + Hi[3 * a + 2] * (g0[2] + g1[2]));
+            st += dx[a] * dx[a];
+        }
+        st = sqrt(st);
+        if (st > 0.25 * L)
+            for (int a = 0; a < 3; ++a) dx[a] *= 0.25 * L / st;
+        for (int a = 0; a < 3; ++a) xm[a] += dx[a];
+        if (st < 1e-12 * (1.0 + L)) return true;
+    }
+    return false;
+}
+
+__device__ int pair_geometry8(const Params &p, const DevParticle &P0, const DevParticle &P1, double xcp[3],
+                              double nrm[3], double &delta, const double *guess, double xm_out[3], int &iters) {
+    double d01[3] = {P1.X[0] - P0.X[0], P1.X[1] - P0.X[1], P1.X[2] - P0.X[2]};
+    min_image(p, d01);
+    const double sh0[3] = {0.0, 0.0, 0.0};
+    const double sh1[3] = {P0.X[0] + d01[0] - P1.X[0], P0.X[1] + d01[1] - P1.X[1], P0.X[2] + d01[2] - P1.X[2]};
+    InnerMB m0, m1;
+    const int n0 = inner_metaball(p, P0, sh0, m0), n1 = inner_metaball(p, P1, sh1, m1);
+    if (n0 < 0 || n1 < 0) return -1;
+    double K0 = 0.0, K1 = 0.0;
+    for (int i = 0; i < n0; ++i) K0 += inner_k(m0, i);
+    for (int i = 0; i < n1; ++i) K1 += inner_k(m1, i);
+    const double rho = cbrt(K0 / K1);
+    double xm[3];
+    const double L = sqrt(d01[0] * d01[0] + d01[1] * d01[1] + d01[2] * d01[2]);
+    bool ok = false;
+    double f0, g0[3], H0[9], f1, g1[3], H1[9];  // at the final point
+    if (guess && isfinite(guess[0]) && isfinite(guess[1]) && isfinite(guess[2])) {
+        for (int a = 0; a < 3; ++a) xm[a] = guess[a];
+        ok = pair_newton8(m0, m1, xm, L, PAIR_WARM_MAX, iters);
+        if (ok) {
+            const double t =
+                ((xm[0] - P0.X[0]) * d01[0] + (xm[1] - P0.X[1]) * d01[1] + (xm[2] - P0.X[2]) * d01[2]) / (L * L);
+            mb_eval3_8(m0, xm, f0, g0, H0);
+            mb_eval3_8(m1, xm, f1, g1, H1);
+            double curv = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) curv += d01[a] * (H0[3 * a + b] + H1[3 * a + b]) * d01[b];
+            ok = t > 0.0 && t < 1.0 && f0 < 1.0 && f1 < 1.0 && curv > 0.0;
+        }
+    }
+    const bool warm_kept = ok;
+    if (!ok) {
+        for (int a = 0; a < 3; ++a) xm[a] = P0.X[a] + d01[a] * rho / (1.0 + rho);
+        ok = pair_newton8(m0, m1, xm, L, PAIR_NR_MAX, iters);
+    }
+    for (int a = 0; a < 3; ++a) xm_out[a] = xm[a];
+    if (!ok) return -1;
+    if (!warm_kept) {
+        mb_eval3_8(m0, xm, f0, g0, H0);
+        mb_eval3_8(m1, xm, f1, g1, H1);
+    }
+    const double G0 = sqrt(g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2]);
+    const double G1 = sqrt(g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
+    if (!(G0 > 0.0 && G1 > 0.0)) return -1;
+    const double q0 = (1.0 - f0) / (G0 * G0);
+    delta = 2.0 * p.c_rs - ((1.0 - f0) / G0 + (1.0 - f1) / G1);
+    for (int a = 0; a < 3; ++a) {
+        nrm[a] = g0[a] / G0;
+        xcp[a] = xm[a] + q0 * g0[a] - (p.c_rs - 0.5 * delta) * nrm[a];
+    }
+    return delta > 0.0 ? 1 : 0;
+}
+
 // Contact with the halfway wall normal to axis ax (side 0 at -1/2, side 1 at
 // L - 1/2) (Eqs. metawallcp, contactprop2): stationary point x_cw of f on the
 // wall plane by 2-D Newton-Raphson from the projection of the control point
@@ -990,6 +1094,10 @@ __device__ __forceinline__ bool contact_candidate(const Params &p, const DevPart
     return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) <= Pi.rb + Pj.rb;
 }
 
+// Contact of the pair q = i np + j (i < j) into its slots.  GROUP8: called by
+// an aligned group of eight lanes for one pair (the geometry shared out,
+// pair_geometry8); lane 0 writes the slots and counts.
+template <bool GROUP8 = false>
 __device__ __forceinline__ void contact_pair(const Params &p, const DevParticle *P, const ContactBufs &cb,
                                              Counters *__restrict__ cnt, int q, double dt, bool use_guess) {
     const int np = p.np;
@@ -1005,11 +1113,19 @@ __device__ __forceinline__ void contact_pair(const Params &p, const DevParticle 
         if (contact_candidate(p, Pi, Pj)) {
             double xm[3];
             int its = 0;
-            r = pair_geometry(p, Pi, Pj, xcp, n, delta, use_guess ? cb.pairGuess + 4ll * q : nullptr, xm, its);
+            const double *guess = use_guess ? cb.pairGuess + 4ll * q : nullptr;
+            if constexpr (GROUP8) {
+                r = pair_geometry8(p, Pi, Pj, xcp, n, delta, guess, xm, its);
+                if (threadIdx.x & 7) return;  // the group's other lanes hold the same results
+            } else {
+                r = pair_geometry(p, Pi, Pj, xcp, n, delta, guess, xm, its);
+            }
             atomicAdd(&cnt->n_contact_nr, 1ull);
             atomicAdd(&cnt->n_contact_it, (unsigned long long)its);
             for (int a = 0; a < 3; ++a) cb.pairXm[3ll * q + a] = xm[a];
             solved = r >= 0 ? 1 : 0;
+        } else if (GROUP8 && (threadIdx.x & 7)) {
+            return;
         }
         if (r < 0) atomicAdd(&cnt->n_contact_fail, 1ull);
         if (r <= 0) {
@@ -1027,6 +1143,7 @@ __device__ __forceinline__ void contact_pair(const Params &p, const DevParticle 
             cross3(rj, Fm, Tj);
         }
     }
+    if (GROUP8 && (threadIdx.x & 7)) return;
     for (int a = 0; a < 3; ++a) {
         cb.pairF[3ll * q + a] = F[a];
         cb.pairTi[3ll * q + a] = Ti[a];
@@ -1126,11 +1243,15 @@ __device__ __forceinline__ void rigid_case(const Params &p, DevParticle *__restr
 // kernel and then the body kernel once per sub-step.
 __global__ __launch_bounds__(256) void k_contact_pairs(Params p, const DevParticle *__restrict__ P, ContactBufs cb,
                                                        Counters *__restrict__ cnt, int use_guess) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int np2 = p.np * p.np;
     const double dt = 1.0 / p.n_sub;
-    if (q < np2) contact_pair(p, P, cb, cnt, q, dt, use_guess != 0);
-    else if (q < np2 + 6 * p.np) contact_wall(p, P, cb, cnt, q - np2, dt);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 8 * np2) {  // eight lanes per pair (group-uniform branch)
+        contact_pair<true>(p, P, cb, cnt, t >> 3, dt, use_guess != 0);
+    } else {
+        const int q = t - 8 * np2;
+        if (q < 6 * p.np) contact_wall(p, P, cb, cnt, q, dt);
+    }
 }
 
 // Warm start of the pair solves: the closest-point task of the MLP for every
@@ -2181,12 +2302,12 @@ static void launch_step_kernels_t(const StepArgs &a) {
             if (p.np <= RIGID_LDS && !a.warm) {  // few bodies: one block, records in LDS
                 k_rigid<<<1, 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt);
             } else {
-                const int nq = p.np * p.np + 6 * p.np;
                 for (int s2 = 0; s2 < p.n_sub; ++s2) {
                     if (a.warm)
                         k_contact_guess<<<cdiv((long long)p.np * p.np, 4), 256, 0, a.stream>>>(p, a.P, a.cb, a.warm,
                                                                                             a.mlp_body);
-                    k_contact_pairs<<<cdiv(nq, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt, a.warm ? 1 : 0);
+                    k_contact_pairs<<<cdiv(8ll * p.np * p.np + 6 * p.np, 256), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt,
+                                                                                                 a.warm ? 1 : 0);
                     k_contact_bodies<<<cdiv(p.np, 4), 256, 0, a.stream>>>(p, a.P, a.cb, a.cnt, s2 == 0,
                                                                           s2 == p.n_sub - 1);
                 }
