@@ -391,11 +391,35 @@ def run_mifit(ga_generations=100, gs_steps=200, gs_batch=256):
                    "loss": [float(v) for v in Lg[0]]}}
 
 
+def dkt_matched_shapes(R=5.0, h=0.05):
+    """Two-point bodies whose Corey shape factor, measured by the shape kernel,
+    matches each of the paper's designed particles P1-P8 (bisection on the
+    elongation a; the CSF falls monotonically with a)."""
+    import paper_2209_10411_amd as mdl
+    import workloads
+
+    out = []
+    for target in workloads.DKT_CSF_TARGETS:
+        if target >= 1.0:
+            out.append(workloads.dkt_body(0.0, R))
+            continue
+        lo, hi = 0.0, 0.98 * R
+        for _ in range(14):
+            mid = 0.5 * (lo + hi)
+            if mdl.shape_descriptors(*workloads.dkt_body(mid, R), h)["CSF"] > target:
+                lo = mid
+            else:
+                hi = mid
+        out.append(workloads.dkt_body(0.5 * (lo + hi), R))
+    return out
+
+
 def run_dkt(steps=8000, every=25):
     """Drafting-kissing-tumbling of pairs of equal bodies with stepped
-    elongation (sec. 4): two-point metaballs a = 0..4 lu apart, scaled to the
-    volume of the sphere of radius 5 (D_e = 10 lu) with the volumes measured
-    by the shape-descriptor kernel, in a 160 x 160 x 240 walled box (the
+    elongation (sec. 4): two-point metaballs whose Corey shape factors match
+    the paper's particles P1-P8 (dkt_matched_shapes), scaled to the volume of
+    the sphere of radius 5 (D_e = 10 lu) with the volumes measured by the
+    shape-descriptor kernel (grid step 0.05 before scaling), in a 160 x 160 x 240 walled box (the
     paper's container scaled to D_e), density ratio 2800/976, tau 0.55,
     gravity 1e-4 (settling Reynolds number near 20), contact on.  Per shape:
     sphericity, d_n/d_s, CSF from the GPU kernel, and from the coupled run
@@ -409,15 +433,16 @@ def run_dkt(steps=8000, every=25):
     import paper_2209_10411_amd as mdl
     import workloads
 
-    shapes = workloads.dkt_shapes()
-    d0 = mdl.shape_descriptors(*shapes[0], 0.25)
+    h = 0.05
+    shapes = dkt_matched_shapes(h=h)
+    d0 = mdl.shape_descriptors(*shapes[0], h)
     out = []
     t0 = time.perf_counter()
-    for cp, k in shapes:
-        d = mdl.shape_descriptors(cp, k, 0.25)
+    for (cp, k), target in zip(shapes, workloads.DKT_CSF_TARGETS):
+        d = mdl.shape_descriptors(cp, k, h)
         sc = (d0["V"] / d["V"]) ** (1.0 / 3.0)
         cp, k = cp * sc, k * sc * sc
-        d = mdl.shape_descriptors(cp, k, 0.25)
+        d = mdl.shape_descriptors(cp, k, h * sc)
         cfg = workloads.dkt_pair(cp, k)
         g = float(-cfg.g_particle[2])
         H = float(cfg.nz)
@@ -444,7 +469,7 @@ def run_dkt(steps=8000, every=25):
                 break
         nc, _ = sim.contact_stats()
         sim.close()
-        out.append({"a": round(float(cp[1, 0]), 4), "Phi": round(d["Phi"], 4),
+        out.append({"paper_CSF": target, "a": round(float(cp[1, 0]), 4), "Phi": round(d["Phi"], 4),
                     "dn_over_ds": round(d["d_n"] / d["d_s"], 4), "CSF": round(d["CSF"], 4),
                     "d_n": round(d["d_n"], 3), "steps_run": done,
                     "closest_centroid_distance_over_De": round(dmin / d0["d_n"], 3),
@@ -455,8 +480,9 @@ def run_dkt(steps=8000, every=25):
                     "peak_angular_velocity_over_2pi_tr": [round(w / wr, 4) for w in wmax],
                     "t_peak_angular_velocity_over_tr": [round(t / tr, 4) for t in tw],
                     "contact_substeps": nc})
-    return {"workload": "DKT pairs of equal-volume two-point metaballs, 160x160x240 walls, D_e = 10 lu, "
-                        "density ratio 2.87, tau 0.55, g 1e-4, contact, IBB; [leading, trailing] per pair",
+    return {"workload": "DKT pairs of equal-volume two-point metaballs with the CSF of the paper's P1-P8, "
+                        "160x160x240 walls, D_e = 10 lu, density ratio 2.87, tau 0.55, g 1e-4, contact, IBB; "
+                        "[leading, trailing] per pair",
             "steps": steps, "seconds": round(time.perf_counter() - t0, 1), "shapes": out}
 
 

@@ -456,18 +456,24 @@ def mi_draws(E: int, N_I: int, n: int, seed: int = 63):
 
 
 # ------------------------------------------------ drafting-kissing-tumbling
+def dkt_body(a: float, R: float = 5.0):
+    """A body of elongation a: two equal control points at +-a along the body
+    x axis, weights summing to R^2 (a = 0: the sphere of radius R).  The set
+    C >= 1 is one body while the value at the midpoint, R^2 / a^2, is at
+    least 1 (a <= R)."""
+    return np.array([[-a, 0.0, 0.0], [a, 0.0, 0.0]]), np.array([0.5 * R * R, 0.5 * R * R])
+
+
+# Corey shape factors of the paper's designed particles P1-P8 (sec. 4, Table
+# T:MP_particles), which the DKT sweep's synthetic bodies are matched to.
+DKT_CSF_TARGETS = (1.0, 0.9563, 0.9173, 0.8535, 0.8002, 0.7521, 0.7075, 0.6648)
+
+
 def dkt_shapes(n_shapes: int = 6, R: float = 5.0, a_max: float = 4.0):
-    """Bodies of stepped elongation: two equal control points at +-a along
-    the body x axis, a = 0 (the sphere of radius R) to a_max, weights summing
-    to R^2 (the far field of a sphere of radius R).  Sizes are made equal in
-    volume by the caller from the measured volumes (exact shape scaling
-    p -> s p, k -> s^2 k)."""
-    out = []
-    for j in range(n_shapes):
-        a = a_max * j / max(n_shapes - 1, 1)
-        cp = np.array([[-a, 0.0, 0.0], [a, 0.0, 0.0]])
-        out.append((cp, np.array([0.5 * R * R, 0.5 * R * R])))
-    return out
+    """Bodies of stepped elongation a = 0 (the sphere of radius R) to a_max
+    (dkt_body).  Sizes are made equal in volume by the caller from the
+    measured volumes (exact shape scaling p -> s p, k -> s^2 k)."""
+    return [dkt_body(a_max * j / max(n_shapes - 1, 1), R) for j in range(n_shapes)]
 
 
 def dkt_pair(cp, k, D_e: float = 10.0, g: float = 1e-4, tau: float = 0.55) -> Config:
