@@ -75,3 +75,34 @@ def test_orientation():
     assert d2["S"] == pytest.approx(d1["S"], rel=5e-3)
     assert d2["Phi"] == pytest.approx(d1["Phi"], abs=5e-3)
     assert d2["CSF"] == pytest.approx(d1["CSF"], abs=0.03)
+
+
+def test_designed_particles_of_the_dkt_table():
+    """The paper's designed particles are made by moving control points
+    apart (sec. 4); a two-point body whose CSF is matched to P3 or P5 of Table
+    T:MP_particles (tests/golden/dkt_table.json) must then show the table's
+    sphericity and d_n/d_s as well.  The match is found by bisection on the
+    points' separation with this oracle (grid step 0.1, which leaves the CSF
+    itself within the grid's resolution of the target); a CSF with the
+    projected-area diameter as numerator, a projection on another plane, or
+    a wrong surface would move Phi or d_n/d_s by far more than 3e-3."""
+    import json
+    import os
+
+    import workloads
+
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "dkt_table.json")))["particles"]
+    for name in ("P3", "P5"):
+        phi, dnds, csf = tab[name]
+        lo, hi = 0.0, 4.9
+        for _ in range(9):
+            mid = 0.5 * (lo + hi)
+            if shape.descriptors(*workloads.dkt_body(mid), 0.1)["CSF"] > csf:
+                lo = mid
+            else:
+                hi = mid
+        d = shape.descriptors(*workloads.dkt_body(0.5 * (lo + hi)), 0.1)
+        print(name, d["CSF"], d["Phi"], d["d_n"] / d["d_s"])
+        assert abs(d["CSF"] - csf) < 0.01
+        assert abs(d["Phi"] - phi) < 3e-3
+        assert abs(d["d_n"] / d["d_s"] - dnds) < 3e-3
