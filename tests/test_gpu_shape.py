@@ -77,8 +77,8 @@ def test_designed_particles_of_the_dkt_table(mdl):
     """The kernel on two-point bodies whose CSF is bisected onto P2-P5 of the
     paper's Table T:MP_particles (tests/golden/dkt_table.json; grid step 0.05,
     as the DKT benchmark uses): the table's sphericity and d_n/d_s follow to
-    2e-3 (measured: Phi within 1.6e-3 for P2, whose printed value is rounded
-    to 1.0000, 7e-4 for P3-P5; d_n/d_s within 1.1e-3)."""
+    2e-3 (measured: Phi within 1.6e-3 for P2, printed as 1.0000, and 7e-4
+    for P3-P5; d_n/d_s within 1.1e-3)."""
     import json
     import os
 
