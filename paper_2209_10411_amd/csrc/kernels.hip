@@ -213,13 +213,24 @@ __device__ __forceinline__ bool metaball_ge1(const Params &p, const CPs &P, cons
 // n-term sum by n u more: rel = u (2.03 (|r|_1 + bp) + 9.5 + n), taken with
 // a factor 1.5.  The FP32 sum decides when it clears L by that bound plus
 // 1e-12 (the exact sum's own rounding); points within 1 of a control point
-// (|d|^2 < 1 in FP32), a body whose terms may take a periodic image
-// (img), and everything within the bound go to the FP64 forms.  Cf: the
-// FP32 sum when it decided, else metaball_fast's value.
+// (|d|^2 < 1 in FP32), points whose differences could reach half a periodic
+// box, and everything within the bound go to the FP64 forms.  Cf: the FP32
+// sum when it decided, else metaball_fast's value.
 __device__ __forceinline__ bool metaball_ge32(const Params &p, const CPs &P, const double x[3], double L,
                                               double &Cf) {
-    if (!P.img) {
-        const float rx = (float)(x[0] - P.anc[0]), ry = (float)(x[1] - P.anc[1]), rz = (float)(x[2] - P.anc[2]);
+    double r[3] = {x[0] - P.anc[0], x[1] - P.anc[1], x[2] - P.anc[2]};
+    bool ok = true;
+    if (P.img) {
+        // a body near a periodic face: the minimum image of x - X once; then
+        // d = r - (p - X) is the minimum image of x - p for every point as
+        // long as it stays below half the box on every periodic axis
+        min_image(p, r);
+        const double Lb[3] = {(double)p.nx, (double)p.ny, (double)p.nz};
+        for (int a = 0; a < 3; ++a)
+            if ((p.periodic >> a) & 1u) ok = ok && fabs(r[a]) + (double)P.bp < 0.5 * Lb[a] - 1.0;
+    }
+    if (ok) {
+        const float rx = (float)r[0], ry = (float)r[1], rz = (float)r[2];
         float C = 0.f, rmin = 1.f;
         for (int i0 = 0; i0 < P.n; i0 += 4) {
 #pragma unroll
@@ -268,11 +279,26 @@ __device__ __forceinline__ double group8_sum(double v) {
 // reciprocals.
 __device__ void metaball_ds8(const Params &p, const CPs &P, const double xf[3], const double e[3], double s,
                              double &C, double &dC) {
-    const double xs[3] = {xf[0] - s * e[0], xf[1] - s * e[1], xf[2] - s * e[2]};
+    double xs[3] = {xf[0] - s * e[0], xf[1] - s * e[1], xf[2] - s * e[2]};
+    bool img = P.img;
+    if (img) {
+        // the image of the point nearest the centroid, once: then x - p needs
+        // no image per point while it stays below half a periodic box
+        double r[3] = {xs[0] - P.anc[0], xs[1] - P.anc[1], xs[2] - P.anc[2]};
+        min_image(p, r);
+        const double Lb[3] = {(double)p.nx, (double)p.ny, (double)p.nz};
+        bool ok = true;
+        for (int a = 0; a < 3; ++a)
+            if ((p.periodic >> a) & 1u) ok = ok && fabs(r[a]) + (double)P.bp < 0.5 * Lb[a] - 1.0;
+        if (ok) {
+            for (int a = 0; a < 3; ++a) xs[a] = P.anc[a] + r[a];
+            img = false;
+        }
+    }
     double c = 0.0, g = 0.0;
     for (int i = threadIdx.x & 7; i < P.n; i += 8) {
         double d[3] = {xs[0] - P.x[i][0], xs[1] - P.x[i][1], xs[2] - P.x[i][2]};
-        if (P.img) min_image(p, d);
+        if (img) min_image(p, d);
         const double r2 = fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
         if (r2 == 0.0) {
             c = __builtin_inf();

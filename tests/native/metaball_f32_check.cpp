@@ -9,7 +9,8 @@
 // down to 1e-8), deep inside, near control points and far out, every decision
 // taken must equal the exact one (C in exact FP64 quotients, summed in
 // order), and at lattice points (what the flagging evaluates) at least 95 %
-// must be decided in FP32.  Prints the counts and exits 1 on any
+// must be decided in FP32.  The same in periodic boxes for bodies near a
+// face (the minimum image of x - X taken once, the exact sum's per point).  Prints the counts and exits 1 on any
 // disagreement.
 #include <cmath>
 #include <cstdio>
@@ -122,6 +123,83 @@ int main() {
             check(x);
         }
     }
+    // Periodic boxes: bodies near a face, points on either side of it.  The
+    // exact sum takes the minimum image of every x - p (floor(d / L + 0.5));
+    // the FP32 form takes the minimum image of x - X once and uses r - (p - X)
+    // where |r| + max |p - X|_1 < L/2 - 1 on every axis, else it leaves the
+    // decision to FP64.
+    long pdec = 0, pwrong = 0, pund = 0;
+    for (int body = 0; body < 3000; ++body) {
+        const int n = 1 + (int)(U(rng) * 20);
+        const int n4 = (n + 3) & ~3;
+        const double R = 4.0 + 10.0 * U(rng);
+        const double Lb = 48.0 + 208.0 * U(rng);
+        double cp[24][3], k[24], ksum = 0.0, X[3] = {0, 0, 0};
+        double base[3];
+        for (int a = 0; a < 3; ++a) base[a] = (U(rng) < 0.5 ? 0.3 * R * U(rng) : Lb - 0.3 * R * U(rng));
+        for (int i = 0; i < n; ++i) {
+            for (int a = 0; a < 3; ++a) cp[i][a] = base[a] + 0.8 * R * (U(rng) - 0.5);
+            k[i] = 20.0 + 40.0 * U(rng);
+            ksum += k[i];
+        }
+        for (int i = 0; i < n; ++i) k[i] *= R * R / ksum;
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) X[a] += cp[i][a] / n;
+        const double L = 1.0;
+        float f[24][4], bp = 0.f;
+        for (int i = 0; i < n4; ++i) {
+            const int s = i < n ? i : 0;
+            for (int a = 0; a < 3; ++a) f[i][a] = (float)(cp[s][a] - X[a]);
+            f[i][3] = i < n ? (float)k[i] : 0.f;
+            bp = std::fmax(bp, std::fabs(f[i][0]) + std::fabs(f[i][1]) + std::fabs(f[i][2]));
+        }
+        bp *= 1.f + 1e-6f;
+        auto mi = [&](double d) { return d - Lb * std::floor(d / Lb + 0.5); };
+        auto exact = [&](const double x[3]) -> double {
+            double C = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double d0 = mi(x[0] - cp[i][0]), d1 = mi(x[1] - cp[i][1]), d2 = mi(x[2] - cp[i][2]);
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                if (r2 == 0.0) return INFINITY;
+                C += k[i] / r2;
+            }
+            return C;
+        };
+        auto f32 = [&](const double x[3]) {
+            double r[3] = {mi(x[0] - X[0]), mi(x[1] - X[1]), mi(x[2] - X[2])};
+            for (int a = 0; a < 3; ++a)
+                if (!(std::fabs(r[a]) + (double)bp < 0.5 * Lb - 1.0)) return -1;
+            const float rx = (float)r[0], ry = (float)r[1], rz = (float)r[2];
+            float C = 0.f, rmin = 1.f;
+            for (int i = 0; i < n4; ++i) {
+                const float dx = rx - f[i][0], dy = ry - f[i][1], dz = rz - f[i][2];
+                const float r2 = std::fma(dx, dx, std::fma(dy, dy, dz * dz));
+                rmin = std::fmin(rmin, r2);
+                C = std::fma(f[i][3], rcp_hw(r2, rng), C);
+            }
+            if (!(rmin >= 1.f)) return -1;
+            const float ax = std::fabs(rx) + std::fabs(ry) + std::fabs(rz);
+            const double rel = 1.5 * 5.9604644775390625e-8 * (2.03 * ((double)ax + (double)bp) + 9.5 + n4);
+            const double Cd = (double)C;
+            if (Cd * (1.0 - rel) > L * (1.0 + 1e-12)) return 1;
+            if (Cd * (1.0 + rel) < L * (1.0 - 1e-12)) return 0;
+            return -1;
+        };
+        for (int j = 0; j < 300; ++j) {
+            double x[3];
+            for (int a = 0; a < 3; ++a) {
+                double v = X[a] + 3.0 * R * (U(rng) - 0.5);
+                v = v - Lb * std::floor(v / Lb);  // a point of the box
+                x[a] = U(rng) < 0.5 ? std::floor(v) : v;
+            }
+            const int d = f32(x);
+            if (d < 0) { ++pund; continue; }
+            ++pdec;
+            if (d != (exact(x) >= L ? 1 : 0)) ++pwrong;
+        }
+    }
+    std::printf("periodic: decided %ld, undecided %ld, %ld disagreements\n", pdec, pund, pwrong);
+    wrong += pwrong;
     std::printf("decided %ld, undecided %ld (to FP64), %ld disagreements; lattice points decided %ld of %ld\n",
                 decided, undecided, wrong, lattice_decided, lattice);
     return wrong == 0 && lattice_decided >= 0.95 * lattice ? 0 : 1;
