@@ -167,8 +167,8 @@ def run_pair(steps, warmup, reps=3):
         ach = alg / k_s / 1e9
         traffic = traffic_from_profile(PMC_PAIR_SUMMARY, f"{name}_hbm_bytes_per_launch")
         out[name] = {"mlups": round(N * steps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / steps, 5),
-                     "kernel": "k_bulk<f32>" if st == workloads.STORE_F32 else
-                     f"k_bulk_pair<{name}>",
+                     "kernel": (f"k_bulk_flat<{name}>" if cfg.nx % 64 else f"k_bulk<{name}>")
+                     if st == workloads.STORE_F32 else f"k_bulk_pair<{name}>",
                      "kernel_avg_ms": round(k_ms / max(k_n, 1), 5), "kernel_achieved_GBs": round(ach, 1),
                      "kernel_frac": round(ach / HBM_PEAK_GBS, 4),
                      "algorithmic_bytes_per_launch": int(alg),

@@ -2360,6 +2360,12 @@ static void launch_step_kernels_t(const StepArgs &a) {
                                   &a.cnt->err);
             return;
         }
+        if (p.nx % 64 != 0 && p.N < (1ll << 31)) {  // rows not a multiple of a wave: lattice order
+            hipExtLaunchKernelGGL(k_bulk_flat<S>, dim3(cdiv(cdiv(p.N, 64), BULK_WAVES)), dim3(64 * BULK_WAVES), lds,
+                                  a.stream, a.ev_start, a.ev_stop, 0, p, (const T *)A, B, (const uint8_t *)a.skip,
+                                  &a.cnt->err);
+            return;
+        }
         const int nseg = cdiv(p.nx, 64);
         const long long waves = (long long)nseg * p.ny * p.nz;
         if (fits)

@@ -231,6 +231,24 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_wide(Params p, const t
     if (bulk_update<S>(p, A, B, x, y, z, (int)n)) atomicOr(err, ERR_FLUID);
 }
 
+// Rows whose length is not a multiple of 64 (the row form would leave the
+// last wave of every row partly idle: a third of it for nx = 160): a wave
+// takes 64 consecutive nodes in lattice order, rows wrapping inside it, and
+// each lane finds its own row.  Offsets as in bulk_update (node index below
+// 2^31).
+template <int S>
+__global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_flat(Params p, const typename Store<S>::T *__restrict__ A,
+                                                               typename Store<S>::T *__restrict__ B,
+                                                               const uint8_t *__restrict__ skip,
+                                                               int *__restrict__ err) {
+    const uint32_t n = (blockIdx.x * (uint32_t)BULK_WAVES + (threadIdx.x >> 6)) * 64u + (threadIdx.x & 63);
+    if (n >= (uint32_t)p.N || skip[n]) return;
+    const uint32_t row = n / (uint32_t)p.nx;
+    const int x = (int)(n - row * (uint32_t)p.nx);
+    const int z = (int)(row / (uint32_t)p.ny), y = (int)row - z * p.ny;
+    if (bulk_update<S>(p, A, B, x, y, z, (int)n)) atomicOr(err, ERR_FLUID);
+}
+
 // 16-bit storage, nx even: a lane takes the node pair (n0, n0 + 1), n0 even,
 // and moves one 32-bit word per population (twice the bytes of a 16-bit
 // access per instruction); a wave covers 64 consecutive pairs in lattice
