@@ -560,7 +560,9 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(cfg, budget_s):
+def _oracle_rate(cfg, budget_s, min_steps=1):
+    """Coupled oracle steps of cfg for about budget_s seconds: (MLUPS, steps,
+    setup seconds)."""
     import oracle
 
     t0 = time.perf_counter()
@@ -568,14 +570,40 @@ def cpu_baseline(cfg, budget_s):
     t_init = time.perf_counter() - t0
     steps = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
+    while steps < min_steps or time.perf_counter() - t0 < budget_s:
         o.step(1)
         steps += 1
     dt = time.perf_counter() - t0
-    return {"value": round(cfg.n_nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
-            "kind": "oracle", "cpu": cpu_model(),
-            "sample": f"{steps} coupled steps of the same 128x128x384 settling case "
-                      f"(FP64, {oracle.threads()} OpenMP threads, {t_init:.1f} s setup excluded)"}
+    del o
+    return cfg.n_nodes * steps / dt / 1e6, steps, t_init
+
+
+def cpu_baseline(cfg, budget_s):
+    """The FP64 oracle on the host: the settling case on every thread (the
+    headline figure), the same case on one thread, and the 200-body
+    suspension on every thread, each a bounded number of coupled steps."""
+    import oracle
+
+    nt = oracle.threads()
+    v, steps, t_init = _oracle_rate(cfg, budget_s)
+    out = {"value": round(v, 3), "unit": "MLUPS", "cores": nt, "kind": "oracle", "cpu": cpu_model(),
+           "sample": f"{steps} coupled steps of the same 128x128x384 settling case "
+                     f"(FP64, {nt} OpenMP threads, {t_init:.1f} s setup excluded)"}
+    oracle.set_threads(1)
+    try:
+        v1, s1, _ = _oracle_rate(cfg, budget_s / 3)
+    finally:
+        oracle.set_threads(nt)
+    out["single_thread"] = {"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
+                            "sample": f"{s1} coupled step(s) of the same settling case on one thread"}
+    import workloads
+
+    c5 = workloads.config5(seed=5)
+    v5, s5, t5 = _oracle_rate(c5, budget_s / 2)
+    out["suspension_256"] = {"value": round(v5, 3), "unit": "MLUPS", "cores": nt,
+                             "sample": f"{s5} coupled step(s) of the 256^3 suspension of 200 bodies with contact "
+                                       f"(FP64, {nt} threads, {t5:.1f} s setup excluded)"}
+    return out
 
 
 def copy_ceiling(n_nodes: int, reps: int = 20):

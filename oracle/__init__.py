@@ -90,6 +90,8 @@ def lib():
         L.orc_n_contact_fail.restype = C.c_long
         L.orc_n_contact_fail.argtypes = [C.c_void_p]
         L.orc_threads.restype = C.c_int
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -110,6 +112,11 @@ def lattice():
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads of the oracle's loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def feq(rho: float, u) -> np.ndarray:

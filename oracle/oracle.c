@@ -1153,6 +1153,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* Sets the number of OpenMP threads the oracle's loops use (n >= 1). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* The lattice table, for tests that check it against the D3Q19 definition. */
 void orc_lattice(int32_t *e, double *w, int32_t *op) {
     for (int i = 0; i < Q; ++i) {
