@@ -254,16 +254,19 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_flat(Params p, const t
 // access per instruction); a wave covers 64 consecutive pairs in lattice
 // order, rows wrapping inside the wave, so no lane idles whatever nx.
 // Fast path (every lane of the wave in a row whose y and z neighbours are
-// inside the box, and not across a periodic seam): the source of node n0 in
-// array i is n0 + delta_i with a uniform delta_i = i Ns - e_y nx - e_z nx ny -
-// e_x, and the word there holds both pulled values of the pair (unaligned by
-// one node when e_x != 0; the hardware reads it whole).  Only at a row's ends
-// does one value come from elsewhere (x0 - 1 or x0 + 2 outside the row: the
-// periodic image in the same row, or the node's own opposite population at a
-// resting wall), by one 16-bit load per x-shifted population, issued by every
-// lane (at the word's own address where no fix is needed) so that all loads
-// stay unconditional.  Other waves: every source by its coordinates.  The
-// collision runs on the scaled stored values (collide<SCALED>).
+// inside the box, and not across a periodic seam): a lane loads, for every
+// population i, the aligned 32-bit word of its own pair (x0, x0 + 1) in the
+// source row, at the uniform offset i Ns - e_y nx - e_z nx ny.  An x-shifted
+// population takes one of its two values from the neighbouring lane's word
+// (lane - 1's high half for e_x = +1, lane + 1's low half for e_x = -1), moved
+// across the wave by DPP, so every load covers whole cache lines.  Where that
+// neighbour is not the right one (the first and last lanes of the wave, a
+// row's ends: the periodic image in the same row, or the node's own opposite
+// population at a resting wall) the value comes from one 16-bit load per
+// x-shifted population, issued by every lane (at the word's own address
+// where no fix is needed) so that all loads stay unconditional.  Other waves:
+// every source by its coordinates.  The collision runs on the scaled stored
+// values (collide<SCALED>).
 template <int S> __device__ __forceinline__ float raw16(uint32_t b) {  // low 16 bits -> stored value, unscaled
     if constexpr (S == 1) return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xffffu));
     else return __uint_as_float(b << 16);
@@ -276,7 +279,10 @@ template <int S> __device__ __forceinline__ uint32_t pack16(float a, float b) { 
     if constexpr (S == 1) return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
     else return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
-typedef uint32_t u32_a2 __attribute__((aligned(2)));
+// DPP controls (gfx9 family): every lane takes the value of lane - 1
+// (wave_shr:1) or lane + 1 (wave_shl:1); lanes without a source keep the
+// given old value.
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
 
 template <int S>
 __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const typename Store<S>::T *__restrict__ A,
@@ -305,25 +311,35 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const t
     if (__all(interior)) {
         const bool perx = p.periodic & 1u;
         const bool lo_edge = x0 == 0, hi_edge = x0 + 2 == nx;
+        // lanes whose x-shifted value lies outside the pair word of their
+        // neighbour lane: the row's ends, and the wave's first and last lanes
+        const bool lo_fix = lo_edge || lane == 0, hi_fix = hi_edge || lane == 63;
         uint32_t w[Q], fx[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            // uniform byte offset of node n0's source in array i
-            const long long db = 2ll * ((long long)i * Ns - EY[i] * nx - EZ[i] * (long long)nxy - EX[i]);
-            w[i] = *(const u32_a2 *)(Ab + db + n0b);
-            if (EX[i] > 0) {  // node 0 pulls x0 - 1: outside the row at its start
-                const long long fb = perx ? db + 2ll * nx : 2ll * OPP[i] * Ns;
-                fx[i] = *(const uint16_t *)(Ab + (lo_edge ? fb : db) + n0b);
-            } else if (EX[i] < 0) {  // node 1 pulls x0 + 2: outside the row at its end
-                const long long fb = perx ? db + 2 - 2ll * nx : 2ll * (OPP[i] * (long long)Ns + 1);
-                fx[i] = *(const uint16_t *)(Ab + (hi_edge ? fb : db + 2) + n0b);
+            // uniform byte offset of the source row's pair (x0, x0 + 1) in array i
+            const long long db = 2ll * ((long long)i * Ns - EY[i] * nx - EZ[i] * (long long)nxy);
+            w[i] = *(const uint32_t *)(Ab + db + n0b);
+            if (EX[i] > 0) {  // node 0 pulls x0 - 1
+                const long long fb = !lo_edge ? db - 2 : perx ? db + 2ll * (nx - 1) : 2ll * OPP[i] * Ns;
+                fx[i] = *(const uint16_t *)(Ab + (lo_fix ? fb : db) + n0b);
+            } else if (EX[i] < 0) {  // node 1 pulls x0 + 2
+                const long long fb = !hi_edge ? db + 4 : perx ? db + 4 - 2ll * nx : 2ll * (OPP[i] * (long long)Ns + 1);
+                fx[i] = *(const uint16_t *)(Ab + (hi_fix ? fb : db) + n0b);
             }
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             uint32_t b0 = w[i], b1 = w[i] >> 16;
-            if (EX[i] > 0) b0 = lo_edge ? fx[i] : b0;
-            else if (EX[i] < 0) b1 = hi_edge ? fx[i] : b1;
+            if (EX[i] > 0) {  // (x0 - 1, x0): the neighbour lane's high half, then the own low half
+                const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w[i], DPP_WAVE_SHR1, 0xf, 0xf, false);
+                b0 = lo_fix ? fx[i] : prev >> 16;
+                b1 = w[i];
+            } else if (EX[i] < 0) {  // (x0 + 1, x0 + 2): the own high half, then the neighbour lane's low half
+                const uint32_t next = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w[i], DPP_WAVE_SHL1, 0xf, 0xf, false);
+                b0 = w[i] >> 16;
+                b1 = hi_fix ? fx[i] : next;
+            }
             d0[i] = raw16<S>(b0);
             d1[i] = raw16<S>(b1);
         }
