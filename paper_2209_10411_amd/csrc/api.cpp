@@ -335,7 +335,7 @@ lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb,
     pl.off_ldo = take(4 * (size_t)std::max(pl.link_cap, 1));
     pl.off_lq = take(8 * (size_t)std::max(pl.link_cap, 1));
     // per-chunk, per-body partial momentum sums: chunk + body < cap/256 + 1 + np
-    pl.off_lpart = take(48 * ((size_t)pl.link_cap / 256 + 2 + np));
+    pl.off_lpart = take(48 * ((size_t)pl.link_cap / 64 + 2 + np));  // a slot per (64-link chunk, body)
     pl.off_special = take(4 * (size_t)std::max(pl.special_cap, 1));
     pl.contact = c->contact_kn > 0.0 && np > 0;
     const size_t npp = pl.contact ? (size_t)np * np : 1, npw = pl.contact ? (size_t)np * 6 : 1;

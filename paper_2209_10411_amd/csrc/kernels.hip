@@ -270,6 +270,16 @@ __device__ __forceinline__ double group8_sum(double v) {
     v += dpp_f64<DPP_XOR2>(v);
     return v + dpp_f64<DPP_HALF_MIRROR>(v);
 }
+// Sum over the 64 lanes of a wave, the same bits in every lane: group8_sum,
+// then the mirror lane of the other half-row (15 - lane), then lane ^ 16 and
+// lane ^ 32 (IEEE addition commutes, so both partners form the same sum).
+constexpr int DPP_ROW_MIRROR = 0x140;
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+    v = group8_sum(v);
+    v += dpp_f64<DPP_ROW_MIRROR>(v);
+    v += __shfl_xor(v, 16);
+    return v + __shfl_xor(v, 32);
+}
 
 // C and dC/ds at x_f - s e_i for one link held by an aligned group of eight
 // lanes: lane j sums control points j, j + 8, ... and the group adds its
@@ -465,8 +475,8 @@ __device__ __forceinline__ float collide_lane(float d, int i, float dr, float jx
 // interpolated rule with the moments of x_f and x_f + e_i in FP64 -- and
 // leaves it in B for the boundary-node pass, then the link's momentum
 // exchange  dP = (e_ib - u_w) f+_ib(x_f) - (e_i - u_w) f_i(x_f, t+1) with
-// both populations relative to w rho0, dT = (x_w - X) x dP.  Each chunk of 256 links sums its links per body
-// segment (fixed segmented tree) into part[chunk + body] (deterministic).
+// both populations relative to w rho0, dT = (x_w - X) x dP.  Each wave's chunk of 64 links sums its links per
+// body (a fixed butterfly) into part[chunk + body] (deterministic).
 // Block bid of nblk (a whole grid, or one system's range of a batched grid).
 template <int S>
 __device__ __forceinline__ void links_body(const Params &p, const typename Store<S>::T *__restrict__ A,
@@ -477,13 +487,11 @@ __device__ __forceinline__ void links_body(const Params &p, const typename Store
                                            const uint32_t *__restrict__ l_do,
                                            const double *__restrict__ l_q, double *__restrict__ part,
                                            Counters *__restrict__ cnt, const int bid, const int nblk) {
-    __shared__ double sv[6][256];
-    __shared__ int spid[256];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
     const int nl = cnt->n_links;
-    const int nchunk = (nl + 255) >> 8;
-    for (int ch = bid; ch < nchunk; ch += nblk) {
-        const int l = (ch << 8) + t;
+    const int nblock = (nl + 255) >> 8;  // 256 links per block and round, a chunk of 64 per wave
+    for (int cb = bid; cb < nblock; cb += nblk) {
+        const int l = (cb << 8) + t, ch = l >> 6;
         double dP[3] = {0, 0, 0}, dT[3] = {0, 0, 0};
         int pi = -1;
         bool ok = l < nl;
@@ -549,24 +557,26 @@ __device__ __forceinline__ void links_body(const Params &p, const typename Store
             dP[2] = (c_ez[ib] - uw[2]) * fbd - (c_ez[i] - uw[2]) * vald;
             cross3(r, dP, dT);
         }
-        double v6[6] = {dP[0], dP[1], dP[2], dT[0], dT[1], dT[2]};
-        for (int c = 0; c < 6; ++c) sv[c][t] = v6[c];
-        spid[t] = pi;
-        __syncthreads();
-        // inclusive segmented scan (segments = runs of one body, contiguous)
-        for (int h = 1; h < 256; h <<= 1) {
-            const bool take = t >= h && spid[t - h] == pi;
-            double add[6];
-            for (int c = 0; c < 6; ++c) add[c] = take ? sv[c][t - h] : 0.0;
-            __syncthreads();
-            for (int c = 0; c < 6; ++c) { v6[c] += add[c]; sv[c][t] = v6[c]; }
-            __syncthreads();
+        // the chunk's sum per body: links are listed body by body, so a wave
+        // holds one run per body it touches; each run is summed over the wave
+        // by a fixed butterfly (the same bits in every lane) and written by
+        // the run's first lane
+        const double v6[6] = {dP[0], dP[1], dP[2], dT[0], dT[1], dT[2]};
+        const int prev = __shfl_up(pi, 1);
+        unsigned long long heads = __ballot(pi >= 0 && (lane == 0 || prev != pi));
+        while (heads) {
+            const int h = __ffsll((long long)heads) - 1;
+            heads &= heads - 1;
+            const int b = __shfl(pi, h);
+            const bool in = pi == b;
+            double sum[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sum[c] = wave_sum_fixed(in ? v6[c] : 0.0);
+            if (lane == h) {
+                double *o = part + 6ll * (ch + b);
+                for (int c = 0; c < 6; ++c) o[c] = sum[c];
+            }
         }
-        if (pi >= 0 && (t == 255 || spid[t + 1] != pi)) {  // tail of a body segment
-            double *o = part + 6ll * (ch + pi);
-            for (int c = 0; c < 6; ++c) o[c] = v6[c];
-        }
-        __syncthreads();
     }
 }
 
@@ -645,8 +655,8 @@ __device__ void reduce_body(const Params &p, DevParticle *__restrict__ P, int pi
     const int t = threadIdx.x;
     double s[6] = {0, 0, 0, 0, 0, 0};
     const int a = max(0, l_off[pi]), b = min(l_off[pi + 1], p.link_cap);
-    if (b > a)  // chunks of 256 links holding this body's links; slot = chunk + body
-        for (int ch = (a >> 8) + t; ch <= ((b - 1) >> 8); ch += 256)
+    if (b > a)  // chunks of 64 links holding this body's links; slot = chunk + body
+        for (int ch = (a >> 6) + t; ch <= ((b - 1) >> 6); ch += 256)
             for (int c = 0; c < 6; ++c) s[c] += part[6ll * (ch + pi) + c];
     for (int c = 0; c < 6; ++c) red[c][t] = s[c];
     __syncthreads();
