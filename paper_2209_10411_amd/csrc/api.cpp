@@ -443,7 +443,11 @@ lbm_status estimate_lists(lbm_ctx *c) {
     // nodes), the stream-collide leaves it more of every CU: two blocks per
     // CU there gave 1.52 against 1.64 ms per step with six; with few links
     // (7.5 k for 6.3 M nodes) six blocks keep the stream-collide at full speed.
-    c->bulk_blocks = 50ll * h.n_links > (long long)c->p.N ? 2 : 0;
+    // The 16-bit form (84 VGPRs, two nodes per lane) does best with four:
+    // its step is the boundary chain's, which runs faster with the room
+    // (settling 128x128x384: 0.118 -> 0.112 ms; two bodies 160x160x640:
+    // 0.262 -> 0.252 ms), while the kernel itself loses 2-3 %.
+    c->bulk_blocks = 50ll * h.n_links > (long long)c->p.N ? 2 : c->p.storage != 0 ? 4 : 0;
     // boundary nodes carry several cut links each (the special list is empty
     // right after set-up, when no previous flags exist)
     c->p.est_special = std::min(c->p.special_cap,

@@ -511,30 +511,38 @@ __device__ __forceinline__ void links_body(const Params &p, const typename Store
             const int ib = c_opp[i];
             int x, y, z;
             node_xyz(p, n, x, y, z);
-            long long ff = -1;
-            const bool ibb = p.bc == 1 && nbr(p, x, y, z, c_ex[i], c_ey[i], c_ez[i], ff) && own[ff] == FLUID;
+            long long ff = n;  // the node itself beyond a wall (its loads then go unused)
+            const bool has_ff = nbr(p, x, y, z, c_ex[i], c_ey[i], c_ez[i], ff);
+            // every load of the link is issued before the first is used: the
+            // owner of x_f + e_i, the fraction, the body's motion, the population
+            // leaving along e_ib, and both nodes' moments (which only the
+            // interpolated rule uses)
+            const int32_t own_ff = own[ff];
+            const double ql = l_q[l];
             const DevParticle &Bd = P[pi];
-            const double q = ibb ? l_q[l] : 0.5;
+            const double fbl = (double)Store<S>::ld(A, (long long)ib * p.Ns + n, p.inv_scale);
+            double m0 = 0, m1 = 0, m2 = 0, m3 = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                const double d0 = (double)Store<S>::ld(A, (long long)j * p.Ns + n, p.inv_scale);
+                const double d1 = (double)Store<S>::ld(A, (long long)j * p.Ns + ff, p.inv_scale);
+                m0 += d0; m1 += EX[j] * d0; m2 += EY[j] * d0; m3 += EZ[j] * d0;
+                k0 += d1; k1 += EX[j] * d1; k2 += EY[j] * d1; k3 += EZ[j] * d1;
+            }
+            const bool ibb = p.bc == 1 && has_ff && own_ff == FLUID;
+            const double q = ibb ? ql : 0.5;
             double r[3] = {x - q * c_ex[i] - Bd.X[0], y - q * c_ey[i] - Bd.X[1], z - q * c_ez[i] - Bd.X[2]};
             min_image(p, r);
             double uw[3];
             cross3(Bd.w, r, uw);
             for (int a = 0; a < 3; ++a) uw[a] += Bd.v[a];
             const double w = c_wd[i];
-            const double fb = w * p.rho0 + (double)Store<S>::ld(A, (long long)ib * p.Ns + n, p.inv_scale);
+            const double fb = w * p.rho0 + fbl;
             const double mw = 6.0 * w * p.rho0 * (c_ex[i] * uw[0] + c_ey[i] * uw[1] + c_ez[i] * uw[2]);
             double val;
             if (!ibb) {
                 val = fb + mw;
             } else {
-                double m0 = 0, m1 = 0, m2 = 0, m3 = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0;
-#pragma unroll
-                for (int j = 0; j < Q; ++j) {
-                    const double d0 = (double)Store<S>::ld(A, (long long)j * p.Ns + n, p.inv_scale);
-                    const double d1 = (double)Store<S>::ld(A, (long long)j * p.Ns + ff, p.inv_scale);
-                    m0 += d0; m1 += EX[j] * d0; m2 += EY[j] * d0; m3 += EZ[j] * d0;
-                    k0 += d1; k1 += EX[j] * d1; k2 += EY[j] * d1; k3 += EZ[j] * d1;
-                }
                 const double rf = p.rho0 + m0, rff = p.rho0 + k0;
                 const double uf[3] = {m1 / rf - 0.5 * p.gfd[0], m2 / rf - 0.5 * p.gfd[1], m3 / rf - 0.5 * p.gfd[2]};
                 const double uff[3] = {k1 / rff - 0.5 * p.gfd[0], k2 / rff - 0.5 * p.gfd[1], k3 / rff - 0.5 * p.gfd[2]};
@@ -1583,22 +1591,23 @@ __device__ void special_update(const Params &p, const typename Store<S>::T *__re
     // the rest population's source is the node itself: solid before for an
     // uncovered node
     if (unc) solid |= 1u;
+    using T = typename Store<S>::T;
     float d[Q];
     uint32_t missing = 0u;
+    // every population's load is issued whatever its case, its address
+    // chosen by selects (the resting wall's own opposite population, the
+    // bounce-back value in B, the pulled value), so that all 19 are in
+    // flight together; a missing one's value is dropped
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        d[i] = 0.f;
-        if ((wall >> i) & 1u) {
-            if (unc) missing |= 1u << i;
-            else d[i] = Store<S>::ld(A, (long long)OPP[i] * p.Ns + n, p.inv_scale);
-        } else if ((solid >> i) & 1u) {
-            if (unc) missing |= 1u << i;
-            else d[i] = Store<S>::ld(B, (long long)i * p.Ns + n, p.inv_scale);
-        } else {
-            long long src;
-            nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], src);
-            d[i] = Store<S>::ld(A, (long long)i * p.Ns + src, p.inv_scale);
-        }
+        const bool w = (wall >> i) & 1u, sd = (solid >> i) & 1u;
+        if (unc && (w || sd)) missing |= 1u << i;
+        long long src = n;  // kept beyond a wall
+        nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], src);
+        const T *base = w ? A + (long long)OPP[i] * p.Ns
+                          : sd ? (const T *)B + (long long)i * p.Ns : A + (long long)i * p.Ns;
+        const float v = Store<S>::ld(base, (w || sd) ? n : src, p.inv_scale);
+        d[i] = (unc && (w || sd)) ? 0.f : v;
     }
     if (missing) {
         const DevParticle &Bd = P[owner];
@@ -1676,17 +1685,31 @@ __device__ __forceinline__ void classify_body(const Params &p, const RegionMap &
         tile_local(rm.first[bid], dx, dy, 0, bx, by, bz);
         const DevParticle &Bp = P[bp];
         const int L[3] = {p.nx, p.ny, p.nz};
-        for (int h = threadIdx.x; h < HN; h += BLK) {
+        // all of a thread's halo loads are issued before the first is
+        // written to LDS (one memory round trip, not one per slot)
+        constexpr int HR = (HN + BLK - 1) / BLK;
+        int32_t vo[HR], vn[HR];
+#pragma unroll
+        for (int r = 0; r < HR; ++r) {
+            const int h = threadIdx.x + r * BLK;
             int c[3] = {Bp.lo[0] + bx - 1 + h % HX, Bp.lo[1] + by - 1 + (h / HX) % HY, Bp.lo[2] + bz - 1 + h / (HX * HY)};
-            bool ok = true;
+            bool ok = h < HN;
             for (int a = 0; a < 3; ++a)
                 if (c[a] < 0 || c[a] >= L[a]) {
                     if ((p.periodic >> a) & 1u) c[a] = ((c[a] % L[a]) + L[a]) % L[a];
                     else ok = false;
                 }
             const long long g = ok ? (long long)c[0] + (long long)p.nx * ((long long)c[1] + (long long)p.ny * c[2]) : 0;
-            h_old[h] = ok ? own_old[g] : OUTSIDE;
-            h_new[h] = ok ? own_new[g] : OUTSIDE;
+            vo[r] = ok ? own_old[g] : OUTSIDE;
+            vn[r] = ok ? own_new[g] : OUTSIDE;
+        }
+#pragma unroll
+        for (int r = 0; r < HR; ++r) {
+            const int h = threadIdx.x + r * BLK;
+            if (h < HN) {
+                h_old[h] = vo[r];
+                h_new[h] = vn[r];
+            }
         }
     }
     __syncthreads();
