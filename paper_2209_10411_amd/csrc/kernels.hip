@@ -1269,8 +1269,12 @@ __device__ __forceinline__ void rigid_case(const Params &p, DevParticle *__restr
     const double dt = 1.0 / p.n_sub;
     for (int s = 0; s < p.n_sub; ++s) {
         if (p.contact) {
-            for (int q = t; q < np * np; q += 256) contact_pair(p, P, cb, cnt, q, dt, false);
-            for (int q = t; q < np * 6; q += 256) contact_wall(p, P, cb, cnt, q, dt);
+            // eight lanes per pair (aligned groups, all active: the branch is
+            // group-uniform), then one thread per face
+            for (int u = t; u < 8 * np * np + 6 * np; u += 256) {
+                if (u < 8 * np * np) contact_pair<true>(p, P, cb, cnt, u >> 3, dt, false);
+                else contact_wall(p, P, cb, cnt, u - 8 * np * np, dt);
+            }
             __syncthreads();
         }
         for (int q = t; q < np; q += 256) contact_body(p, P[q], q, cb, dt);
