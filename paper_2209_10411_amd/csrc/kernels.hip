@@ -2058,13 +2058,12 @@ __global__ __launch_bounds__(BLK) void k_link_emit_tiles(Params p, RegionMap rm,
 }
 
 // Link build, third pass: the link fractions of the whole list, eight lanes
-// per link (32 links per block, blocks stride over the list), each group
-// with its body's control points staged in its own LDS slot.  With WARM the
-// group first evaluates the warm-start MLP for its link (FP16 weights staged
-// in LDS once per block, FP16 activations, FP32 sums; lane j computes hidden
-// units 8j..8j+7) and starts the Newton iteration at its q guess; a
-// warm-started iteration that has not converged in NR_WARM_MAX evaluations
-// is replaced by the plain one.  Per block: iteration histogram and largest
+// per link (32 links per block, blocks stride over the list), each wave
+// staging one body's control points at a time in its LDS slot (a small slot
+// per wave leaves room for several blocks per CU beside the stream-collide).
+// With WARM the Newton iteration starts at the network's guess that the first
+// pass (k_link_guess) left in l_q; a warm-started iteration that has not
+// converged in NR_WARM_MAX evaluations is replaced by the plain one.  Per block: iteration histogram and largest
 // final |C - 1|, added to the statistics.
 constexpr int NR_WARM_MAX = 30, NR_MAX = 100;
 // Warm start, first pass: the network's q for every link of the list, written
@@ -2143,19 +2142,19 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
                                             const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
                                             Counters *cnt, const NrStats &nrs, const _Float16 *__restrict__ wts,
                                             const int bid, const int nblk) {
-    __shared__ CPs cps[32];
+    __shared__ CPs cps[4];  // one per wave
     __shared__ int sh[256];
     __shared__ unsigned hist[NR_HIST];
     __shared__ unsigned rmax;
-    const int t = threadIdx.x, g = t >> 3, j = t & 7;
+    const int t = threadIdx.x, g = t >> 3, j = t & 7, w = t >> 6;
     const bool warm = WARM && wts != nullptr;  // block-uniform
     for (int b = t; b < NR_HIST; b += 256) hist[b] = 0u;
     if (t == 0) rmax = 0u;
     __syncthreads();
-    // From here each wave runs its own eight groups through the rounds: a
-    // group's slot cps[g] is written and read only by the lanes of its wave,
-    // so the rounds need no block barrier (a wave does not wait for the
-    // slowest link of the other three).
+    // From here each wave runs its own eight groups through the rounds: the
+    // wave's slot cps[w] is written and read only by its own lanes, so the
+    // rounds need no block barrier (a wave does not wait for the slowest
+    // link of the other three).
     const int nl = min(cnt->n_links, p.link_cap);
     int it_sum = 0, links = 0;
     // the next round's link record is loaded while this round solves
@@ -2184,52 +2183,61 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
         }
         const bool ok = ok0 && n < p.N && pid < p.np && i >= 1 && i < Q;
         int x = 0, y = 0, z = 0;
-        if (ok) {  // stage this group's control points (padded to a multiple of 4, weight 0)
-            const DevParticle &B = P[pid];
+        if (ok) node_xyz(p, n, x, y, z);
+        double guess = -1.0;
+        if (warm && ok) guess = l_q[l];  // the first pass's network output
+        // The wave's links come body by body from the list, so its eight
+        // groups nearly always share one body: the wave stages one body's
+        // points at a time into its slot (lane k point k, padded to a
+        // multiple of 4 with weight 0) and the groups of that body solve;
+        // a wave across a body boundary takes a second turn.
+        bool pending = ok;
+        for (;;) {  // wave-uniform
+            const unsigned long long pm = __ballot(pending);
+            if (!pm) break;
+            const int bpid = __shfl(pid, __ffsll((long long)pm) - 1);
+            const DevParticle &B = P[bpid];
             const int n4 = (B.n_cp + 3) & ~3;
             // sphero-metaball level: the inner body (scaled by s about the
             // centroid, weights s^2 k) at the level c_0 = s^2
             const bool inner = p.link_c0 && p.c_rs > 0.0;
             const double sc = inner ? 1.0 - p.c_rs * B.rsk : 1.0;
+            const int k = t & 63;
             float bmax = 0.f;
-            for (int k = j; k < n4; k += 8) {
+            if (k < n4) {
                 const int src = k < B.n_cp ? k : 0;
                 double xk[3];
                 for (int a = 0; a < 3; ++a) xk[a] = inner ? B.X[a] + sc * (B.cpl[src][a] - B.X[a]) : B.cpl[src][a];
-                bmax = fmaxf(bmax, stage_cp(cps[g], k, xk, k < B.n_cp ? (inner ? sc * sc * B.k[k] : B.k[k]) : 0.0,
-                                            B.X));
+                bmax = stage_cp(cps[w], k, xk, k < B.n_cp ? (inner ? sc * sc * B.k[k] : B.k[k]) : 0.0, B.X);
             }
-#pragma unroll
-            for (int o = 1; o < 8; o <<= 1) bmax = fmaxf(bmax, __shfl_xor(bmax, o));  // the group's 8 lanes
-            if (j == 0) {
-                cps[g].anc[0] = B.X[0]; cps[g].anc[1] = B.X[1]; cps[g].anc[2] = B.X[2];
-                cps[g].n = n4;
-                cps[g].img = B.img;
-                cps[g].level = sc * sc;
-                cps[g].bp = bmax * (1.f + 1e-6f);
+            bmax = wave_fmax(bmax);
+            if (k == 0) {
+                cps[w].anc[0] = B.X[0]; cps[w].anc[1] = B.X[1]; cps[w].anc[2] = B.X[2];
+                cps[w].n = n4;
+                cps[w].img = B.img;
+                cps[w].level = sc * sc;
+                cps[w].bp = bmax * (1.f + 1e-6f);
             }
-            node_xyz(p, n, x, y, z);
+            wave_sync();  // the slot is staged
+            if (pending && pid == bpid) {  // group-uniform
+                pending = false;
+                double q, resid;
+                bool conv;
+                int its = link_fraction8(p, cps[w], x, y, z, i, guess, warm ? NR_WARM_MAX : NR_MAX, q, resid,
+                                         conv);
+                if (warm && !conv) {
+                    its += link_fraction8(p, cps[w], x, y, z, i, -1.0, NR_MAX, q, resid, conv);
+                }
+                if (j == 0) {
+                    l_q[l] = q;
+                    it_sum += its;
+                    ++links;
+                    atomicAdd(&hist[min(its, NR_HIST - 1)], 1u);
+                    atomicMax(&rmax, __float_as_uint((float)fabs(resid)));
+                }
+            }
+            wave_sync();  // the slot is restaged next
         }
-        double guess = -1.0;
-        if (warm && ok) guess = l_q[l];  // the first pass's network output
-        wave_sync();  // the group's slot is staged
-        if (ok) {
-            double q, resid;
-            bool conv;
-            int its = link_fraction8(p, cps[g], x, y, z, i, guess, warm ? NR_WARM_MAX : NR_MAX, q, resid,
-                                     conv);
-            if (warm && !conv) {
-                its += link_fraction8(p, cps[g], x, y, z, i, -1.0, NR_MAX, q, resid, conv);
-            }
-            if (j == 0) {
-                l_q[l] = q;
-                it_sum += its;
-                ++links;
-                atomicAdd(&hist[min(its, NR_HIST - 1)], 1u);
-                atomicMax(&rmax, __float_as_uint((float)fabs(resid)));
-            }
-        }
-        wave_sync();  // the group's slot is restaged in the next round
     }
     __syncthreads();
     const int its = block_sum(it_sum, sh);
@@ -2246,7 +2254,7 @@ __device__ __forceinline__ void link_q_body(const Params &p, const DevParticle *
 }
 
 template <bool WARM>
-__global__ __launch_bounds__(256) void k_link_q(Params p, const DevParticle *__restrict__ P,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_link_q(Params p, const DevParticle *__restrict__ P,
                                                 const uint32_t *__restrict__ l_node,
                                                 const uint32_t *__restrict__ l_do, double *__restrict__ l_q,
                                                 Counters *cnt, NrStats nrs, const _Float16 *__restrict__ wts) {
