@@ -101,6 +101,28 @@ def test_flags_links_q_random_body(mdl, seed):
     assert np.quantile(dq, 0.99) < 1e-12 and dq.max() < 1e-6
 
 
+@pytest.mark.parametrize("case", ["six_periodic", "forty"])
+def test_flags_links_q_many_bodies(mdl, case):
+    """Many bodies at their initial poses (the same on both sides): flags, the
+    body-major link list and every link fraction against the oracle.  The
+    solver stages one body's control points per wave at a time, so a wave
+    whose eight links span two bodies takes a turn per body; the lists here
+    hold such waves at most body boundaries."""
+    if case == "six_periodic":
+        cfg = workloads.suspension_small()
+    else:
+        cfg = workloads.suspension_small(n_bodies=40, box=64, seed=52)
+    sim = mdl.Simulation(cfg)
+    ref = oracle.Oracle(cfg)
+    assert np.array_equal(sim.owner(), ref.owner())
+    dq = compare_links(sim, ref)
+    _, _, og, _ = sim.links()  # list order: eight consecutive links per wave of the solver
+    spans = sum(1 for w in range(0, len(og), 8) if len(set(og[w:w + 8].tolist())) > 1)
+    print(f"{case}: {len(og)} links, {spans} waves across a body boundary, max |dq| {dq.max():.1e}", flush=True)
+    assert spans >= 3
+    assert np.quantile(dq, 0.99) < 1e-12 and dq.max() < 1e-6
+
+
 @pytest.mark.parametrize("bc", [workloads.BC_SBB, workloads.BC_IBB])
 def test_config1_200_steps(mdl, bc):
     """64^3 periodic, fixed sphere k = 64, body force 1e-6, 200 steps;
