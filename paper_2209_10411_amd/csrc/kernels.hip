@@ -1961,6 +1961,12 @@ __device__ __forceinline__ void emit_body(const Params &p, const RegionMap &rm, 
     // nor does a tile without links when the dead flags were cleared by the
     // classification (clear == NULL)
     if (!clear && blk_cnt[bid] == 0 && part_first_blk[pid] != bid && bid != nblk - 1) return;
+    // the tile's own mask is loaded together with the counts before it (one
+    // memory round trip for both)
+    int pi, x, y, z;
+    long long n;
+    const bool in = region_node(p, rm, P, bid, rad, pi, x, y, z, n);
+    const uint32_t m = in ? lmask[bid * BLK + t] : 0u;
     int before = 0;
     for (int q = t; q < pid; q += BLK) before += body_stats[4 * q];
     for (int b = part_first_blk[pid] + t; b < bid; b += BLK) before += blk_cnt[b];
@@ -1975,10 +1981,6 @@ __device__ __forceinline__ void emit_body(const Params &p, const RegionMap &rm, 
             l_off[p.np] = min(total, p.link_cap);
         }
     }
-    int pi, x, y, z;
-    long long n;
-    const bool in = region_node(p, rm, P, bid, rad, pi, x, y, z, n);
-    const uint32_t m = in ? lmask[bid * BLK + t] : 0u;
     if (in && clear) clear[n] = FLUID;
     // exclusive prefix of the link counts over the block: inclusive scan
     // within the wave, plus the totals of the earlier waves
@@ -2050,7 +2052,10 @@ __global__ __launch_bounds__(BLK) void k_link_emit_tiles(Params p, RegionMap rm,
                                                          uint32_t *__restrict__ l_do, Counters *cnt) {
     const int nblk = p.region_blocks;
     visit_tiles(
-        nblk, [&](int b) { return blk_cnt[b] > 0 || part_first_blk[rm.part[b]] == b || b == nblk - 1; },
+        nblk,
+        [&](int b) {  // a body's tiles are consecutive: its first tile follows another body's
+            return blk_cnt[b] > 0 || b == 0 || rm.part[b - 1] != rm.part[b] || b == nblk - 1;
+        },
         [&](int b) {
             emit_body(p, rm, P, lmask, blk_cnt, body_stats, part_first_blk, l_off, l_node, l_do, cnt, nullptr, b,
                       nblk);
