@@ -45,3 +45,23 @@ def test_traffic_follows_the_kernel_source(monkeypatch):
     assert t is not None and 9.0e8 < t < 1.1e9  # ~961.6e6 algorithmic bytes per launch
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0" * 16)  # the kernel changed since
     assert bench.traffic_from_profile() is None
+
+
+def test_oracle_rate_runs_a_bounded_sample_on_the_requested_threads():
+    """The CPU baseline's sampler: at least the minimum number of coupled
+    oracle steps, a positive rate, and the oracle's thread count set back."""
+    import oracle
+    import workloads
+
+    cfg = workloads.small_settling(n=16, nz=24, R=3.0)
+    nt = oracle.threads()
+    v, steps, t_init = bench._oracle_rate(cfg, 0.0, min_steps=2)
+    assert steps == 2 and v > 0.0 and t_init >= 0.0
+    oracle.set_threads(1)
+    try:
+        assert oracle.threads() == 1
+        v1, s1, _ = bench._oracle_rate(cfg, 0.0, min_steps=1)
+        assert s1 == 1 and v1 > 0.0
+    finally:
+        oracle.set_threads(nt)
+    assert oracle.threads() == nt
