@@ -200,12 +200,14 @@ lbm_status lbm_set_particles(lbm_ctx *ctx, const lbm_particle_state *in /* [n_p]
 lbm_status lbm_get_gfluid(lbm_ctx *ctx, double *g3);
 
 /* ---- measurement ---- */
-/* When enabled, the stream-collide kernel of every step (up to 4096 steps
- * between reads) is bracketed by HIP events on the context's stream;
- * lbm_timing_read returns the summed elapsed milliseconds and the launch
- * count since the last read, and the number of nodes that kernel updated in
- * the last step (all nodes but solid, boundary and uncovered ones); it
- * synchronises. */
+/* on > 0: the stream-collide kernel of every on-th step (the step count
+ * since lbm_init a multiple of on; up to 4096 timed launches between reads)
+ * is bracketed by HIP events on the context's stream (events on a launch add
+ * a few microseconds to its step, so a stride above 1 keeps the steps
+ * between timed ones free of them); on <= 0: off.  lbm_timing_read returns
+ * the summed elapsed milliseconds and the count of timed launches since the
+ * last read, and the number of nodes that kernel updated in the last step
+ * (all nodes but solid, boundary and uncovered ones); it synchronises. */
 lbm_status lbm_timing_enable(lbm_ctx *ctx, int32_t on);
 lbm_status lbm_timing_read(lbm_ctx *ctx, double *ms, int64_t *launches, int64_t *nodes_per_launch);
 /* Link fractions solved and Newton/bisection iterations spent on them since

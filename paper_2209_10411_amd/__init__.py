@@ -389,8 +389,9 @@ class Simulation:
         self._warm = mlp
         _check(lib().lbm_set_warmstart(self._ctx, C.c_void_p(mlp.blob.data_ptr()) if mlp is not None else None))
 
-    def timing(self, on: bool = True):
-        _check(lib().lbm_timing_enable(self._ctx, int(bool(on))))
+    def timing(self, on: bool = True, every: int = 1):
+        """Time the stream-collide of every `every`-th step with HIP events."""
+        _check(lib().lbm_timing_enable(self._ctx, max(1, int(every)) if on else 0))
 
     def timing_read(self):
         ms, n, nodes = C.c_double(0), C.c_int64(0), C.c_int64(0)

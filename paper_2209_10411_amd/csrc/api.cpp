@@ -385,6 +385,7 @@ struct lbm_ctx {
     hipEvent_t ev_main, ev_flags, ev_links, ev_bulk;
     bool pending_refill;
     bool timing;
+    int timing_every;  // time the stream-collide of every timing_every-th step
     int bulk_blocks;  // stream-collide blocks per CU (0: the default cap), from the link count
     std::vector<hipEvent_t> ev;  // start/stop pairs
     size_t ev_used;
@@ -668,6 +669,7 @@ lbm_status lbm_init(const lbm_config *cfg, int32_t n_p, const lbm_particle *part
     c->aux = nullptr;
     c->ev_main = c->ev_flags = c->ev_links = c->ev_bulk = nullptr;
     c->timing = false;
+    c->timing_every = 1;
     c->bulk_blocks = 0;
     c->ev_used = 0;
     c->timed_launches = 0;
@@ -857,7 +859,7 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n_steps, int32_t mode) {
             b.phase = PHASE_LINKBUILD;
             launch_phase(b);
         }
-        const bool t = c->timing && c->ev_used + 2 <= c->ev.size();
+        const bool t = c->timing && c->steps % c->timing_every == 0 && c->ev_used + 2 <= c->ev.size();
         a.phase = PHASE_BULK;
         a.ev_start = t ? c->ev[c->ev_used] : nullptr;
         a.ev_stop = t ? c->ev[c->ev_used + 1] : c->ev_bulk;
@@ -1075,7 +1077,8 @@ lbm_status lbm_timing_enable(lbm_ctx *c, int32_t on) {
         c->ev.resize(2 * 4096);
         for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
     }
-    c->timing = on != 0;
+    c->timing = on > 0;
+    c->timing_every = on > 1 ? on : 1;
     return LBM_OK;
 }
 
