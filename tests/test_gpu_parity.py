@@ -563,3 +563,22 @@ def test_sphero_metaball_link_level(mdl):
         dq = compare_links(sim, ref)
         assert np.median(dq) < 1e-7 and dq.max() < 1e-4
         assert np.abs(sim.particles()[0]["x"] - ref.particle(0)["x"]).max() < 1e-6
+
+
+def test_kernel_timing_every_nth_step(mdl):
+    """lbm_timing_enable's stride: with every = 4, ten of forty steps have
+    their stream-collide timed; with 1 every step; with timing off none."""
+    cfg = workloads.small_settling()
+    sim = mdl.Simulation(cfg)
+    sim.timing(True, every=4)
+    sim.timing_read()
+    sim.step(40)
+    ms, n, nodes = sim.timing_read()
+    assert n == 10 and ms > 0.0 and 0 < nodes <= cfg.n_nodes
+    sim.timing(True)
+    sim.step(6)
+    assert sim.timing_read()[1] == 6
+    sim.timing(False)
+    sim.step(3)
+    assert sim.timing_read()[1] == 0
+    sim.close()
