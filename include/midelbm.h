@@ -242,15 +242,18 @@ lbm_status lbm_save(lbm_ctx *ctx, const char *path);
 lbm_status lbm_load(lbm_ctx *ctx, const char *path);
 
 /* ---- measurement aid: streaming-copy ceiling ----
- * Times a plain copy with the stream-collide's access shape: 19 arrays of n
- * elements (elem_bytes 4 or 2) at a stride of `stride` elements in dev_src are
- * read and written to dev_dst with non-temporal stores, one element per lane
- * per array.  One warm-up launch, then reps launches bracketed by HIP events
- * on hip_stream; *ms receives the mean duration of one launch, which moves
+ * Times a plain copy with the stream-collide's access shape: the 19
+ * populations of n nodes (elem_bytes 4 or 2) in the library's population
+ * layout (runs of 1024 nodes, each run holding its 19 populations one after
+ * another; stride = the padded node count, a multiple of 1024) are read from
+ * dev_src and written to dev_dst with non-temporal stores, one node per lane.
+ * One warm-up launch, then reps launches bracketed by HIP events on
+ * hip_stream; *ms receives the mean duration of one launch, which moves
  * 2 * 19 * n * elem_bytes bytes.  Both buffers are caller-owned device memory
  * of at least 19 * stride elements (dev_dst is overwritten).  Synchronises.
- * Errors: LBM_E_INVALID (NULL pointer, n <= 0, stride < n, reps < 1, other
- * element size), LBM_E_HIP.  lbm_last_error() is not set by this call. */
+ * Errors: LBM_E_INVALID (NULL pointer, n <= 0, stride < n or not a multiple
+ * of 1024, reps < 1, other element size), LBM_E_HIP.  lbm_last_error() is not
+ * set by this call. */
 lbm_status lbm_copy_probe(const void *dev_src, void *dev_dst, int64_t n, int64_t stride, int32_t elem_bytes,
                           int32_t reps, void *hip_stream, double *ms);
 

@@ -554,7 +554,7 @@ def copy_probe(n: int, elem_bytes: int = 4, reps: int = 20, device: str = "cuda:
     ``device``; buffers are allocated here and freed on return."""
     import torch
 
-    stride = (n + 127) // 128 * 128
+    stride = (n + 1023) // 1024 * 1024  # the population layout's padded node count
     dev = torch.device(device)
     src = torch.zeros(19 * stride * elem_bytes, dtype=torch.uint8, device=dev)
     dst = torch.empty_like(src)

@@ -174,7 +174,7 @@ bool finite_all(const double *v, int n) {
 // configuration; lbm_arena_bytes and lbm_init share this plan.
 struct Plan {
     long long N;
-    long long Ns;  // population array stride (N rounded up to 128)
+    long long Ns;  // N rounded up to POP_RUN (the population buffer holds Q * Ns elements)
     int np;
     int storage_bytes;
     int region_blocks;
@@ -260,7 +260,7 @@ double bounding_radius(int n_cp, const double *cp, const double *k, const double
 lbm_status make_plan(const lbm_config *c, int np, const std::vector<double> &rb, const std::vector<double> &re,
                      Plan &pl) {
     pl.N = (long long)c->nx * c->ny * c->nz;
-    pl.Ns = (pl.N + 127) / 128 * 128;
+    pl.Ns = (pl.N + POP_RUN - 1) / POP_RUN * POP_RUN;
     pl.np = np;
     pl.storage_bytes = c->storage == 0 ? 4 : 2;
     pl.dims.assign(3 * np, 0);
@@ -911,7 +911,7 @@ static lbm_status read_state(lbm_ctx *c, double *host) {
     HIPCHK(hipMemcpy(raw.data(), c->A, raw.size(), hipMemcpyDeviceToHost));
     for (int i = 0; i < Q; ++i)
         for (long long n = 0; n < N; ++n) {
-            const size_t k = (size_t)i * Ns + n;  // device layout: stride Ns
+            const size_t k = (size_t)pidx(n, i);  // device layout (pidx)
             double d;
             if (sb == 4) {
                 d = ((const float *)raw.data())[k];
@@ -943,7 +943,7 @@ lbm_status lbm_set_populations(lbm_ctx *c, const double *f, int32_t post_collisi
     std::vector<char> raw((size_t)Q * Ns * c->pl.storage_bytes, 0);
     for (int i = 0; i < Q; ++i)
         for (long long n = 0; n < N; ++n) {
-            const size_t k = (size_t)i * Ns + n;  // device layout: stride Ns
+            const size_t k = (size_t)pidx(n, i);  // device layout (pidx)
             const double d = f[(size_t)i * N + n] - WD[i] * c->p.rho0;
             if (c->pl.storage_bytes == 4) {
                 ((float *)raw.data())[k] = (float)d;

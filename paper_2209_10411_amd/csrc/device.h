@@ -18,6 +18,21 @@ constexpr int TILE_X = 8, TILE_Y = 8, TILE_Z = 4;  // a region block is a tile o
 enum : int { ERR_LINK_OVERFLOW = 1, ERR_SPECIAL_OVERFLOW = 2, ERR_FAST_PARTICLE = 4,
              ERR_NONFINITE = 8, ERR_BAD_INDEX = 16, ERR_FLUID = 32 };
 
+// Population layout: the nodes in runs of POP_RUN consecutive nodes, each
+// run holding its Q populations one after another (POP_RUN elements each).
+// A wave's load of one population covers a whole run segment, and the 19
+// loads of a node range fall in one region of 19 x POP_RUN elements instead
+// of 19 arrays far apart.  Node counts are padded to a multiple of POP_RUN
+// (the array size Q * Ns).
+constexpr int POP_RUN_LOG2 = 10, POP_RUN = 1 << POP_RUN_LOG2;
+__host__ __device__ __forceinline__ long long pidx(long long n, int i) {
+    return (((n >> POP_RUN_LOG2) * Q + i) << POP_RUN_LOG2) | (n & (POP_RUN - 1));
+}
+// The same in 32 bits (Q * Ns elements below 2^32).
+__host__ __device__ __forceinline__ uint32_t pidx32(uint32_t n, int i) {
+    return (((n >> POP_RUN_LOG2) * (uint32_t)Q + (uint32_t)i) << POP_RUN_LOG2) | (n & (uint32_t)(POP_RUN - 1));
+}
+
 // D3Q19 velocities in the order documented in midelbm.h.
 constexpr int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int EY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
@@ -87,7 +102,7 @@ struct Params {
     int nx, ny, nz;
     unsigned periodic;
     long long N;
-    long long Ns;  // stride of the population arrays: N rounded up to 128 (each array 256-byte aligned)
+    long long Ns;  // N rounded up to POP_RUN (the population buffer holds Q * Ns elements, layout pidx)
     int np;
     int bc;
     int n_sub;

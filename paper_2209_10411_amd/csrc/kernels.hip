@@ -520,12 +520,12 @@ __device__ __forceinline__ void links_body(const Params &p, const typename Store
             const int32_t own_ff = own[ff];
             const double ql = l_q[l];
             const DevParticle &Bd = P[pi];
-            const double fbl = (double)Store<S>::ld(A, (long long)ib * p.Ns + n, p.inv_scale);
+            const double fbl = (double)Store<S>::ld(A, pidx(n, ib), p.inv_scale);
             double m0 = 0, m1 = 0, m2 = 0, m3 = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0;
 #pragma unroll
             for (int j = 0; j < Q; ++j) {
-                const double d0 = (double)Store<S>::ld(A, (long long)j * p.Ns + n, p.inv_scale);
-                const double d1 = (double)Store<S>::ld(A, (long long)j * p.Ns + ff, p.inv_scale);
+                const double d0 = (double)Store<S>::ld(A, pidx(n, j), p.inv_scale);
+                const double d1 = (double)Store<S>::ld(A, pidx(ff, j), p.inv_scale);
                 m0 += d0; m1 += EX[j] * d0; m2 += EY[j] * d0; m3 += EZ[j] * d0;
                 k0 += d1; k1 += EX[j] * d1; k2 += EY[j] * d1; k3 += EZ[j] * d1;
             }
@@ -555,7 +555,7 @@ __device__ __forceinline__ void links_body(const Params &p, const typename Store
                 }
                 val = feq64d(ib, rf, ud) + fb - feq64d(ib, rf, uf) + mw;
             }
-            Store<S>::st(B, (long long)i * p.Ns + n, (float)(val - w * p.rho0), p.scale);
+            Store<S>::st(B, pidx(n, i), (float)(val - w * p.rho0), p.scale);
             // exchanged populations relative to w rho0: the uniform reference
             // pressure exerts no force (its per-link terms cancel over a closed
             // surface; a surface touching a wall has no links there)
@@ -1608,9 +1608,8 @@ __device__ void special_update(const Params &p, const typename Store<S>::T *__re
         if (unc && (w || sd)) missing |= 1u << i;
         long long src = n;  // kept beyond a wall
         nbr(p, x, y, z, -EX[i], -EY[i], -EZ[i], src);
-        const T *base = w ? A + (long long)OPP[i] * p.Ns
-                          : sd ? (const T *)B + (long long)i * p.Ns : A + (long long)i * p.Ns;
-        const float v = Store<S>::ld(base, (w || sd) ? n : src, p.inv_scale);
+        const T *base = sd && !w ? (const T *)B : A;
+        const float v = Store<S>::ld(base, w ? pidx(n, OPP[i]) : pidx(sd ? n : src, i), p.inv_scale);
         d[i] = (unc && (w || sd)) ? 0.f : v;
     }
     if (missing) {
@@ -1638,7 +1637,7 @@ __device__ void special_update(const Params &p, const typename Store<S>::T *__re
     }
     collide(d, p);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Store<S>::st(B, (long long)i * p.Ns + n, d[i], p.scale);
+    for (int i = 0; i < Q; ++i) Store<S>::st(B, pidx(n, i), d[i], p.scale);
 }
 
 // Node classification over the body regions.  Where regions overlap, one
@@ -1860,12 +1859,12 @@ __global__ __launch_bounds__(256) void k_special(Params p, const typename Store<
             long long s;
             if (!nbr(p, x, y, z, -c_ex[i], -c_ey[i], -c_ez[i], s)) {
                 if (unc) missing = true;
-                else d = Store<S>::ld(A, (long long)c_opp[i] * p.Ns + n, p.inv_scale);
+                else d = Store<S>::ld(A, pidx(n, c_opp[i]), p.inv_scale);
             } else if (own_old[s] != FLUID) {
                 if (unc) missing = true;
-                else d = Store<S>::ld(B, (long long)i * p.Ns + n, p.inv_scale);
+                else d = Store<S>::ld(B, pidx(n, i), p.inv_scale);
             } else {
-                d = Store<S>::ld(A, (long long)i * p.Ns + s, p.inv_scale);
+                d = Store<S>::ld(A, pidx(s, i), p.inv_scale);
             }
         }
         if (unc) {
@@ -1892,7 +1891,7 @@ __global__ __launch_bounds__(256) void k_special(Params p, const typename Store<
         const float jx = wave_sum(lane < Q ? c_ex[i] * dv : 0.f);
         const float jy = wave_sum(lane < Q ? c_ey[i] * dv : 0.f);
         const float jz = wave_sum(lane < Q ? c_ez[i] * dv : 0.f);
-        if (lane < Q) Store<S>::st(B, (long long)i * p.Ns + n, collide_lane(d, i, dr, jx, jy, jz, p), p.scale);
+        if (lane < Q) Store<S>::st(B, pidx(n, i), collide_lane(d, i, dr, jx, jy, jz, p), p.scale);
     }
 }
 
@@ -1906,7 +1905,7 @@ __global__ void k_init_state(Params p, typename Store<S>::T *A, const int32_t *o
         for (int i = 0; i < Q; ++i) d[i] = 0.f;
         if (own[n] == FLUID) collide(d, p);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Store<S>::st(A, (long long)i * p.Ns + n, d[i], p.scale);
+        for (int i = 0; i < Q; ++i) Store<S>::st(A, pidx(n, i), d[i], p.scale);
     }
 }
 
@@ -1919,10 +1918,10 @@ __global__ void k_collide_stored(Params p, typename Store<S>::T *A, const int32_
         if (own[n] != FLUID) continue;
         float d[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = Store<S>::ld(A, (long long)i * p.Ns + n, p.inv_scale);
+        for (int i = 0; i < Q; ++i) d[i] = Store<S>::ld(A, pidx(n, i), p.inv_scale);
         collide(d, p);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Store<S>::st(A, (long long)i * p.Ns + n, d[i], p.scale);
+        for (int i = 0; i < Q; ++i) Store<S>::st(A, pidx(n, i), d[i], p.scale);
     }
 }
 

@@ -136,13 +136,12 @@ __device__ __forceinline__ bool bulk_update(const Params &p, const typename Stor
     for (int i = 0; i < Q; ++i) {
         const int xs = sx[EX[i] + 1], ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
         const bool wall = (xs | ys | zs) < 0;
-        const T *Ai = wall ? A + (long long)OPP[i] * p.Ns : A + (long long)i * p.Ns;
-        const int src = wall ? n : (zs * p.ny + ys) * p.nx + xs;
-        d[i] = Store<S>::ld(Ai, src, p.inv_scale);
+        d[i] = Store<S>::ld(A, wall ? pidx(n, OPP[i]) : pidx((long long)(zs * p.ny + ys) * p.nx + xs, i),
+                            p.inv_scale);
     }
     const bool bad = collide(d, p);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Store<S>::st_nt(B + (long long)i * p.Ns, n, d[i], p.scale);
+    for (int i = 0; i < Q; ++i) Store<S>::st_nt(B, pidx(n, i), d[i], p.scale);
     return bad;
 }
 
@@ -187,21 +186,21 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typena
     int xm = x - 1, xp = x + 1;  // sources for e_x = +1 and -1; -1 = wall
     if (xm < 0) xm = (p.periodic & 1u) ? p.nx - 1 : -1;
     if (xp >= p.nx) xp = (p.periodic & 1u) ? 0 : -1;
-    const uint32_t Ns = (uint32_t)p.Ns;
     const char *Ab = (const char *)A;
     float d[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ys = sy[EY[i] + 1], zs = sz[EZ[i] + 1];
         const bool rwall = (ys | zs) < 0;  // uniform: the node's own opposite population
-        const uint32_t base = rwall ? (uint32_t)OPP[i] * Ns + (uint32_t)(row * p.nx)
-                                    : (uint32_t)i * Ns + (uint32_t)((zs * p.ny + ys) * p.nx);
+        const uint32_t rb = (uint32_t)((zs * p.ny + ys) * p.nx);  // source row (uniform)
         uint32_t off;
-        if (EX[i] == 0) {
-            off = base + (uint32_t)x;
+        if (rwall) {
+            off = pidx32(n, OPP[i]);
+        } else if (EX[i] == 0) {
+            off = pidx32(rb + (uint32_t)x, i);
         } else {
             const int xs = EX[i] > 0 ? xm : xp;
-            off = rwall ? base + (uint32_t)x : (xs < 0 ? (uint32_t)OPP[i] * Ns + n : base + (uint32_t)xs);
+            off = xs < 0 ? pidx32(n, OPP[i]) : pidx32(rb + (uint32_t)xs, i);
         }
         d[i] = Store<S>::ld((const T *)(Ab + off * (uint32_t)sizeof(T)), 0, p.inv_scale);
     }
@@ -209,7 +208,7 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk(Params p, const typena
     char *Bb = (char *)B;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        Store<S>::st_nt((T *)(Bb + ((uint32_t)i * Ns + n) * (uint32_t)sizeof(T)), 0, d[i], p.scale);
+        Store<S>::st_nt((T *)(Bb + pidx32(n, i) * (uint32_t)sizeof(T)), 0, d[i], p.scale);
     if (bad) atomicOr(err, ERR_FLUID);
 }
 
@@ -256,7 +255,8 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_flat(Params p, const t
 // Fast path (every lane of the wave in a row whose y and z neighbours are
 // inside the box, and not across a periodic seam): a lane loads, for every
 // population i, the aligned 32-bit word of its own pair (x0, x0 + 1) in the
-// source row, at the uniform offset i Ns - e_y nx - e_z nx ny.  An x-shifted
+// source row (node n0 - e_y nx - e_z nx ny; a pair never straddles a run of
+// the population layout).  An x-shifted
 // population takes one of its two values from the neighbouring lane's word
 // (lane - 1's high half for e_x = +1, lane + 1's low half for e_x = -1), moved
 // across the wave by DPP, so every load covers whole cache lines.  Where that
@@ -302,10 +302,8 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const t
     const uint32_t row = n0 / (uint32_t)p.nx;
     const int x0 = (int)(n0 - row * (uint32_t)p.nx);  // even
     const int z = (int)(row / (uint32_t)p.ny), y = (int)row - z * p.ny;
-    const uint32_t Ns = (uint32_t)p.Ns;
     const int nx = p.nx, nxy = p.nx * p.ny;
     const bool interior = y >= 1 && y <= p.ny - 2 && z >= 1 && z <= p.nz - 2;
-    const uint32_t n0b = n0 * 2u;  // byte offset of the pair in every array
     const char *Ab = (const char *)A;
     float d0[Q], d1[Q];
     if (__all(interior)) {
@@ -317,15 +315,19 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const t
         uint32_t w[Q], fx[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            // uniform byte offset of the source row's pair (x0, x0 + 1) in array i
-            const long long db = 2ll * ((long long)i * Ns - EY[i] * nx - EZ[i] * (long long)nxy);
-            w[i] = *(const uint32_t *)(Ab + db + n0b);
+            // the source row's pair (x0, x0 + 1): an even node, so both lie in one run
+            const uint32_t ms = n0 - (uint32_t)(EY[i] * nx) - (uint32_t)(EZ[i] * nxy);
+            w[i] = *(const uint32_t *)(Ab + 2u * pidx32(ms, i));
             if (EX[i] > 0) {  // node 0 pulls x0 - 1
-                const long long fb = !lo_edge ? db - 2 : perx ? db + 2ll * (nx - 1) : 2ll * OPP[i] * Ns;
-                fx[i] = *(const uint16_t *)(Ab + (lo_fix ? fb : db) + n0b);
+                const uint32_t f = !lo_fix ? pidx32(ms, i)
+                                   : !lo_edge ? pidx32(ms - 1u, i)
+                                   : perx ? pidx32(ms + (uint32_t)(nx - 1), i) : pidx32(n0, OPP[i]);
+                fx[i] = *(const uint16_t *)(Ab + 2u * f);
             } else if (EX[i] < 0) {  // node 1 pulls x0 + 2
-                const long long fb = !hi_edge ? db + 4 : perx ? db + 4 - 2ll * nx : 2ll * (OPP[i] * (long long)Ns + 1);
-                fx[i] = *(const uint16_t *)(Ab + (hi_fix ? fb : db) + n0b);
+                const uint32_t f = !hi_fix ? pidx32(ms, i)
+                                   : !hi_edge ? pidx32(ms + 2u, i)
+                                   : perx ? pidx32(ms + 2u - (uint32_t)nx, i) : pidx32(n0 + 1u, OPP[i]);
+                fx[i] = *(const uint16_t *)(Ab + 2u * f);
             }
         }
 #pragma unroll
@@ -366,8 +368,8 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const t
             for (int k = 0; k < 2; ++k) {
                 const int xs = sx[EX[i] + 1][k];
                 const bool wall = (xs | ys | zs) < 0;
-                const uint32_t off = wall ? (uint32_t)OPP[i] * Ns + n0 + k
-                                          : (uint32_t)i * Ns + (uint32_t)((zs * p.ny + ys) * nx + xs);
+                const uint32_t off = wall ? pidx32(n0 + (uint32_t)k, OPP[i])
+                                          : pidx32((uint32_t)((zs * p.ny + ys) * nx + xs), i);
                 const float v = raw16<S>((uint32_t)*(const uint16_t *)(Ab + off * 2u));
                 if (k == 0) d0[i] = v;
                 else d1[i] = v;
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(64 * BULK_WAVES) void k_bulk_pair(Params p, const t
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const uint32_t v = pack16<S>(d0[i], d1[i]);
-        char *q = Bb + 2ull * ((uint32_t)i * Ns) + n0b;
+        char *q = Bb + 2u * pidx32(n0, i);
         if (live0 && live1) __builtin_nontemporal_store(v, (uint32_t *)q);
         else if (live0) __builtin_nontemporal_store((uint16_t)(v & 0xffffu), (uint16_t *)q);
         else __builtin_nontemporal_store((uint16_t)(v >> 16), (uint16_t *)(q + 2));
