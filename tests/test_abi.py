@@ -36,6 +36,20 @@ def test_header_lists_the_hot_path_calls():
         assert n in names
 
 
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises at its first call: a
+    simulation or an ensemble is never set up on anything else."""
+    import paper_2209_10411_amd as m
+    monkeypatch.setattr(m, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(m, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        m.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        m.Simulation(workloads.config1(), device="cpu")
+    with pytest.raises(RuntimeError, match="missing"):
+        m.Ensemble([workloads.config1()], device="cpu")
+
+
 def test_library_exports_every_declared_symbol(mdl):
     L = mdl.lib()
     for n in header_functions():
